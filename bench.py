@@ -1,0 +1,152 @@
+#!/usr/bin/env python3
+"""Benchmark: TV/L2 reconstructions per second on one MI355X.
+
+Workload (the single-image configuration of the method's dense-A path): n = 128
+(16384 pixels), m = 4096 Gaussian rows (25 %), FP32 A (256 MiB), 20 random
+rectangles/disks plus a linear ramp, noise sigma = 1e-3, mu = 1e3, beta = 10,
+500 iterations of the accelerated inexact ADM (Alg. 2), tol = 0.  One step is
+one full reconstruction; inputs are resident in HBM before the timed region.
+
+Prints one JSON line with the throughput, the roofline of the dominant kernel
+(the A u product, timed with HIP events on the stream it runs on), the FP64
+oracle timed on the host cores, and the relative error of the GPU result
+against that oracle run (same tau on both sides).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        n = [i.get("num_threads", 0) for i in threadpool_info() if i.get("user_api") == "blas"]
+        if n:
+            return int(max(n))
+    except Exception:
+        pass
+    return len(os.sched_getaffinity(0))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--iters", type=int, default=500)
+    ap.add_argument("--alg", choices=["iadm", "ftvcs"], default="iadm")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "bench.py measures one GPU: the method's images are "
+                          "independent given A, so more GPUs only replicate A and split the "
+                          "batch; run with --gpus 1"}), flush=True)
+        sys.exit(2)
+
+    import torch
+
+    import oracle as O
+    from paper_1001_1774_amd import synth, tvcs
+
+    t0 = time.time()
+    p = synth.workload("n128_m4096")            # FP64 A, FP64 f
+    log(f"workload n128_m4096 generated in {time.time() - t0:.1f}s")
+    tau = O.default_tau(p.A)
+    flags_alg = tvcs.TVCS_IADM if args.alg == "iadm" else 0
+
+    # ---- FP64 oracle on the host cores (one full reconstruction) ----------------
+    cpu = None
+    ref_u = None
+    if not args.no_cpu_baseline:
+        alg = O.iadm if args.alg == "iadm" else O.ftvcs
+        t0 = time.perf_counter()
+        ref = alg(p.A, p.f[:1], p.n, p.mu, p.beta, tau, tol=0, maxit=args.iters)
+        dt = time.perf_counter() - t0
+        ref_u = ref.u[0]
+        cpu = {"value": 1.0 / dt, "unit": "reconstructions/s", "cores": cpu_threads(),
+               "kind": "oracle",
+               "sample": f"one full reconstruction of image 0 ({args.iters} {args.alg.upper()} "
+                         f"iterations, FP64 numpy, {dt:.2f} s)"}
+        log(f"cpu oracle: {dt:.2f}s per reconstruction")
+
+    # ---- GPU --------------------------------------------------------------------
+    assert torch.cuda.is_available(), "no GPU"
+    dev = torch.device("cuda:0")
+    solver = tvcs.Solver(p.A.astype(np.float32), p.n, storage="fp32")
+    solver.tau = tau
+    h = solver.h
+    f = torch.from_numpy(p.f[0].astype(np.float32)).to(dev)
+    u = torch.empty(p.N, dtype=torch.float32, device=dev)
+    st = tvcs.tvcs_stats()
+
+    def step():
+        rc = tvcs.tvcs_solve(h, f, p.mu, p.beta, 0.0, args.iters, flags_alg, u, None, st)
+        if rc < 0:
+            raise tvcs.TvcsError(rc, tvcs.tvcs_last_error())
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    rec_s = args.steps / elapsed
+    rel_err = None
+    if ref_u is not None:
+        ug = u.cpu().numpy().astype(np.float64).reshape(p.n, p.n)
+        rel_err = float(np.linalg.norm(ug - ref_u) / np.linalg.norm(ref_u))
+
+    # ---- roofline of the products (HIP events on the solver's stream) -------------
+    ms_fwd, ms_adj = solver.time_products(B=1, reps=20)
+    a_bytes = 4.0 * p.m * p.N
+    fwd_bytes = a_bytes + 4.0 * (p.N + 2 * p.m)        # A, u, f, r
+    adj_bytes = a_bytes + 4.0 * (p.m + p.N)            # A, r, g
+    fwd_gbs = fwd_bytes / (ms_fwd * 1e-3) / 1e9
+    adj_gbs = adj_bytes / (ms_adj * 1e-3) / 1e9
+
+    out = {
+        "metric": "reconstructions/sec at <=1e-4 rel err vs FP64 (batched vs plain); GEMV GB/s",
+        "value": rec_s,
+        "unit": "reconstructions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"n128_m4096_fp32_{args.alg}{args.iters}", "n": p.n, "m": p.m,
+                   "iterations": args.iters, "algorithm": args.alg.upper(), "storage": "fp32",
+                   "mu": p.mu, "beta": p.beta, "tau": tau, "batch": 1, "seed_A": p.seed_A},
+        "rel_err_vs_fp64_oracle": rel_err,
+        "gemv_gbs": {"forward": fwd_gbs, "adjoint": adj_gbs,
+                     "forward_ms": ms_fwd, "adjoint_ms": ms_adj},
+        "roofline": {"bound": "hbm", "achieved": fwd_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": fwd_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_gemv_rows<1,4> (r = A u - f)"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    solver.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * tvcs.h -- C ABI of the MI355X (gfx950) library for total-variation image
+ * reconstruction from dense random projections.
+ *
+ * The library solves, for an n x n image u (row-major, pixel r*n + c) observed
+ * through a dense m x n^2 matrix A as f = A u + noise (Sec. 1, eq. (obser)),
+ *
+ *     min_u  sum_i ||D_i u||_2 + mu/2 ||A u - f||_2^2             (eq. (tv))
+ *
+ * with the alternating minimisation of Algorithm 1 (FTVCS: shrinkage eq.
+ * (shrink), linearised-proximal u-step eq. (eqnorm)) or the accelerated
+ * inexact ADM of Algorithm 2 (IADM: eqs. (iadmw), (eqnorm11), (udlamb)).
+ * D_i are forward differences with periodic boundary conditions, so each
+ * u-step is solved exactly by a forward and an inverse 2-D FFT (Sec. 2.1).
+ * Every iteration costs two dense products (A u, A^T r), one shrinkage and
+ * two FFTs, all of them hand-written HIP kernels.
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * - Pointers may be host or device memory of the calling process (the library
+ *   copies with hipMemcpyDefault).  Input buffers are only read during the call;
+ *   output buffers are written before the call returns.
+ * - All calls are synchronous for the host: they return after the device work
+ *   they enqueue has finished.  Work is ordered after everything already
+ *   enqueued on the handle's stream (see tvcs_set_stream).
+ * - Return codes: TVCS_OK (0) on success, TVCS_MAXIT (1) when a tolerance was
+ *   given and not met within maxit iterations (outputs are still valid), and a
+ *   negative TVCS_E* code on error, with a message from tvcs_last_error().
+ * - One call per handle at a time; different handles are independent.
+ */
+#ifndef TVCS_H
+#define TVCS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes -------------------------------------------------------- */
+#define TVCS_OK            0
+#define TVCS_MAXIT         1   /* tol > 0 was not met within maxit: outputs valid   */
+#define TVCS_EINVAL       -1   /* bad argument (NULL, size, non-positive parameter) */
+#define TVCS_ENOMEM       -2   /* device allocation failed / HBM budget exceeded    */
+#define TVCS_EDEVICE      -3   /* HIP runtime error                                 */
+#define TVCS_ENONFINITE   -4   /* NaN or Inf appeared in an iterate                 */
+#define TVCS_EUNSUPPORTED -5   /* n not a power of two in [8, 512], or similar      */
+
+/* ---- solve flags --------------------------------------------------------- */
+/* Algorithm 2 (IADM) instead of Algorithm 1 (FTVCS). */
+#define TVCS_IADM     0x1u
+/* Start from u^0 = 0 instead of u^0 = A^T f.  (Alg. 1 and 2 print "u^0 = f",
+ * which has the wrong length; A^T f is the default reading.) */
+#define TVCS_U0_ZERO  0x2u
+/* Compute stats.objective (one extra product with A and a TV sum). */
+#define TVCS_OBJECTIVE 0x4u
+/* Warm start: on entry u holds u^0 and, with TVCS_IADM and a non-NULL lambda,
+ * lambda holds lambda^0 (otherwise lambda^0 = 0).  Used to continue a run, e.g.
+ * across the stages of a continuation in beta (Sec. 3.1). */
+#define TVCS_WARM_START 0x8u
+
+/* ---- storage of A on the device ------------------------------------------ */
+/* A is first rounded to FP32 (nearest-even), then to the storage format.    */
+#define TVCS_A_FP32          0  /* FP32, 4 bytes/entry; FP32 GEMV kernels           */
+#define TVCS_A_BF16          1  /* bf16(A), 2 bytes/entry; MFMA with FP32 accumulate */
+#define TVCS_A_BF16_SPLIT    2  /* hi = bf16(A), lo = bf16(A - hi); hi*x_hi +
+                                   hi*x_lo + lo*x_hi on MFMA, 4 bytes/entry          */
+#define TVCS_A_FP8_ROWSCALE  3  /* s_i = max_j |A_ij| / 448 (FP32), q_ij = OCP E4M3
+                                   nearest-even of A_ij / s_i; 1 byte/entry + 4/row  */
+
+typedef struct tvcs_ctx *tvcs_handle;
+
+/* Per-image results of a solve. */
+typedef struct {
+    int    iters;       /* u-updates performed (eq. (stop) is tested after each) */
+    int    status;      /* TVCS_OK, TVCS_MAXIT or TVCS_ENONFINITE for this image */
+    double rel_change;  /* last ||u^{k+1} - u^k|| / ||u^k||, FP64                */
+    double objective;   /* sum_i ||D_i u|| + mu/2 ||A u - f||^2 at the returned u
+                           with the stored A (only with TVCS_OBJECTIVE, else 0)  */
+    double tau;         /* step parameter tau used                               */
+    float  ms;          /* device time of the whole solve call, milliseconds     */
+} tvcs_stats;
+
+/*
+ * tvcs_create: copy a dense FP32 A (m x n*n, row-major: column r*n + c
+ * multiplies pixel (r, c)) to the device in TVCS_A_FP32 storage, and estimate
+ * lambda_max(A^T A) for the default step tau = 1.9 / lambda_max (Thm. 1 needs
+ * 0 < tau < 2 / lambda_max).  The caller keeps ownership of A and may free it
+ * when the call returns.  Uses the default stream.
+ * Returns NULL on error (see tvcs_last_error): m < 1, n not a power of two in
+ * [8, 512], A NULL, or out of device memory.
+ */
+tvcs_handle tvcs_create(const float *A, int m, int n);
+
+/*
+ * tvcs_create_ex: as tvcs_create, with
+ *   a_is_fp64  0: A holds float, 1: A holds double (rounded to FP32 first);
+ *   storage    one of TVCS_A_*;
+ *   stream     a hipStream_t (may be NULL for the default stream) on which all
+ *              work of this handle is ordered.
+ * Storage formats other than FP32 also keep a transposed copy of A so that
+ * both products read their reduction dimension contiguously (2x the bytes of
+ * the format; the HBM traffic per product is unchanged).
+ */
+tvcs_handle tvcs_create_ex(const void *A, int a_is_fp64, int m, int n, int storage,
+                           void *stream);
+
+/* Set the stream the handle's work is ordered on (hipStream_t or NULL). */
+int tvcs_set_stream(tvcs_handle h, void *stream);
+
+/* Set tau explicitly (> 0), or restore the automatic 1.9 / lambda_max (<= 0). */
+int tvcs_set_tau(tvcs_handle h, double tau);
+
+/* Current tau and the power-iteration estimate of lambda_max(A^T A) for the
+ * stored A (FP64 norms, start vector 1/sqrt(N), up to 100 steps or relative
+ * Rayleigh-quotient change < 1e-10).  Return a negative value on error. */
+double tvcs_get_tau(tvcs_handle h);
+double tvcs_lambda_max(tvcs_handle h);
+
+/* Bytes of device memory held by the handle (A storage and workspaces). */
+size_t tvcs_device_bytes(tvcs_handle h);
+
+/*
+ * tvcs_solve: reconstruct one image.
+ *   f      m observations (FP32);
+ *   mu     fidelity weight > 0;  beta  penalty parameter > 0;
+ *   tol    stop when ||u^{k+1} - u^k|| <= tol ||u^k|| (eq. (stop), FP64 norms,
+ *          inclusive); tol = 0 runs exactly maxit iterations; tol < 0 is EINVAL;
+ *   maxit  iteration cap >= 1;
+ *   flags  TVCS_IADM | TVCS_U0_ZERO | TVCS_OBJECTIVE | TVCS_WARM_START;
+ *   u      n*n output (FP32, caller-owned); input u^0 with TVCS_WARM_START;
+ *   lambda optional 2*n*n output (FP64, planar: horizontal then vertical
+ *          component) of the IADM multiplier after the last iteration; NULL to
+ *          skip; ignored without TVCS_IADM; input lambda^0 with TVCS_WARM_START;
+ *   st     optional stats (NULL to skip).
+ * Returns TVCS_OK, TVCS_MAXIT, or an error code.
+ */
+int tvcs_solve(tvcs_handle h, const float *f, double mu, double beta, double tol, int maxit,
+               unsigned flags, float *u, double *lambda, tvcs_stats *st);
+
+/*
+ * tvcs_solve_batch: reconstruct B images that share A, in one run of the loop.
+ *   F  B x m observations (image-major); U  B x n*n outputs; lambda  optional
+ *   B x 2*n*n (FP64); st  optional array of B stats.
+ * Each image stops on its own by eq. (stop); an image that has stopped is not
+ * updated any more, so its result and iteration count equal those of a solve
+ * of that image alone (up to the products' rounding, which does not depend on
+ * the image's slot).  FP32 storage applies A to up to 8 images per pass of A;
+ * the other storage formats use MFMA GEMMs over the whole batch.
+ * Returns TVCS_OK if every image met tol (or tol = 0), else TVCS_MAXIT, or an
+ * error code (TVCS_ENONFINITE if any image became non-finite).
+ */
+int tvcs_solve_batch(tvcs_handle h, const float *F, int B, double mu, double beta, double tol,
+                     int maxit, unsigned flags, float *U, double *lambda, tvcs_stats *st);
+
+/*
+ * tvcs_time_products: measurement helper.  Average device time in milliseconds
+ * of one forward product (r = A u - f, all images of a batch of B) and of one
+ * adjoint product (A^T r, including its partial-sum reduction), over `reps`
+ * launches of each timed with HIP events on the stream the solver launches them
+ * on, with the launch configuration a solve of B images uses.  Inputs are the
+ * handle's workspace contents (any values).  Either output may be NULL.
+ */
+int tvcs_time_products(tvcs_handle h, int B, int reps, float *ms_forward, float *ms_adjoint);
+
+/* Release the handle and all its device memory.  NULL is ignored. */
+void tvcs_destroy(tvcs_handle h);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *tvcs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TVCS_H */

@@ -1,0 +1,204 @@
+// FP32 dense products A u and A^T r for a row-major A (m x N), streamed from HBM.
+//
+// These are the "two matrix-vector multiplications" of each iteration (Sec. 2.1,
+// g_k = A^T (A u^k - f) in eq. (line)).  Both read A once per call with 16-byte
+// coalesced loads along its rows, so one row-major copy of A serves both:
+//   * rows: one workgroup owns ROWS consecutive rows and sweeps them together, so
+//     each u element loaded from cache feeds ROWS rows; the dot products are
+//     reduced across the workgroup (wave shuffles, then LDS).
+//   * cols: one workgroup owns 1024 consecutive columns (a float4 per thread) and
+//     a chunk of rows; each row segment is a contiguous 4 KiB read.  Per-chunk
+//     partial sums go to a buffer and are added in a fixed order by the consumer
+//     (no atomics), so results are bit-reproducible run to run.
+// Up to NV right-hand sides share one pass over A (batched solves).
+//
+// Products and sums are formed in FP64 from the FP32 operands (each product is
+// exact).  r = A u - f is a small residual of O(1) terms, so FP32 accumulation
+// would put an error of ~sqrt(N) eps |A||u| into it; the FP64 units have an
+// order of magnitude more throughput than this HBM-bound loop needs.
+#include "tvcs_internal.h"
+
+#include <algorithm>
+
+namespace tvcs {
+namespace {
+
+constexpr int kThreads = 256;
+
+// native 4-wide vector (the nontemporal load builtin needs a clang vector type)
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ inline bool any_active(const ImgState *st, int nact) {
+    if (st == nullptr) return true;
+    int a = 0;
+    for (int i = 0; i < nact; ++i) a |= st[i].active;
+    return a != 0;
+}
+
+__device__ inline double dot4(f4 a, const double (&x)[4], double acc) {
+    acc = fma((double)a.x, x[0], acc);
+    acc = fma((double)a.y, x[1], acc);
+    acc = fma((double)a.z, x[2], acc);
+    return fma((double)a.w, x[3], acc);
+}
+
+template <int NV, int ROWS>
+__global__ __launch_bounds__(kThreads) void k_gemv_rows(
+    const float *__restrict__ A, int m, int N, const float *__restrict__ U, int ldu,
+    const float *__restrict__ F, int ldf, float *__restrict__ R, int ldr,
+    const ImgState *__restrict__ st, int nact) {
+    if (!any_active(st, nact)) return;
+    const int row0 = blockIdx.x * ROWS;
+    const int N4 = N >> 2;
+    const f4 *rowp[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int row = min(row0 + r, m - 1);   // ragged tail: re-read a valid row
+        rowp[r] = reinterpret_cast<const f4 *>(A + (size_t)row * N);
+    }
+    double acc[ROWS][NV];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[r][v] = 0.0;
+
+#pragma unroll 4
+    for (int j = threadIdx.x; j < N4; j += kThreads) {
+        f4 a[ROWS];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) a[r] = __builtin_nontemporal_load(rowp[r] + j);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const f4 x = reinterpret_cast<const f4 *>(U + (size_t)v * ldu)[j];
+            const double xd[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) acc[r][v] = dot4(a[r], xd, acc[r][v]);
+        }
+    }
+
+    // reduce over the 64 lanes of each wave, then over the 4 waves
+    __shared__ double red[kThreads / 64][ROWS * NV];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double x = acc[r][v];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+            if (lane == 0) red[wave][r * NV + v] = x;
+        }
+    __syncthreads();
+    if (threadIdx.x < ROWS * NV) {
+        const int r = threadIdx.x / NV, v = threadIdx.x % NV;
+        const int row = row0 + r;
+        if (row < m) {
+            double x = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                       (red[2][threadIdx.x] + red[3][threadIdx.x]);
+            if (F) x -= (double)F[(size_t)v * ldf + row];
+            R[(size_t)v * ldr + row] = (float)x;
+        }
+    }
+}
+
+template <int NV>
+__global__ __launch_bounds__(kThreads) void k_gemv_cols(
+    const float *__restrict__ A, int m, int N, const float *__restrict__ Rv, int ldr,
+    float *__restrict__ P, long long chunk_stride, int rows_per_chunk,
+    const ImgState *__restrict__ st, int nact) {
+    if (!any_active(st, nact)) return;
+    extern __shared__ double rs[];           // rows_per_chunk x NV coefficients
+    const int chunk = blockIdx.y;
+    const int i0 = chunk * rows_per_chunk;
+    const int rows = min(rows_per_chunk, m - i0);
+    for (int t = threadIdx.x; t < rows * NV; t += kThreads) {
+        const int i = t / NV, v = t % NV;
+        rs[t] = Rv[(size_t)v * ldr + i0 + i];
+    }
+    __syncthreads();
+    const int N4 = N >> 2;
+    const int j4 = blockIdx.x * kThreads + threadIdx.x;
+    if (j4 >= N4) return;
+    const f4 *col = reinterpret_cast<const f4 *>(A + (size_t)i0 * N) + j4;
+    double acc[NV][4];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v][0] = acc[v][1] = acc[v][2] = acc[v][3] = 0.0;
+#pragma unroll 8
+    for (int i = 0; i < rows; ++i) {
+        const f4 a = __builtin_nontemporal_load(col + (size_t)i * N4);
+        const double ax = a.x, ay = a.y, az = a.z, aw = a.w;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double r = rs[i * NV + v];
+            acc[v][0] = fma(ax, r, acc[v][0]);
+            acc[v][1] = fma(ay, r, acc[v][1]);
+            acc[v][2] = fma(az, r, acc[v][2]);
+            acc[v][3] = fma(aw, r, acc[v][3]);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+        reinterpret_cast<f4 *>(P + chunk * chunk_stride + (size_t)v * N)[j4] =
+            f4{(float)acc[v][0], (float)acc[v][1], (float)acc[v][2], (float)acc[v][3]};
+}
+
+template <int NV>
+void rows_dispatch(const float *A, int m, int N, const float *U, int ldu, const float *F,
+                   int ldf, float *R, int ldr, const ImgState *st, int nact, hipStream_t s) {
+    constexpr int ROWS = NV <= 2 ? 4 : 2;
+    const int grid = (m + ROWS - 1) / ROWS;
+    hipLaunchKernelGGL((k_gemv_rows<NV, ROWS>), dim3(grid), dim3(kThreads), 0, s, A, m, N, U,
+                       ldu, F, ldf, R, ldr, st, nact);
+}
+
+template <int NV>
+void cols_dispatch(const float *A, int m, int N, const float *R, int ldr, float *P,
+                   long long chunk_stride, const ImgState *st, int nact, hipStream_t s) {
+    const int nchunk = gemv_cols_chunks(m, N, NV);
+    const int rpc = (m + nchunk - 1) / nchunk;
+    const int colblocks = (N / 4 + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL((k_gemv_cols<NV>), dim3(colblocks, nchunk), dim3(kThreads),
+                       sizeof(double) * rpc * NV, s, A, m, N, R, ldr, P, chunk_stride, rpc, st,
+                       nact);
+}
+
+}  // namespace
+
+int gemv_cols_chunks(int m, int N, int nv) {
+    // Aim for ~1024 workgroups; keep chunks >= 16 rows so partial-sum traffic
+    // stays a few percent of the A stream, and the chunk's coefficients
+    // (rows x nv doubles) within 64 KiB of LDS.
+    const int colblocks = (N / 4 + kThreads - 1) / kThreads;
+    int nchunk = (1024 + colblocks - 1) / colblocks;
+    nchunk = std::max(1, std::min(nchunk, (m + 15) / 16));
+    nchunk = std::max(nchunk, (m * nv + 8191) / 8192);
+    // rows per chunk is ceil(m / nchunk); recompute nchunk so none is empty
+    const int rpc = (m + nchunk - 1) / nchunk;
+    return (m + rpc - 1) / rpc;
+}
+
+void launch_gemv_rows(const float *A, int m, int N, const float *U, int ldu, const float *F,
+                      int ldf, float *R, int ldr, int nv, const ImgState *st, int nact,
+                      hipStream_t s) {
+    switch (nv) {
+        case 1: rows_dispatch<1>(A, m, N, U, ldu, F, ldf, R, ldr, st, nact, s); break;
+        case 2: rows_dispatch<2>(A, m, N, U, ldu, F, ldf, R, ldr, st, nact, s); break;
+        case 4: rows_dispatch<4>(A, m, N, U, ldu, F, ldf, R, ldr, st, nact, s); break;
+        case 8: rows_dispatch<8>(A, m, N, U, ldu, F, ldf, R, ldr, st, nact, s); break;
+        default: fail(TVCS_EINVAL, "gemv_rows: nv must be 1, 2, 4 or 8");
+    }
+}
+
+void launch_gemv_cols(const float *A, int m, int N, const float *R, int ldr, float *P,
+                      long long chunk_stride, int nv, const ImgState *st, int nact,
+                      hipStream_t s) {
+    switch (nv) {
+        case 1: cols_dispatch<1>(A, m, N, R, ldr, P, chunk_stride, st, nact, s); break;
+        case 2: cols_dispatch<2>(A, m, N, R, ldr, P, chunk_stride, st, nact, s); break;
+        case 4: cols_dispatch<4>(A, m, N, R, ldr, P, chunk_stride, st, nact, s); break;
+        case 8: cols_dispatch<8>(A, m, N, R, ldr, P, chunk_stride, st, nact, s); break;
+        default: fail(TVCS_EINVAL, "gemv_cols: nv must be 1, 2, 4 or 8");
+    }
+}
+
+}  // namespace tvcs

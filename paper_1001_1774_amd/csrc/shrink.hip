@@ -1,0 +1,192 @@
+// Fused finite differences + two-dimensional shrinkage + D^T, producing the
+// right-hand side of the u-step.
+//
+// FTVCS (Alg. 1): w = s(D u^k) (eq. (shrink)); the u-step (eq. (eqnorm)) is
+// (D^T D + c I) u^{k+1} = D^T w + c (u^k - tau g_k), c = mu / (beta tau),
+// g_k = A^T (A u^k - f).  Subtracting (D^T D + c I) u^k from both sides gives the
+// same step for the increment,
+//     (D^T D + c I) (u^{k+1} - u^k) = D^T (w - D u^k) - c tau g_k,
+// which is what this kernel's right-hand side holds: the FP32 FFT solve then only
+// carries the small increment, so its rounding (~eps ||rhs||) scales with
+// ||u^{k+1} - u^k|| instead of with c ||u^k||, and does not pile up over hundreds
+// of iterations.  The inverse row pass adds the increment to u^k.
+//
+// IADM (Alg. 2) keeps one planar FP64 field q = w^{k+1} - lambda^k / beta instead
+// of the pair (w, lambda).  With lambda^{k} = lambda^{k-1} - beta (w^k - D u^k)
+// (eq. (udlamb)) this gives lambda^k / beta = D u^k - q^{k-1}, so the w-step
+// (eq. (iadmw), shrinkage centre D u^k + lambda^k / beta) and the right-hand side
+// of eq. (eqnorm11) become
+//     q^k = s(2 D u^k - q^{k-1}) - D u^k + q^{k-1},   rhs = D^T (q^k - D u^k) - c tau g_k
+// (increment form as above),
+// and lambda^K = beta (D u^K - q^{K-1}) is recovered at the end.  q^{-1} is set to
+// D u^0 - lambda^0 / beta.  This reads 16 bytes and writes 16 per pixel instead of
+// the 48 that separate (w, lambda) fields would move.
+//
+// D is the periodic forward difference: (D u)[r,c] = (u[r,c+1] - u[r,c],
+// u[r+1,c] - u[r,c]); (D^T q)[r,c] = q1[r,c-1] - q1[r,c] + q2[r-1,c] - q2[r,c].
+// Each thread owns one pixel and recomputes q at its left and upper neighbours,
+// so no LDS halo exchange or second pass is needed; the neighbours' u and q come
+// from L1/L2.  All per-pixel arithmetic is FP64; rhs is rounded to FP32 for the FFT.
+#include "tvcs_internal.h"
+
+namespace tvcs {
+namespace {
+
+struct D2 {
+    double x, y;
+};
+
+__device__ inline D2 shrink2(D2 z, double inv_beta) {
+    const double t = sqrt(z.x * z.x + z.y * z.y);
+    const double s = t > inv_beta ? (t - inv_beta) / t : 0.0;   // 0 * (0/0) = 0
+    return {z.x * s, z.y * s};
+}
+
+__device__ inline int log2i(int n) { return __ffs(n) - 1; }
+
+template <bool IADM>
+__global__ __launch_bounds__(256) void k_shrink_rhs(ShrinkArgs a) {
+    const int b = blockIdx.y;
+    if (!a.st[b].active) return;
+    const int n = a.n, N = n * n, mask = n - 1, ln = log2i(n);
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int r = p >> ln, c = p & mask;
+    const float *u = a.U + (size_t)b * N;
+    auto U = [&](int rr, int cc) -> double { return (double)u[((rr & mask) << ln) | (cc & mask)]; };
+    const double u0 = U(r, c), uE = U(r, c + 1), uS = U(r + 1, c), uW = U(r, c - 1),
+                 uSW = U(r + 1, c - 1), uN = U(r - 1, c), uNE = U(r - 1, c + 1);
+    const D2 d0 = {uE - u0, uS - u0};      // D u at (r, c)
+    const D2 dW = {u0 - uW, uSW - uW};     // D u at (r, c-1)
+    const D2 dN = {uNE - uN, u0 - uN};     // D u at (r-1, c)
+    const double ib = 1.0 / a.beta;
+    D2 q0, qW, qN;
+    if (IADM) {
+        const double *Q1 = a.Qold + (size_t)b * 2 * N, *Q2 = Q1 + N;
+        const int pW = (r << ln) | ((c - 1) & mask), pN = (((r - 1) & mask) << ln) | c;
+        const D2 o0 = {Q1[p], Q2[p]}, oW = {Q1[pW], Q2[pW]}, oN = {Q1[pN], Q2[pN]};
+        auto step = [&](D2 d, D2 o) {
+            const D2 s = shrink2({2.0 * d.x - o.x, 2.0 * d.y - o.y}, ib);
+            return D2{s.x - d.x + o.x, s.y - d.y + o.y};
+        };
+        q0 = step(d0, o0);
+        qW = step(dW, oW);
+        qN = step(dN, oN);
+        double *W1 = a.Qnew + (size_t)b * 2 * N;
+        W1[p] = q0.x;
+        W1[N + p] = q0.y;
+    } else {
+        q0 = shrink2(d0, ib);
+        qW = shrink2(dW, ib);
+        qN = shrink2(dN, ib);
+    }
+    // g_k at this pixel: fixed-order sum of the A^T r partials, eight independent
+    // loads in flight (the sum is latency-bound, not bandwidth-bound)
+    const float *g = a.G + (size_t)(b / a.gnv) * a.g_group_stride + (size_t)(b % a.gnv) * N + p;
+    double gs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int k = 0;
+    for (; k + 8 <= a.nchunk; k += 8) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) gs[j] += (double)g[(size_t)(k + j) * a.g_chunk_stride];
+    }
+    for (int j = 0; k < a.nchunk; ++k, ++j) gs[j] += (double)g[(size_t)k * a.g_chunk_stride];
+    const double gk = ((gs[0] + gs[1]) + (gs[2] + gs[3])) + ((gs[4] + gs[5]) + (gs[6] + gs[7]));
+    // D^T (q - D u) at (r, c): needs (q - D u) here, at (r, c-1) and at (r-1, c)
+    const double dtq = ((qW.x - dW.x) - (q0.x - d0.x)) + ((qN.y - dN.y) - (q0.y - d0.y));
+    a.RHS[(size_t)b * N + p] = (float)(dtq - a.ctau * gk);
+}
+
+__global__ void k_init_q(int n, const float *__restrict__ U, const double *__restrict__ lam0,
+                         double inv_beta, double *__restrict__ Q) {
+    const int b = blockIdx.y, N = n * n, mask = n - 1, ln = log2i(n);
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int r = p >> ln, c = p & mask;
+    const float *u = U + (size_t)b * N;
+    const double u0 = u[p], uE = u[(r << ln) | ((c + 1) & mask)],
+                 uS = u[(((r + 1) & mask) << ln) | c];
+    double q1 = uE - u0, q2 = uS - u0;
+    if (lam0) {
+        q1 -= lam0[(size_t)b * 2 * N + p] * inv_beta;
+        q2 -= lam0[(size_t)b * 2 * N + N + p] * inv_beta;
+    }
+    Q[(size_t)b * 2 * N + p] = q1;
+    Q[(size_t)b * 2 * N + N + p] = q2;
+}
+
+__global__ void k_lambda_out(int n, const float *__restrict__ U, const double *__restrict__ Q0,
+                             const double *__restrict__ Q1, const ImgState *__restrict__ st,
+                             double beta, double *__restrict__ lam) {
+    const int b = blockIdx.y, N = n * n, mask = n - 1, ln = log2i(n);
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const double *Q = (st[b].iters & 1) ? Q1 : Q0;
+    const int r = p >> ln, c = p & mask;
+    const float *u = U + (size_t)b * N;
+    const double u0 = u[p], uE = u[(r << ln) | ((c + 1) & mask)],
+                 uS = u[(((r + 1) & mask) << ln) | c];
+    lam[(size_t)b * 2 * N + p] = beta * ((uE - u0) - Q[(size_t)b * 2 * N + p]);
+    lam[(size_t)b * 2 * N + N + p] = beta * ((uS - u0) - Q[(size_t)b * 2 * N + N + p]);
+}
+
+__global__ __launch_bounds__(256) void k_objective(int n, int m, const float *__restrict__ U,
+                                                   const float *__restrict__ R, int ldr,
+                                                   double mu, double *__restrict__ obj) {
+    const int b = blockIdx.x, N = n * n, mask = n - 1, ln = log2i(n);
+    const float *u = U + (size_t)b * N;
+    double tv = 0.0, rr = 0.0;
+    for (int p = threadIdx.x; p < N; p += blockDim.x) {
+        const int r = p >> ln, c = p & mask;
+        const double u0 = u[p], d1 = u[(r << ln) | ((c + 1) & mask)] - u0,
+                     d2 = u[(((r + 1) & mask) << ln) | c] - u0;
+        tv += sqrt(d1 * d1 + d2 * d2);
+    }
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        const double x = R[(size_t)b * ldr + i];
+        rr += x * x;
+    }
+    __shared__ double s_tv[256], s_rr[256];
+    s_tv[threadIdx.x] = tv;
+    s_rr[threadIdx.x] = rr;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s_tv[threadIdx.x] += s_tv[threadIdx.x + w];
+            s_rr[threadIdx.x] += s_rr[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) obj[b] = s_tv[0] + 0.5 * mu * s_rr[0];
+}
+
+}  // namespace
+
+void launch_shrink_rhs(const ShrinkArgs &a, bool iadm, hipStream_t s) {
+    const int N = a.n * a.n;
+    const dim3 grid((N + 255) / 256, a.B);
+    if (iadm)
+        hipLaunchKernelGGL(k_shrink_rhs<true>, grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_shrink_rhs<false>, grid, dim3(256), 0, s, a);
+}
+
+void launch_init_q(int n, int B, const float *U, const double *lam0, double beta, double *Q,
+                   hipStream_t s) {
+    const int N = n * n;
+    hipLaunchKernelGGL(k_init_q, dim3((N + 255) / 256, B), dim3(256), 0, s, n, U, lam0,
+                       1.0 / beta, Q);
+}
+
+void launch_lambda_out(int n, int B, const float *U, const double *Q0, const double *Q1,
+                       const ImgState *st, double beta, double *lam, hipStream_t s) {
+    const int N = n * n;
+    hipLaunchKernelGGL(k_lambda_out, dim3((N + 255) / 256, B), dim3(256), 0, s, n, U, Q0, Q1, st,
+                       beta, lam);
+}
+
+void launch_objective(int n, int m, int B, const float *U, const float *R, int ldr, double mu,
+                      double *obj, hipStream_t s) {
+    hipLaunchKernelGGL(k_objective, dim3(B), dim3(256), 0, s, n, m, U, R, ldr, mu, obj);
+}
+
+}  // namespace tvcs

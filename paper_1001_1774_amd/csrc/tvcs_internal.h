@@ -1,0 +1,156 @@
+// Internal declarations shared by the library's HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "tvcs.h"
+
+namespace tvcs {
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string &msg);
+
+#define TVCS_HIP(call)                                                                 \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            ::tvcs::fail(TVCS_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Per-image loop state kept on the device.  `active` predicates every per-image
+// kernel: once an image meets the stop rule (or maxit), its kernels return at
+// entry, so no extra iterations touch it.
+struct ImgState {
+    int iters;      // u-updates performed
+    int active;     // 1 while the image still iterates
+    int status;     // TVCS_OK / TVCS_MAXIT / TVCS_ENONFINITE
+    int maxit;      // iteration cap of this image
+    double rel;     // last ||u^{k+1}-u^k|| / ||u^k||
+    double du2;     // last ||u^{k+1}-u^k||^2
+    double u2;      // last ||u^k||^2
+    double tol;     // stop tolerance of this image (0: run maxit iterations)
+};
+
+// Largest image side the FFT kernels handle (LDS twiddle table length).
+constexpr int kMaxN = 512;
+
+// ---------------------------------------------------------------------------
+// FP32 dense products (gemv.hip).  A is m x N row-major FP32.
+//   rows: R[v*ldr + i] = sum_j A[i*N + j] U[v*ldu + j] - F[v*ldf + i], v < nv
+//   cols: P[c*chunk_stride + v*N + j] = sum_{i in chunk c} A[i*N + j] R[v*ldr + i]
+// Both return at entry when `active` is given and none of its `nact` flags is set.
+// ---------------------------------------------------------------------------
+void launch_gemv_rows(const float *A, int m, int N, const float *U, int ldu, const float *F,
+                      int ldf, float *R, int ldr, int nv, const ImgState *active, int nact,
+                      hipStream_t s);
+int gemv_cols_chunks(int m, int N, int nv);   // row chunks used for a given shape
+// chunk c of vector v goes to P[c*chunk_stride + v*N + j]
+void launch_gemv_cols(const float *A, int m, int N, const float *R, int ldr, float *P,
+                      long long chunk_stride, int nv, const ImgState *active, int nact,
+                      hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Reductions and small kernels (util.hip)
+// ---------------------------------------------------------------------------
+// out[v*ldo + j] = sum_c P[c*chunk_stride + v*N + j]  (fixed order, FP64 accumulate)
+void launch_sum_partials(const float *P, int nchunk, long long chunk_stride, int nv, int N,
+                         float *out, int ldo, hipStream_t s);
+void launch_fill(float *x, size_t count, float value, hipStream_t s);
+void launch_init_state(ImgState *st, int B, double tol, int maxit, hipStream_t s);
+// Per-image stop rule after a u-update: sums norm partials, updates state.
+void launch_finalize(ImgState *st, const double *parts, int nparts, int B, hipStream_t s);
+// Power-iteration step for lambda_max(A^T A): rq = v.w, v <- w/||w||; st->rel = rq,
+// st->iters counts steps, st->active cleared once |rq - rq_prev| <= rtol rq.
+void launch_power_normalize(float *v, const float *w, int N, ImgState *st, double rtol,
+                            hipStream_t s);
+// dst[i] = (float)src[i], nearest-even
+void launch_round_f64_f32(const double *src, float *dst, size_t count, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Shrinkage and right-hand side (shrink.hip)
+//   FTVCS: q = s(D u);  IADM: q = s(2 D u - q_old) - D u + q_old
+//   rhs = D^T (q - D u) - c tau g (right side for the increment u^{k+1} - u^k),
+//   g = sum over `nchunk` partials of A^T r
+// ---------------------------------------------------------------------------
+struct ShrinkArgs {
+    int n, B;
+    const float *U;        // B x N
+    // partial sums of A^T r: chunk c of image b at
+    //   G + (b / gnv) * g_group_stride + c * g_chunk_stride + (b % gnv) * N
+    const float *G;
+    int gnv;
+    long long g_group_stride;
+    int nchunk;
+    long long g_chunk_stride;
+    const double *Qold;    // B x 2N (IADM)
+    double *Qnew;          // B x 2N (IADM)
+    float *RHS;            // B x N
+    double beta, c, ctau;  // c = mu/(beta tau), ctau = c*tau = mu/beta
+    const ImgState *st;
+};
+void launch_shrink_rhs(const ShrinkArgs &a, bool iadm, hipStream_t s);
+void launch_init_q(int n, int B, const float *U, const double *lam0, double beta, double *Q,
+                   hipStream_t s);
+// lambda^K = beta (D u^K - q^{K-1}); q^{K-1} is in Q0 when the image's iteration count
+// is even and in Q1 when it is odd (the fields alternate every iteration).
+void launch_lambda_out(int n, int B, const float *U, const double *Q0, const double *Q1,
+                       const ImgState *st, double beta, double *lam, hipStream_t s);
+// obj[b] = TV(u_b) + mu/2 ||r_b||^2
+void launch_objective(int n, int m, int B, const float *U, const float *R, int ldr, double mu,
+                      double *obj, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// FFT solve of (D^T D + c I) u = rhs under periodic BC (fft.hip)
+// Spectrum S: B x (n/2+1) x n complex FP32, k2-major ([b][k2][r]).
+// inv_d: (n/2+1) x n FP64, 1 / (n^2 (4 sin^2(pi k1/n) + 4 sin^2(pi k2/n) + c)).
+// ---------------------------------------------------------------------------
+void launch_twiddles(float2 *tw, hipStream_t s);
+void launch_denominators(int n, double c, double *inv_d, hipStream_t s);
+int fft_row_parts(int n, int B);   // number of norm partials per image written by rows_inv
+void launch_fft_rows_fwd(int n, int B, const float *RHS, float2 *S, const float2 *tw,
+                         const ImgState *st, hipStream_t s);
+void launch_fft_cols_solve(int n, int B, float2 *S, const double *inv_d, const float2 *tw,
+                           const ImgState *st, hipStream_t s);
+void launch_fft_rows_inv(int n, int B, const float2 *S, float *U, double *parts,
+                         const float2 *tw, const ImgState *st, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// MFMA products for bf16 / split-bf16 / fp8 storage (gemm.hip)
+// ---------------------------------------------------------------------------
+struct LowpA {
+    int storage;                 // TVCS_A_BF16 / _BF16_SPLIT / _FP8_ROWSCALE
+    int m, N, mp, Np;            // logical and padded sizes (mp multiple of kMPad)
+    void *X_hi, *X_lo;           // m_p x N   (row products, K = N contiguous)
+    void *XT_hi, *XT_lo;         // N   x m_p (column products, K = m contiguous)
+    float *scale;                // m_p row scales (fp8)
+};
+constexpr int kMPad = 256;       // row padding of A (and K padding of A^T)
+constexpr int kBTile = 16;       // batch granularity of the MFMA products
+
+size_t lowp_storage_bytes(const LowpA &L);          // bytes for the formats of L.storage
+void lowp_bind_storage(LowpA &L, void *base);        // fills mp, Np and the pointers
+void lowp_convert(LowpA &L, const float *A32, hipStream_t s);
+// R[b*ldr + i] = (A u_b)_i - F[b*ldf + i] for b < B (B padded to kBTile in workspace)
+struct LowpWork {
+    void *Ubf_hi, *Ubf_lo;       // Bp x N   bf16 copies of U
+    void *Rbf_hi, *Rbf_lo;       // Bp x m_p bf16 copies of (scaled) R
+    float *Rpart;                // ksplit x Bp x m_p
+    int Bp;
+};
+size_t lowp_work_bytes(const LowpA &L, int B);
+void lowp_work_bind(LowpWork &W, const LowpA &L, int B, void *base);
+void lowp_apply_A(const LowpA &L, LowpWork &W, int B, const float *U, const float *F, float *R,
+                  const ImgState *st, hipStream_t s);
+// G[b*N + j] = (A^T r_b)_j  (G has one chunk)
+void lowp_apply_At(const LowpA &L, LowpWork &W, int B, const float *R, float *G,
+                   const ImgState *st, hipStream_t s);
+
+}  // namespace tvcs

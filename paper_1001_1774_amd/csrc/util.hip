@@ -1,0 +1,164 @@
+// Small kernels: partial-sum reduction, fills, the per-image stop rule and the
+// power iteration that estimates lambda_max(A^T A) for the step tau (Thm. 1).
+// Every reduction adds its terms in a fixed order, so results are reproducible.
+#include "tvcs_internal.h"
+
+#include <algorithm>
+
+namespace tvcs {
+namespace {
+
+__global__ void k_sum_partials(const float *__restrict__ P, int nchunk, long long chunk_stride,
+                               int nv, int N, float *__restrict__ out, int ldo) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y;
+    if (j >= N) return;
+    double acc = 0.0;
+    for (int c = 0; c < nchunk; ++c) acc += (double)P[c * chunk_stride + (size_t)v * N + j];
+    out[(size_t)v * ldo + j] = (float)acc;
+}
+
+__global__ void k_fill(float *x, size_t count, float value) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
+         i += (size_t)gridDim.x * blockDim.x)
+        x[i] = value;
+}
+
+__global__ void k_init_state(ImgState *st, int B, double tol, int maxit) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    ImgState s;
+    s.iters = 0;
+    s.active = 1;
+    s.status = TVCS_OK;
+    s.maxit = maxit;
+    s.rel = 0.0;
+    s.du2 = 0.0;
+    s.u2 = 0.0;
+    s.tol = tol;
+    st[b] = s;
+}
+
+__device__ inline double wave_sum(double x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// One 64-lane block per image.  The stop rule of eq. (stop):
+//   ||u^{k+1} - u^k|| <= tol ||u^k||   (inclusive, FP64, tested after each u-update)
+__global__ __launch_bounds__(64) void k_finalize(ImgState *st, const double *__restrict__ parts,
+                                                 int nparts) {
+    const int b = blockIdx.x;
+    if (!st[b].active) return;
+    double du2 = 0.0, u2 = 0.0;
+    for (int p = threadIdx.x; p < nparts; p += 64) {
+        du2 += parts[((size_t)b * nparts + p) * 2 + 0];
+        u2 += parts[((size_t)b * nparts + p) * 2 + 1];
+    }
+    du2 = wave_sum(du2);
+    u2 = wave_sum(u2);
+    if (threadIdx.x == 0) {
+        ImgState s = st[b];
+        const double tol = s.tol;
+        s.iters += 1;
+        s.du2 = du2;
+        s.u2 = u2;
+        const double du = sqrt(du2), nu = sqrt(u2);
+        s.rel = nu > 0.0 ? du / nu : (du > 0.0 ? INFINITY : 0.0);
+        if (!isfinite(du2) || !isfinite(u2)) {
+            s.status = TVCS_ENONFINITE;
+            s.active = 0;
+        } else if (tol > 0.0 && du <= tol * nu) {
+            s.status = TVCS_OK;
+            s.active = 0;
+        } else if (s.iters >= s.maxit) {
+            s.status = tol > 0.0 ? TVCS_MAXIT : TVCS_OK;
+            s.active = 0;
+        }
+        st[b] = s;
+    }
+}
+
+// Power-iteration step: rq = v . w (= ||A v||^2 for unit v), v <- w / ||w||.
+// Stops (clears st->active) when |rq - rq_prev| <= rtol * rq.
+__global__ __launch_bounds__(1024) void k_power_normalize(float *v, const float *__restrict__ w,
+                                                          int N, ImgState *st, double rtol) {
+    if (!st->active) return;
+    __shared__ double s_dot[16], s_nrm[16];
+    double d = 0.0, q = 0.0;
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+        const double wj = w[j];
+        d += (double)v[j] * wj;
+        q += wj * wj;
+    }
+    d = wave_sum(d);
+    q = wave_sum(q);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        s_dot[wave] = d;
+        s_nrm[wave] = q;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double dd = 0.0, qq = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+            dd += s_dot[i];
+            qq += s_nrm[i];
+        }
+        s_dot[0] = dd;
+        s_nrm[0] = qq;
+    }
+    __syncthreads();
+    const double rq = s_dot[0];
+    const double inv = s_nrm[0] > 0.0 ? 1.0 / sqrt(s_nrm[0]) : 0.0;
+    for (int j = threadIdx.x; j < N; j += blockDim.x) v[j] = (float)(w[j] * inv);
+    if (threadIdx.x == 0) {
+        const double prev = st->rel;
+        st->iters += 1;
+        st->rel = rq;
+        if (st->iters > 1 && fabs(rq - prev) <= rtol * rq) st->active = 0;
+    }
+}
+
+__global__ void k_round_f64_f32(const double *__restrict__ src, float *__restrict__ dst,
+                                size_t count) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = (float)src[i];
+}
+
+}  // namespace
+
+void launch_round_f64_f32(const double *src, float *dst, size_t count, hipStream_t s) {
+    if (count == 0) return;
+    const int grid = (int)std::min<size_t>((count + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_round_f64_f32, dim3(grid), dim3(256), 0, s, src, dst, count);
+}
+
+void launch_sum_partials(const float *P, int nchunk, long long chunk_stride, int nv, int N,
+                         float *out, int ldo, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_partials, dim3((N + 255) / 256, nv), dim3(256), 0, s, P, nchunk,
+                       chunk_stride, nv, N, out, ldo);
+}
+
+void launch_fill(float *x, size_t count, float value, hipStream_t s) {
+    if (count == 0) return;
+    const int grid = (int)std::min<size_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill, dim3(grid), dim3(256), 0, s, x, count, value);
+}
+
+void launch_init_state(ImgState *st, int B, double tol, int maxit, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_state, dim3((B + 63) / 64), dim3(64), 0, s, st, B, tol, maxit);
+}
+
+void launch_finalize(ImgState *st, const double *parts, int nparts, int B, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(B), dim3(64), 0, s, st, parts, nparts);
+}
+
+void launch_power_normalize(float *v, const float *w, int N, ImgState *st, double rtol,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_power_normalize, dim3(1), dim3(1024), 0, s, v, w, N, st, rtol);
+}
+
+}  // namespace tvcs

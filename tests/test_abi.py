@@ -1,0 +1,75 @@
+"""The C ABI: the library loads and exports every declared symbol; the header is
+plain C; argument errors are reported before any device work (CPU only)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tvcs.h")
+LIB = os.path.join(ROOT, "paper_1001_1774_amd", "libtvcs.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tvcs_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for want in ("tvcs_create", "tvcs_create_ex", "tvcs_solve", "tvcs_solve_batch",
+                 "tvcs_destroy", "tvcs_last_error", "tvcs_set_tau"):
+        assert want in names
+
+
+def test_header_is_plain_c(tmp_path):
+    src = tmp_path / "t.c"
+    src.write_text('#include "tvcs.h"\nint main(void){ tvcs_stats s; (void)s; '
+                   'return TVCS_OK + (int)sizeof(tvcs_handle); }\n')
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only",
+                    f"-I{os.path.dirname(HEADER)}", str(src)], check=True)
+
+
+@pytest.fixture(scope="module")
+def clib():
+    if not os.path.exists(LIB):
+        pytest.fail("libtvcs.so not built (python -m paper_1001_1774_amd.build)")
+    import torch  # noqa: F401  same HIP runtime as the binding
+    return ctypes.CDLL(LIB)
+
+
+def test_library_exports_every_declared_symbol(clib):
+    for name in declared_functions():
+        assert hasattr(clib, name), name
+
+
+def test_argument_errors_without_device(clib):
+    from paper_1001_1774_amd import tvcs as T
+    A = np.zeros((4, 64), np.float32)
+    # NULL A, bad m, unsupported n: rejected before any HIP call
+    assert not T.tvcs_create(None, 4, 8)
+    assert "NULL" in T.tvcs_last_error()
+    assert not T.tvcs_create(A, 0, 8)
+    assert "m must be" in T.tvcs_last_error()
+    for n in (7, 4, 1024, 96):
+        assert not T.tvcs_create(np.zeros((4, n * n), np.float32), 4, n)
+        assert "power of two" in T.tvcs_last_error()
+    assert not T.tvcs_create_ex(A, 0, 4, 8, 9, None)
+    assert "storage" in T.tvcs_last_error()
+    # NULL handle
+    u = np.zeros(64, np.float32)
+    f = np.zeros(4, np.float32)
+    assert T.tvcs_solve(None, f, 1.0, 1.0, 0.0, 1, 0, u) == T.TVCS_EINVAL
+    assert T.tvcs_set_tau(None, 1.0) == T.TVCS_EINVAL
+    assert T.tvcs_get_tau(None) < 0
+    T.tvcs_destroy(None)
+
+
+def test_stats_struct_layout():
+    from paper_1001_1774_amd import tvcs as T
+    # int, int, double, double, double, float (+ tail padding) = 40 bytes on x86-64
+    assert ctypes.sizeof(T.tvcs_stats) == 40
