@@ -49,6 +49,9 @@ def main():
     ap.add_argument("--iters", type=int, default=500)
     ap.add_argument("--alg", choices=["iadm", "ftvcs"], default="iadm")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the n = 256 batched-vs-plain section")
+    ap.add_argument("--batched-iters", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py measures one GPU: the method's images are "
@@ -144,8 +147,71 @@ def main():
                      "kernel": "k_gemv_rows<1,4> (r = A u - f)"},
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
     solver.close()
+    del solver
+    if not args.no_batched:
+        out["batched_n256"] = bench_batched(args, np, torch, O, synth, tvcs)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args, np, torch, O, synth, tvcs):
+    """n = 256, m = 13107 (20 %), 64 images sharing A: plain FP32 (one image per
+    solve) against the batched MFMA path in split and plain BF16 storage, at a fixed
+    number of IADM iterations.  Error against the FP64 oracle is checked on image 0
+    after a bounded number of iterations (the FP64 A is 6.9 GB)."""
+    K = args.batched_iters
+    t0 = time.time()
+    p = synth.workload("n256_m13107_b64", sigma=[1e-3 if i % 2 == 0 else 1e-2 for i in range(64)])
+    log(f"workload n256_m13107_b64 generated in {time.time() - t0:.1f}s")
+    A32 = p.A.astype(np.float32)
+    F = torch.from_numpy(p.f.astype(np.float32)).cuda()
+    res = {"workload": "n256_m13107_b64", "n": p.n, "m": p.m, "batch": p.B, "iterations": K,
+           "algorithm": "IADM", "seed_A": p.seed_A}
+    tau = None
+    # plain FP32: one image per solve
+    with tvcs.Solver(A32, p.n, storage="fp32") as s:
+        tau = s.tau
+        s.solve(F[0], mu=p.mu, beta=p.beta, maxit=20, iadm=True)          # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.solve(F[0], mu=p.mu, beta=p.beta, maxit=K, iadm=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ms_f, ms_a = s.time_products(B=1, reps=10)
+    gbs = 4.0 * p.m * p.N / 1e9
+    res["plain_fp32"] = {"rec_per_s": 1.0 / dt, "ms_per_iter": 1e3 * dt / K,
+                         "gemv_gbs_forward": gbs / (ms_f * 1e-3),
+                         "gemv_gbs_adjoint": gbs / (ms_a * 1e-3)}
+    log(f"plain fp32 n=256: {1e3 * dt / K:.3f} ms/iter")
+    # FP64 oracle on image 0, bounded: KC iterations
+    KC = 20
+    ref = O.iadm(p.A, p.f[:1], p.n, p.mu, p.beta, tau, tol=0, maxit=KC)
+    for storage, elem in (("bf16_split", 4), ("bf16", 2)):
+        with tvcs.Solver(A32, p.n, storage=storage) as s:
+            s.tau = tau
+            chk = s.solve_batch(F, mu=p.mu, beta=p.beta, maxit=KC, iadm=True)
+            u0 = chk["u"][0].cpu().numpy().astype(np.float64)
+            err = float(np.linalg.norm(u0 - ref.u[0]) / np.linalg.norm(ref.u[0]))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.solve_batch(F, mu=p.mu, beta=p.beta, maxit=K, iadm=True)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ms_f, ms_a = s.time_products(B=p.B, reps=10)
+        a_bytes = elem * p.m * p.N
+        flops = 2.0 * p.m * p.N * p.B * (3 if storage == "bf16_split" else 1)
+        res[storage] = {
+            "rec_per_s": p.B / dt, "ms_per_iter": 1e3 * dt / K,
+            "speedup_vs_plain_fp32": (p.B / dt) / res["plain_fp32"]["rec_per_s"],
+            "rel_err_vs_fp64_oracle_image0": err, "oracle_check_iterations": KC,
+            "gemm_forward_ms": ms_f, "gemm_adjoint_ms": ms_a,
+            "gemm_forward_gbs": a_bytes / (ms_f * 1e-3) / 1e9,
+            "gemm_adjoint_gbs": a_bytes / (ms_a * 1e-3) / 1e9,
+            "mfma_tflops_forward": flops / (ms_f * 1e-3) / 1e12,
+            "mfma_frac_of_bf16_peak_forward": flops / (ms_f * 1e-3) / 2.5e15,
+        }
+        log(f"{storage} B=64: {1e3 * dt / K:.3f} ms/iter, err {err:.2e}")
+    return res
 
 
 if __name__ == "__main__":

@@ -163,6 +163,62 @@ int tvcs_solve_batch(tvcs_handle h, const float *F, int B, double mu, double bet
  */
 int tvcs_time_products(tvcs_handle h, int B, int reps, float *ms_forward, float *ms_adjoint);
 
+/* ---- continuous-batching request loop ------------------------------------ */
+typedef struct tvcs_server *tvcs_server_handle;
+
+/*
+ * tvcs_server_create: a request loop over encoding matrices registered with
+ * tvcs_server_add_matrix (the batched solve of Sec. 2 applied to a stream of
+ * reconstruction requests).  Each matrix gets `slots` image slots (1..1024): its
+ * batch.  A matrix's slots are allocated when its first request is admitted, and
+ * only if the device bytes of all registered matrices and allocated slot groups
+ * stay within hbm_budget (0: no limit); a group with no request in flight or queued
+ * gives its slots back when another matrix's requests wait for room.  mu, beta and
+ * flags (0 or TVCS_IADM) apply to every request; each request has its own tol and
+ * maxit.  Returns NULL on error (see tvcs_last_error).
+ */
+tvcs_server_handle tvcs_server_create(size_t hbm_budget, int slots, double mu, double beta,
+                                      unsigned flags);
+
+/* Register a matrix.  The server borrows h: it must outlive the server and must not
+ * be used for tvcs_solve / tvcs_solve_batch while the server runs.  Returns the
+ * matrix id (>= 0) or a negative error code. */
+int tvcs_server_add_matrix(tvcs_server_handle s, tvcs_handle h);
+
+/* Queue a reconstruction of f (m floats of that matrix, host or device; copied before
+ * the call returns) with its own stop tolerance tol >= 0 (eq. (stop); 0: exactly
+ * maxit iterations) and cap maxit >= 1.  Returns a request id >= 0, or a negative
+ * error code. */
+long long tvcs_server_submit(tvcs_server_handle s, int matrix, const float *f, double tol,
+                             int maxit);
+
+/*
+ * tvcs_server_step: one scheduling round.  Admits queued requests into free slots
+ * (u^0 = A^T f for the new slots), advances every matrix that holds requests by one
+ * replay of its captured iteration graph (10 iterations; each matrix on its own
+ * stream, so their work overlaps on the device), and retires the requests that met
+ * their stop rule or cap mid-replay.  Requests submitted between rounds join the
+ * running batches at the next round.  A request's iterates do not depend on its
+ * slot, on the other requests or on when it was admitted.  Returns the number of
+ * requests queued or in flight after the round, or a negative error code.
+ */
+int tvcs_server_step(tvcs_server_handle s);
+
+/* Result of a request: returns 1 and fills u (n*n floats, host or device; NULL to
+ * skip) and st (may be NULL; st->ms is the time from admission to retirement) once it
+ * has finished, after which the request id is forgotten; 0 if it has not finished;
+ * TVCS_EINVAL for an unknown id. */
+int tvcs_server_result(tvcs_server_handle s, long long request, float *u, tvcs_stats *st);
+
+/* Requests queued or in flight. */
+int tvcs_server_pending(tvcs_server_handle s);
+
+/* Device bytes counted against the budget (registered matrices and slot groups). */
+size_t tvcs_server_device_bytes(tvcs_server_handle s);
+
+/* Release the server (not the registered handles).  NULL is ignored. */
+void tvcs_server_destroy(tvcs_server_handle s);
+
 /* Release the handle and all its device memory.  NULL is ignored. */
 void tvcs_destroy(tvcs_handle h);
 

@@ -249,10 +249,11 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
 
 // Rows (columns) per workgroup: enough workgroups for one image to spread over
 // the chip, and at most 64 KiB of LDS per workgroup (rpb * n <= 4096 complex,
-// cpb * n <= 2048 complex per buffer).
-int rows_per_block(int n, int B) {
-    int rpb = B == 1 ? std::max(2, n / 32) : 16;
-    return std::max(2, std::min(std::min(rpb, 4096 / n), n));
+// cpb * n <= 2048 complex per buffer).  The row blocking fixes the order in which
+// the stop-rule norms are summed, so it depends on n only: an image's iterates and
+// stop decisions are then the same whatever batch it is solved in.
+int rows_per_block(int n, int /*B*/) {
+    return std::max(2, std::min(n / 32, 4096 / n));
 }
 int cols_per_block(int n, int B) {
     const int h = n / 2 + 1;

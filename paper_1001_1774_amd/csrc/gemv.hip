@@ -154,7 +154,7 @@ void rows_dispatch(const float *A, int m, int N, const float *U, int ldu, const 
 template <int NV>
 void cols_dispatch(const float *A, int m, int N, const float *R, int ldr, float *P,
                    long long chunk_stride, const ImgState *st, int nact, hipStream_t s) {
-    const int nchunk = gemv_cols_chunks(m, N, NV);
+    const int nchunk = gemv_cols_chunks(m, N);   // the same chunks for every NV
     const int rpc = (m + nchunk - 1) / nchunk;
     const int colblocks = (N / 4 + kThreads - 1) / kThreads;
     hipLaunchKernelGGL((k_gemv_cols<NV>), dim3(colblocks, nchunk), dim3(kThreads),
@@ -164,10 +164,12 @@ void cols_dispatch(const float *A, int m, int N, const float *R, int ldr, float 
 
 }  // namespace
 
-int gemv_cols_chunks(int m, int N, int nv) {
+int gemv_cols_chunks(int m, int N) {
     // Aim for ~1024 workgroups; keep chunks >= 16 rows so partial-sum traffic
     // stays a few percent of the A stream, and the chunk's coefficients
-    // (rows x nv doubles) within 64 KiB of LDS.
+    // (rows x nv doubles, nv <= 8) within 64 KiB of LDS.  Independent of nv, so
+    // the order of the sums does not depend on how many vectors share a pass.
+    const int nv = 8;
     const int colblocks = (N / 4 + kThreads - 1) / kThreads;
     int nchunk = (1024 + colblocks - 1) / colblocks;
     nchunk = std::max(1, std::min(nchunk, (m + 15) / 16));

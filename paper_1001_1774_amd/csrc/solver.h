@@ -1,0 +1,358 @@
+// The solver context behind a tvcs_handle: device storage of A, workspaces for a
+// batch, the captured iteration graph, and the product/iteration plan.  Shared by
+// the C entry points (api.cpp) and the serving loop (server.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "tvcs_internal.h"
+
+namespace tvcs {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void ensure(size_t b) {
+        if (b <= bytes && p) return;
+        release();
+        if (b == 0) return;
+        if (hipMalloc(&p, b) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            fail(TVCS_ENOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
+        }
+        bytes = b;
+    }
+    template <class T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+constexpr int kGraphIters = 10;   // iterations per captured graph (even: q ping-pong)
+constexpr int kPowerIters = 100;
+constexpr double kPowerRtol = 1e-10;
+
+}  // namespace tvcs
+
+using namespace tvcs;
+
+struct tvcs_ctx {
+    int m = 0, n = 0, N = 0, storage = TVCS_A_FP32;
+    hipStream_t user = nullptr;   // caller's stream (may be null)
+    hipStream_t work = nullptr;   // internal stream all work and captures run on
+    hipEvent_t ev_in = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
+
+    DevBuf A32;            // FP32 storage
+    LowpA lowp{};          // low-precision storage
+    DevBuf lowp_mem;
+    DevBuf tw;             // FFT twiddles
+    DevBuf invd;           // FFT denominators for invd_c
+    double invd_c = -1.0;
+    double lmax = 0.0, tau_user = 0.0;
+
+    // workspace for a batch of up to `cap` images (Bp padded)
+    int cap = 0, capP = 0;
+    int gnv = 1;           // largest images-per-pass of the FP32 products
+    DevBuf U, F, R, P, RHS, Q0, Q1, S, parts, state, obj, lowp_work, lamb;
+    LowpWork lw{};
+    ImgState *host_state = nullptr;   // pinned mirror for polling
+    int host_state_cap = 0;
+
+    // graph cache
+    hipGraphExec_t exec = nullptr;
+    int g_B = -1;
+    unsigned g_flags = 0;
+    double g_beta = 0, g_c = 0, g_ctau = 0;
+
+    ~tvcs_ctx() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (host_state) (void)hipHostFree(host_state);
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_t0) (void)hipEventDestroy(ev_t0);
+        if (ev_t1) (void)hipEventDestroy(ev_t1);
+        if (work) (void)hipStreamDestroy(work);
+    }
+
+    bool lowprec() const { return storage != TVCS_A_FP32; }
+    double tau() const { return tau_user > 0 ? tau_user : 1.9 / lmax; }
+
+    // padded batch: FP32 products take 1, 2, 4 or 8 vectors per pass of A
+    int padded(int B) const {
+        if (lowprec()) return ((B + kBTile - 1) / kBTile) * kBTile;
+        if (B <= 2) return B;
+        if (B <= 4) return 4;
+        return ((B + 7) / 8) * 8;
+    }
+
+    void ensure_workspace(int B) {
+        if (B <= cap) return;
+        if (exec) {
+            TVCS_HIP(hipGraphExecDestroy(exec));
+            exec = nullptr;
+        }
+        const int Bp = padded(B);
+        const size_t Nn = (size_t)N, mm = (size_t)m, h = (size_t)(n / 2 + 1);
+        gnv = lowprec() ? Bp : std::min(Bp, 8);
+        const int nchunk = lowprec() ? 1 : chunks(Bp);
+        U.ensure(sizeof(float) * Bp * Nn);
+        F.ensure(sizeof(float) * Bp * mm);
+        R.ensure(sizeof(float) * Bp * mm);
+        P.ensure(sizeof(float) * (size_t)nchunk * Bp * Nn);
+        RHS.ensure(sizeof(float) * Bp * Nn);
+        Q0.ensure(sizeof(double) * 2 * B * Nn);
+        Q1.ensure(sizeof(double) * 2 * B * Nn);
+        S.ensure(sizeof(float2) * B * h * n);
+        parts.ensure(sizeof(double) * 2 * B * (size_t)n);   // >= n / rows-per-block
+        state.ensure(sizeof(ImgState) * B);
+        obj.ensure(sizeof(double) * B);
+        if (lowprec()) {
+            lowp_work.ensure(lowp_work_bytes(lowp, Bp));
+            lowp_work_bind(lw, lowp, Bp, lowp_work.p);
+        }
+        if (host_state_cap < B) {
+            if (host_state) TVCS_HIP(hipHostFree(host_state));
+            host_state = nullptr;
+            TVCS_HIP(hipHostMalloc((void **)&host_state, sizeof(ImgState) * B));
+            host_state_cap = B;
+        }
+        cap = B;
+        capP = Bp;
+        // padded images must hold zeros (their products are computed and ignored)
+        launch_fill(U.as<float>(), (size_t)Bp * Nn, 0.f, work);
+        launch_fill(F.as<float>(), (size_t)Bp * mm, 0.f, work);
+    }
+
+    // vectors per pass and row chunks of the FP32 products for a padded batch Bp.
+    // The chunking (the order of the A^T r sums) is that of the widest pass for
+    // every batch, so an image's g_k does not depend on the batch it is in.
+    int pass_nv(int Bp) const { return std::min(Bp, 8); }
+    int chunks(int /*Bp*/) const { return gemv_cols_chunks(m, N); }
+
+    // device bytes of the workspace ensure_workspace(B) allocates
+    size_t workspace_bytes(int B) const {
+        const int Bp = padded(B);
+        const size_t Nn = (size_t)N, mm = (size_t)m, h = (size_t)(n / 2 + 1);
+        const int nchunk = lowprec() ? 1 : chunks(Bp);
+        size_t b = sizeof(float) * Bp * (2 * Nn + 2 * mm) + sizeof(float) * (size_t)nchunk * Bp * Nn +
+                   2 * sizeof(double) * 2 * B * Nn + sizeof(float2) * B * h * n +
+                   sizeof(double) * 2 * B * (size_t)n + sizeof(ImgState) * B + sizeof(double) * B;
+        if (lowprec()) b += lowp_work_bytes(lowp, Bp);
+        return b;
+    }
+
+    // device bytes of A's storage and the FFT tables
+    size_t storage_bytes() const { return A32.bytes + lowp_mem.bytes + tw.bytes + invd.bytes; }
+
+    // give the batch workspace back (the next call re-allocates what it needs)
+    void release_workspace() {
+        if (exec) {
+            TVCS_HIP(hipGraphExecDestroy(exec));
+            exec = nullptr;
+        }
+        for (DevBuf *b : {&U, &F, &R, &P, &RHS, &Q0, &Q1, &S, &parts, &state, &obj, &lowp_work, &lamb})
+            b->release();
+        cap = capP = 0;
+    }
+
+    void ensure_denominators(double c) {
+        const size_t cnt = (size_t)(n / 2 + 1) * n;
+        invd.ensure(sizeof(double) * cnt);
+        if (c != invd_c) {
+            launch_denominators(n, c, invd.as<double>(), work);
+            invd_c = c;
+        }
+    }
+
+    // R = A U - F for the first Bp images (F may be null)
+    void apply_A(int Bp, int B, const float *Uin, const float *Fin, float *Rout,
+                 const ImgState *st) {
+        if (lowprec()) {
+            lowp_apply_A(lowp, lw, B, Uin, Fin, Rout, st, work);
+            return;
+        }
+        const int nv = pass_nv(Bp);
+        for (int g = 0; g * nv < Bp; ++g) {
+            const int real = std::max(0, std::min(nv, B - g * nv));
+            if (real == 0) continue;
+            launch_gemv_rows(A32.as<float>(), m, N, Uin + (size_t)g * nv * N, N,
+                             Fin ? Fin + (size_t)g * nv * m : nullptr, m,
+                             Rout + (size_t)g * nv * m, m, nv, st ? st + g * nv : nullptr,
+                             real, work);
+        }
+    }
+
+    // partial sums of A^T Rin into P (layout described by shrink_args)
+    void apply_At(int Bp, int B, const float *Rin, const ImgState *st) {
+        if (lowprec()) {
+            lowp_apply_At(lowp, lw, B, Rin, P.as<float>(), st, work);
+            return;
+        }
+        const int nv = pass_nv(Bp), nchunk = chunks(Bp);
+        const long long cs = (long long)nv * N;
+        for (int g = 0; g * nv < Bp; ++g) {
+            const int real = std::max(0, std::min(nv, B - g * nv));
+            if (real == 0) continue;
+            launch_gemv_cols(A32.as<float>(), m, N, Rin + (size_t)g * nv * m, m,
+                             P.as<float>() + (size_t)g * nchunk * cs, cs, nv,
+                             st ? st + g * nv : nullptr, real, work);
+        }
+    }
+
+    // out = A^T Rin (full sums) for the first Bp images
+    void apply_At_full(int Bp, int B, const float *Rin, float *out, const ImgState *st) {
+        apply_At(Bp, B, Rin, st);
+        if (lowprec()) {
+            TVCS_HIP(hipMemcpyAsync(out, P.p, sizeof(float) * (size_t)Bp * N,
+                                    hipMemcpyDeviceToDevice, work));
+            return;
+        }
+        const int nv = pass_nv(Bp), nchunk = chunks(Bp);
+        const long long cs = (long long)nv * N;
+        for (int g = 0; g * nv < Bp; ++g)
+            launch_sum_partials(P.as<float>() + (size_t)g * nchunk * cs, nchunk, cs, nv, N,
+                                out + (size_t)g * nv * N, N, work);
+    }
+
+    ShrinkArgs shrink_args(int B, int Bp) const {
+        ShrinkArgs a{};
+        a.n = n;
+        a.B = B;
+        a.U = U.as<float>();
+        a.G = P.as<float>();
+        if (lowprec()) {
+            a.gnv = Bp;
+            a.g_group_stride = 0;
+            a.nchunk = 1;
+            a.g_chunk_stride = 0;
+        } else {
+            const int nv = pass_nv(Bp), nchunk = chunks(Bp);
+            a.gnv = nv;
+            a.g_chunk_stride = (long long)nv * N;
+            a.g_group_stride = (long long)nchunk * nv * N;
+            a.nchunk = nchunk;
+        }
+        a.RHS = RHS.as<float>();
+        a.st = state.as<ImgState>();
+        return a;
+    }
+
+    void enqueue_iteration(int B, int parity, bool iadm, double beta, double c, double ctau) {
+        const int Bp = padded(B);
+        ImgState *st = state.as<ImgState>();
+        apply_A(Bp, B, U.as<float>(), F.as<float>(), R.as<float>(), st);
+        apply_At(Bp, B, R.as<float>(), st);
+        ShrinkArgs a = shrink_args(B, Bp);
+        a.beta = beta;
+        a.c = c;
+        a.ctau = ctau;
+        a.Qold = parity ? Q1.as<double>() : Q0.as<double>();
+        a.Qnew = parity ? Q0.as<double>() : Q1.as<double>();
+        launch_shrink_rhs(a, iadm, work);
+        const float2 *twp = tw.as<float2>();
+        float2 *Sp = S.as<float2>();
+        launch_fft_rows_fwd(n, B, RHS.as<float>(), Sp, twp, st, work);
+        launch_fft_cols_solve(n, B, Sp, invd.as<double>(), twp, st, work);
+        launch_fft_rows_inv(n, B, Sp, U.as<float>(), parts.as<double>(), twp, st, work);
+        launch_finalize(st, parts.as<double>(), fft_row_parts(n, B), B, work);
+    }
+
+    void build_graph(int B, unsigned flags, double beta, double c, double ctau) {
+        if (exec && g_B == B && g_flags == flags && g_beta == beta && g_c == c && g_ctau == ctau)
+            return;
+        if (exec) {
+            TVCS_HIP(hipGraphExecDestroy(exec));
+            exec = nullptr;
+        }
+        hipGraph_t graph = nullptr;
+        TVCS_HIP(hipStreamBeginCapture(work, hipStreamCaptureModeRelaxed));
+        try {
+            for (int i = 0; i < kGraphIters; ++i)
+                enqueue_iteration(B, i & 1, (flags & TVCS_IADM) != 0, beta, c, ctau);
+        } catch (...) {
+            (void)hipStreamEndCapture(work, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        TVCS_HIP(hipStreamEndCapture(work, &graph));
+        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            exec = nullptr;
+            fail(TVCS_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        g_B = B;
+        g_flags = flags;
+        g_beta = beta;
+        g_c = c;
+        g_ctau = ctau;
+    }
+
+    void begin_call() {
+        if (user) {
+            TVCS_HIP(hipEventRecord(ev_in, user));
+            TVCS_HIP(hipStreamWaitEvent(work, ev_in, 0));
+        } else {
+            TVCS_HIP(hipStreamSynchronize(nullptr));
+        }
+    }
+
+    void estimate_lambda_max() {
+        ensure_workspace(1);
+        const int Bp = padded(1);
+        ImgState *st = state.as<ImgState>();
+        launch_init_state(st, 1, 0.0, kPowerIters, work);
+        float *v = U.as<float>();
+        launch_fill(v, (size_t)N, (float)(1.0 / std::sqrt((double)N)), work);
+        for (int it = 0; it < kPowerIters; ++it) {
+            apply_A(Bp, 1, v, nullptr, R.as<float>(), st);
+            apply_At_full(Bp, 1, R.as<float>(), RHS.as<float>(), st);
+            launch_power_normalize(v, RHS.as<float>(), N, st, kPowerRtol, work);
+        }
+        ImgState hs;
+        TVCS_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, work));
+        TVCS_HIP(hipStreamSynchronize(work));
+        TVCS_HIP(hipGetLastError());
+        lmax = hs.rel;
+        if (!(lmax > 0) || !std::isfinite(lmax))
+            fail(TVCS_ENONFINITE, "power iteration gave a non-positive lambda_max");
+    }
+
+    size_t device_bytes() const {
+        return A32.bytes + lowp_mem.bytes + tw.bytes + invd.bytes + U.bytes + F.bytes + R.bytes +
+               P.bytes + RHS.bytes + Q0.bytes + Q1.bytes + S.bytes + parts.bytes + state.bytes +
+               obj.bytes + lowp_work.bytes + lamb.bytes;
+    }
+};
+
+namespace tvcs {
+// error-to-code wrapper used by every C entry point
+extern thread_local std::string g_last_error;
+template <class F>
+int guarded(F &&fn) {
+    try {
+        g_last_error.clear();
+        return fn();
+    } catch (const Error &e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return TVCS_ENOMEM;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return TVCS_EDEVICE;
+    }
+}
+}  // namespace tvcs

@@ -51,7 +51,7 @@ constexpr int kMaxN = 512;
 void launch_gemv_rows(const float *A, int m, int N, const float *U, int ldu, const float *F,
                       int ldf, float *R, int ldr, int nv, const ImgState *active, int nact,
                       hipStream_t s);
-int gemv_cols_chunks(int m, int N, int nv);   // row chunks used for a given shape
+int gemv_cols_chunks(int m, int N);   // row chunks of the A^T r partial sums
 // chunk c of vector v goes to P[c*chunk_stride + v*N + j]
 void launch_gemv_cols(const float *A, int m, int N, const float *R, int ldr, float *P,
                       long long chunk_stride, int nv, const ImgState *active, int nact,

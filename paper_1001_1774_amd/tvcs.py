@@ -75,6 +75,17 @@ _SIGS = {
     "tvcs_time_products": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_void_p, ctypes.c_void_p]),
     "tvcs_destroy": (None, [ctypes.c_void_p]),
+    "tvcs_server_create": (ctypes.c_void_p, [ctypes.c_size_t, ctypes.c_int, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_uint]),
+    "tvcs_server_add_matrix": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "tvcs_server_submit": (ctypes.c_longlong, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                               ctypes.c_double, ctypes.c_int]),
+    "tvcs_server_step": (ctypes.c_int, [ctypes.c_void_p]),
+    "tvcs_server_result": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_void_p,
+                                          ctypes.c_void_p]),
+    "tvcs_server_pending": (ctypes.c_int, [ctypes.c_void_p]),
+    "tvcs_server_device_bytes": (ctypes.c_size_t, [ctypes.c_void_p]),
+    "tvcs_server_destroy": (None, [ctypes.c_void_p]),
     "tvcs_last_error": (ctypes.c_char_p, []),
 }
 
@@ -182,6 +193,41 @@ def tvcs_destroy(h):
 
 def tvcs_last_error():
     return lib().tvcs_last_error().decode()
+
+
+def tvcs_server_create(hbm_budget, slots, mu, beta, flags):
+    return lib().tvcs_server_create(int(hbm_budget), int(slots), float(mu), float(beta),
+                                    int(flags))
+
+
+def tvcs_server_add_matrix(s, h):
+    return lib().tvcs_server_add_matrix(s, h)
+
+
+def tvcs_server_submit(s, matrix, f, tol, maxit):
+    return lib().tvcs_server_submit(s, int(matrix), _ptr(f, torch.float32), float(tol),
+                                    int(maxit))
+
+
+def tvcs_server_step(s):
+    return lib().tvcs_server_step(s)
+
+
+def tvcs_server_result(s, request, u=None, st=None):
+    return lib().tvcs_server_result(s, int(request), _ptr(u, torch.float32),
+                                    ctypes.byref(st) if st is not None else None)
+
+
+def tvcs_server_pending(s):
+    return lib().tvcs_server_pending(s)
+
+
+def tvcs_server_device_bytes(s):
+    return lib().tvcs_server_device_bytes(s)
+
+
+def tvcs_server_destroy(s):
+    lib().tvcs_server_destroy(s)
 
 
 # --- a small convenience wrapper -------------------------------------------------------
