@@ -148,6 +148,8 @@ tvcs_ctx *create_impl(const void *A, int a_is_fp64, int m, int n, int storage, v
         fail(TVCS_EUNSUPPORTED, "n must be a power of two in [8, 512], got " + std::to_string(n));
     if (storage < TVCS_A_FP32 || storage > TVCS_A_FP8_ROWSCALE)
         fail(TVCS_EINVAL, "unknown storage format");
+    if (storage != TVCS_A_FP32 && n < 16)
+        fail(TVCS_EUNSUPPORTED, "low-precision storage needs n >= 16");
     std::unique_ptr<tvcs_ctx> h(new tvcs_ctx());
     h->m = m;
     h->n = n;

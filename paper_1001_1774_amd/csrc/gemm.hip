@@ -8,7 +8,12 @@
 // Both orientations are stored so that each product is a GEMM whose operands are
 // contiguous along the reduction dimension; the HBM bytes per product are the same
 // as for one copy (each product streams one copy once).  m_p = m rounded up to
-// 256 with zero rows.
+// 256 with zero rows.  Both copies are stored in MFMA fragment order: the 16 x 32
+// block (rows 16 t .. +15, k 32 u .. +31) is 512 contiguous elements laid out as
+// the A operand of v_mfma_f32_16x16x32_bf16 expects them (lane l holds row l % 16,
+// k 8 (l / 16) .. +7), blocks ordered row-tile major.  A wave's operand load is then
+// one contiguous 1 KiB read (512 B for fp8) instead of 16 rows x 64 B, and a wave
+// streams each of its row tiles sequentially.
 //
 // GEMM: C[b][row] = sum_k X[row][k] Y[b][k] with X the streamed matrix (A or A^T)
 // and Y the small batch operand (U or R in bf16).  A workgroup (4 waves) owns
@@ -41,8 +46,7 @@ typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 constexpr int kThreads = 256;
 constexpr int KT = 64;           // reduction step per loop iteration
 constexpr int YLD = KT + 8;      // LDS row stride (bf16 elements), padded against bank conflicts
-constexpr int kFwdRT = 4;        // forward: 4 x 16 rows per wave, 256 per workgroup
-constexpr int kAdjRT = 2;        // adjoint: 2 x 16 rows per wave, 128 per workgroup
+constexpr int kRowsRT4 = 4 * 4 * 16;   // rows per workgroup with 4 row tiles per wave
 
 enum { M_BF16 = 0, M_SPLIT = 1, M_FP8 = 2 };
 
@@ -101,7 +105,10 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
     if (L >= total) return;
     const int ks = L / RB, rb = L % RB;
 
-    constexpr int NY = (MODE == M_SPLIT) ? 2 : 1;
+    constexpr bool SPLIT = MODE == M_SPLIT;
+    constexpr int NY = SPLIT ? 2 : 1;
+    constexpr int YPIECES = NT * 16 * (KT / 8);                       // 16-byte pieces per tile
+    constexpr int YP = (YPIECES + kThreads - 1) / kThreads;           // per thread
     __shared__ u16 ys[NY][NT * 16][YLD];
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -115,40 +122,57 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    // fragment-ordered X: block (row tile t, k tile u) at (t * ldx/32 + u) * 512, lane at +8 l
+    const long long ktiles = ldx >> 5;
     long long xoff[RT];
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) xoff[rt] = (long long)min(row_wave + rt * 16 + lr, M - 1) * ldx;
+    for (int rt = 0; rt < RT; ++rt)
+        xoff[rt] = (long long)min((row_wave >> 4) + rt, (M >> 4) - 1) * ktiles * 512 + lane * 8;
 
-    for (int k0 = k_begin; k0 < k_end; k0 += KT) {
-        // this wave's X fragments: row (tile rt, lane lr), k = k0 + 32 s + lk .. +7
-        bf16x8 xh[RT][2], xl[RT][2];
+    // this wave's X fragments for one K step: tile rt, k tiles (k0 + 32 s) / 32
+    auto load_x = [&](int k0, bf16x8 (&xh)[RT][2], bf16x8 (&xl)[RT][2]) {
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                const long long o = xoff[rt] + k0 + 32 * s + lk;
+                const long long o = xoff[rt] + (long long)((k0 >> 5) + s) * 512;
                 if (MODE == M_FP8) {
-                    xh[rt][s] = fp8x8_to_bf16(
-                        __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>((const u8 *)Xhi + o)));
+                    xh[rt][s] = fp8x8_to_bf16(__builtin_nontemporal_load(
+                        reinterpret_cast<const u32x2 *>((const u8 *)Xhi + o)));
                 } else {
                     xh[rt][s] = __builtin_nontemporal_load(
                         reinterpret_cast<const bf16x8 *>((const u16 *)Xhi + o));
-                    if (MODE == M_SPLIT)
+                    if (SPLIT)
                         xl[rt][s] = __builtin_nontemporal_load(
                             reinterpret_cast<const bf16x8 *>((const u16 *)Xlo + o));
                 }
             }
-        // stage the Y tile (NT*16 images x KT) in LDS
-        __syncthreads();
-        for (int t = threadIdx.x; t < NT * 16 * (KT / 8); t += kThreads) {
-            const int yr = t / (KT / 8), yc = (t % (KT / 8)) * 8;
-            *reinterpret_cast<uint4 *>(&ys[0][yr][yc]) =
-                *reinterpret_cast<const uint4 *>(Yhi + yr * ldy + k0 + yc);
-            if (MODE == M_SPLIT)
-                *reinterpret_cast<uint4 *>(&ys[NY - 1][yr][yc]) =
-                    *reinterpret_cast<const uint4 *>(Ylo + yr * ldy + k0 + yc);
+    };
+    // the workgroup's Y tile (NT*16 images x KT) goes global -> registers -> LDS
+    uint4 yh_r[YP], yl_r[YP];
+    auto load_y = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < YP; ++q) {
+            const int t = threadIdx.x + q * kThreads;
+            if (t < YPIECES) {
+                const int yr = t / (KT / 8), yc = (t % (KT / 8)) * 8;
+                yh_r[q] = *reinterpret_cast<const uint4 *>(Yhi + yr * ldy + k0 + yc);
+                if (SPLIT) yl_r[q] = *reinterpret_cast<const uint4 *>(Ylo + yr * ldy + k0 + yc);
+            }
         }
-        __syncthreads();
+    };
+    auto store_y = [&]() {
+#pragma unroll
+        for (int q = 0; q < YP; ++q) {
+            const int t = threadIdx.x + q * kThreads;
+            if (t < YPIECES) {
+                const int yr = t / (KT / 8), yc = (t % (KT / 8)) * 8;
+                *reinterpret_cast<uint4 *>(&ys[0][yr][yc]) = yh_r[q];
+                if (SPLIT) *reinterpret_cast<uint4 *>(&ys[NY - 1][yr][yc]) = yl_r[q];
+            }
+        }
+    };
+    auto compute = [&](const bf16x8 (&xh)[RT][2], const bf16x8 (&xl)[RT][2]) {
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -157,7 +181,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt)
                     acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[rt][s], yh, acc[rt][nt], 0, 0, 0);
-                if (MODE == M_SPLIT) {
+                if (SPLIT) {
                     const bf16x8 yl =
                         *reinterpret_cast<const bf16x8 *>(&ys[NY - 1][nt * 16 + lr][32 * s + lk]);
 #pragma unroll
@@ -167,6 +191,33 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
                     }
                 }
             }
+    };
+    // One K step: prefetch the next step's X (registers) and Y (registers) before
+    // the MFMAs of this step, so a step's loads overlap the previous step's math.
+    auto step = [&](int k0, const bf16x8 (&xh)[RT][2], const bf16x8 (&xl)[RT][2],
+                    bf16x8 (&nh)[RT][2], bf16x8 (&nl)[RT][2]) {
+        const bool more = k0 + KT < k_end;
+        if (more) {
+            load_x(k0 + KT, nh, nl);
+            load_y(k0 + KT);
+        }
+        compute(xh, xl);
+        __syncthreads();   // all waves are done reading this step's Y tile
+        if (more) {
+            store_y();
+            __syncthreads();
+        }
+    };
+
+    bf16x8 xa_h[RT][2], xa_l[RT][2], xb_h[RT][2], xb_l[RT][2];
+    load_x(k_begin, xa_h, xa_l);
+    load_y(k_begin);
+    store_y();
+    __syncthreads();
+    // kspan is a multiple of 2 KT: alternate the two register sets
+    for (int k0 = k_begin; k0 < k_end; k0 += 2 * KT) {
+        step(k0, xa_h, xa_l, xb_h, xb_l);
+        step(k0 + KT, xb_h, xb_l, xa_h, xa_l);
     }
     // lane holds rows 4*(lane/16) .. +3 of its 16-row tile, image lane % 16 of its tile
     float *o = out + ks * split_stride;
@@ -183,27 +234,11 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
 }
 
 // ---- conversions ---------------------------------------------------------------
-// rows >= m are zero
-__global__ void k_to_bf16(const float *__restrict__ A, int m, int N, int mp, u16 *__restrict__ hi,
-                          u16 *__restrict__ lo) {
-    const size_t total = (size_t)mp * N;
-    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
-         e += (size_t)gridDim.x * blockDim.x) {
-        const size_t i = e / N;
-        const float a = i < (size_t)m ? A[e] : 0.f;
-        const u16 h = bf16_rne(a);
-        hi[e] = h;
-        if (lo) lo[e] = bf16_rne(a - bf16_f32(h));   // a - hi is exact in FP32
-    }
-}
-
-// per-row scale and E4M3 codes, one workgroup per row
-__global__ __launch_bounds__(256) void k_to_fp8(const float *__restrict__ A, int m, int N,
-                                               u8 *__restrict__ Q, float *__restrict__ scale) {
+// per-row scale of the fp8 format: s_i = max_j |A_ij| / 448 (1 for empty rows)
+__global__ __launch_bounds__(256) void k_fp8_scale(const float *__restrict__ A, int m, int N,
+                                                  float *__restrict__ scale) {
     const int i = blockIdx.x;
-    u8 *q = Q + (size_t)i * N;
     if (i >= m) {
-        for (int j = threadIdx.x; j < N; j += 256) q[j] = 0;
         if (threadIdx.x == 0) scale[i] = 1.f;
         return;
     }
@@ -217,30 +252,51 @@ __global__ __launch_bounds__(256) void k_to_fp8(const float *__restrict__ A, int
         if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
         __syncthreads();
     }
-    float s = red[0] / 448.0f;
-    if (!(s > 0.f)) s = 1.f;
-    for (int j = threadIdx.x; j < N; j += 256) {
-        const float x = fminf(fmaxf(a[j] / s, -448.f), 448.f);
-        const int packed = __builtin_amdgcn_cvt_pk_fp8_f32(x, 0.f, 0, false);
-        q[j] = (u8)(packed & 0xFF);
+    if (threadIdx.x == 0) {
+        const float s = red[0] / 448.0f;
+        scale[i] = s > 0.f ? s : 1.f;
     }
-    if (threadIdx.x == 0) scale[i] = s;
 }
 
-// XT[j][i] = X[i][j], X rows x cols, 64 x 64 tiles through LDS
-template <class T>
-__global__ __launch_bounds__(256) void k_transpose(const T *__restrict__ X, int rows, int cols,
-                                                   T *__restrict__ XT) {
-    __shared__ T tile[64][65];
-    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
-    for (int t = threadIdx.x; t < 64 * 64; t += 256) {
-        const int r = t / 64, c = t % 64;
-        if (r0 + r < rows && c0 + c < cols) tile[r][c] = X[(size_t)(r0 + r) * cols + c0 + c];
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < 64 * 64; t += 256) {
-        const int c = t / 64, r = t % 64;
-        if (r0 + r < rows && c0 + c < cols) XT[(size_t)(c0 + c) * rows + r0 + r] = tile[r][c];
+__device__ inline unsigned fp8_pack4(float a, float b, float c, float d) {
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);   // bytes 0, 1
+    return (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);   // bytes 2, 3
+}
+
+// Fragment-ordered copy of A (TRANS = false: rows i < m_p, reduction over columns;
+// TRANS = true: rows j < N of A^T, reduction over i < m_p).  Each thread writes one
+// lane's 8 consecutive elements of a block; rows i >= m are zero.
+template <int MODE, bool TRANS>
+__global__ void k_frag(const float *__restrict__ A, int m, int N, int mp,
+                       const float *__restrict__ scale, void *__restrict__ hi,
+                       void *__restrict__ lo) {
+    const size_t R = TRANS ? (size_t)N : (size_t)mp, K = TRANS ? (size_t)mp : (size_t)N;
+    const size_t chunks = R * K / 8, ktiles = K / 32;
+    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < chunks;
+         c += (size_t)gridDim.x * blockDim.x) {
+        const size_t f = c >> 6;
+        const int lane = (int)(c & 63);
+        const size_t r = (f / ktiles) * 16 + (lane & 15), k0 = (f % ktiles) * 32 + 8 * (lane >> 4);
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const size_t i = TRANS ? k0 + j : r, col = TRANS ? r : k0 + j;   // A[i][col]
+            v[j] = i < (size_t)m ? A[i * N + col] : 0.f;
+            if (MODE == M_FP8) v[j] = fminf(fmaxf(v[j] / scale[i], -448.f), 448.f);
+        }
+        if (MODE == M_FP8) {
+            const unsigned w0 = fp8_pack4(v[0], v[1], v[2], v[3]), w1 = fp8_pack4(v[4], v[5], v[6], v[7]);
+            reinterpret_cast<u32x2 *>(hi)[c] = u32x2{w0, w1};
+        } else {
+            u16 h[8], l[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                h[j] = bf16_rne(v[j]);
+                l[j] = bf16_rne(v[j] - bf16_f32(h[j]));   // exact in FP32
+            }
+            reinterpret_cast<uint4 *>(hi)[c] = *reinterpret_cast<const uint4 *>(h);
+            if (MODE == M_SPLIT) reinterpret_cast<uint4 *>(lo)[c] = *reinterpret_cast<const uint4 *>(l);
+        }
     }
 }
 
@@ -309,9 +365,10 @@ void gemm_dispatch(int NT, const void *Xhi, const void *Xlo, long long ldx, cons
 }
 
 template <int RT>
-void gemm_any(int mode, int NT, const void *Xhi, const void *Xlo, long long ldx, const u16 *Yhi,
-              const u16 *Ylo, long long ldy, int M, int kspan, int RB, int KS, float *out,
-              long long split_stride, long long ldo, const ImgState *st, int nact, hipStream_t s) {
+void gemm_mode(int mode, int NT, const void *Xhi, const void *Xlo, long long ldx, const u16 *Yhi,
+               const u16 *Ylo, long long ldy, int M, int kspan, int RB, int KS, float *out,
+               long long split_stride, long long ldo, const ImgState *st, int nact,
+               hipStream_t s) {
     switch (mode) {
         case M_BF16:
             gemm_dispatch<M_BF16, RT>(NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out,
@@ -327,14 +384,29 @@ void gemm_any(int mode, int NT, const void *Xhi, const void *Xlo, long long ldx,
     }
 }
 
+// RT (16-row tiles per wave) is chosen at run time by the autotuner
+void gemm_any(int RT, int mode, int NT, const void *Xhi, const void *Xlo, long long ldx,
+              const u16 *Yhi, const u16 *Ylo, long long ldy, int M, int kspan, int KS,
+              float *out, long long split_stride, long long ldo, const ImgState *st, int nact,
+              hipStream_t s) {
+    const int RB = (M + 4 * RT * 16 - 1) / (4 * RT * 16);
+    if (RT == 4)
+        gemm_mode<4>(mode, NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out, split_stride,
+                     ldo, st, nact, s);
+    else
+        gemm_mode<2>(mode, NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out, split_stride,
+                     ldo, st, nact, s);
+}
+
 size_t elem_bytes(int mode) { return mode == M_FP8 ? 1 : 2; }
 
 // K slices of the forward product: enough workgroups to fill the chip, slices a
-// multiple of KT long
+// multiple of 2 KT long.  Depends on (m, N) only, so the order of every sum, and
+// with it each image's result, is the same for every batch size and tile choice.
 int fwd_splits(const LowpA &L) {
-    const int RB = L.mp / (4 * kFwdRT * 16);
+    const int RB = L.mp / kRowsRT4;
     int KS = 1;
-    while (RB * KS < 512 && (L.N / (KS * 2)) % KT == 0 && L.N / (KS * 2) >= 8 * KT) KS *= 2;
+    while (RB * KS < 512 && (L.N / (KS * 2)) % (2 * KT) == 0 && L.N / (KS * 2) >= 8 * KT) KS *= 2;
     return KS;
 }
 
@@ -390,22 +462,22 @@ void lowp_bind_storage(LowpA &L, void *base) {
 
 void lowp_convert(LowpA &L, const float *A32, hipStream_t s) {
     const int mode = mode_of(L.storage);
-    const dim3 tgrid((L.N + 63) / 64, (L.mp + 63) / 64);
+    const int grid = grid1d((size_t)L.mp * L.N / 8);
+    if (mode == M_FP8)
+        hipLaunchKernelGGL(k_fp8_scale, dim3(L.mp), dim3(256), 0, s, A32, L.m, L.N, L.scale);
+#define TVCS_FRAG(MODEV)                                                                     \
+    hipLaunchKernelGGL((k_frag<MODEV, false>), dim3(grid), dim3(256), 0, s, A32, L.m, L.N,    \
+                       L.mp, L.scale, L.X_hi, L.X_lo);                                        \
+    hipLaunchKernelGGL((k_frag<MODEV, true>), dim3(grid), dim3(256), 0, s, A32, L.m, L.N, L.mp, \
+                       L.scale, L.XT_hi, L.XT_lo);
     if (mode == M_FP8) {
-        hipLaunchKernelGGL(k_to_fp8, dim3(L.mp), dim3(256), 0, s, A32, L.m, L.N, (u8 *)L.X_hi,
-                           L.scale);
-        hipLaunchKernelGGL(k_transpose<u8>, tgrid, dim3(256), 0, s, (const u8 *)L.X_hi, L.mp, L.N,
-                           (u8 *)L.XT_hi);
-        return;
+        TVCS_FRAG(M_FP8)
+    } else if (mode == M_SPLIT) {
+        TVCS_FRAG(M_SPLIT)
+    } else {
+        TVCS_FRAG(M_BF16)
     }
-    const size_t total = (size_t)L.mp * L.N;
-    hipLaunchKernelGGL(k_to_bf16, dim3(grid1d(total)), dim3(256), 0, s, A32, L.m, L.N, L.mp,
-                       (u16 *)L.X_hi, (u16 *)L.X_lo);
-    hipLaunchKernelGGL(k_transpose<u16>, tgrid, dim3(256), 0, s, (const u16 *)L.X_hi, L.mp, L.N,
-                       (u16 *)L.XT_hi);
-    if (mode == M_SPLIT)
-        hipLaunchKernelGGL(k_transpose<u16>, tgrid, dim3(256), 0, s, (const u16 *)L.X_lo, L.mp,
-                           L.N, (u16 *)L.XT_lo);
+#undef TVCS_FRAG
 }
 
 size_t lowp_work_bytes(const LowpA &L, int Bp) {
@@ -427,6 +499,48 @@ void lowp_work_bind(LowpWork &W, const LowpA &L, int Bp, void *base) {
     W.Rbf_lo = take(r);
     W.Rpart = static_cast<float *>(take((size_t)fwd_splits(L) * Bp * L.mp * sizeof(float)));
     W.Bp = Bp;
+    W.fwd_rt = 4;
+    W.adj_rt = 2;
+}
+
+// Autotuner: time each product with 2 and 4 row tiles per wave on this shape and
+// batch (one warm-up and three timed launches each, HIP events) and keep the
+// faster.  G is scratch for the adjoint output (Bp x N floats).
+void lowp_autotune(const LowpA &L, LowpWork &W, int Bp, const float *U, float *R, float *G,
+                   hipStream_t s) {
+    hipEvent_t e0, e1;
+    TVCS_HIP(hipEventCreate(&e0));
+    TVCS_HIP(hipEventCreate(&e1));
+    auto time_it = [&](auto &&launch) {
+        launch();
+        TVCS_HIP(hipEventRecord(e0, s));
+        for (int i = 0; i < 3; ++i) launch();
+        TVCS_HIP(hipEventRecord(e1, s));
+        TVCS_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        TVCS_HIP(hipEventElapsedTime(&ms, e0, e1));
+        return ms;
+    };
+    float best_f = 1e30f, best_a = 1e30f;
+    int fr = 4, ar = 2;
+    for (int rt : {2, 4}) {
+        W.fwd_rt = rt;
+        W.adj_rt = rt;
+        const float tf = time_it([&] { lowp_apply_A(L, W, Bp, U, nullptr, R, nullptr, s); });
+        const float ta = time_it([&] { lowp_apply_At(L, W, Bp, R, G, nullptr, s); });
+        if (tf < best_f) {
+            best_f = tf;
+            fr = rt;
+        }
+        if (ta < best_a) {
+            best_a = ta;
+            ar = rt;
+        }
+    }
+    W.fwd_rt = fr;
+    W.adj_rt = ar;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
 }
 
 void lowp_apply_A(const LowpA &L, LowpWork &W, int B, const float *U, const float *F, float *R,
@@ -438,13 +552,13 @@ void lowp_apply_A(const LowpA &L, LowpWork &W, int B, const float *U, const floa
     hipLaunchKernelGGL(k_split_vec, dim3(grid1d(cnt)), dim3(256), 0, s, U, cnt, (u16 *)W.Ubf_hi,
                        mode == M_SPLIT ? (u16 *)W.Ubf_lo : nullptr);
     const int KS = fwd_splits(L);
-    const int RB = L.mp / (4 * kFwdRT * 16);
     const long long split_stride = (long long)Bp * L.mp;
     for_each_group(Bp, B, [&](int img0, int nt, int nact) {
-        gemm_any<kFwdRT>(mode, nt, L.X_hi, L.X_lo, L.N, (const u16 *)W.Ubf_hi + (size_t)img0 * L.N,
-                         (const u16 *)W.Ubf_lo + (size_t)img0 * L.N, L.N, L.mp, L.N / KS, RB, KS,
-                         W.Rpart + (size_t)img0 * L.mp, split_stride, L.mp,
-                         st ? st + img0 : nullptr, nact, s);
+        gemm_any(W.fwd_rt, mode, nt, L.X_hi, L.X_lo, L.N,
+                 (const u16 *)W.Ubf_hi + (size_t)img0 * L.N,
+                 (const u16 *)W.Ubf_lo + (size_t)img0 * L.N, L.N, L.mp, L.N / KS, KS,
+                 W.Rpart + (size_t)img0 * L.mp, split_stride, L.mp, st ? st + img0 : nullptr,
+                 nact, s);
     });
     hipLaunchKernelGGL(k_reduce_r, dim3((L.m + 255) / 256, Bp), dim3(256), 0, s, W.Rpart, KS,
                        split_stride, L.mp, F, L.scale, L.m, R);
@@ -457,12 +571,11 @@ void lowp_apply_At(const LowpA &L, LowpWork &W, int B, const float *R, float *G,
     if (Bp > W.Bp) fail(TVCS_EINVAL, "MFMA workspace too small for the batch");
     hipLaunchKernelGGL(k_split_r, dim3((L.mp + 255) / 256, Bp), dim3(256), 0, s, R, L.m, L.mp,
                        L.scale, (u16 *)W.Rbf_hi, mode == M_SPLIT ? (u16 *)W.Rbf_lo : nullptr);
-    const int rows_per_wg = 4 * kAdjRT * 16;
-    const int RB = (L.N + rows_per_wg - 1) / rows_per_wg;
     for_each_group(Bp, B, [&](int img0, int nt, int nact) {
-        gemm_any<kAdjRT>(mode, nt, L.XT_hi, L.XT_lo, L.mp, (const u16 *)W.Rbf_hi + (size_t)img0 * L.mp,
-                         (const u16 *)W.Rbf_lo + (size_t)img0 * L.mp, L.mp, L.N, L.mp, RB, 1,
-                         G + (size_t)img0 * L.N, 0, L.N, st ? st + img0 : nullptr, nact, s);
+        gemm_any(W.adj_rt, mode, nt, L.XT_hi, L.XT_lo, L.mp,
+                 (const u16 *)W.Rbf_hi + (size_t)img0 * L.mp,
+                 (const u16 *)W.Rbf_lo + (size_t)img0 * L.mp, L.mp, L.N, L.mp, 1,
+                 G + (size_t)img0 * L.N, 0, L.N, st ? st + img0 : nullptr, nact, s);
     });
 }
 

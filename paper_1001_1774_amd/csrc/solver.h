@@ -132,6 +132,7 @@ struct tvcs_ctx {
         // padded images must hold zeros (their products are computed and ignored)
         launch_fill(U.as<float>(), (size_t)Bp * Nn, 0.f, work);
         launch_fill(F.as<float>(), (size_t)Bp * mm, 0.f, work);
+        if (lowprec()) lowp_autotune(lowp, lw, Bp, U.as<float>(), R.as<float>(), RHS.as<float>(), work);
     }
 
     // vectors per pass and row chunks of the FP32 products for a padded batch Bp.

@@ -144,6 +144,7 @@ struct LowpWork {
     void *Rbf_hi, *Rbf_lo;       // Bp x m_p bf16 copies of (scaled) R
     float *Rpart;                // ksplit x Bp x m_p
     int Bp;
+    int fwd_rt, adj_rt;          // 16-row tiles per wave of the two products (autotuned)
 };
 size_t lowp_work_bytes(const LowpA &L, int B);
 void lowp_work_bind(LowpWork &W, const LowpA &L, int B, void *base);
@@ -152,5 +153,8 @@ void lowp_apply_A(const LowpA &L, LowpWork &W, int B, const float *U, const floa
 // G[b*N + j] = (A^T r_b)_j  (G has one chunk)
 void lowp_apply_At(const LowpA &L, LowpWork &W, int B, const float *R, float *G,
                    const ImgState *st, hipStream_t s);
+// pick the tile shape of each product by timing the candidates on this batch
+void lowp_autotune(const LowpA &L, LowpWork &W, int Bp, const float *U, float *R, float *G,
+                   hipStream_t s);
 
 }  // namespace tvcs
