@@ -29,22 +29,24 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
-def command(out: str = LIB):
+def command(out: str = LIB, defines=()):
     return [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+            *[f"-D{d}" for d in defines],
             "-Wall", "-Wno-unused-function", "-Wno-unused-result",
             # no packed-FP32 instructions in device code
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             f"-I{INCLUDE}", f"-I{CSRC}", *sources(), "-o", out]
 
 
-def build(verbose: bool = True) -> str:
-    tmp = LIB + ".tmp"
-    cmd = command(tmp)
+def build(verbose: bool = True, out: str = LIB, defines=()) -> str:
+    """Compile every source into one shared library (`defines`: extra -D tuning knobs)."""
+    tmp = out + ".tmp"
+    cmd = command(tmp, defines)
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True, cwd=ROOT)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

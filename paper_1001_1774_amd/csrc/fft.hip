@@ -18,86 +18,15 @@
 // radix-2 stage first when log2 n is odd), the indexing of Govindaraju et al.,
 // "High performance discrete Fourier transforms on graphics processors" (SC 2008).
 // Twiddles come from a 512-entry table of exp(-2 pi i t / 512) computed in FP64.
-#include "tvcs_internal.h"
+#include "device_fft.h"
+#include "device_shrink.h"
 
 #include <algorithm>
 
 namespace tvcs {
 namespace {
 
-constexpr int kThreads = 256;
-
-__device__ inline float2 cmul(float2 a, float2 b) {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ inline float2 cmulc(float2 a, float2 b) {   // a * conj(b)
-    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
-}
-__device__ inline float2 operator+(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ inline float2 operator-(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-
-// nf transforms of length L = 2^logL, transform f at src[f*fs .. f*fs + L).
-// Returns the buffer (src or dst) that holds the result.  Ends with a barrier.
-template <bool INV>
-__device__ float2 *lds_fft(float2 *src, float2 *dst, int L, int logL, int nf, int fs,
-                           const float2 *tw) {
-    const int tid = threadIdx.x;
-    int Ns = 1, lNs = 0;
-    if (logL & 1) {   // radix-2 stage, Ns = 1 (unit twiddles)
-        const int h = L >> 1;
-        for (int t = tid; t < nf * h; t += kThreads) {
-            const int f = t >> (logL - 1), j = t & (h - 1);
-            const float2 v0 = src[f * fs + j], v1 = src[f * fs + j + h];
-            dst[f * fs + 2 * j] = v0 + v1;
-            dst[f * fs + 2 * j + 1] = v0 - v1;
-        }
-        __syncthreads();
-        float2 *x = src;
-        src = dst;
-        dst = x;
-        Ns = 2;
-        lNs = 1;
-    }
-    const int q = L >> 2;
-    for (; Ns < L; Ns <<= 2, lNs += 2) {
-        for (int t = tid; t < nf * q; t += kThreads) {
-            const int f = t >> (logL - 2), j = t & (q - 1);
-            const int k = j & (Ns - 1);
-            const float2 *s = src + f * fs;
-            float2 v0 = s[j], v1 = s[j + q], v2 = s[j + 2 * q], v3 = s[j + 3 * q];
-            // twiddle exp(-+2 pi i k r / (4 Ns)) = table[k r 128 / Ns]
-            const int step = (k << 7) >> lNs;
-            if (INV) {
-                v1 = cmulc(v1, tw[step]);
-                v2 = cmulc(v2, tw[2 * step]);
-                v3 = cmulc(v3, tw[3 * step]);
-            } else {
-                v1 = cmul(v1, tw[step]);
-                v2 = cmul(v2, tw[2 * step]);
-                v3 = cmul(v3, tw[3 * step]);
-            }
-            const float2 a = v0 + v2, bb = v0 - v2, c = v1 + v3, d = v1 - v3;
-            // -i d = (d.y, -d.x); +i d = (-d.y, d.x)
-            const float2 mid = INV ? make_float2(-d.y, d.x) : make_float2(d.y, -d.x);
-            float2 *o = dst + f * fs + ((j >> lNs) << (lNs + 2)) + k;
-            o[0] = a + c;
-            o[Ns] = bb + mid;
-            o[2 * Ns] = a - c;
-            o[3 * Ns] = bb - mid;
-        }
-        __syncthreads();
-        float2 *x = src;
-        src = dst;
-        dst = x;
-    }
-    return src;
-}
-
-__device__ inline int log2i(int n) { return __ffs(n) - 1; }
-
-__device__ inline void load_twiddles(float2 *tl, const float2 *tw) {
-    for (int t = threadIdx.x; t < kMaxN; t += kThreads) tl[t] = tw[t];
-}
+using namespace fftdev;
 
 __global__ void k_twiddles(float2 *tw) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -118,26 +47,12 @@ __global__ void k_denominators(int n, double c, double *inv_d) {
     inv_d[e] = 1.0 / ((double)n * (double)n * d);
 }
 
-__global__ __launch_bounds__(kThreads) void k_rows_fwd(int n, int rpb, const float *__restrict__ RHS,
-                                                       float2 *__restrict__ S,
-                                                       const float2 *__restrict__ tw,
-                                                       const ImgState *__restrict__ st) {
-    const int b = blockIdx.y;
-    if (!st[b].active) return;
-    extern __shared__ float2 lds[];
+// FFT of the block's packed row pairs in X, split into the half spectra and
+// written to S (rows row0 .. row0 + rpb - 1 of image b).
+__device__ inline void rows_fwd_tail(int n, int rpb, float2 *X, float2 *Y, const float2 *tl,
+                                     float2 *dstS) {
     const int ln = log2i(n), npair = rpb >> 1, h = n / 2 + 1;
-    const int bufsz = npair * n + rpb;
-    float2 *tl = lds, *X = lds + kMaxN, *Y = X + bufsz;
-    load_twiddles(tl, tw);
-    const int row0 = blockIdx.x * rpb;
-    const float *src = RHS + (size_t)b * n * n + (size_t)row0 * n;
-    for (int e = threadIdx.x; e < npair * n; e += kThreads) {
-        const int pr = e >> ln, j = e & (n - 1);
-        X[e] = make_float2(src[(2 * pr) * n + j], src[(2 * pr + 1) * n + j]);
-    }
-    __syncthreads();
     const float2 *Z = lds_fft<false>(X, Y, n, ln, npair, n, tl);
-    float2 *dstS = S + (size_t)b * h * n + row0;
     for (int e = threadIdx.x; e < h * rpb; e += kThreads) {
         const int k = e / rpb, rr = e - k * rpb, pr = rr >> 1;
         const float2 zk = Z[pr * n + k], znk = Z[pr * n + ((n - k) & (n - 1))];
@@ -148,6 +63,30 @@ __global__ __launch_bounds__(kThreads) void k_rows_fwd(int n, int rpb, const flo
             v = make_float2(0.5f * (zk.y + znk.y), -0.5f * (zk.x - znk.x));
         dstS[(size_t)k * n + rr] = v;
     }
+}
+
+// Fused shrinkage + forward row FFT: the right-hand side of the block's rows is
+// computed (shrinkdev::rhs_at) straight into the packed FFT input in LDS.
+template <bool IADM>
+__global__ __launch_bounds__(kThreads) void k_shrink_rows(ShrinkArgs a, int rpb,
+                                                          float2 *__restrict__ S,
+                                                          const float2 *__restrict__ tw) {
+    const int b = blockIdx.y;
+    if (!a.st[b].active) return;
+    extern __shared__ float2 lds[];
+    const int n = a.n, ln = log2i(n), npair = rpb >> 1, h = n / 2 + 1;
+    const int bufsz = npair * n + rpb;
+    float2 *tl = lds, *X = lds + kMaxN, *Y = X + bufsz;
+    load_twiddles(tl, tw);
+    const int row0 = blockIdx.x * rpb;
+    float *Xf = reinterpret_cast<float *>(X);
+    for (int e = threadIdx.x; e < rpb * n; e += kThreads) {
+        const int rr = e >> ln, c = e & (n - 1);
+        const float v = (float)shrinkdev::rhs_at<IADM>(a, b, ((row0 + rr) << ln) | c);
+        Xf[2 * ((rr >> 1) * n + c) + (rr & 1)] = v;   // even row: real part, odd row: imaginary
+    }
+    __syncthreads();
+    rows_fwd_tail(n, rpb, X, Y, tl, S + (size_t)b * h * n + row0);
 }
 
 __global__ __launch_bounds__(kThreads) void k_cols_solve(int n, int cpb, float2 *__restrict__ S,
@@ -178,11 +117,14 @@ __global__ __launch_bounds__(kThreads) void k_cols_solve(int n, int cpb, float2 
     for (int e = threadIdx.x; e < nc * n; e += kThreads) col[e] = out[e];
 }
 
+// Inverse row pass + stop rule (see the file header).  `counters` holds one zero
+// int per image; the last block of an image to finish resets it.
 __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const float2 *__restrict__ S,
                                                        float *__restrict__ U,
                                                        double *__restrict__ parts,
                                                        const float2 *__restrict__ tw,
-                                                       const ImgState *__restrict__ st) {
+                                                       ImgState *__restrict__ st,
+                                                       int *__restrict__ counters) {
     const int b = blockIdx.y;
     if (!st[b].active) return;
     extern __shared__ float2 lds[];
@@ -229,21 +171,63 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
         u2 += __shfl_xor(u2, off, 64);
     }
     __shared__ double red[2][kThreads / 64];
+    __shared__ int s_last;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) {
         red[0][wave] = du2;
         red[1][wave] = u2;
     }
     __syncthreads();
+    double *myparts = parts + (size_t)b * gridDim.x * 2;
     if (threadIdx.x == 0) {
         double a = 0.0, c = 0.0;
         for (int w = 0; w < kThreads / 64; ++w) {
             a += red[0][w];
             c += red[1][w];
         }
-        double *pp = parts + ((size_t)b * gridDim.x + blockIdx.x) * 2;
-        pp[0] = a;
-        pp[1] = c;
+        // publish this block's sums device-wide, then count the block as done
+        __hip_atomic_store(myparts + 2 * blockIdx.x, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(myparts + 2 * blockIdx.x + 1, c, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        s_last = atomicAdd(&counters[b], 1) == (int)gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    // The last block of image b applies the stop rule of eq. (stop):
+    //   ||u^{k+1} - u^k|| <= tol ||u^k||  (inclusive, FP64), summing the blocks'
+    // partial sums in block order.
+    __threadfence();
+    if (threadIdx.x >= 64) return;
+    double sd = 0.0, su = 0.0;
+    for (int p = lane; p < (int)gridDim.x; p += 64) {
+        sd += __hip_atomic_load(myparts + 2 * p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        su += __hip_atomic_load(myparts + 2 * p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        sd += __shfl_xor(sd, off, 64);
+        su += __shfl_xor(su, off, 64);
+    }
+    if (lane == 0) {
+        ImgState s = st[b];
+        s.iters += 1;
+        s.du2 = sd;
+        s.u2 = su;
+        const double du = sqrt(sd), nu = sqrt(su);
+        s.rel = nu > 0.0 ? du / nu : (du > 0.0 ? INFINITY : 0.0);
+        if (!isfinite(sd) || !isfinite(su)) {
+            s.status = TVCS_ENONFINITE;
+            s.active = 0;
+        } else if (s.tol > 0.0 && du <= s.tol * nu) {
+            s.status = TVCS_OK;
+            s.active = 0;
+        } else if (s.iters >= s.maxit) {
+            s.status = s.tol > 0.0 ? TVCS_MAXIT : TVCS_OK;
+            s.active = 0;
+        }
+        st[b] = s;
+        counters[b] = 0;   // ready for the next pass
     }
 }
 
@@ -272,16 +256,6 @@ void launch_denominators(int n, double c, double *inv_d, hipStream_t s) {
     hipLaunchKernelGGL(k_denominators, dim3((cnt + 255) / 256), dim3(256), 0, s, n, c, inv_d);
 }
 
-int fft_row_parts(int n, int B) { return n / rows_per_block(n, B); }
-
-void launch_fft_rows_fwd(int n, int B, const float *RHS, float2 *S, const float2 *tw,
-                         const ImgState *st, hipStream_t s) {
-    const int rpb = rows_per_block(n, B);
-    const size_t lds = sizeof(float2) * (kMaxN + 2 * ((rpb / 2) * n + rpb));
-    hipLaunchKernelGGL(k_rows_fwd, dim3(n / rpb, B), dim3(kThreads), lds, s, n, rpb, RHS, S, tw,
-                       st);
-}
-
 void launch_fft_cols_solve(int n, int B, float2 *S, const double *inv_d, const float2 *tw,
                            const ImgState *st, hipStream_t s) {
     const int cpb = cols_per_block(n, B), h = n / 2 + 1;
@@ -291,11 +265,23 @@ void launch_fft_cols_solve(int n, int B, float2 *S, const double *inv_d, const f
 }
 
 void launch_fft_rows_inv(int n, int B, const float2 *S, float *U, double *parts,
-                         const float2 *tw, const ImgState *st, hipStream_t s) {
+                         const float2 *tw, ImgState *st, int *counters, hipStream_t s) {
     const int rpb = rows_per_block(n, B);
     const size_t lds = sizeof(float2) * (kMaxN + 2 * ((rpb / 2) * n + rpb));
     hipLaunchKernelGGL(k_rows_inv, dim3(n / rpb, B), dim3(kThreads), lds, s, n, rpb, S, U, parts,
-                       tw, st);
+                       tw, st, counters);
+}
+
+void launch_shrink_rows(const ShrinkArgs &a, bool iadm, float2 *S, const float2 *tw,
+                        hipStream_t s) {
+    const int n = a.n, rpb = rows_per_block(n, a.B);
+    const size_t lds = sizeof(float2) * (kMaxN + 2 * ((rpb / 2) * n + rpb));
+    if (iadm)
+        hipLaunchKernelGGL(k_shrink_rows<true>, dim3(n / rpb, a.B), dim3(kThreads), lds, s, a,
+                           rpb, S, tw);
+    else
+        hipLaunchKernelGGL(k_shrink_rows<false>, dim3(n / rpb, a.B), dim3(kThreads), lds, s, a,
+                           rpb, S, tw);
 }
 
 }  // namespace tvcs

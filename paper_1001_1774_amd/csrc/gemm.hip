@@ -34,6 +34,20 @@
 
 #include <algorithm>
 
+// Tile parameters (compile-time; the defaults are the measured best on MI355X)
+#ifndef TVCS_GEMM_KF_FWD
+#define TVCS_GEMM_KF_FWD 4     // 32-wide k tiles per loop step, forward product (2 or 4)
+#endif
+#ifndef TVCS_GEMM_KF_ADJ
+#define TVCS_GEMM_KF_ADJ 2     // the same for the adjoint product
+#endif
+#ifndef TVCS_FWD_TARGET_WG
+#define TVCS_FWD_TARGET_WG 256 // K slices of the forward product grow until this many tiles
+#endif
+#ifndef TVCS_ADJ_SPLIT
+#define TVCS_ADJ_SPLIT 2       // K slices of the adjoint product (partial sums added later)
+#endif
+
 namespace tvcs {
 namespace {
 
@@ -44,8 +58,7 @@ typedef unsigned char u8;
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kThreads = 256;
-constexpr int KT = 64;           // reduction step per loop iteration
-constexpr int YLD = KT + 8;      // LDS row stride (bf16 elements), padded against bank conflicts
+constexpr int KMAX = 128;        // longest reduction step; every K slice is a multiple of it
 constexpr int kRowsRT4 = 4 * 4 * 16;   // rows per workgroup with 4 row tiles per wave
 
 enum { M_BF16 = 0, M_SPLIT = 1, M_FP8 = 2 };
@@ -91,7 +104,7 @@ __device__ inline bf16x8 fp8x8_to_bf16(u32x2 q) {
     return r;
 }
 
-template <int MODE, int RT, int NT>
+template <int MODE, int RT, int NT, int KF>
 __global__ __launch_bounds__(kThreads) void k_gemm(
     const void *__restrict__ Xhi, const void *__restrict__ Xlo, long long ldx,
     const u16 *__restrict__ Yhi, const u16 *__restrict__ Ylo, long long ldy, int M, int kspan,
@@ -107,8 +120,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
 
     constexpr bool SPLIT = MODE == M_SPLIT;
     constexpr int NY = SPLIT ? 2 : 1;
-    constexpr int YPIECES = NT * 16 * (KT / 8);                       // 16-byte pieces per tile
-    constexpr int YP = (YPIECES + kThreads - 1) / kThreads;           // per thread
+    constexpr int KT = 32 * KF;                // reduction step
+    constexpr int YLD = KT + 8;                // LDS row stride, padded against bank conflicts
     __shared__ u16 ys[NY][NT * 16][YLD];
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -129,12 +142,13 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
     for (int rt = 0; rt < RT; ++rt)
         xoff[rt] = (long long)min((row_wave >> 4) + rt, (M >> 4) - 1) * ktiles * 512 + lane * 8;
 
-    // this wave's X fragments for one K step: tile rt, k tiles (k0 + 32 s) / 32
-    auto load_x = [&](int k0, bf16x8 (&xh)[RT][2], bf16x8 (&xl)[RT][2]) {
+    for (int k0 = k_begin; k0 < k_end; k0 += KT) {
+        // this wave's X fragments: tile rt, k tiles k0/32 .. + KF - 1 (contiguous 1 KiB each)
+        bf16x8 xh[RT][KF], xl[RT][KF];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
+            for (int s = 0; s < KF; ++s) {
                 const long long o = xoff[rt] + (long long)((k0 >> 5) + s) * 512;
                 if (MODE == M_FP8) {
                     xh[rt][s] = fp8x8_to_bf16(__builtin_nontemporal_load(
@@ -147,34 +161,19 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
                             reinterpret_cast<const bf16x8 *>((const u16 *)Xlo + o));
                 }
             }
-    };
-    // the workgroup's Y tile (NT*16 images x KT) goes global -> registers -> LDS
-    uint4 yh_r[YP], yl_r[YP];
-    auto load_y = [&](int k0) {
-#pragma unroll
-        for (int q = 0; q < YP; ++q) {
-            const int t = threadIdx.x + q * kThreads;
-            if (t < YPIECES) {
-                const int yr = t / (KT / 8), yc = (t % (KT / 8)) * 8;
-                yh_r[q] = *reinterpret_cast<const uint4 *>(Yhi + yr * ldy + k0 + yc);
-                if (SPLIT) yl_r[q] = *reinterpret_cast<const uint4 *>(Ylo + yr * ldy + k0 + yc);
-            }
+        // stage the Y tile (NT*16 images x KT) in LDS
+        __syncthreads();
+        for (int t = threadIdx.x; t < NT * 16 * (KT / 8); t += kThreads) {
+            const int yr = t / (KT / 8), yc = (t % (KT / 8)) * 8;
+            *reinterpret_cast<uint4 *>(&ys[0][yr][yc]) =
+                *reinterpret_cast<const uint4 *>(Yhi + yr * ldy + k0 + yc);
+            if (SPLIT)
+                *reinterpret_cast<uint4 *>(&ys[NY - 1][yr][yc]) =
+                    *reinterpret_cast<const uint4 *>(Ylo + yr * ldy + k0 + yc);
         }
-    };
-    auto store_y = [&]() {
+        __syncthreads();
 #pragma unroll
-        for (int q = 0; q < YP; ++q) {
-            const int t = threadIdx.x + q * kThreads;
-            if (t < YPIECES) {
-                const int yr = t / (KT / 8), yc = (t % (KT / 8)) * 8;
-                *reinterpret_cast<uint4 *>(&ys[0][yr][yc]) = yh_r[q];
-                if (SPLIT) *reinterpret_cast<uint4 *>(&ys[NY - 1][yr][yc]) = yl_r[q];
-            }
-        }
-    };
-    auto compute = [&](const bf16x8 (&xh)[RT][2], const bf16x8 (&xl)[RT][2]) {
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
+        for (int s = 0; s < KF; ++s)
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const bf16x8 yh = *reinterpret_cast<const bf16x8 *>(&ys[0][nt * 16 + lr][32 * s + lk]);
@@ -191,33 +190,6 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
                     }
                 }
             }
-    };
-    // One K step: prefetch the next step's X (registers) and Y (registers) before
-    // the MFMAs of this step, so a step's loads overlap the previous step's math.
-    auto step = [&](int k0, const bf16x8 (&xh)[RT][2], const bf16x8 (&xl)[RT][2],
-                    bf16x8 (&nh)[RT][2], bf16x8 (&nl)[RT][2]) {
-        const bool more = k0 + KT < k_end;
-        if (more) {
-            load_x(k0 + KT, nh, nl);
-            load_y(k0 + KT);
-        }
-        compute(xh, xl);
-        __syncthreads();   // all waves are done reading this step's Y tile
-        if (more) {
-            store_y();
-            __syncthreads();
-        }
-    };
-
-    bf16x8 xa_h[RT][2], xa_l[RT][2], xb_h[RT][2], xb_l[RT][2];
-    load_x(k_begin, xa_h, xa_l);
-    load_y(k_begin);
-    store_y();
-    __syncthreads();
-    // kspan is a multiple of 2 KT: alternate the two register sets
-    for (int k0 = k_begin; k0 < k_end; k0 += 2 * KT) {
-        step(k0, xa_h, xa_l, xb_h, xb_l);
-        step(k0 + KT, xb_h, xb_l, xa_h, xa_l);
     }
     // lane holds rows 4*(lane/16) .. +3 of its 16-row tile, image lane % 16 of its tile
     float *o = out + ks * split_stride;
@@ -342,18 +314,22 @@ __global__ void k_split_r(const float *__restrict__ R, int m, int mp, const floa
     if (lo) lo[(size_t)b * mp + i] = bf16_rne(x - bf16_f32(h));
 }
 
-template <int MODE, int RT>
+template <int MODE, int RT, int KFREQ>
 void gemm_dispatch(int NT, const void *Xhi, const void *Xlo, long long ldx, const u16 *Yhi,
                    const u16 *Ylo, long long ldy, int M, int kspan, int RB, int KS, float *out,
                    long long split_stride, long long ldo, const ImgState *st, int nact,
                    hipStream_t s) {
     const int total = RB * KS;
     const dim3 grid(((total + 7) / 8) * 8);
+    // the longer step needs twice the LDS; split batches of 128 keep the short one
 #define TVCS_GEMM_CASE(NTV)                                                                    \
-    case NTV:                                                                                  \
-        hipLaunchKernelGGL((k_gemm<MODE, RT, NTV>), grid, dim3(kThreads), 0, s, Xhi, Xlo, ldx, \
-                           Yhi, Ylo, ldy, M, kspan, RB, KS, out, split_stride, ldo, st, nact); \
-        break;
+    case NTV: {                                                                                \
+        constexpr int KF = (MODE == M_SPLIT && NTV == 8) ? 2 : KFREQ;                          \
+        hipLaunchKernelGGL((k_gemm<MODE, RT, NTV, KF>), grid, dim3(kThreads), 0, s, Xhi, Xlo,  \
+                           ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out, split_stride, ldo, st,   \
+                           nact);                                                              \
+        break;                                                                                 \
+    }
     switch (NT) {
         TVCS_GEMM_CASE(1)
         TVCS_GEMM_CASE(2)
@@ -364,49 +340,52 @@ void gemm_dispatch(int NT, const void *Xhi, const void *Xlo, long long ldx, cons
 #undef TVCS_GEMM_CASE
 }
 
-template <int RT>
+template <int RT, int KF>
 void gemm_mode(int mode, int NT, const void *Xhi, const void *Xlo, long long ldx, const u16 *Yhi,
                const u16 *Ylo, long long ldy, int M, int kspan, int RB, int KS, float *out,
                long long split_stride, long long ldo, const ImgState *st, int nact,
                hipStream_t s) {
     switch (mode) {
         case M_BF16:
-            gemm_dispatch<M_BF16, RT>(NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out,
+            gemm_dispatch<M_BF16, RT, KF>(NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out,
                                       split_stride, ldo, st, nact, s);
             break;
         case M_SPLIT:
-            gemm_dispatch<M_SPLIT, RT>(NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out,
+            gemm_dispatch<M_SPLIT, RT, KF>(NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out,
                                        split_stride, ldo, st, nact, s);
             break;
         default:
-            gemm_dispatch<M_FP8, RT>(NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out,
+            gemm_dispatch<M_FP8, RT, KF>(NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out,
                                      split_stride, ldo, st, nact, s);
     }
 }
 
-// RT (16-row tiles per wave) is chosen at run time by the autotuner
+// RT (16-row tiles per wave) is chosen at run time by the autotuner; KF is per product
+template <int KF>
 void gemm_any(int RT, int mode, int NT, const void *Xhi, const void *Xlo, long long ldx,
               const u16 *Yhi, const u16 *Ylo, long long ldy, int M, int kspan, int KS,
               float *out, long long split_stride, long long ldo, const ImgState *st, int nact,
               hipStream_t s) {
     const int RB = (M + 4 * RT * 16 - 1) / (4 * RT * 16);
     if (RT == 4)
-        gemm_mode<4>(mode, NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out, split_stride,
+        gemm_mode<4, KF>(mode, NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out, split_stride,
                      ldo, st, nact, s);
     else
-        gemm_mode<2>(mode, NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out, split_stride,
+        gemm_mode<2, KF>(mode, NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out, split_stride,
                      ldo, st, nact, s);
 }
 
 size_t elem_bytes(int mode) { return mode == M_FP8 ? 1 : 2; }
 
 // K slices of the forward product: enough workgroups to fill the chip, slices a
-// multiple of 2 KT long.  Depends on (m, N) only, so the order of every sum, and
+// multiple of KMAX long.  Depends on (m, N) only, so the order of every sum, and
 // with it each image's result, is the same for every batch size and tile choice.
 int fwd_splits(const LowpA &L) {
     const int RB = L.mp / kRowsRT4;
     int KS = 1;
-    while (RB * KS < 512 && (L.N / (KS * 2)) % (2 * KT) == 0 && L.N / (KS * 2) >= 8 * KT) KS *= 2;
+    while (RB * KS < TVCS_FWD_TARGET_WG && (L.N / (KS * 2)) % KMAX == 0 &&
+           L.N / (KS * 2) >= 4 * KMAX)
+        KS *= 2;
     return KS;
 }
 
@@ -428,6 +407,12 @@ void for_each_group(int Bp, int B, Fn &&fn) {
 int grid1d(size_t count) { return (int)std::min<size_t>((count + 255) / 256, 16384); }
 
 }  // namespace
+
+int lowp_adj_splits(const LowpA &L) {
+    int KS = 1;
+    while (KS < TVCS_ADJ_SPLIT && (L.mp / (KS * 2)) % KMAX == 0) KS *= 2;
+    return KS;
+}
 
 size_t lowp_storage_bytes(const LowpA &L0) {
     LowpA L = L0;
@@ -505,7 +490,7 @@ void lowp_work_bind(LowpWork &W, const LowpA &L, int Bp, void *base) {
 
 // Autotuner: time each product with 2 and 4 row tiles per wave on this shape and
 // batch (one warm-up and three timed launches each, HIP events) and keep the
-// faster.  G is scratch for the adjoint output (Bp x N floats).
+// faster.  G is scratch for the adjoint output (lowp_adj_splits(L) x Bp x N floats).
 void lowp_autotune(const LowpA &L, LowpWork &W, int Bp, const float *U, float *R, float *G,
                    hipStream_t s) {
     hipEvent_t e0, e1;
@@ -554,7 +539,7 @@ void lowp_apply_A(const LowpA &L, LowpWork &W, int B, const float *U, const floa
     const int KS = fwd_splits(L);
     const long long split_stride = (long long)Bp * L.mp;
     for_each_group(Bp, B, [&](int img0, int nt, int nact) {
-        gemm_any(W.fwd_rt, mode, nt, L.X_hi, L.X_lo, L.N,
+        gemm_any<TVCS_GEMM_KF_FWD>(W.fwd_rt, mode, nt, L.X_hi, L.X_lo, L.N,
                  (const u16 *)W.Ubf_hi + (size_t)img0 * L.N,
                  (const u16 *)W.Ubf_lo + (size_t)img0 * L.N, L.N, L.mp, L.N / KS, KS,
                  W.Rpart + (size_t)img0 * L.mp, split_stride, L.mp, st ? st + img0 : nullptr,
@@ -571,11 +556,13 @@ void lowp_apply_At(const LowpA &L, LowpWork &W, int B, const float *R, float *G,
     if (Bp > W.Bp) fail(TVCS_EINVAL, "MFMA workspace too small for the batch");
     hipLaunchKernelGGL(k_split_r, dim3((L.mp + 255) / 256, Bp), dim3(256), 0, s, R, L.m, L.mp,
                        L.scale, (u16 *)W.Rbf_hi, mode == M_SPLIT ? (u16 *)W.Rbf_lo : nullptr);
+    const int KS = lowp_adj_splits(L);
+    const long long split_stride = (long long)Bp * L.N;
     for_each_group(Bp, B, [&](int img0, int nt, int nact) {
-        gemm_any(W.adj_rt, mode, nt, L.XT_hi, L.XT_lo, L.mp,
+        gemm_any<TVCS_GEMM_KF_ADJ>(W.adj_rt, mode, nt, L.XT_hi, L.XT_lo, L.mp,
                  (const u16 *)W.Rbf_hi + (size_t)img0 * L.mp,
-                 (const u16 *)W.Rbf_lo + (size_t)img0 * L.mp, L.mp, L.N, L.mp, 1,
-                 G + (size_t)img0 * L.N, 0, L.N, st ? st + img0 : nullptr, nact, s);
+                 (const u16 *)W.Rbf_lo + (size_t)img0 * L.mp, L.mp, L.N, L.mp / KS, KS,
+                 G + (size_t)img0 * L.N, split_stride, L.N, st ? st + img0 : nullptr, nact, s);
     });
 }
 

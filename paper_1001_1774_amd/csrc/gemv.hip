@@ -20,6 +20,23 @@
 
 #include <algorithm>
 
+// Tile parameters (compile-time; the defaults are the measured best on MI355X)
+#ifndef TVCS_GEMV_ROWS
+#define TVCS_GEMV_ROWS 2      // rows per workgroup of the A u product (1-2 vectors)
+#endif
+#ifndef TVCS_GEMV_UNROLL
+#define TVCS_GEMV_UNROLL 8    // float4 loads per row in flight
+#endif
+#ifndef TVCS_COLS_VEC
+#define TVCS_COLS_VEC 4       // float4 column groups per thread of the A^T r product
+#endif
+#ifndef TVCS_COLS_TARGET_WG
+#define TVCS_COLS_TARGET_WG 1024   // workgroups the A^T r product aims for
+#endif
+#ifndef TVCS_COLS_REVERSE
+#define TVCS_COLS_REVERSE 0   // 1: sweep row chunks last-to-first (after A u read first-to-last)
+#endif
+
 namespace tvcs {
 namespace {
 
@@ -62,7 +79,7 @@ __global__ __launch_bounds__(kThreads) void k_gemv_rows(
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[r][v] = 0.0;
 
-#pragma unroll 4
+#pragma unroll TVCS_GEMV_UNROLL
     for (int j = threadIdx.x; j < N4; j += kThreads) {
         f4 a[ROWS];
 #pragma unroll
@@ -106,9 +123,10 @@ __global__ __launch_bounds__(kThreads) void k_gemv_cols(
     const float *__restrict__ A, int m, int N, const float *__restrict__ Rv, int ldr,
     float *__restrict__ P, long long chunk_stride, int rows_per_chunk,
     const ImgState *__restrict__ st, int nact) {
+    constexpr int VEC = TVCS_COLS_VEC;
     if (!any_active(st, nact)) return;
     extern __shared__ double rs[];           // rows_per_chunk x NV coefficients
-    const int chunk = blockIdx.y;
+    const int chunk = TVCS_COLS_REVERSE ? (int)(gridDim.y - 1 - blockIdx.y) : (int)blockIdx.y;
     const int i0 = chunk * rows_per_chunk;
     const int rows = min(rows_per_chunk, m - i0);
     for (int t = threadIdx.x; t < rows * NV; t += kThreads) {
@@ -117,35 +135,50 @@ __global__ __launch_bounds__(kThreads) void k_gemv_cols(
     }
     __syncthreads();
     const int N4 = N >> 2;
-    const int j4 = blockIdx.x * kThreads + threadIdx.x;
-    if (j4 >= N4) return;
-    const f4 *col = reinterpret_cast<const f4 *>(A + (size_t)i0 * N) + j4;
-    double acc[NV][4];
+    // the workgroup covers VEC * 256 consecutive float4 columns; thread t owns
+    // columns t, t + 256, ... so each wave still reads contiguous 1 KiB pieces
+    const int jb = blockIdx.x * kThreads * VEC + threadIdx.x;
+    const f4 *col = reinterpret_cast<const f4 *>(A + (size_t)i0 * N);
+    double acc[VEC][NV][4];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v][0] = acc[v][1] = acc[v][2] = acc[v][3] = 0.0;
+    for (int c = 0; c < VEC; ++c)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[c][v][0] = acc[c][v][1] = acc[c][v][2] = acc[c][v][3] = 0.0;
 #pragma unroll 8
     for (int i = 0; i < rows; ++i) {
-        const f4 a = __builtin_nontemporal_load(col + (size_t)i * N4);
-        const double ax = a.x, ay = a.y, az = a.z, aw = a.w;
+        f4 a[VEC];
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) {
+            const int j4 = jb + c * kThreads;
+            a[c] = j4 < N4 ? __builtin_nontemporal_load(col + (size_t)i * N4 + j4) : f4{0, 0, 0, 0};
+        }
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const double r = rs[i * NV + v];
-            acc[v][0] = fma(ax, r, acc[v][0]);
-            acc[v][1] = fma(ay, r, acc[v][1]);
-            acc[v][2] = fma(az, r, acc[v][2]);
-            acc[v][3] = fma(aw, r, acc[v][3]);
+#pragma unroll
+            for (int c = 0; c < VEC; ++c) {
+                acc[c][v][0] = fma((double)a[c].x, r, acc[c][v][0]);
+                acc[c][v][1] = fma((double)a[c].y, r, acc[c][v][1]);
+                acc[c][v][2] = fma((double)a[c].z, r, acc[c][v][2]);
+                acc[c][v][3] = fma((double)a[c].w, r, acc[c][v][3]);
+            }
         }
     }
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
-        reinterpret_cast<f4 *>(P + chunk * chunk_stride + (size_t)v * N)[j4] =
-            f4{(float)acc[v][0], (float)acc[v][1], (float)acc[v][2], (float)acc[v][3]};
+    for (int c = 0; c < VEC; ++c) {
+        const int j4 = jb + c * kThreads;
+        if (j4 >= N4) continue;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            reinterpret_cast<f4 *>(P + chunk * chunk_stride + (size_t)v * N)[j4] =
+                f4{(float)acc[c][v][0], (float)acc[c][v][1], (float)acc[c][v][2], (float)acc[c][v][3]};
+    }
 }
 
 template <int NV>
 void rows_dispatch(const float *A, int m, int N, const float *U, int ldu, const float *F,
                    int ldf, float *R, int ldr, const ImgState *st, int nact, hipStream_t s) {
-    constexpr int ROWS = NV <= 2 ? 4 : 2;
+    constexpr int ROWS = NV <= 2 ? TVCS_GEMV_ROWS : 2;
     const int grid = (m + ROWS - 1) / ROWS;
     hipLaunchKernelGGL((k_gemv_rows<NV, ROWS>), dim3(grid), dim3(kThreads), 0, s, A, m, N, U,
                        ldu, F, ldf, R, ldr, st, nact);
@@ -156,7 +189,7 @@ void cols_dispatch(const float *A, int m, int N, const float *R, int ldr, float 
                    long long chunk_stride, const ImgState *st, int nact, hipStream_t s) {
     const int nchunk = gemv_cols_chunks(m, N);   // the same chunks for every NV
     const int rpc = (m + nchunk - 1) / nchunk;
-    const int colblocks = (N / 4 + kThreads - 1) / kThreads;
+    const int colblocks = (N / 4 + kThreads * TVCS_COLS_VEC - 1) / (kThreads * TVCS_COLS_VEC);
     hipLaunchKernelGGL((k_gemv_cols<NV>), dim3(colblocks, nchunk), dim3(kThreads),
                        sizeof(double) * rpc * NV, s, A, m, N, R, ldr, P, chunk_stride, rpc, st,
                        nact);
@@ -170,8 +203,8 @@ int gemv_cols_chunks(int m, int N) {
     // (rows x nv doubles, nv <= 8) within 64 KiB of LDS.  Independent of nv, so
     // the order of the sums does not depend on how many vectors share a pass.
     const int nv = 8;
-    const int colblocks = (N / 4 + kThreads - 1) / kThreads;
-    int nchunk = (1024 + colblocks - 1) / colblocks;
+    const int colblocks = (N / 4 + kThreads - 1) / kThreads;   // of 1024 columns
+    int nchunk = (TVCS_COLS_TARGET_WG + colblocks - 1) / colblocks;
     nchunk = std::max(1, std::min(nchunk, (m + 15) / 16));
     nchunk = std::max(nchunk, (m * nv + 8191) / 8192);
     // rows per chunk is ceil(m / nchunk); recompute nchunk so none is empty

@@ -27,74 +27,12 @@
 // Each thread owns one pixel and recomputes q at its left and upper neighbours,
 // so no LDS halo exchange or second pass is needed; the neighbours' u and q come
 // from L1/L2.  All per-pixel arithmetic is FP64; rhs is rounded to FP32 for the FFT.
-#include "tvcs_internal.h"
+#include "device_shrink.h"
 
 namespace tvcs {
 namespace {
 
-struct D2 {
-    double x, y;
-};
-
-__device__ inline D2 shrink2(D2 z, double inv_beta) {
-    const double t = sqrt(z.x * z.x + z.y * z.y);
-    const double s = t > inv_beta ? (t - inv_beta) / t : 0.0;   // 0 * (0/0) = 0
-    return {z.x * s, z.y * s};
-}
-
-__device__ inline int log2i(int n) { return __ffs(n) - 1; }
-
-template <bool IADM>
-__global__ __launch_bounds__(256) void k_shrink_rhs(ShrinkArgs a) {
-    const int b = blockIdx.y;
-    if (!a.st[b].active) return;
-    const int n = a.n, N = n * n, mask = n - 1, ln = log2i(n);
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= N) return;
-    const int r = p >> ln, c = p & mask;
-    const float *u = a.U + (size_t)b * N;
-    auto U = [&](int rr, int cc) -> double { return (double)u[((rr & mask) << ln) | (cc & mask)]; };
-    const double u0 = U(r, c), uE = U(r, c + 1), uS = U(r + 1, c), uW = U(r, c - 1),
-                 uSW = U(r + 1, c - 1), uN = U(r - 1, c), uNE = U(r - 1, c + 1);
-    const D2 d0 = {uE - u0, uS - u0};      // D u at (r, c)
-    const D2 dW = {u0 - uW, uSW - uW};     // D u at (r, c-1)
-    const D2 dN = {uNE - uN, u0 - uN};     // D u at (r-1, c)
-    const double ib = 1.0 / a.beta;
-    D2 q0, qW, qN;
-    if (IADM) {
-        const double *Q1 = a.Qold + (size_t)b * 2 * N, *Q2 = Q1 + N;
-        const int pW = (r << ln) | ((c - 1) & mask), pN = (((r - 1) & mask) << ln) | c;
-        const D2 o0 = {Q1[p], Q2[p]}, oW = {Q1[pW], Q2[pW]}, oN = {Q1[pN], Q2[pN]};
-        auto step = [&](D2 d, D2 o) {
-            const D2 s = shrink2({2.0 * d.x - o.x, 2.0 * d.y - o.y}, ib);
-            return D2{s.x - d.x + o.x, s.y - d.y + o.y};
-        };
-        q0 = step(d0, o0);
-        qW = step(dW, oW);
-        qN = step(dN, oN);
-        double *W1 = a.Qnew + (size_t)b * 2 * N;
-        W1[p] = q0.x;
-        W1[N + p] = q0.y;
-    } else {
-        q0 = shrink2(d0, ib);
-        qW = shrink2(dW, ib);
-        qN = shrink2(dN, ib);
-    }
-    // g_k at this pixel: fixed-order sum of the A^T r partials, eight independent
-    // loads in flight (the sum is latency-bound, not bandwidth-bound)
-    const float *g = a.G + (size_t)(b / a.gnv) * a.g_group_stride + (size_t)(b % a.gnv) * N + p;
-    double gs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int k = 0;
-    for (; k + 8 <= a.nchunk; k += 8) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) gs[j] += (double)g[(size_t)(k + j) * a.g_chunk_stride];
-    }
-    for (int j = 0; k < a.nchunk; ++k, ++j) gs[j] += (double)g[(size_t)k * a.g_chunk_stride];
-    const double gk = ((gs[0] + gs[1]) + (gs[2] + gs[3])) + ((gs[4] + gs[5]) + (gs[6] + gs[7]));
-    // D^T (q - D u) at (r, c): needs (q - D u) here, at (r, c-1) and at (r-1, c)
-    const double dtq = ((qW.x - dW.x) - (q0.x - d0.x)) + ((qN.y - dN.y) - (q0.y - d0.y));
-    a.RHS[(size_t)b * N + p] = (float)(dtq - a.ctau * gk);
-}
+using namespace shrinkdev;
 
 __global__ void k_init_q(int n, const float *__restrict__ U, const double *__restrict__ lam0,
                          double inv_beta, double *__restrict__ Q) {
@@ -160,15 +98,6 @@ __global__ __launch_bounds__(256) void k_objective(int n, int m, const float *__
 }
 
 }  // namespace
-
-void launch_shrink_rhs(const ShrinkArgs &a, bool iadm, hipStream_t s) {
-    const int N = a.n * a.n;
-    const dim3 grid((N + 255) / 256, a.B);
-    if (iadm)
-        hipLaunchKernelGGL(k_shrink_rhs<true>, grid, dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_shrink_rhs<false>, grid, dim3(256), 0, s, a);
-}
 
 void launch_init_q(int n, int B, const float *U, const double *lam0, double beta, double *Q,
                    hipStream_t s) {

@@ -65,7 +65,7 @@ struct tvcs_ctx {
     // workspace for a batch of up to `cap` images (Bp padded)
     int cap = 0, capP = 0;
     int gnv = 1;           // largest images-per-pass of the FP32 products
-    DevBuf U, F, R, P, RHS, Q0, Q1, S, parts, state, obj, lowp_work, lamb;
+    DevBuf U, F, R, P, RHS, Q0, Q1, S, parts, state, obj, lowp_work, lamb, counters;
     LowpWork lw{};
     ImgState *host_state = nullptr;   // pinned mirror for polling
     int host_state_cap = 0;
@@ -105,7 +105,7 @@ struct tvcs_ctx {
         const int Bp = padded(B);
         const size_t Nn = (size_t)N, mm = (size_t)m, h = (size_t)(n / 2 + 1);
         gnv = lowprec() ? Bp : std::min(Bp, 8);
-        const int nchunk = lowprec() ? 1 : chunks(Bp);
+        const int nchunk = lowprec() ? lowp_adj_splits(lowp) : chunks(Bp);
         U.ensure(sizeof(float) * Bp * Nn);
         F.ensure(sizeof(float) * Bp * mm);
         R.ensure(sizeof(float) * Bp * mm);
@@ -117,6 +117,8 @@ struct tvcs_ctx {
         parts.ensure(sizeof(double) * 2 * B * (size_t)n);   // >= n / rows-per-block
         state.ensure(sizeof(ImgState) * B);
         obj.ensure(sizeof(double) * B);
+        counters.ensure(sizeof(int) * B);
+        launch_fill(counters.as<float>(), (size_t)B, 0.f, work);   // all-zero bits
         if (lowprec()) {
             lowp_work.ensure(lowp_work_bytes(lowp, Bp));
             lowp_work_bind(lw, lowp, Bp, lowp_work.p);
@@ -132,7 +134,8 @@ struct tvcs_ctx {
         // padded images must hold zeros (their products are computed and ignored)
         launch_fill(U.as<float>(), (size_t)Bp * Nn, 0.f, work);
         launch_fill(F.as<float>(), (size_t)Bp * mm, 0.f, work);
-        if (lowprec()) lowp_autotune(lowp, lw, Bp, U.as<float>(), R.as<float>(), RHS.as<float>(), work);
+        // the adjoint writes all its K slices: P is sized for them
+        if (lowprec()) lowp_autotune(lowp, lw, Bp, U.as<float>(), R.as<float>(), P.as<float>(), work);
     }
 
     // vectors per pass and row chunks of the FP32 products for a padded batch Bp.
@@ -145,10 +148,11 @@ struct tvcs_ctx {
     size_t workspace_bytes(int B) const {
         const int Bp = padded(B);
         const size_t Nn = (size_t)N, mm = (size_t)m, h = (size_t)(n / 2 + 1);
-        const int nchunk = lowprec() ? 1 : chunks(Bp);
+        const int nchunk = lowprec() ? lowp_adj_splits(lowp) : chunks(Bp);
         size_t b = sizeof(float) * Bp * (2 * Nn + 2 * mm) + sizeof(float) * (size_t)nchunk * Bp * Nn +
                    2 * sizeof(double) * 2 * B * Nn + sizeof(float2) * B * h * n +
-                   sizeof(double) * 2 * B * (size_t)n + sizeof(ImgState) * B + sizeof(double) * B;
+                   sizeof(double) * 2 * B * (size_t)n + sizeof(ImgState) * B + sizeof(double) * B +
+                   sizeof(int) * B;
         if (lowprec()) b += lowp_work_bytes(lowp, Bp);
         return b;
     }
@@ -162,7 +166,8 @@ struct tvcs_ctx {
             TVCS_HIP(hipGraphExecDestroy(exec));
             exec = nullptr;
         }
-        for (DevBuf *b : {&U, &F, &R, &P, &RHS, &Q0, &Q1, &S, &parts, &state, &obj, &lowp_work, &lamb})
+        for (DevBuf *b : {&U, &F, &R, &P, &RHS, &Q0, &Q1, &S, &parts, &state, &obj, &lowp_work, &lamb,
+                          &counters})
             b->release();
         cap = capP = 0;
     }
@@ -215,8 +220,8 @@ struct tvcs_ctx {
     void apply_At_full(int Bp, int B, const float *Rin, float *out, const ImgState *st) {
         apply_At(Bp, B, Rin, st);
         if (lowprec()) {
-            TVCS_HIP(hipMemcpyAsync(out, P.p, sizeof(float) * (size_t)Bp * N,
-                                    hipMemcpyDeviceToDevice, work));
+            launch_sum_partials(P.as<float>(), lowp_adj_splits(lowp), (long long)Bp * N, Bp, N,
+                                out, N, work);
             return;
         }
         const int nv = pass_nv(Bp), nchunk = chunks(Bp);
@@ -235,8 +240,8 @@ struct tvcs_ctx {
         if (lowprec()) {
             a.gnv = Bp;
             a.g_group_stride = 0;
-            a.nchunk = 1;
-            a.g_chunk_stride = 0;
+            a.nchunk = lowp_adj_splits(lowp);
+            a.g_chunk_stride = (long long)Bp * N;
         } else {
             const int nv = pass_nv(Bp), nchunk = chunks(Bp);
             a.gnv = nv;
@@ -244,7 +249,6 @@ struct tvcs_ctx {
             a.g_group_stride = (long long)nchunk * nv * N;
             a.nchunk = nchunk;
         }
-        a.RHS = RHS.as<float>();
         a.st = state.as<ImgState>();
         return a;
     }
@@ -260,13 +264,12 @@ struct tvcs_ctx {
         a.ctau = ctau;
         a.Qold = parity ? Q1.as<double>() : Q0.as<double>();
         a.Qnew = parity ? Q0.as<double>() : Q1.as<double>();
-        launch_shrink_rhs(a, iadm, work);
         const float2 *twp = tw.as<float2>();
         float2 *Sp = S.as<float2>();
-        launch_fft_rows_fwd(n, B, RHS.as<float>(), Sp, twp, st, work);
+        launch_shrink_rows(a, iadm, Sp, twp, work);
         launch_fft_cols_solve(n, B, Sp, invd.as<double>(), twp, st, work);
-        launch_fft_rows_inv(n, B, Sp, U.as<float>(), parts.as<double>(), twp, st, work);
-        launch_finalize(st, parts.as<double>(), fft_row_parts(n, B), B, work);
+        launch_fft_rows_inv(n, B, Sp, U.as<float>(), parts.as<double>(), twp, st,
+                            counters.as<int>(), work);
     }
 
     void build_graph(int B, unsigned flags, double beta, double c, double ctau) {
@@ -333,7 +336,7 @@ struct tvcs_ctx {
     size_t device_bytes() const {
         return A32.bytes + lowp_mem.bytes + tw.bytes + invd.bytes + U.bytes + F.bytes + R.bytes +
                P.bytes + RHS.bytes + Q0.bytes + Q1.bytes + S.bytes + parts.bytes + state.bytes +
-               obj.bytes + lowp_work.bytes + lamb.bytes;
+               obj.bytes + lowp_work.bytes + lamb.bytes + counters.bytes;
     }
 };
 

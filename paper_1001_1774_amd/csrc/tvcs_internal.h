@@ -65,8 +65,6 @@ void launch_sum_partials(const float *P, int nchunk, long long chunk_stride, int
                          float *out, int ldo, hipStream_t s);
 void launch_fill(float *x, size_t count, float value, hipStream_t s);
 void launch_init_state(ImgState *st, int B, double tol, int maxit, hipStream_t s);
-// Per-image stop rule after a u-update: sums norm partials, updates state.
-void launch_finalize(ImgState *st, const double *parts, int nparts, int B, hipStream_t s);
 // Power-iteration step for lambda_max(A^T A): rq = v.w, v <- w/||w||; st->rel = rq,
 // st->iters counts steps, st->active cleared once |rq - rq_prev| <= rtol rq.
 void launch_power_normalize(float *v, const float *w, int N, ImgState *st, double rtol,
@@ -75,7 +73,8 @@ void launch_power_normalize(float *v, const float *w, int N, ImgState *st, doubl
 void launch_round_f64_f32(const double *src, float *dst, size_t count, hipStream_t s);
 
 // ---------------------------------------------------------------------------
-// Shrinkage and right-hand side (shrink.hip)
+// Shrinkage and right-hand side (device_shrink.h, consumed by the fused
+// shrink + forward row-FFT pass in fft.hip)
 //   FTVCS: q = s(D u);  IADM: q = s(2 D u - q_old) - D u + q_old
 //   rhs = D^T (q - D u) - c tau g (right side for the increment u^{k+1} - u^k),
 //   g = sum over `nchunk` partials of A^T r
@@ -92,11 +91,9 @@ struct ShrinkArgs {
     long long g_chunk_stride;
     const double *Qold;    // B x 2N (IADM)
     double *Qnew;          // B x 2N (IADM)
-    float *RHS;            // B x N
     double beta, c, ctau;  // c = mu/(beta tau), ctau = c*tau = mu/beta
     const ImgState *st;
 };
-void launch_shrink_rhs(const ShrinkArgs &a, bool iadm, hipStream_t s);
 void launch_init_q(int n, int B, const float *U, const double *lam0, double beta, double *Q,
                    hipStream_t s);
 // lambda^K = beta (D u^K - q^{K-1}); q^{K-1} is in Q0 when the image's iteration count
@@ -114,13 +111,15 @@ void launch_objective(int n, int m, int B, const float *U, const float *R, int l
 // ---------------------------------------------------------------------------
 void launch_twiddles(float2 *tw, hipStream_t s);
 void launch_denominators(int n, double c, double *inv_d, hipStream_t s);
-int fft_row_parts(int n, int B);   // number of norm partials per image written by rows_inv
-void launch_fft_rows_fwd(int n, int B, const float *RHS, float2 *S, const float2 *tw,
-                         const ImgState *st, hipStream_t s);
 void launch_fft_cols_solve(int n, int B, float2 *S, const double *inv_d, const float2 *tw,
                            const ImgState *st, hipStream_t s);
+// inverse row pass, u += increment, and the stop rule of every image (the last
+// workgroup of an image sums the norm partials; counters: one zeroed int per image)
 void launch_fft_rows_inv(int n, int B, const float2 *S, float *U, double *parts,
-                         const float2 *tw, const ImgState *st, hipStream_t s);
+                         const float2 *tw, ImgState *st, int *counters, hipStream_t s);
+// shrinkage + right-hand side fused with the forward row FFT
+void launch_shrink_rows(const ShrinkArgs &a, bool iadm, float2 *S, const float2 *tw,
+                        hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // MFMA products for bf16 / split-bf16 / fp8 storage (gemm.hip)
@@ -150,7 +149,9 @@ size_t lowp_work_bytes(const LowpA &L, int B);
 void lowp_work_bind(LowpWork &W, const LowpA &L, int B, void *base);
 void lowp_apply_A(const LowpA &L, LowpWork &W, int B, const float *U, const float *F, float *R,
                   const ImgState *st, hipStream_t s);
-// G[b*N + j] = (A^T r_b)_j  (G has one chunk)
+// K slices of the adjoint product: G holds that many partial sums, [slice][Bp][N]
+int lowp_adj_splits(const LowpA &L);
+// G[(k*Bp + b)*N + j] = slice k of (A^T r_b)_j
 void lowp_apply_At(const LowpA &L, LowpWork &W, int B, const float *R, float *G,
                    const ImgState *st, hipStream_t s);
 // pick the tile shape of each product by timing the candidates on this batch

@@ -45,41 +45,6 @@ __device__ inline double wave_sum(double x) {
     return x;
 }
 
-// One 64-lane block per image.  The stop rule of eq. (stop):
-//   ||u^{k+1} - u^k|| <= tol ||u^k||   (inclusive, FP64, tested after each u-update)
-__global__ __launch_bounds__(64) void k_finalize(ImgState *st, const double *__restrict__ parts,
-                                                 int nparts) {
-    const int b = blockIdx.x;
-    if (!st[b].active) return;
-    double du2 = 0.0, u2 = 0.0;
-    for (int p = threadIdx.x; p < nparts; p += 64) {
-        du2 += parts[((size_t)b * nparts + p) * 2 + 0];
-        u2 += parts[((size_t)b * nparts + p) * 2 + 1];
-    }
-    du2 = wave_sum(du2);
-    u2 = wave_sum(u2);
-    if (threadIdx.x == 0) {
-        ImgState s = st[b];
-        const double tol = s.tol;
-        s.iters += 1;
-        s.du2 = du2;
-        s.u2 = u2;
-        const double du = sqrt(du2), nu = sqrt(u2);
-        s.rel = nu > 0.0 ? du / nu : (du > 0.0 ? INFINITY : 0.0);
-        if (!isfinite(du2) || !isfinite(u2)) {
-            s.status = TVCS_ENONFINITE;
-            s.active = 0;
-        } else if (tol > 0.0 && du <= tol * nu) {
-            s.status = TVCS_OK;
-            s.active = 0;
-        } else if (s.iters >= s.maxit) {
-            s.status = tol > 0.0 ? TVCS_MAXIT : TVCS_OK;
-            s.active = 0;
-        }
-        st[b] = s;
-    }
-}
-
 // Power-iteration step: rq = v . w (= ||A v||^2 for unit v), v <- w / ||w||.
 // Stops (clears st->active) when |rq - rq_prev| <= rtol * rq.
 __global__ __launch_bounds__(1024) void k_power_normalize(float *v, const float *__restrict__ w,
@@ -150,10 +115,6 @@ void launch_fill(float *x, size_t count, float value, hipStream_t s) {
 
 void launch_init_state(ImgState *st, int B, double tol, int maxit, hipStream_t s) {
     hipLaunchKernelGGL(k_init_state, dim3((B + 63) / 64), dim3(64), 0, s, st, B, tol, maxit);
-}
-
-void launch_finalize(ImgState *st, const double *parts, int nparts, int B, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(B), dim3(64), 0, s, st, parts, nparts);
 }
 
 void launch_power_normalize(float *v, const float *w, int N, ImgState *st, double rtol,

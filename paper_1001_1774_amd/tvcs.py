@@ -17,7 +17,9 @@ import threading
 import numpy as np
 import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtvcs.so")
+# the in-tree build; TVCS_LIBRARY may name another build of the same sources
+LIB_PATH = os.environ.get("TVCS_LIBRARY") or os.path.join(
+    os.path.dirname(os.path.abspath(__file__)), "libtvcs.so")
 
 TVCS_OK = 0
 TVCS_MAXIT = 1
