@@ -52,6 +52,11 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the n = 256 batched-vs-plain section")
     ap.add_argument("--batched-iters", type=int, default=300)
+    ap.add_argument("--no-serving", action="store_true", help="skip the request-loop section")
+    ap.add_argument("--serving-full", action="store_true",
+                    help="4 matrices per (n, ratio) instead of 1 in the request-loop section")
+    ap.add_argument("--large", action="store_true",
+                    help="add the n = 512, m = 26214, B = 128 section (FP8 vs BF16 storage)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py measures one GPU: the method's images are "
@@ -151,6 +156,10 @@ def main():
     del solver
     if not args.no_batched:
         out["batched_n256"] = bench_batched(args, np, torch, O, synth, tvcs)
+    if not args.no_serving:
+        out["serving"] = bench_serving(args, np, synth, tvcs)
+    if args.large:
+        out["large_n512"] = bench_large(args, np, torch, synth, tvcs)
     print(json.dumps(out), flush=True)
 
 
@@ -211,6 +220,91 @@ def bench_batched(args, np, torch, O, synth, tvcs):
             "mfma_frac_of_bf16_peak_forward": flops / (ms_f * 1e-3) / 2.5e15,
         }
         log(f"{storage} B=64: {1e3 * dt / K:.3f} ms/iter, err {err:.2e}")
+    return res
+
+
+
+def bench_serving(args, np, synth, tvcs):
+    """Request loop: Poisson arrivals over resident BF16 matrices for n in {64, 128,
+    256} and sampling ratios {0.1, 0.2, 0.3} (1 or 4 matrices per pair), per-request
+    tol in {1e-3, 1e-4}, IADM, mu = 1e3, beta = 10.  First the saturated throughput
+    (all requests at t = 0), then arrival rates of 0.5, 0.8 and 0.95 of it."""
+    from paper_1001_1774_amd import serving as S
+    per = 4 if args.serving_full else 1
+    t0 = time.time()
+    pools, solvers = [], []
+    seed = 2001
+    for n in (64, 128, 256):
+        for r in (0.1, 0.2, 0.3):
+            for _ in range(per):
+                p = synth.make_problem(f"srv{seed}", n=n, ratio=r, batch=16, seed_A=seed,
+                                       image_index0=100 * seed, dtype=np.float32)
+                solvers.append(tvcs.Solver(p.A, n, storage="bf16"))
+                pools.append(p.f.astype(np.float32))
+                seed += 1
+    log(f"serving: {len(solvers)} matrices ready in {time.time() - t0:.1f}s")
+    rng = np.random.default_rng(7)
+    count = 300
+
+    def requests(rate):
+        reqs = []
+        for _ in range(count):
+            mi = int(rng.integers(len(solvers)))
+            reqs.append(S.Request(matrix=mi, f=pools[mi][int(rng.integers(16))],
+                                  tol=float(rng.choice([1e-3, 1e-4])), maxit=3000))
+        arr = S.poisson_arrivals(count, rate, int(rng.integers(1 << 30))) if rate else np.zeros(count)
+        for r_, a in zip(reqs, arr):
+            r_.arrival = float(a)
+        return reqs
+
+    res = {"matrices": len(solvers), "storage": "bf16", "slots_per_matrix": 32,
+           "requests_per_run": count, "algorithm": "IADM"}
+    with S.Server(slots=32, mu=1e3, beta=10.0, iadm=True) as srv:
+        for s_ in solvers:
+            srv.add_matrix(s_)
+        sat = S.run_arrivals(srv, requests(None))
+        res["saturated"] = {k: sat[k] for k in ("rec_per_s", "p50_ms", "p99_ms", "mean_iters")}
+        log(f"serving saturated: {sat['rec_per_s']:.1f} rec/s")
+        for frac in (0.5, 0.8, 0.95):
+            o = S.run_arrivals(srv, requests(frac * sat["rec_per_s"]))
+            res[f"poisson_{frac}"] = {k: o[k] for k in ("rec_per_s", "p50_ms", "p99_ms",
+                                                          "mean_iters")}
+            log(f"serving at {frac} of saturation: p50 {o['p50_ms']:.1f} ms, "
+                f"p99 {o['p99_ms']:.1f} ms")
+        res["device_bytes"] = srv.device_bytes
+    for s_ in solvers:
+        s_.close()
+    return res
+
+
+def bench_large(args, np, torch, synth, tvcs):
+    """n = 512, m = 26214 (10 %), 128 images sharing A, IADM, 300 iterations:
+    FP8-E4M3 with row scales against BF16 storage."""
+    t0 = time.time()
+    p = synth.workload("n512_m26214_b128", dtype=np.float32)
+    log(f"workload n512_m26214_b128 generated in {time.time() - t0:.1f}s")
+    F = torch.from_numpy(p.f.astype(np.float32)).cuda()
+    K = 300
+    res = {"workload": "n512_m26214_b128", "n": p.n, "m": p.m, "batch": p.B, "iterations": K,
+           "algorithm": "IADM"}
+    A = p.A
+    p.A = None
+    for storage, elem in (("fp8_rowscale", 1), ("bf16", 2)):
+        with tvcs.Solver(A, p.n, storage=storage) as s:
+            s.solve_batch(F, mu=p.mu, beta=p.beta, maxit=10, iadm=True)     # warm-up
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            s.solve_batch(F, mu=p.mu, beta=p.beta, maxit=K, iadm=True)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            ms_f, ms_a = s.time_products(B=p.B, reps=5)
+        a_bytes = elem * p.m * p.N
+        res[storage] = {"rec_per_s": p.B / dt, "ms_per_iter": 1e3 * dt / K,
+                        "gemm_forward_gbs": a_bytes / (ms_f * 1e-3) / 1e9,
+                        "gemm_adjoint_gbs": a_bytes / (ms_a * 1e-3) / 1e9,
+                        "mfma_frac_of_bf16_peak_forward":
+                            2.0 * p.m * p.N * p.B / (ms_f * 1e-3) / 2.5e15}
+        log(f"{storage} n=512 B=128: {1e3 * dt / K:.3f} ms/iter")
     return res
 
 

@@ -7,6 +7,10 @@
 
 #include "tvcs_internal.h"
 
+#ifndef TVCS_PARTIAL_LOADS
+#define TVCS_PARTIAL_LOADS 16  // A^T r partial sums loaded in flight per pixel (8 or 16)
+#endif
+
 namespace tvcs {
 namespace shrinkdev {
 
@@ -55,17 +59,24 @@ __device__ inline double rhs_at(const ShrinkArgs &a, int b, int p) {
         qW = shrink2(dW, ib);
         qN = shrink2(dN, ib);
     }
-    // g_k at this pixel: fixed-order sum of the A^T r partials, eight independent
-    // loads in flight (the sum is latency-bound, not bandwidth-bound)
+    // g_k at this pixel: fixed-order sum of the A^T r partials, TVCS_PARTIAL_LOADS
+    // independent loads in flight (the sum is latency-bound, not bandwidth-bound)
+    constexpr int PL = TVCS_PARTIAL_LOADS;
     const float *g = a.G + (size_t)(b / a.gnv) * a.g_group_stride + (size_t)(b % a.gnv) * N + p;
-    double gs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int k = 0;
-    for (; k + 8 <= a.nchunk; k += 8) {
+    double gs[PL];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) gs[j] += (double)g[(size_t)(k + j) * a.g_chunk_stride];
+    for (int j = 0; j < PL; ++j) gs[j] = 0.0;
+    int k = 0;
+    for (; k + PL <= a.nchunk; k += PL) {
+#pragma unroll
+        for (int j = 0; j < PL; ++j) gs[j] += (double)g[(size_t)(k + j) * a.g_chunk_stride];
     }
     for (int j = 0; k < a.nchunk; ++k, ++j) gs[j] += (double)g[(size_t)k * a.g_chunk_stride];
-    const double gk = ((gs[0] + gs[1]) + (gs[2] + gs[3])) + ((gs[4] + gs[5]) + (gs[6] + gs[7]));
+#pragma unroll
+    for (int w = PL / 2; w > 0; w >>= 1)
+#pragma unroll
+        for (int j = 0; j < w; ++j) gs[j] += gs[j + w];
+    const double gk = gs[0];
     // D^T (q - D u) at (r, c): needs (q - D u) here, at (r, c-1) and at (r-1, c)
     const double dtq = ((qW.x - dW.x) - (q0.x - d0.x)) + ((qN.y - dN.y) - (q0.y - d0.y));
     return dtq - a.ctau * gk;

@@ -236,8 +236,11 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
 // cpb * n <= 2048 complex per buffer).  The row blocking fixes the order in which
 // the stop-rule norms are summed, so it depends on n only: an image's iterates and
 // stop decisions are then the same whatever batch it is solved in.
+#ifndef TVCS_FFT_ROW_DIV
+#define TVCS_FFT_ROW_DIV 64    // rows per workgroup = n / TVCS_FFT_ROW_DIV (at least 2)
+#endif
 int rows_per_block(int n, int /*B*/) {
-    return std::max(2, std::min(n / 32, 4096 / n));
+    return std::max(2, std::min(n / TVCS_FFT_ROW_DIV, 4096 / n));
 }
 int cols_per_block(int n, int B) {
     const int h = n / 2 + 1;

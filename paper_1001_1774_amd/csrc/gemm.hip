@@ -16,15 +16,19 @@
 // streams each of its row tiles sequentially.
 //
 // GEMM: C[b][row] = sum_k X[row][k] Y[b][k] with X the streamed matrix (A or A^T)
-// and Y the small batch operand (U or R in bf16).  A workgroup (4 waves) owns
-// 4*RT*16 consecutive rows of X and all Bp = 16*NT images; each wave streams
-// its RT 16-row tiles of X straight from HBM into registers (every X element
-// is used by exactly one wave, so it never goes through LDS) and multiplies
-// them with the Y tile that the workgroup stages in LDS, with
-// v_mfma_f32_16x16x32_bf16 and FP32 accumulation.  Split storage adds the
-// products X_hi Y_lo and X_lo Y_hi (X_lo Y_lo, of relative size 2^-18, is left
-// out).  FP8 X is widened to bf16 in registers (exact) and multiplied with Y_hi;
-// the row scale folds into vectors: (A u)_i = s_i sum_j q_ij u_j and
+// and Y the small batch operand (U or R).  Y is always split, Y = Y_hi + Y_lo with
+// Y_hi = bf16(Y), Y_lo = bf16(Y - Y_hi): a bf16-only Y would add fresh relative
+// noise of ~2^-9 to every product in every iteration, which puts a floor under the
+// relative change of the iterates and keeps the stop rule (eq. (stop)) from ever
+// firing at tol = 1e-3.  With the split, the products carry only the fixed
+// rounding of A's storage format.  A workgroup (4 waves) owns 4*RT*16 consecutive
+// rows of X and all Bp = 16*NT images; each wave streams its RT 16-row tiles of X
+// straight from HBM into registers (every X element is used by exactly one wave,
+// so it never goes through LDS) and multiplies them with the Y tile that the
+// workgroup stages in LDS, with v_mfma_f32_16x16x32_bf16 and FP32 accumulation:
+// X Y_hi + X Y_lo, plus X_lo Y_hi for split storage (X_lo Y_lo, of relative size
+// 2^-18, is left out).  FP8 X is widened to bf16 in registers (exact); the row
+// scale folds into vectors: (A u)_i = s_i sum_j q_ij u_j and
 // (A^T r)_j = sum_i q_ij (s_i r_i).
 // The forward product splits its reduction (length N) into KS slices whose FP32
 // partial results are added in a fixed order by k_reduce_r; workgroups are
@@ -118,8 +122,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
     if (L >= total) return;
     const int ks = L / RB, rb = L % RB;
 
-    constexpr bool SPLIT = MODE == M_SPLIT;
-    constexpr int NY = SPLIT ? 2 : 1;
+    constexpr bool SPLIT = MODE == M_SPLIT;    // X has a lo part
+    constexpr int NY = 2;                      // Y is always hi + lo
     constexpr int KT = 32 * KF;                // reduction step
     constexpr int YLD = KT + 8;                // LDS row stride, padded against bank conflicts
     __shared__ u16 ys[NY][NT * 16][YLD];
@@ -167,9 +171,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
             const int yr = t / (KT / 8), yc = (t % (KT / 8)) * 8;
             *reinterpret_cast<uint4 *>(&ys[0][yr][yc]) =
                 *reinterpret_cast<const uint4 *>(Yhi + yr * ldy + k0 + yc);
-            if (SPLIT)
-                *reinterpret_cast<uint4 *>(&ys[NY - 1][yr][yc]) =
-                    *reinterpret_cast<const uint4 *>(Ylo + yr * ldy + k0 + yc);
+            *reinterpret_cast<uint4 *>(&ys[1][yr][yc]) =
+                *reinterpret_cast<const uint4 *>(Ylo + yr * ldy + k0 + yc);
         }
         __syncthreads();
 #pragma unroll
@@ -177,17 +180,13 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const bf16x8 yh = *reinterpret_cast<const bf16x8 *>(&ys[0][nt * 16 + lr][32 * s + lk]);
+                const bf16x8 yl = *reinterpret_cast<const bf16x8 *>(&ys[1][nt * 16 + lr][32 * s + lk]);
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt)
+                for (int rt = 0; rt < RT; ++rt) {
                     acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[rt][s], yh, acc[rt][nt], 0, 0, 0);
-                if (SPLIT) {
-                    const bf16x8 yl =
-                        *reinterpret_cast<const bf16x8 *>(&ys[NY - 1][nt * 16 + lr][32 * s + lk]);
-#pragma unroll
-                    for (int rt = 0; rt < RT; ++rt) {
-                        acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[rt][s], yl, acc[rt][nt], 0, 0, 0);
+                    acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[rt][s], yl, acc[rt][nt], 0, 0, 0);
+                    if (SPLIT)
                         acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl[rt][s], yh, acc[rt][nt], 0, 0, 0);
-                    }
                 }
             }
     }
@@ -321,10 +320,10 @@ void gemm_dispatch(int NT, const void *Xhi, const void *Xlo, long long ldx, cons
                    hipStream_t s) {
     const int total = RB * KS;
     const dim3 grid(((total + 7) / 8) * 8);
-    // the longer step needs twice the LDS; split batches of 128 keep the short one
+    // the longer step needs twice the LDS; batches of 128 keep the short one
 #define TVCS_GEMM_CASE(NTV)                                                                    \
     case NTV: {                                                                                \
-        constexpr int KF = (MODE == M_SPLIT && NTV == 8) ? 2 : KFREQ;                          \
+        constexpr int KF = NTV == 8 ? 2 : KFREQ;                                               \
         hipLaunchKernelGGL((k_gemm<MODE, RT, NTV, KF>), grid, dim3(kThreads), 0, s, Xhi, Xlo,  \
                            ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out, split_stride, ldo, st,   \
                            nact);                                                              \
@@ -535,7 +534,7 @@ void lowp_apply_A(const LowpA &L, LowpWork &W, int B, const float *U, const floa
     if (Bp > W.Bp) fail(TVCS_EINVAL, "MFMA workspace too small for the batch");
     const size_t cnt = (size_t)Bp * L.N;
     hipLaunchKernelGGL(k_split_vec, dim3(grid1d(cnt)), dim3(256), 0, s, U, cnt, (u16 *)W.Ubf_hi,
-                       mode == M_SPLIT ? (u16 *)W.Ubf_lo : nullptr);
+                       (u16 *)W.Ubf_lo);
     const int KS = fwd_splits(L);
     const long long split_stride = (long long)Bp * L.mp;
     for_each_group(Bp, B, [&](int img0, int nt, int nact) {
@@ -555,7 +554,7 @@ void lowp_apply_At(const LowpA &L, LowpWork &W, int B, const float *R, float *G,
     const int Bp = ((B + kBTile - 1) / kBTile) * kBTile;
     if (Bp > W.Bp) fail(TVCS_EINVAL, "MFMA workspace too small for the batch");
     hipLaunchKernelGGL(k_split_r, dim3((L.mp + 255) / 256, Bp), dim3(256), 0, s, R, L.m, L.mp,
-                       L.scale, (u16 *)W.Rbf_hi, mode == M_SPLIT ? (u16 *)W.Rbf_lo : nullptr);
+                       L.scale, (u16 *)W.Rbf_hi, (u16 *)W.Rbf_lo);
     const int KS = lowp_adj_splits(L);
     const long long split_stride = (long long)Bp * L.N;
     for_each_group(Bp, B, [&](int img0, int nt, int nact) {

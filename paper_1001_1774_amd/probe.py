@@ -1,0 +1,42 @@
+"""Run only the two dense products of a workload, for profilers.
+
+    python -m paper_1001_1774_amd.probe --workload n128_m4096 --storage fp32 --batch 1 --reps 5
+
+First copies a 256 MiB device buffer once (a plain copy of known size: reads and
+writes 268435456 bytes), which calibrates hardware byte counters such as
+FETCH_SIZE / WRITE_SIZE; then launches the forward product (r = A u - f) and the
+adjoint product (A^T r) `reps` times each through tvcs_time_products and prints
+the HIP-event times.  Inputs are the seeded synthetic workloads.
+"""
+import argparse
+import json
+
+import numpy as np
+import torch
+
+from . import synth, tvcs
+
+COPY_BYTES = 256 << 20
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="n128_m4096", choices=sorted(synth.WORKLOADS))
+    ap.add_argument("--storage", default="fp32", choices=sorted(tvcs.STORAGE))
+    ap.add_argument("--batch", type=int, default=1)
+    ap.add_argument("--reps", type=int, default=5)
+    args = ap.parse_args()
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    p = synth.workload(args.workload, batch=1, dtype=np.float32)
+    with tvcs.Solver(p.A, p.n, storage=args.storage) as s:
+        fwd, adj = s.time_products(args.batch, args.reps)
+    print(json.dumps({"workload": args.workload, "storage": args.storage, "batch": args.batch,
+                      "reps": args.reps, "forward_ms": fwd, "adjoint_ms": adj,
+                      "copy_bytes": COPY_BYTES}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,12 +1,12 @@
 """GPU parity of the batched MFMA path (BF16, split BF16, FP8 storage of A).
 
-Bars: split storage (hi + lo, with the batch operand split the same way) must stay
-within 1e-4 relative iterate error of the FP64 oracle on the FP64 A after a fixed
-number of iterations.  Plain BF16 and FP8 storage are measured against the
-oracle run on the de-quantised A they represent (FP64 arithmetic), which leaves
-only the rounding of the batch operand to bf16 (relative 2^-9) and FP32
-accumulation; their error against the FP64-A oracle is reported, not bounded
-tightly (it is set by the storage format, not by the kernels).
+Bars: split storage must stay within 1e-4 relative iterate error of the FP64
+oracle on the FP64 A after a fixed number of iterations.  Plain BF16 and FP8
+storage must stay within 1e-4 of the oracle run on the de-quantised A they
+represent (FP64 arithmetic): the batch operand is split hi + lo in every mode, so
+what remains is the products' FP32 accumulation and the 2^-18 cross term.  Their
+error against the FP64-A oracle is set by the storage format itself; it is
+reported (relative error and PSNR), not bounded tightly.
 """
 import sys
 
@@ -87,7 +87,7 @@ def test_lowp_against_dequantised_oracle(T, batch64, storage):
                for b in range(p.B))
     say(f"  max rel err vs dequantised-A oracle {eq:.3e}; vs FP64-A oracle {e64:.3e} "
         f"(min PSNR {psnr:.1f} dB)")
-    assert eq <= 2e-2
+    assert eq <= 1e-4
     assert e64 <= 0.2
 
 
@@ -109,6 +109,25 @@ def test_lowp_batch_invariance(T, batch64):
         for slot in (0, 3, 12):
             b = perm[slot]
             assert np.array_equal(rp["u"][slot].cpu().numpy(), rb["u"][b].cpu().numpy())
+
+
+@pytest.mark.parametrize("storage", ["bf16", "fp8_rowscale"])
+def test_lowp_storage_reaches_tolerance(T, batch64, storage):
+    """With the batch operand split hi + lo, plain BF16 / FP8 storage converges: the
+    stop rule fires at tol = 1e-3 well before the cap, at the iteration the oracle on
+    the de-quantised A stops (+-1)."""
+    p = batch64
+    Aq = O.dequantized_A(p.A, storage)
+    tau = tau_for(Aq)
+    ref = O.iadm(Aq, p.f, p.n, p.mu, p.beta, tau, tol=1e-3, maxit=1000)
+    with T.Solver(p.A, p.n, storage=storage) as s:
+        s.tau = tau
+        out = s.solve_batch(p.f.astype(np.float32), mu=p.mu, beta=p.beta, tol=1e-3, maxit=1000,
+                            iadm=True)
+    it = np.array([st["iters"] for st in out["stats"]])
+    say(f"  {storage}: iters {it.tolist()}\n  oracle {ref.iters.tolist()}")
+    assert out["rc"] == T.TVCS_OK and it.max() < 1000
+    assert np.all(np.abs(it - ref.iters) <= 1)
 
 
 def test_lowp_stop_rule_per_image(T, batch64):
