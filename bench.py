@@ -24,6 +24,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_gemv_n128_m4096.md")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
+    summary of the n = 128, m = 4096 products (None if absent)."""
+    try:
+        for line in open(TRAFFIC_FILE):
+            if line.startswith(f"traffic_bytes_per_launch {kernel}:"):
+                return float(line.split(":")[1])
+    except OSError:
+        pass
+    return None
 
 
 def log(*a):
@@ -148,8 +161,10 @@ def main():
         "gemv_gbs": {"forward": fwd_gbs, "adjoint": adj_gbs,
                      "forward_ms": ms_fwd, "adjoint_ms": ms_adj},
         "roofline": {"bound": "hbm", "achieved": fwd_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": fwd_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_gemv_rows<1,4> (r = A u - f)"},
+                     "frac": fwd_gbs / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("k_gemv_rows"),
+                     "algorithmic_bytes": fwd_bytes,
+                     "kernel": "k_gemv_rows<1,2> (r = A u - f)"},
         "cpu_baseline": cpu,
     }
     solver.close()

@@ -117,8 +117,48 @@ __global__ __launch_bounds__(kThreads) void k_cols_solve(int n, int cpb, float2 
     for (int e = threadIdx.x; e < nc * n; e += kThreads) col[e] = out[e];
 }
 
-// Inverse row pass + stop rule (see the file header).  `counters` holds one zero
-// int per image; the last block of an image to finish resets it.
+// The stop rule of eq. (stop), ||u^{k+1} - u^k|| <= tol ||u^k|| (inclusive, FP64),
+// for one image from its row blocks' partial sums (added in block order by one
+// 64-lane wave, so the result does not depend on how the pass was launched).
+__device__ void stop_rule(ImgState *st, const double *parts, int nparts, int *counter) {
+    const int lane = threadIdx.x & 63;
+    double sd = 0.0, su = 0.0;
+    for (int p = lane; p < nparts; p += 64) {
+        sd += __hip_atomic_load(parts + 2 * p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        su += __hip_atomic_load(parts + 2 * p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        sd += __shfl_xor(sd, off, 64);
+        su += __shfl_xor(su, off, 64);
+    }
+    if (lane == 0) {
+        ImgState s = *st;
+        s.iters += 1;
+        s.du2 = sd;
+        s.u2 = su;
+        const double du = sqrt(sd), nu = sqrt(su);
+        s.rel = nu > 0.0 ? du / nu : (du > 0.0 ? INFINITY : 0.0);
+        if (!isfinite(sd) || !isfinite(su)) {
+            s.status = TVCS_ENONFINITE;
+            s.active = 0;
+        } else if (s.tol > 0.0 && du <= s.tol * nu) {
+            s.status = TVCS_OK;
+            s.active = 0;
+        } else if (s.iters >= s.maxit) {
+            s.status = s.tol > 0.0 ? TVCS_MAXIT : TVCS_OK;
+            s.active = 0;
+        }
+        *st = s;
+        if (counter) *counter = 0;   // ready for the next pass
+    }
+}
+
+// Inverse row pass (see the file header).  FUSED: the last block of each image to
+// finish (counted in `counters`, one zeroed int per image) also applies the stop
+// rule; this needs a device-scope fence per block, cheap for one image but not for
+// thousands of blocks, so batches use k_stop_rule instead.
+template <bool FUSED>
 __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const float2 *__restrict__ S,
                                                        float *__restrict__ U,
                                                        double *__restrict__ parts,
@@ -189,46 +229,26 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
         __hip_atomic_store(myparts + 2 * blockIdx.x, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(myparts + 2 * blockIdx.x + 1, c, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        s_last = atomicAdd(&counters[b], 1) == (int)gridDim.x - 1;
+        if (FUSED) {
+            __threadfence();
+            s_last = atomicAdd(&counters[b], 1) == (int)gridDim.x - 1;
+        }
     }
+    if (!FUSED) return;
     __syncthreads();
     if (!s_last) return;
-    // The last block of image b applies the stop rule of eq. (stop):
-    //   ||u^{k+1} - u^k|| <= tol ||u^k||  (inclusive, FP64), summing the blocks'
-    // partial sums in block order.
+    // The last block of image b applies the stop rule
     __threadfence();
-    if (threadIdx.x >= 64) return;
-    double sd = 0.0, su = 0.0;
-    for (int p = lane; p < (int)gridDim.x; p += 64) {
-        sd += __hip_atomic_load(myparts + 2 * p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        su += __hip_atomic_load(myparts + 2 * p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        sd += __shfl_xor(sd, off, 64);
-        su += __shfl_xor(su, off, 64);
-    }
-    if (lane == 0) {
-        ImgState s = st[b];
-        s.iters += 1;
-        s.du2 = sd;
-        s.u2 = su;
-        const double du = sqrt(sd), nu = sqrt(su);
-        s.rel = nu > 0.0 ? du / nu : (du > 0.0 ? INFINITY : 0.0);
-        if (!isfinite(sd) || !isfinite(su)) {
-            s.status = TVCS_ENONFINITE;
-            s.active = 0;
-        } else if (s.tol > 0.0 && du <= s.tol * nu) {
-            s.status = TVCS_OK;
-            s.active = 0;
-        } else if (s.iters >= s.maxit) {
-            s.status = s.tol > 0.0 ? TVCS_MAXIT : TVCS_OK;
-            s.active = 0;
-        }
-        st[b] = s;
-        counters[b] = 0;   // ready for the next pass
-    }
+    if (threadIdx.x < 64) stop_rule(st + b, myparts, gridDim.x, counters + b);
+}
+
+// Stop rule after an inverse row pass, for images whose row passes ran without
+// the fused reduction (batches): one 64-lane block per image.
+__global__ __launch_bounds__(64) void k_stop_rule(ImgState *__restrict__ st,
+                                                  const double *__restrict__ parts, int nparts) {
+    const int b = blockIdx.x;
+    if (!st[b].active) return;
+    stop_rule(st + b, parts + (size_t)b * nparts * 2, nparts, nullptr);
 }
 
 // Rows (columns) per workgroup: enough workgroups for one image to spread over
@@ -271,8 +291,14 @@ void launch_fft_rows_inv(int n, int B, const float2 *S, float *U, double *parts,
                          const float2 *tw, ImgState *st, int *counters, hipStream_t s) {
     const int rpb = rows_per_block(n, B);
     const size_t lds = sizeof(float2) * (kMaxN + 2 * ((rpb / 2) * n + rpb));
-    hipLaunchKernelGGL(k_rows_inv, dim3(n / rpb, B), dim3(kThreads), lds, s, n, rpb, S, U, parts,
-                       tw, st, counters);
+    if (B == 1) {
+        hipLaunchKernelGGL(k_rows_inv<true>, dim3(n / rpb, B), dim3(kThreads), lds, s, n, rpb, S, U,
+                           parts, tw, st, counters);
+    } else {
+        hipLaunchKernelGGL(k_rows_inv<false>, dim3(n / rpb, B), dim3(kThreads), lds, s, n, rpb, S,
+                           U, parts, tw, st, counters);
+        hipLaunchKernelGGL(k_stop_rule, dim3(B), dim3(64), 0, s, st, parts, n / rpb);
+    }
 }
 
 void launch_shrink_rows(const ShrinkArgs &a, bool iadm, float2 *S, const float2 *tw,

@@ -21,11 +21,14 @@
 // noise of ~2^-9 to every product in every iteration, which puts a floor under the
 // relative change of the iterates and keeps the stop rule (eq. (stop)) from ever
 // firing at tol = 1e-3.  With the split, the products carry only the fixed
-// rounding of A's storage format.  A workgroup (4 waves) owns 4*RT*16 consecutive
-// rows of X and all Bp = 16*NT images; each wave streams its RT 16-row tiles of X
-// straight from HBM into registers (every X element is used by exactly one wave,
-// so it never goes through LDS) and multiplies them with the Y tile that the
-// workgroup stages in LDS, with v_mfma_f32_16x16x32_bf16 and FP32 accumulation:
+// rounding of A's storage format.  Y is written in the same fragment order as X
+// (16 images x 32 k per 1 KiB block).  A workgroup (4 waves) owns 4*RT*16
+// consecutive rows of X and all 16*NT images of its group; each wave streams its
+// RT 16-row tiles of X straight from HBM into registers (every X element is used
+// by exactly one wave, so it never goes through LDS), while the workgroup stages
+// the Y blocks of each step in LDS (double-buffered, moved through registers).
+// The loop is software-pipelined: X of step t + 1 and Y of step t + 2 are in
+// flight while step t runs v_mfma_f32_16x16x32_bf16 with FP32 accumulation:
 // X Y_hi + X Y_lo, plus X_lo Y_hi for split storage (X_lo Y_lo, of relative size
 // 2^-18, is left out).  FP8 X is widened to bf16 in registers (exact); the row
 // scale folds into vectors: (A u)_i = s_i sum_j q_ij u_j and
@@ -33,17 +36,27 @@
 // The forward product splits its reduction (length N) into KS slices whose FP32
 // partial results are added in a fixed order by k_reduce_r; workgroups are
 // ordered so that each XCD works on one K slice and its Y slice stays in that
-// XCD's L2.
+// XCD's L2.  No order of summation depends on the batch, the image group or the
+// tile shape, so an image's products are the same bits in any batch.
 #include "tvcs_internal.h"
 
 #include <algorithm>
 
 // Tile parameters (compile-time; the defaults are the measured best on MI355X)
-#ifndef TVCS_GEMM_KF_FWD
-#define TVCS_GEMM_KF_FWD 4     // 32-wide k tiles per loop step, forward product (2 or 4)
+#ifndef TVCS_GEMM_KF_NT8
+#define TVCS_GEMM_KF_NT8 1     // 32-wide k tiles per pipeline step for 128-image groups
 #endif
-#ifndef TVCS_GEMM_KF_ADJ
-#define TVCS_GEMM_KF_ADJ 2     // the same for the adjoint product
+#ifndef TVCS_GEMM_KF_NT4
+#define TVCS_GEMM_KF_NT4 2     // ... 64-image groups
+#endif
+#ifndef TVCS_GEMM_KF_NT2
+#define TVCS_GEMM_KF_NT2 4     // ... 32-image groups
+#endif
+#ifndef TVCS_GEMM_KF_NT1
+#define TVCS_GEMM_KF_NT1 4     // ... 16-image groups (at least 2)
+#endif
+#ifndef TVCS_GEMM_FORCE_RT
+#define TVCS_GEMM_FORCE_RT 0   // 2 or 4: skip the autotuner's choice of row tiles per wave
 #endif
 #ifndef TVCS_FWD_TARGET_WG
 #define TVCS_FWD_TARGET_WG 256 // K slices of the forward product grow until this many tiles
@@ -60,6 +73,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16;
 typedef unsigned char u8;
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
 constexpr int KMAX = 128;        // longest reduction step; every K slice is a multiple of it
@@ -108,10 +122,47 @@ __device__ inline bf16x8 fp8x8_to_bf16(u32x2 q) {
     return r;
 }
 
+// X fragments of one reduction step held in registers (FP8 stays packed until use)
+template <int MODE, int RT, int KF>
+struct XRegs {
+    bf16x8 h[RT][KF];
+    bf16x8 l[MODE == M_SPLIT ? RT : 1][MODE == M_SPLIT ? KF : 1];
+};
+template <int RT, int KF>
+struct XRegs<M_FP8, RT, KF> {
+    u32x2 q[RT][KF];
+};
+
+template <int MODE, int RT, int KF>
+__device__ inline void load_x(XRegs<MODE, RT, KF> &x, const void *Xhi, const void *Xlo,
+                              const long long (&xoff)[RT], int kt0) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int s = 0; s < KF; ++s) {
+            const long long o = xoff[rt] + (long long)(kt0 + s) * 512;
+            if constexpr (MODE == M_FP8) {
+                x.q[rt][s] = __builtin_nontemporal_load(
+                    reinterpret_cast<const u32x2 *>((const u8 *)Xhi + o));
+            } else {
+                x.h[rt][s] = __builtin_nontemporal_load(
+                    reinterpret_cast<const bf16x8 *>((const u16 *)Xhi + o));
+                if constexpr (MODE == M_SPLIT)
+                    x.l[rt][s] = __builtin_nontemporal_load(
+                        reinterpret_cast<const bf16x8 *>((const u16 *)Xlo + o));
+            }
+        }
+}
+
+// Y (the batch operand) is stored in the same fragment order as X: image tile t
+// (16 images), k tile u (32) is the 512-element block (t * ktiles + u), so the Y
+// fragments of one step are whole 1 KiB blocks.  Per step the workgroup needs
+// 2 (hi, lo) x NT x KF blocks; wave w moves blocks w, w + 4, ... through registers
+// into LDS, where every fragment read is one contiguous 1 KiB (no bank conflicts).
 template <int MODE, int RT, int NT, int KF>
 __global__ __launch_bounds__(kThreads) void k_gemm(
-    const void *__restrict__ Xhi, const void *__restrict__ Xlo, long long ldx,
-    const u16 *__restrict__ Yhi, const u16 *__restrict__ Ylo, long long ldy, int M, int kspan,
+    const void *__restrict__ Xhi, const void *__restrict__ Xlo, long long xkt,
+    const u16 *__restrict__ Yhi, const u16 *__restrict__ Ylo, long long ykt, int M, int kspan,
     int RB, int KS, float *__restrict__ out, long long split_stride, long long ldo,
     const ImgState *__restrict__ st, int nact) {
     if (!any_active(st, nact)) return;
@@ -122,16 +173,15 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
     if (L >= total) return;
     const int ks = L / RB, rb = L % RB;
 
-    constexpr bool SPLIT = MODE == M_SPLIT;    // X has a lo part
-    constexpr int NY = 2;                      // Y is always hi + lo
-    constexpr int KT = 32 * KF;                // reduction step
-    constexpr int YLD = KT + 8;                // LDS row stride, padded against bank conflicts
-    __shared__ u16 ys[NY][NT * 16][YLD];
+    constexpr int NB = NT * KF;       // Y blocks per step and part
+    constexpr int YPW = 2 * NB / 4;   // Y blocks moved per wave and step
+    static_assert(2 * NB % 4 == 0, "the four waves share the Y blocks evenly");
+    __shared__ __attribute__((aligned(16))) u16 ys[2][2 * NB][512];
 
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int lr = lane & 15, lk = (lane >> 4) * 8;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int row_wave = rb * (4 * RT * 16) + wave * RT * 16;
-    const int k_begin = ks * kspan, k_end = k_begin + kspan;
+    const int kt_begin = (ks * kspan) >> 5;
+    const int steps = kspan / (32 * KF);
 
     f32x4 acc[RT][NT];
 #pragma unroll
@@ -139,59 +189,94 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    // fragment-ordered X: block (row tile t, k tile u) at (t * ldx/32 + u) * 512, lane at +8 l
-    const long long ktiles = ldx >> 5;
     long long xoff[RT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
-        xoff[rt] = (long long)min((row_wave >> 4) + rt, (M >> 4) - 1) * ktiles * 512 + lane * 8;
+        xoff[rt] = (long long)min((row_wave >> 4) + rt, (M >> 4) - 1) * xkt * 512 + lane * 8;
 
-    for (int k0 = k_begin; k0 < k_end; k0 += KT) {
-        // this wave's X fragments: tile rt, k tiles k0/32 .. + KF - 1 (contiguous 1 KiB each)
-        bf16x8 xh[RT][KF], xl[RT][KF];
+    // this wave's Y blocks: j = wave + 4 q -> part j / NB, image tile (j % NB) / KF, k tile j % KF
+    const u16 *ysrc[YPW];
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
+    for (int q = 0; q < YPW; ++q) {
+        const int j = wave + 4 * q, part = j / NB, r = j % NB;
+        ysrc[q] = (part ? Ylo : Yhi) + ((long long)(r / KF) * ykt + kt_begin + r % KF) * 512 + lane * 8;
+    }
+    u32x4 yr[YPW];
+    auto load_y = [&](int t) {
 #pragma unroll
-            for (int s = 0; s < KF; ++s) {
-                const long long o = xoff[rt] + (long long)((k0 >> 5) + s) * 512;
-                if (MODE == M_FP8) {
-                    xh[rt][s] = fp8x8_to_bf16(__builtin_nontemporal_load(
-                        reinterpret_cast<const u32x2 *>((const u8 *)Xhi + o)));
-                } else {
-                    xh[rt][s] = __builtin_nontemporal_load(
-                        reinterpret_cast<const bf16x8 *>((const u16 *)Xhi + o));
-                    if (SPLIT)
-                        xl[rt][s] = __builtin_nontemporal_load(
-                            reinterpret_cast<const bf16x8 *>((const u16 *)Xlo + o));
-                }
+        for (int q = 0; q < YPW; ++q)
+            yr[q] = *reinterpret_cast<const u32x4 *>(ysrc[q] + (long long)t * KF * 512);
+    };
+    auto store_y = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < YPW; ++q)
+            *reinterpret_cast<u32x4 *>(&ys[buf][wave + 4 * q][lane * 8]) = yr[q];
+    };
+    auto compute = [&](const XRegs<MODE, RT, KF> &x, int buf) {
+#pragma unroll
+        for (int s = 0; s < KF; ++s) {
+            bf16x8 xc[RT];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                if constexpr (MODE == M_FP8)
+                    xc[rt] = fp8x8_to_bf16(x.q[rt][s]);
+                else
+                    xc[rt] = x.h[rt][s];
             }
-        // stage the Y tile (NT*16 images x KT) in LDS
-        __syncthreads();
-        for (int t = threadIdx.x; t < NT * 16 * (KT / 8); t += kThreads) {
-            const int yr = t / (KT / 8), yc = (t % (KT / 8)) * 8;
-            *reinterpret_cast<uint4 *>(&ys[0][yr][yc]) =
-                *reinterpret_cast<const uint4 *>(Yhi + yr * ldy + k0 + yc);
-            *reinterpret_cast<uint4 *>(&ys[1][yr][yc]) =
-                *reinterpret_cast<const uint4 *>(Ylo + yr * ldy + k0 + yc);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int s = 0; s < KF; ++s)
+            // the RT accumulators of an image tile are updated in turn, so RT - 1
+            // independent MFMAs separate two that share an accumulator
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
-                const bf16x8 yh = *reinterpret_cast<const bf16x8 *>(&ys[0][nt * 16 + lr][32 * s + lk]);
-                const bf16x8 yl = *reinterpret_cast<const bf16x8 *>(&ys[1][nt * 16 + lr][32 * s + lk]);
+                const bf16x8 yh = *reinterpret_cast<const bf16x8 *>(&ys[buf][nt * KF + s][lane * 8]);
+                const bf16x8 yl = *reinterpret_cast<const bf16x8 *>(&ys[buf][NB + nt * KF + s][lane * 8]);
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt) {
-                    acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[rt][s], yh, acc[rt][nt], 0, 0, 0);
-                    acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[rt][s], yl, acc[rt][nt], 0, 0, 0);
-                    if (SPLIT)
-                        acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl[rt][s], yh, acc[rt][nt], 0, 0, 0);
+                for (int rt = 0; rt < RT; ++rt)
+                    acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[rt], yh, acc[rt][nt], 0, 0, 0);
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+                    acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[rt], yl, acc[rt][nt], 0, 0, 0);
+                if constexpr (MODE == M_SPLIT) {
+#pragma unroll
+                    for (int rt = 0; rt < RT; ++rt)
+                        acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x.l[rt][s], yh, acc[rt][nt], 0, 0, 0);
                 }
             }
+        }
+    };
+
+    // Software pipeline: the X fragments of step t + 1 and the Y blocks of step
+    // t + 2 are in flight while step t computes; Y is double-buffered in LDS.  The
+    // loop takes steps in pairs (X alternates between two register sets) and a
+    // last odd step follows it, so the accumulators never change registers.  Loads
+    // past the last step re-read the last step (in bounds, results unused), which
+    // keeps the body branch-free so that each wait covers only the data it needs;
+    // scheduling barriers keep the compiler from sinking the prefetches.
+    XRegs<MODE, RT, KF> xa, xb;
+    const int last = steps - 1;
+    load_y(0);
+    store_y(0);
+    load_x(xa, Xhi, Xlo, xoff, kt_begin);
+    load_y(min(1, last));
+    __syncthreads();
+    int t = 0;
+    for (; t + 1 < steps; t += 2) {
+        load_x(xb, Xhi, Xlo, xoff, kt_begin + (t + 1) * KF);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(xa, 0);
+        store_y(1);
+        load_y(min(t + 2, last));
+        __syncthreads();
+        load_x(xa, Xhi, Xlo, xoff, kt_begin + min(t + 2, last) * KF);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(xb, 1);
+        store_y(0);
+        load_y(min(t + 3, last));
+        __syncthreads();
     }
+    if (t < steps) compute(xa, 0);
     // lane holds rows 4*(lane/16) .. +3 of its 16-row tile, image lane % 16 of its tile
     float *o = out + ks * split_stride;
+    const int lr = lane & 15;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
         const int row = row_wave + rt * 16 + 4 * (lane >> 4);
@@ -271,15 +356,35 @@ __global__ void k_frag(const float *__restrict__ A, int m, int N, int mp,
     }
 }
 
-// per-iteration: U (Bp x N, FP32) -> bf16 hi (and lo)
-__global__ void k_split_vec(const float *__restrict__ U, size_t count, u16 *__restrict__ hi,
-                            u16 *__restrict__ lo) {
-    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < count;
-         e += (size_t)gridDim.x * blockDim.x) {
-        const float x = U[e];
-        const u16 h = bf16_rne(x);
-        hi[e] = h;
-        if (lo) lo[e] = bf16_rne(x - bf16_f32(h));
+// Batch operand Y of a product, in fragment order: V (Bp rows of length kv, FP32)
+// -> bf16 hi and lo = bf16(v - hi) over K >= kv columns (columns >= kv are zero),
+// each column optionally multiplied by scale[k] first (FP64 product, FP32 result).
+// One thread per lane-chunk of 8 elements: block f = (image tile, k tile), lane l
+// holds image 16 t + l % 16, columns 32 u + 8 (l / 16) .. +7.
+__global__ void k_split_frag(const float *__restrict__ V, int kv, int K, int Bp,
+                             const float *__restrict__ scale, u16 *__restrict__ hi,
+                             u16 *__restrict__ lo) {
+    const size_t chunks = (size_t)Bp * K / 8, ktiles = (size_t)K / 32;
+    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < chunks;
+         c += (size_t)gridDim.x * blockDim.x) {
+        const size_t f = c >> 6;
+        const int l = (int)(c & 63);
+        const size_t b = (f / ktiles) * 16 + (l & 15);
+        const int k0 = (int)(f % ktiles) * 32 + 8 * (l >> 4);
+        u16 h[8], w[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = k0 + j;
+            float x = 0.f;
+            if (k < kv) {
+                x = V[b * kv + k];
+                if (scale) x = (float)((double)x * (double)scale[k]);
+            }
+            h[j] = bf16_rne(x);
+            w[j] = bf16_rne(x - bf16_f32(h[j]));   // exact in FP32
+        }
+        reinterpret_cast<uint4 *>(hi)[c] = *reinterpret_cast<const uint4 *>(h);
+        reinterpret_cast<uint4 *>(lo)[c] = *reinterpret_cast<const uint4 *>(w);
     }
 }
 
@@ -297,80 +402,60 @@ __global__ void k_reduce_r(const float *__restrict__ P, int KS, long long split_
     R[(size_t)b * m + i] = (float)acc;
 }
 
-// Y operand of the adjoint: bf16(s_i r_i) hi (and lo), rows padded to mp with zeros
-__global__ void k_split_r(const float *__restrict__ R, int m, int mp, const float *__restrict__ scale,
-                          u16 *__restrict__ hi, u16 *__restrict__ lo) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = blockIdx.y;
-    if (i >= mp) return;
-    float x = 0.f;
-    if (i < m) {
-        x = R[(size_t)b * m + i];
-        if (scale) x = (float)((double)x * (double)scale[i]);
-    }
-    const u16 h = bf16_rne(x);
-    hi[(size_t)b * mp + i] = h;
-    if (lo) lo[(size_t)b * mp + i] = bf16_rne(x - bf16_f32(h));
-}
-
-template <int MODE, int RT, int KFREQ>
+template <int MODE, int RT>
 void gemm_dispatch(int NT, const void *Xhi, const void *Xlo, long long ldx, const u16 *Yhi,
                    const u16 *Ylo, long long ldy, int M, int kspan, int RB, int KS, float *out,
                    long long split_stride, long long ldo, const ImgState *st, int nact,
                    hipStream_t s) {
     const int total = RB * KS;
     const dim3 grid(((total + 7) / 8) * 8);
-    // the longer step needs twice the LDS; batches of 128 keep the short one
-#define TVCS_GEMM_CASE(NTV)                                                                    \
-    case NTV: {                                                                                \
-        constexpr int KF = NTV == 8 ? 2 : KFREQ;                                               \
-        hipLaunchKernelGGL((k_gemm<MODE, RT, NTV, KF>), grid, dim3(kThreads), 0, s, Xhi, Xlo,  \
-                           ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out, split_stride, ldo, st,   \
-                           nact);                                                              \
-        break;                                                                                 \
-    }
+#define TVCS_GEMM_CASE(NTV, KFV)                                                               \
+    case NTV:                                                                                  \
+        hipLaunchKernelGGL((k_gemm<MODE, RT, NTV, KFV>), grid, dim3(kThreads), 0, s, Xhi, Xlo,  \
+                           ldx >> 5, Yhi, Ylo, ldy >> 5, M, kspan, RB, KS, out, split_stride,  \
+                           ldo, st, nact);                                                     \
+        break;
     switch (NT) {
-        TVCS_GEMM_CASE(1)
-        TVCS_GEMM_CASE(2)
-        TVCS_GEMM_CASE(4)
-        TVCS_GEMM_CASE(8)
+        TVCS_GEMM_CASE(1, TVCS_GEMM_KF_NT1)
+        TVCS_GEMM_CASE(2, TVCS_GEMM_KF_NT2)
+        TVCS_GEMM_CASE(4, TVCS_GEMM_KF_NT4)
+        TVCS_GEMM_CASE(8, TVCS_GEMM_KF_NT8)
         default: fail(TVCS_EUNSUPPORTED, "MFMA product: padded batch must be 16, 32, 64 or 128");
     }
 #undef TVCS_GEMM_CASE
 }
 
-template <int RT, int KF>
+template <int RT>
 void gemm_mode(int mode, int NT, const void *Xhi, const void *Xlo, long long ldx, const u16 *Yhi,
                const u16 *Ylo, long long ldy, int M, int kspan, int RB, int KS, float *out,
                long long split_stride, long long ldo, const ImgState *st, int nact,
                hipStream_t s) {
     switch (mode) {
         case M_BF16:
-            gemm_dispatch<M_BF16, RT, KF>(NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out,
+            gemm_dispatch<M_BF16, RT>(NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out,
                                       split_stride, ldo, st, nact, s);
             break;
         case M_SPLIT:
-            gemm_dispatch<M_SPLIT, RT, KF>(NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out,
+            gemm_dispatch<M_SPLIT, RT>(NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out,
                                        split_stride, ldo, st, nact, s);
             break;
         default:
-            gemm_dispatch<M_FP8, RT, KF>(NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out,
+            gemm_dispatch<M_FP8, RT>(NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out,
                                      split_stride, ldo, st, nact, s);
     }
 }
 
-// RT (16-row tiles per wave) is chosen at run time by the autotuner; KF is per product
-template <int KF>
+// RT (16-row tiles per wave) is chosen at run time by the autotuner
 void gemm_any(int RT, int mode, int NT, const void *Xhi, const void *Xlo, long long ldx,
               const u16 *Yhi, const u16 *Ylo, long long ldy, int M, int kspan, int KS,
               float *out, long long split_stride, long long ldo, const ImgState *st, int nact,
               hipStream_t s) {
     const int RB = (M + 4 * RT * 16 - 1) / (4 * RT * 16);
     if (RT == 4)
-        gemm_mode<4, KF>(mode, NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out, split_stride,
+        gemm_mode<4>(mode, NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out, split_stride,
                      ldo, st, nact, s);
     else
-        gemm_mode<2, KF>(mode, NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out, split_stride,
+        gemm_mode<2>(mode, NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out, split_stride,
                      ldo, st, nact, s);
 }
 
@@ -521,8 +606,8 @@ void lowp_autotune(const LowpA &L, LowpWork &W, int Bp, const float *U, float *R
             ar = rt;
         }
     }
-    W.fwd_rt = fr;
-    W.adj_rt = ar;
+    W.fwd_rt = TVCS_GEMM_FORCE_RT ? TVCS_GEMM_FORCE_RT : fr;
+    W.adj_rt = TVCS_GEMM_FORCE_RT ? TVCS_GEMM_FORCE_RT : ar;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
 }
@@ -532,13 +617,12 @@ void lowp_apply_A(const LowpA &L, LowpWork &W, int B, const float *U, const floa
     const int mode = mode_of(L.storage);
     const int Bp = ((B + kBTile - 1) / kBTile) * kBTile;
     if (Bp > W.Bp) fail(TVCS_EINVAL, "MFMA workspace too small for the batch");
-    const size_t cnt = (size_t)Bp * L.N;
-    hipLaunchKernelGGL(k_split_vec, dim3(grid1d(cnt)), dim3(256), 0, s, U, cnt, (u16 *)W.Ubf_hi,
-                       (u16 *)W.Ubf_lo);
+    hipLaunchKernelGGL(k_split_frag, dim3(grid1d((size_t)Bp * L.N / 8)), dim3(256), 0, s, U, L.N,
+                       L.N, Bp, nullptr, (u16 *)W.Ubf_hi, (u16 *)W.Ubf_lo);
     const int KS = fwd_splits(L);
     const long long split_stride = (long long)Bp * L.mp;
     for_each_group(Bp, B, [&](int img0, int nt, int nact) {
-        gemm_any<TVCS_GEMM_KF_FWD>(W.fwd_rt, mode, nt, L.X_hi, L.X_lo, L.N,
+        gemm_any(W.fwd_rt, mode, nt, L.X_hi, L.X_lo, L.N,
                  (const u16 *)W.Ubf_hi + (size_t)img0 * L.N,
                  (const u16 *)W.Ubf_lo + (size_t)img0 * L.N, L.N, L.mp, L.N / KS, KS,
                  W.Rpart + (size_t)img0 * L.mp, split_stride, L.mp, st ? st + img0 : nullptr,
@@ -553,12 +637,12 @@ void lowp_apply_At(const LowpA &L, LowpWork &W, int B, const float *R, float *G,
     const int mode = mode_of(L.storage);
     const int Bp = ((B + kBTile - 1) / kBTile) * kBTile;
     if (Bp > W.Bp) fail(TVCS_EINVAL, "MFMA workspace too small for the batch");
-    hipLaunchKernelGGL(k_split_r, dim3((L.mp + 255) / 256, Bp), dim3(256), 0, s, R, L.m, L.mp,
-                       L.scale, (u16 *)W.Rbf_hi, (u16 *)W.Rbf_lo);
+    hipLaunchKernelGGL(k_split_frag, dim3(grid1d((size_t)Bp * L.mp / 8)), dim3(256), 0, s, R, L.m,
+                       L.mp, Bp, L.scale, (u16 *)W.Rbf_hi, (u16 *)W.Rbf_lo);
     const int KS = lowp_adj_splits(L);
     const long long split_stride = (long long)Bp * L.N;
     for_each_group(Bp, B, [&](int img0, int nt, int nact) {
-        gemm_any<TVCS_GEMM_KF_ADJ>(W.adj_rt, mode, nt, L.XT_hi, L.XT_lo, L.mp,
+        gemm_any(W.adj_rt, mode, nt, L.XT_hi, L.XT_lo, L.mp,
                  (const u16 *)W.Rbf_hi + (size_t)img0 * L.mp,
                  (const u16 *)W.Rbf_lo + (size_t)img0 * L.mp, L.mp, L.N, L.mp / KS, KS,
                  G + (size_t)img0 * L.N, split_stride, L.N, st ? st + img0 : nullptr, nact, s);
