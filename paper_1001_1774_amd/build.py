@@ -29,19 +29,23 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
-def command(out: str = LIB, defines=()):
+def command(out: str = LIB, defines=(), extra=()):
     return [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-            *[f"-D{d}" for d in defines],
+            *[f"-D{d}" for d in defines], *extra,
             "-Wall", "-Wno-unused-function", "-Wno-unused-result",
             # no packed-FP32 instructions in device code
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # MFMA accumulators in ordinary VGPRs: no AGPR copies in the product
+            # loops, and fewer registers per wave
+            "-mllvm", "-amdgpu-mfma-vgpr-form=1",
             f"-I{INCLUDE}", f"-I{CSRC}", *sources(), "-o", out]
 
 
-def build(verbose: bool = True, out: str = LIB, defines=()) -> str:
-    """Compile every source into one shared library (`defines`: extra -D tuning knobs)."""
+def build(verbose: bool = True, out: str = LIB, defines=(), extra=()) -> str:
+    """Compile every source into one shared library (`defines`: extra -D tuning knobs,
+    `extra`: extra compiler flags)."""
     tmp = out + ".tmp"
-    cmd = command(tmp, defines)
+    cmd = command(tmp, defines, extra)
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True, cwd=ROOT)

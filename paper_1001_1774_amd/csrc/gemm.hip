@@ -55,6 +55,9 @@
 #ifndef TVCS_GEMM_KF_NT1
 #define TVCS_GEMM_KF_NT1 4     // ... 16-image groups (at least 2)
 #endif
+#ifndef TVCS_GEMM_YPRELOAD
+#define TVCS_GEMM_YPRELOAD 0   // 1: read all Y fragments of a step from LDS before its MFMAs
+#endif
 #ifndef TVCS_GEMM_FORCE_RT
 #define TVCS_GEMM_FORCE_RT 0   // 2 or 4: skip the autotuner's choice of row tiles per wave
 #endif
@@ -213,6 +216,17 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
             *reinterpret_cast<u32x4 *>(&ys[buf][wave + 4 * q][lane * 8]) = yr[q];
     };
     auto compute = [&](const XRegs<MODE, RT, KF> &x, int buf) {
+#if TVCS_GEMM_YPRELOAD
+        // all Y fragments of the step first, so LDS latency overlaps the MFMAs
+        bf16x8 yf[2][KF][NT];
+#pragma unroll
+        for (int s = 0; s < KF; ++s)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                yf[0][s][nt] = *reinterpret_cast<const bf16x8 *>(&ys[buf][nt * KF + s][lane * 8]);
+                yf[1][s][nt] = *reinterpret_cast<const bf16x8 *>(&ys[buf][NB + nt * KF + s][lane * 8]);
+            }
+#endif
 #pragma unroll
         for (int s = 0; s < KF; ++s) {
             bf16x8 xc[RT];
@@ -227,8 +241,12 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
             // independent MFMAs separate two that share an accumulator
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
+#if TVCS_GEMM_YPRELOAD
+                const bf16x8 yh = yf[0][s][nt], yl = yf[1][s][nt];
+#else
                 const bf16x8 yh = *reinterpret_cast<const bf16x8 *>(&ys[buf][nt * KF + s][lane * 8]);
                 const bf16x8 yl = *reinterpret_cast<const bf16x8 *>(&ys[buf][NB + nt * KF + s][lane * 8]);
+#endif
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt)
                     acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[rt], yh, acc[rt][nt], 0, 0, 0);
