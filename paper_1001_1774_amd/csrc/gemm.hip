@@ -55,6 +55,15 @@
 #ifndef TVCS_GEMM_KF_NT1
 #define TVCS_GEMM_KF_NT1 4     // ... 16-image groups (at least 2)
 #endif
+#ifndef TVCS_Y_KMAJOR
+#define TVCS_Y_KMAJOR 1        // batch operand blocks k-tile major, hi/lo interleaved
+#endif
+#ifndef TVCS_X_GROUP
+#define TVCS_X_GROUP 16        // row tiles per group in the fragment order of A and A^T
+#endif
+#ifndef TVCS_GEMM_DEPTH
+#define TVCS_GEMM_DEPTH 1      // steps of X prefetched ahead (1 or 2)
+#endif
 #ifndef TVCS_GEMM_YPRELOAD
 #define TVCS_GEMM_YPRELOAD 0   // 1: read all Y fragments of a step from LDS before its MFMAs
 #endif
@@ -79,6 +88,15 @@ typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
+// Row tiles per group of the streamed matrix's fragment order: the blocks of a
+// group's kXGroup row tiles for one k tile are adjacent, so one workgroup step
+// (up to 16 row tiles x KF k tiles) reads one contiguous span of HBM.
+constexpr int kXGroup = TVCS_X_GROUP;
+// Batch operand order: k-tile major with hi and lo blocks interleaved (one step's
+// Y blocks of a workgroup are then adjacent), or image-tile major in two arrays.
+constexpr bool kYKMajor = TVCS_Y_KMAJOR != 0;
+static_assert(kMPad % (16 * kXGroup) == 0 && 16 * kXGroup <= 256,
+              "row counts (m_p, and n * n for n >= 16) must be whole groups");
 constexpr int KMAX = 128;        // longest reduction step; every K slice is a multiple of it
 constexpr int kRowsRT4 = 4 * 4 * 16;   // rows per workgroup with 4 row tiles per wave
 
@@ -143,7 +161,7 @@ __device__ inline void load_x(XRegs<MODE, RT, KF> &x, const void *Xhi, const voi
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int s = 0; s < KF; ++s) {
-            const long long o = xoff[rt] + (long long)(kt0 + s) * 512;
+            const long long o = xoff[rt] + (long long)(kt0 + s) * (kXGroup * 512);
             if constexpr (MODE == M_FP8) {
                 x.q[rt][s] = __builtin_nontemporal_load(
                     reinterpret_cast<const u32x2 *>((const u8 *)Xhi + o));
@@ -165,7 +183,8 @@ __device__ inline void load_x(XRegs<MODE, RT, KF> &x, const void *Xhi, const voi
 template <int MODE, int RT, int NT, int KF>
 __global__ __launch_bounds__(kThreads) void k_gemm(
     const void *__restrict__ Xhi, const void *__restrict__ Xlo, long long xkt,
-    const u16 *__restrict__ Yhi, const u16 *__restrict__ Ylo, long long ykt, int M, int kspan,
+    const u16 *__restrict__ Yhi, const u16 *__restrict__ Ylo, long long yimg, long long ytile,
+    int M, int kspan,
     int RB, int KS, float *__restrict__ out, long long split_stride, long long ldo,
     const ImgState *__restrict__ st, int nact) {
     if (!any_active(st, nact)) return;
@@ -195,20 +214,24 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
     long long xoff[RT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
-        xoff[rt] = (long long)min((row_wave >> 4) + rt, (M >> 4) - 1) * xkt * 512 + lane * 8;
+    {
+        const int tile = min((row_wave >> 4) + rt, (M >> 4) - 1);
+        xoff[rt] = (((long long)(tile / kXGroup) * xkt) * kXGroup + tile % kXGroup) * 512 + lane * 8;
+    }
 
     // this wave's Y blocks: j = wave + 4 q -> part j / NB, image tile (j % NB) / KF, k tile j % KF
     const u16 *ysrc[YPW];
 #pragma unroll
     for (int q = 0; q < YPW; ++q) {
         const int j = wave + 4 * q, part = j / NB, r = j % NB;
-        ysrc[q] = (part ? Ylo : Yhi) + ((long long)(r / KF) * ykt + kt_begin + r % KF) * 512 + lane * 8;
+        ysrc[q] = (part ? Ylo : Yhi) + (long long)(r / KF) * yimg +
+                  (long long)(kt_begin + r % KF) * ytile + lane * 8;
     }
     u32x4 yr[YPW];
     auto load_y = [&](int t) {
 #pragma unroll
         for (int q = 0; q < YPW; ++q)
-            yr[q] = *reinterpret_cast<const u32x4 *>(ysrc[q] + (long long)t * KF * 512);
+            yr[q] = *reinterpret_cast<const u32x4 *>(ysrc[q] + (long long)t * KF * ytile);
     };
     auto store_y = [&](int buf) {
 #pragma unroll
@@ -269,29 +292,72 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
     // past the last step re-read the last step (in bounds, results unused), which
     // keeps the body branch-free so that each wait covers only the data it needs;
     // scheduling barriers keep the compiler from sinking the prefetches.
-    XRegs<MODE, RT, KF> xa, xb;
     const int last = steps - 1;
-    load_y(0);
-    store_y(0);
-    load_x(xa, Xhi, Xlo, xoff, kt_begin);
-    load_y(min(1, last));
-    __syncthreads();
-    int t = 0;
-    for (; t + 1 < steps; t += 2) {
-        load_x(xb, Xhi, Xlo, xoff, kt_begin + (t + 1) * KF);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(xa, 0);
-        store_y(1);
-        load_y(min(t + 2, last));
-        __syncthreads();
-        load_x(xa, Xhi, Xlo, xoff, kt_begin + min(t + 2, last) * KF);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(xb, 1);
+    if constexpr (TVCS_GEMM_DEPTH == 1) {
+        XRegs<MODE, RT, KF> xa, xb;
+        load_y(0);
         store_y(0);
-        load_y(min(t + 3, last));
+        load_x(xa, Xhi, Xlo, xoff, kt_begin);
+        load_y(min(1, last));
         __syncthreads();
+        int t = 0;
+        for (; t + 1 < steps; t += 2) {
+            load_x(xb, Xhi, Xlo, xoff, kt_begin + (t + 1) * KF);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(xa, 0);
+            store_y(1);
+            load_y(min(t + 2, last));
+            __syncthreads();
+            load_x(xa, Xhi, Xlo, xoff, kt_begin + min(t + 2, last) * KF);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(xb, 1);
+            store_y(0);
+            load_y(min(t + 3, last));
+            __syncthreads();
+        }
+        if (t < steps) compute(xa, 0);
+    } else {
+        // prefetch distance 2: three X register sets, loop unrolled by three;
+        // invariant at the top of the loop: x0 = X(t), x1 = X(t + 1), LDS buffer
+        // t & 1 = Y(t), yr = Y(t + 1) (indices clamped to the last step)
+        XRegs<MODE, RT, KF> x0, x1, x2;
+        load_y(0);
+        store_y(0);
+        load_x(x0, Xhi, Xlo, xoff, kt_begin);
+        load_x(x1, Xhi, Xlo, xoff, kt_begin + min(1, last) * KF);
+        load_y(min(1, last));
+        __syncthreads();
+        int t = 0;
+        for (; t + 3 <= steps; t += 3) {
+            const int p = t & 1;
+            load_x(x2, Xhi, Xlo, xoff, kt_begin + min(t + 2, last) * KF);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(x0, p);
+            store_y(p ^ 1);
+            load_y(min(t + 2, last));
+            __syncthreads();
+            load_x(x0, Xhi, Xlo, xoff, kt_begin + min(t + 3, last) * KF);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(x1, p ^ 1);
+            store_y(p);
+            load_y(min(t + 3, last));
+            __syncthreads();
+            load_x(x1, Xhi, Xlo, xoff, kt_begin + min(t + 4, last) * KF);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(x2, p);
+            store_y(p ^ 1);
+            load_y(min(t + 4, last));
+            __syncthreads();
+        }
+        if (t < steps) {   // one or two steps left
+            compute(x0, t & 1);
+            if (t + 1 < steps) {
+                store_y((t & 1) ^ 1);
+                __syncthreads();
+                compute(x1, (t & 1) ^ 1);
+            }
+        }
     }
-    if (t < steps) compute(xa, 0);
     // lane holds rows 4*(lane/16) .. +3 of its 16-row tile, image lane % 16 of its tile
     float *o = out + ks * split_stride;
     const int lr = lane & 15;
@@ -350,7 +416,10 @@ __global__ void k_frag(const float *__restrict__ A, int m, int N, int mp,
          c += (size_t)gridDim.x * blockDim.x) {
         const size_t f = c >> 6;
         const int lane = (int)(c & 63);
-        const size_t r = (f / ktiles) * 16 + (lane & 15), k0 = (f % ktiles) * 32 + 8 * (lane >> 4);
+        // block f = ((t / G) * ktiles + u) * G + t % G for row tile t, k tile u
+        const size_t g = f / (ktiles * kXGroup), rem = f % (ktiles * kXGroup);
+        const size_t t = g * kXGroup + rem % kXGroup, u = rem / kXGroup;
+        const size_t r = t * 16 + (lane & 15), k0 = u * 32 + 8 * (lane >> 4);
         float v[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -377,18 +446,20 @@ __global__ void k_frag(const float *__restrict__ A, int m, int N, int mp,
 // Batch operand Y of a product, in fragment order: V (Bp rows of length kv, FP32)
 // -> bf16 hi and lo = bf16(v - hi) over K >= kv columns (columns >= kv are zero),
 // each column optionally multiplied by scale[k] first (FP64 product, FP32 result).
-// One thread per lane-chunk of 8 elements: block f = (image tile, k tile), lane l
-// holds image 16 t + l % 16, columns 32 u + 8 (l / 16) .. +7.
+// Block (image tile t, k tile u) of part p sits at (p ? lo : hi) + t * yimg + u * ytile;
+// lane l of a block holds image 16 t + l % 16, columns 32 u + 8 (l / 16) .. +7.
+// One thread per lane-chunk of 8 elements, blocks visited in storage order.
 __global__ void k_split_frag(const float *__restrict__ V, int kv, int K, int Bp,
                              const float *__restrict__ scale, u16 *__restrict__ hi,
-                             u16 *__restrict__ lo) {
-    const size_t chunks = (size_t)Bp * K / 8, ktiles = (size_t)K / 32;
+                             u16 *__restrict__ lo, long long yimg, long long ytile) {
+    const size_t chunks = (size_t)Bp * K / 8, ktiles = (size_t)K / 32, itiles = (size_t)Bp / 16;
     for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < chunks;
          c += (size_t)gridDim.x * blockDim.x) {
         const size_t f = c >> 6;
         const int l = (int)(c & 63);
-        const size_t b = (f / ktiles) * 16 + (l & 15);
-        const int k0 = (int)(f % ktiles) * 32 + 8 * (l >> 4);
+        const size_t it = kYKMajor ? f % itiles : f / ktiles, u = kYKMajor ? f / itiles : f % ktiles;
+        const size_t b = it * 16 + (l & 15);
+        const int k0 = (int)u * 32 + 8 * (l >> 4);
         u16 h[8], w[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -401,8 +472,9 @@ __global__ void k_split_frag(const float *__restrict__ V, int kv, int K, int Bp,
             h[j] = bf16_rne(x);
             w[j] = bf16_rne(x - bf16_f32(h[j]));   // exact in FP32
         }
-        reinterpret_cast<uint4 *>(hi)[c] = *reinterpret_cast<const uint4 *>(h);
-        reinterpret_cast<uint4 *>(lo)[c] = *reinterpret_cast<const uint4 *>(w);
+        const size_t o = it * yimg + u * ytile + l * 8;
+        *reinterpret_cast<uint4 *>(hi + o) = *reinterpret_cast<const uint4 *>(h);
+        *reinterpret_cast<uint4 *>(lo + o) = *reinterpret_cast<const uint4 *>(w);
     }
 }
 
@@ -422,7 +494,7 @@ __global__ void k_reduce_r(const float *__restrict__ P, int KS, long long split_
 
 template <int MODE, int RT>
 void gemm_dispatch(int NT, const void *Xhi, const void *Xlo, long long ldx, const u16 *Yhi,
-                   const u16 *Ylo, long long ldy, int M, int kspan, int RB, int KS, float *out,
+                   const u16 *Ylo, long long yimg, long long ytile, int M, int kspan, int RB, int KS, float *out,
                    long long split_stride, long long ldo, const ImgState *st, int nact,
                    hipStream_t s) {
     const int total = RB * KS;
@@ -430,8 +502,8 @@ void gemm_dispatch(int NT, const void *Xhi, const void *Xlo, long long ldx, cons
 #define TVCS_GEMM_CASE(NTV, KFV)                                                               \
     case NTV:                                                                                  \
         hipLaunchKernelGGL((k_gemm<MODE, RT, NTV, KFV>), grid, dim3(kThreads), 0, s, Xhi, Xlo,  \
-                           ldx >> 5, Yhi, Ylo, ldy >> 5, M, kspan, RB, KS, out, split_stride,  \
-                           ldo, st, nact);                                                     \
+                           ldx >> 5, Yhi, Ylo, yimg, ytile, M, kspan, RB, KS, out,            \
+                           split_stride, ldo, st, nact);                                       \
         break;
     switch (NT) {
         TVCS_GEMM_CASE(1, TVCS_GEMM_KF_NT1)
@@ -445,35 +517,36 @@ void gemm_dispatch(int NT, const void *Xhi, const void *Xlo, long long ldx, cons
 
 template <int RT>
 void gemm_mode(int mode, int NT, const void *Xhi, const void *Xlo, long long ldx, const u16 *Yhi,
-               const u16 *Ylo, long long ldy, int M, int kspan, int RB, int KS, float *out,
+               const u16 *Ylo, long long yimg, long long ytile, int M, int kspan, int RB, int KS, float *out,
                long long split_stride, long long ldo, const ImgState *st, int nact,
                hipStream_t s) {
     switch (mode) {
         case M_BF16:
-            gemm_dispatch<M_BF16, RT>(NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out,
+            gemm_dispatch<M_BF16, RT>(NT, Xhi, Xlo, ldx, Yhi, Ylo, yimg, ytile, M, kspan, RB, KS, out,
                                       split_stride, ldo, st, nact, s);
             break;
         case M_SPLIT:
-            gemm_dispatch<M_SPLIT, RT>(NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out,
+            gemm_dispatch<M_SPLIT, RT>(NT, Xhi, Xlo, ldx, Yhi, Ylo, yimg, ytile, M, kspan, RB, KS, out,
                                        split_stride, ldo, st, nact, s);
             break;
         default:
-            gemm_dispatch<M_FP8, RT>(NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out,
+            gemm_dispatch<M_FP8, RT>(NT, Xhi, Xlo, ldx, Yhi, Ylo, yimg, ytile, M, kspan, RB, KS, out,
                                      split_stride, ldo, st, nact, s);
     }
 }
 
 // RT (16-row tiles per wave) is chosen at run time by the autotuner
 void gemm_any(int RT, int mode, int NT, const void *Xhi, const void *Xlo, long long ldx,
-              const u16 *Yhi, const u16 *Ylo, long long ldy, int M, int kspan, int KS,
+              const u16 *Yhi, const u16 *Ylo, long long yimg, long long ytile, int M, int kspan,
+              int KS,
               float *out, long long split_stride, long long ldo, const ImgState *st, int nact,
               hipStream_t s) {
     const int RB = (M + 4 * RT * 16 - 1) / (4 * RT * 16);
     if (RT == 4)
-        gemm_mode<4>(mode, NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out, split_stride,
+        gemm_mode<4>(mode, NT, Xhi, Xlo, ldx, Yhi, Ylo, yimg, ytile, M, kspan, RB, KS, out, split_stride,
                      ldo, st, nact, s);
     else
-        gemm_mode<2>(mode, NT, Xhi, Xlo, ldx, Yhi, Ylo, ldy, M, kspan, RB, KS, out, split_stride,
+        gemm_mode<2>(mode, NT, Xhi, Xlo, ldx, Yhi, Ylo, yimg, ytile, M, kspan, RB, KS, out, split_stride,
                      ldo, st, nact, s);
 }
 
@@ -489,6 +562,18 @@ int fwd_splits(const LowpA &L) {
            L.N / (KS * 2) >= 4 * KMAX)
         KS *= 2;
     return KS;
+}
+
+// Element strides of the batch operand (K columns, Bp images) between image tiles
+// and between k tiles of one part.
+void y_strides(long long K, int Bp, long long &yimg, long long &ytile) {
+    if (kYKMajor) {
+        yimg = 1024;
+        ytile = (long long)(Bp / 16) * 1024;
+    } else {
+        yimg = (K / 32) * 512;
+        ytile = 512;
+    }
 }
 
 // Cover the padded batch with image groups of 16 * nt, nt in {8, 4, 2, 1}; groups
@@ -580,10 +665,17 @@ void lowp_work_bind(LowpWork &W, const LowpA &L, int Bp, void *base) {
         return r;
     };
     const size_t u = (size_t)Bp * L.N * sizeof(u16), r = (size_t)Bp * L.mp * sizeof(u16);
-    W.Ubf_hi = take(u);
-    W.Ubf_lo = take(u);
-    W.Rbf_hi = take(r);
-    W.Rbf_lo = take(r);
+    if (kYKMajor) {   // one array per operand, hi and lo blocks interleaved
+        W.Ubf_hi = take(2 * u);
+        W.Ubf_lo = (u16 *)W.Ubf_hi + 512;
+        W.Rbf_hi = take(2 * r);
+        W.Rbf_lo = (u16 *)W.Rbf_hi + 512;
+    } else {
+        W.Ubf_hi = take(u);
+        W.Ubf_lo = take(u);
+        W.Rbf_hi = take(r);
+        W.Rbf_lo = take(r);
+    }
     W.Rpart = static_cast<float *>(take((size_t)fwd_splits(L) * Bp * L.mp * sizeof(float)));
     W.Bp = Bp;
     W.fwd_rt = 4;
@@ -635,14 +727,16 @@ void lowp_apply_A(const LowpA &L, LowpWork &W, int B, const float *U, const floa
     const int mode = mode_of(L.storage);
     const int Bp = ((B + kBTile - 1) / kBTile) * kBTile;
     if (Bp > W.Bp) fail(TVCS_EINVAL, "MFMA workspace too small for the batch");
+    long long yimg, ytile;
+    y_strides(L.N, Bp, yimg, ytile);
     hipLaunchKernelGGL(k_split_frag, dim3(grid1d((size_t)Bp * L.N / 8)), dim3(256), 0, s, U, L.N,
-                       L.N, Bp, nullptr, (u16 *)W.Ubf_hi, (u16 *)W.Ubf_lo);
+                       L.N, Bp, nullptr, (u16 *)W.Ubf_hi, (u16 *)W.Ubf_lo, yimg, ytile);
     const int KS = fwd_splits(L);
     const long long split_stride = (long long)Bp * L.mp;
     for_each_group(Bp, B, [&](int img0, int nt, int nact) {
         gemm_any(W.fwd_rt, mode, nt, L.X_hi, L.X_lo, L.N,
-                 (const u16 *)W.Ubf_hi + (size_t)img0 * L.N,
-                 (const u16 *)W.Ubf_lo + (size_t)img0 * L.N, L.N, L.mp, L.N / KS, KS,
+                 (const u16 *)W.Ubf_hi + (img0 / 16) * yimg,
+                 (const u16 *)W.Ubf_lo + (img0 / 16) * yimg, yimg, ytile, L.mp, L.N / KS, KS,
                  W.Rpart + (size_t)img0 * L.mp, split_stride, L.mp, st ? st + img0 : nullptr,
                  nact, s);
     });
@@ -655,14 +749,16 @@ void lowp_apply_At(const LowpA &L, LowpWork &W, int B, const float *R, float *G,
     const int mode = mode_of(L.storage);
     const int Bp = ((B + kBTile - 1) / kBTile) * kBTile;
     if (Bp > W.Bp) fail(TVCS_EINVAL, "MFMA workspace too small for the batch");
+    long long yimg, ytile;
+    y_strides(L.mp, Bp, yimg, ytile);
     hipLaunchKernelGGL(k_split_frag, dim3(grid1d((size_t)Bp * L.mp / 8)), dim3(256), 0, s, R, L.m,
-                       L.mp, Bp, L.scale, (u16 *)W.Rbf_hi, (u16 *)W.Rbf_lo);
+                       L.mp, Bp, L.scale, (u16 *)W.Rbf_hi, (u16 *)W.Rbf_lo, yimg, ytile);
     const int KS = lowp_adj_splits(L);
     const long long split_stride = (long long)Bp * L.N;
     for_each_group(Bp, B, [&](int img0, int nt, int nact) {
         gemm_any(W.adj_rt, mode, nt, L.XT_hi, L.XT_lo, L.mp,
-                 (const u16 *)W.Rbf_hi + (size_t)img0 * L.mp,
-                 (const u16 *)W.Rbf_lo + (size_t)img0 * L.mp, L.mp, L.N, L.mp / KS, KS,
+                 (const u16 *)W.Rbf_hi + (img0 / 16) * yimg,
+                 (const u16 *)W.Rbf_lo + (img0 / 16) * yimg, yimg, ytile, L.N, L.mp / KS, KS,
                  G + (size_t)img0 * L.N, split_stride, L.N, st ? st + img0 : nullptr, nact, s);
     });
 }
