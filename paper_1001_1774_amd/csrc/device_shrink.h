@@ -26,42 +26,39 @@ __device__ inline D2 shrink2(D2 z, double inv_beta) {
 
 __device__ inline int log2i(int n) { return __ffs(n) - 1; }
 
-// Right-hand side at pixel p of image b (IADM also writes q^k at p into Qnew).
-template <bool IADM>
-__device__ inline double rhs_at(const ShrinkArgs &a, int b, int p) {
+// Everything the right-hand side at one pixel reads from memory.  Loading several
+// pixels' inputs before computing any of them keeps many loads in flight (the
+// pass is latency-bound); the stores of q^k come after all loads of a round.
+struct PixIn {
+    float u0, uE, uS, uW, uSW, uN, uNE;   // u at (r,c), (r,c+1), (r+1,c), (r,c-1), (r+1,c-1), (r-1,c), (r-1,c+1)
+    D2 o0, oW, oN;                        // q^{k-1} at (r,c), (r,c-1), (r-1,c) (IADM)
+    double gk;                            // g_k = (A^T (A u - f)) at (r,c)
+};
+
+// PL: partial sums loaded in flight.  For nchunk <= PL every PL gives the same
+// bits (the pairwise tree over the first nchunk slots, the rest exact zeros).
+template <bool IADM, int PL = TVCS_PARTIAL_LOADS>
+__device__ inline PixIn load_pix(const ShrinkArgs &a, int b, int p) {
     const int n = a.n, N = n * n, mask = n - 1, ln = log2i(n);
     const int r = p >> ln, c = p & mask;
     const float *u = a.U + (size_t)b * N;
-    auto U = [&](int rr, int cc) -> double { return (double)u[((rr & mask) << ln) | (cc & mask)]; };
-    const double u0 = U(r, c), uE = U(r, c + 1), uS = U(r + 1, c), uW = U(r, c - 1),
-                 uSW = U(r + 1, c - 1), uN = U(r - 1, c), uNE = U(r - 1, c + 1);
-    const D2 d0 = {uE - u0, uS - u0};      // D u at (r, c)
-    const D2 dW = {u0 - uW, uSW - uW};     // D u at (r, c-1)
-    const D2 dN = {uNE - uN, u0 - uN};     // D u at (r-1, c)
-    const double ib = 1.0 / a.beta;
-    D2 q0, qW, qN;
+    auto U = [&](int rr, int cc) { return u[((rr & mask) << ln) | (cc & mask)]; };
+    PixIn in;
+    in.u0 = U(r, c);
+    in.uE = U(r, c + 1);
+    in.uS = U(r + 1, c);
+    in.uW = U(r, c - 1);
+    in.uSW = U(r + 1, c - 1);
+    in.uN = U(r - 1, c);
+    in.uNE = U(r - 1, c + 1);
     if (IADM) {
         const double *Q1 = a.Qold + (size_t)b * 2 * N, *Q2 = Q1 + N;
         const int pW = (r << ln) | ((c - 1) & mask), pN = (((r - 1) & mask) << ln) | c;
-        const D2 o0 = {Q1[p], Q2[p]}, oW = {Q1[pW], Q2[pW]}, oN = {Q1[pN], Q2[pN]};
-        auto step = [&](D2 d, D2 o) {
-            const D2 s = shrink2({2.0 * d.x - o.x, 2.0 * d.y - o.y}, ib);
-            return D2{s.x - d.x + o.x, s.y - d.y + o.y};
-        };
-        q0 = step(d0, o0);
-        qW = step(dW, oW);
-        qN = step(dN, oN);
-        double *W1 = a.Qnew + (size_t)b * 2 * N;
-        W1[p] = q0.x;
-        W1[N + p] = q0.y;
-    } else {
-        q0 = shrink2(d0, ib);
-        qW = shrink2(dW, ib);
-        qN = shrink2(dN, ib);
+        in.o0 = {Q1[p], Q2[p]};
+        in.oW = {Q1[pW], Q2[pW]};
+        in.oN = {Q1[pN], Q2[pN]};
     }
-    // g_k at this pixel: fixed-order sum of the A^T r partials, TVCS_PARTIAL_LOADS
-    // independent loads in flight (the sum is latency-bound, not bandwidth-bound)
-    constexpr int PL = TVCS_PARTIAL_LOADS;
+    // g_k: fixed-order sum of the A^T r partials, PL loads in flight
     const float *g = a.G + (size_t)(b / a.gnv) * a.g_group_stride + (size_t)(b % a.gnv) * N + p;
     double gs[PL];
 #pragma unroll
@@ -76,10 +73,40 @@ __device__ inline double rhs_at(const ShrinkArgs &a, int b, int p) {
     for (int w = PL / 2; w > 0; w >>= 1)
 #pragma unroll
         for (int j = 0; j < w; ++j) gs[j] += gs[j + w];
-    const double gk = gs[0];
+    in.gk = gs[0];
+    return in;
+}
+
+// Right-hand side at pixel p of image b from its inputs (IADM also writes q^k at p
+// into Qnew).
+template <bool IADM>
+__device__ inline double finish_pix(const ShrinkArgs &a, int b, int p, const PixIn &in) {
+    const double u0 = in.u0;
+    const D2 d0 = {in.uE - u0, in.uS - u0};                              // D u at (r, c)
+    const D2 dW = {u0 - in.uW, (double)in.uSW - in.uW};                  // D u at (r, c-1)
+    const D2 dN = {(double)in.uNE - in.uN, u0 - in.uN};                  // D u at (r-1, c)
+    const double ib = 1.0 / a.beta;
+    D2 q0, qW, qN;
+    if (IADM) {
+        auto step = [&](D2 d, D2 o) {
+            const D2 s = shrink2({2.0 * d.x - o.x, 2.0 * d.y - o.y}, ib);
+            return D2{s.x - d.x + o.x, s.y - d.y + o.y};
+        };
+        q0 = step(d0, in.o0);
+        qW = step(dW, in.oW);
+        qN = step(dN, in.oN);
+        const int N = a.n * a.n;
+        double *W1 = a.Qnew + (size_t)b * 2 * N;
+        W1[p] = q0.x;
+        W1[N + p] = q0.y;
+    } else {
+        q0 = shrink2(d0, ib);
+        qW = shrink2(dW, ib);
+        qN = shrink2(dN, ib);
+    }
     // D^T (q - D u) at (r, c): needs (q - D u) here, at (r, c-1) and at (r-1, c)
     const double dtq = ((qW.x - dW.x) - (q0.x - d0.x)) + ((qN.y - dN.y) - (q0.y - d0.y));
-    return dtq - a.ctau * gk;
+    return dtq - a.ctau * in.gk;
 }
 
 }  // namespace shrinkdev

@@ -66,8 +66,9 @@ __device__ inline void rows_fwd_tail(int n, int rpb, float2 *X, float2 *Y, const
 }
 
 // Fused shrinkage + forward row FFT: the right-hand side of the block's rows is
-// computed (shrinkdev::rhs_at) straight into the packed FFT input in LDS.
-template <bool IADM>
+// computed straight into the packed FFT input in LDS, PX pixels per thread and
+// round with all their loads issued before any of them is computed.
+template <bool IADM, int PX>
 __global__ __launch_bounds__(kThreads) void k_shrink_rows(ShrinkArgs a, int rpb,
                                                           float2 *__restrict__ S,
                                                           const float2 *__restrict__ tw) {
@@ -80,10 +81,24 @@ __global__ __launch_bounds__(kThreads) void k_shrink_rows(ShrinkArgs a, int rpb,
     load_twiddles(tl, tw);
     const int row0 = blockIdx.x * rpb;
     float *Xf = reinterpret_cast<float *>(X);
-    for (int e = threadIdx.x; e < rpb * n; e += kThreads) {
-        const int rr = e >> ln, c = e & (n - 1);
-        const float v = (float)shrinkdev::rhs_at<IADM>(a, b, ((row0 + rr) << ln) | c);
-        Xf[2 * ((rr >> 1) * n + c) + (rr & 1)] = v;   // even row: real part, odd row: imaginary
+    const int total = rpb * n;
+    for (int e0 = threadIdx.x; e0 < total; e0 += kThreads * PX) {
+        shrinkdev::PixIn in[PX];
+#pragma unroll
+        for (int j = 0; j < PX; ++j) {
+            const int e = e0 + j * kThreads;
+            if (e < total)
+                in[j] = shrinkdev::load_pix<IADM, (PX > 1 ? 4 : TVCS_PARTIAL_LOADS)>(
+                    a, b, (row0 << ln) + e);
+        }
+#pragma unroll
+        for (int j = 0; j < PX; ++j) {
+            const int e = e0 + j * kThreads;
+            if (e >= total) break;
+            const int rr = e >> ln, c = e & (n - 1);
+            const float v = (float)shrinkdev::finish_pix<IADM>(a, b, (row0 << ln) + e, in[j]);
+            Xf[2 * ((rr >> 1) * n + c) + (rr & 1)] = v;   // even row: real part, odd row: imaginary
+        }
     }
     __syncthreads();
     rows_fwd_tail(n, rpb, X, Y, tl, S + (size_t)b * h * n + row0);
@@ -256,6 +271,9 @@ __global__ __launch_bounds__(64) void k_stop_rule(ImgState *__restrict__ st,
 // cpb * n <= 2048 complex per buffer).  The row blocking fixes the order in which
 // the stop-rule norms are summed, so it depends on n only: an image's iterates and
 // stop decisions are then the same whatever batch it is solved in.
+#ifndef TVCS_SHRINK_PX
+#define TVCS_SHRINK_PX 4       // pixels per thread and round of the batched shrink pass
+#endif
 #ifndef TVCS_FFT_ROW_DIV
 #define TVCS_FFT_ROW_DIV 64    // rows per workgroup = n / TVCS_FFT_ROW_DIV (at least 2)
 #endif
@@ -305,12 +323,20 @@ void launch_shrink_rows(const ShrinkArgs &a, bool iadm, float2 *S, const float2 
                         hipStream_t s) {
     const int n = a.n, rpb = rows_per_block(n, a.B);
     const size_t lds = sizeof(float2) * (kMaxN + 2 * ((rpb / 2) * n + rpb));
-    if (iadm)
-        hipLaunchKernelGGL(k_shrink_rows<true>, dim3(n / rpb, a.B), dim3(kThreads), lds, s, a,
-                           rpb, S, tw);
-    else
-        hipLaunchKernelGGL(k_shrink_rows<false>, dim3(n / rpb, a.B), dim3(kThreads), lds, s, a,
-                           rpb, S, tw);
+    // several pixels per round where the partial sums of g are few (their loads
+    // would otherwise cost registers) and each thread has several pixels
+    const bool multi = a.nchunk <= 4 && rpb * n >= 2 * kThreads;
+#define TVCS_SHRINK_LAUNCH(IADMV, PXV)                                                         \
+    hipLaunchKernelGGL((k_shrink_rows<IADMV, PXV>), dim3(n / rpb, a.B), dim3(kThreads), lds, s, \
+                       a, rpb, S, tw)
+    if (iadm) {
+        if (multi) TVCS_SHRINK_LAUNCH(true, TVCS_SHRINK_PX);
+        else TVCS_SHRINK_LAUNCH(true, 1);
+    } else {
+        if (multi) TVCS_SHRINK_LAUNCH(false, TVCS_SHRINK_PX);
+        else TVCS_SHRINK_LAUNCH(false, 1);
+    }
+#undef TVCS_SHRINK_LAUNCH
 }
 
 }  // namespace tvcs

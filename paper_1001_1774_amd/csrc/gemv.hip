@@ -33,6 +33,12 @@
 #ifndef TVCS_COLS_TARGET_WG
 #define TVCS_COLS_TARGET_WG 1024   // workgroups the A^T r product aims for
 #endif
+#ifndef TVCS_GEMV_NT
+#define TVCS_GEMV_NT 0        // 1: nontemporal (streaming) loads of A; 0: ordinary loads
+#endif
+#ifndef TVCS_COLS_SLOTS
+#define TVCS_COLS_SLOTS 0     // >0: row-chunk slots per column block of A^T r (0: one per chunk)
+#endif
 #ifndef TVCS_COLS_REVERSE
 #define TVCS_COLS_REVERSE 0   // 1: sweep row chunks last-to-first (after A u read first-to-last)
 #endif
@@ -44,6 +50,11 @@ constexpr int kThreads = 256;
 
 // native 4-wide vector (the nontemporal load builtin needs a clang vector type)
 typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ inline f4 load_a(const f4 *p) {
+    if (TVCS_GEMV_NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
 
 __device__ inline bool any_active(const ImgState *st, int nact) {
     if (st == nullptr) return true;
@@ -83,7 +94,7 @@ __global__ __launch_bounds__(kThreads) void k_gemv_rows(
     for (int j = threadIdx.x; j < N4; j += kThreads) {
         f4 a[ROWS];
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) a[r] = __builtin_nontemporal_load(rowp[r] + j);
+        for (int r = 0; r < ROWS; ++r) a[r] = load_a(rowp[r] + j);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const f4 x = reinterpret_cast<const f4 *>(U + (size_t)v * ldu)[j];
@@ -118,49 +129,56 @@ __global__ __launch_bounds__(kThreads) void k_gemv_rows(
     }
 }
 
+// Row chunks are visited by gridDim.y slots: slot s takes chunks s, s + slots, ...
+// (counted from the last chunk when TVCS_COLS_REVERSE), accumulating all of them
+// before it writes its partial sums, so at any time the workgroups sweep one band
+// of rows.  The chunking and the slots depend on (m, N) only.
 template <int NV>
 __global__ __launch_bounds__(kThreads) void k_gemv_cols(
     const float *__restrict__ A, int m, int N, const float *__restrict__ Rv, int ldr,
-    float *__restrict__ P, long long chunk_stride, int rows_per_chunk,
+    float *__restrict__ P, long long chunk_stride, int rows_per_chunk, int nrowchunk,
     const ImgState *__restrict__ st, int nact) {
     constexpr int VEC = TVCS_COLS_VEC;
     if (!any_active(st, nact)) return;
     extern __shared__ double rs[];           // rows_per_chunk x NV coefficients
-    const int chunk = TVCS_COLS_REVERSE ? (int)(gridDim.y - 1 - blockIdx.y) : (int)blockIdx.y;
-    const int i0 = chunk * rows_per_chunk;
-    const int rows = min(rows_per_chunk, m - i0);
-    for (int t = threadIdx.x; t < rows * NV; t += kThreads) {
-        const int i = t / NV, v = t % NV;
-        rs[t] = Rv[(size_t)v * ldr + i0 + i];
-    }
-    __syncthreads();
     const int N4 = N >> 2;
     // the workgroup covers VEC * 256 consecutive float4 columns; thread t owns
     // columns t, t + 256, ... so each wave still reads contiguous 1 KiB pieces
     const int jb = blockIdx.x * kThreads * VEC + threadIdx.x;
-    const f4 *col = reinterpret_cast<const f4 *>(A + (size_t)i0 * N);
     double acc[VEC][NV][4];
 #pragma unroll
     for (int c = 0; c < VEC; ++c)
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[c][v][0] = acc[c][v][1] = acc[c][v][2] = acc[c][v][3] = 0.0;
-#pragma unroll 8
-    for (int i = 0; i < rows; ++i) {
-        f4 a[VEC];
-#pragma unroll
-        for (int c = 0; c < VEC; ++c) {
-            const int j4 = jb + c * kThreads;
-            a[c] = j4 < N4 ? __builtin_nontemporal_load(col + (size_t)i * N4 + j4) : f4{0, 0, 0, 0};
+    for (int idx = blockIdx.y; idx < nrowchunk; idx += gridDim.y) {
+        const int chunk = TVCS_COLS_REVERSE ? nrowchunk - 1 - idx : idx;
+        const int i0 = chunk * rows_per_chunk;
+        const int rows = min(rows_per_chunk, m - i0);
+        __syncthreads();   // the previous chunk's coefficients are no longer read
+        for (int t = threadIdx.x; t < rows * NV; t += kThreads) {
+            const int i = t / NV, v = t % NV;
+            rs[t] = Rv[(size_t)v * ldr + i0 + i];
         }
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const double r = rs[i * NV + v];
+        __syncthreads();
+        const f4 *col = reinterpret_cast<const f4 *>(A + (size_t)i0 * N);
+#pragma unroll 8
+        for (int i = 0; i < rows; ++i) {
+            f4 a[VEC];
 #pragma unroll
             for (int c = 0; c < VEC; ++c) {
-                acc[c][v][0] = fma((double)a[c].x, r, acc[c][v][0]);
-                acc[c][v][1] = fma((double)a[c].y, r, acc[c][v][1]);
-                acc[c][v][2] = fma((double)a[c].z, r, acc[c][v][2]);
-                acc[c][v][3] = fma((double)a[c].w, r, acc[c][v][3]);
+                const int j4 = jb + c * kThreads;
+                a[c] = j4 < N4 ? load_a(col + (size_t)i * N4 + j4) : f4{0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double r = rs[i * NV + v];
+#pragma unroll
+                for (int c = 0; c < VEC; ++c) {
+                    acc[c][v][0] = fma((double)a[c].x, r, acc[c][v][0]);
+                    acc[c][v][1] = fma((double)a[c].y, r, acc[c][v][1]);
+                    acc[c][v][2] = fma((double)a[c].z, r, acc[c][v][2]);
+                    acc[c][v][3] = fma((double)a[c].w, r, acc[c][v][3]);
+                }
             }
         }
     }
@@ -170,7 +188,7 @@ __global__ __launch_bounds__(kThreads) void k_gemv_cols(
         if (j4 >= N4) continue;
 #pragma unroll
         for (int v = 0; v < NV; ++v)
-            reinterpret_cast<f4 *>(P + chunk * chunk_stride + (size_t)v * N)[j4] =
+            reinterpret_cast<f4 *>(P + blockIdx.y * chunk_stride + (size_t)v * N)[j4] =
                 f4{(float)acc[c][v][0], (float)acc[c][v][1], (float)acc[c][v][2], (float)acc[c][v][3]};
     }
 }
@@ -184,24 +202,12 @@ void rows_dispatch(const float *A, int m, int N, const float *U, int ldu, const 
                        ldu, F, ldf, R, ldr, st, nact);
 }
 
-template <int NV>
-void cols_dispatch(const float *A, int m, int N, const float *R, int ldr, float *P,
-                   long long chunk_stride, const ImgState *st, int nact, hipStream_t s) {
-    const int nchunk = gemv_cols_chunks(m, N);   // the same chunks for every NV
-    const int rpc = (m + nchunk - 1) / nchunk;
-    const int colblocks = (N / 4 + kThreads * TVCS_COLS_VEC - 1) / (kThreads * TVCS_COLS_VEC);
-    hipLaunchKernelGGL((k_gemv_cols<NV>), dim3(colblocks, nchunk), dim3(kThreads),
-                       sizeof(double) * rpc * NV, s, A, m, N, R, ldr, P, chunk_stride, rpc, st,
-                       nact);
-}
-
-}  // namespace
-
-int gemv_cols_chunks(int m, int N) {
-    // Aim for ~1024 workgroups; keep chunks >= 16 rows so partial-sum traffic
-    // stays a few percent of the A stream, and the chunk's coefficients
-    // (rows x nv doubles, nv <= 8) within 64 KiB of LDS.  Independent of nv, so
-    // the order of the sums does not depend on how many vectors share a pass.
+// Row chunks of the A^T r product: aim for ~TVCS_COLS_TARGET_WG chunk x column
+// block pairs; keep chunks >= 16 rows so partial-sum traffic stays a few percent
+// of the A stream, and a chunk's coefficients (rows x nv doubles, nv <= 8) within
+// 64 KiB of LDS.  Independent of nv, so the order of the sums does not depend on
+// how many vectors share a pass.
+int cols_rowchunks(int m, int N) {
     const int nv = 8;
     const int colblocks = (N / 4 + kThreads - 1) / kThreads;   // of 1024 columns
     int nchunk = (TVCS_COLS_TARGET_WG + colblocks - 1) / colblocks;
@@ -210,6 +216,27 @@ int gemv_cols_chunks(int m, int N) {
     // rows per chunk is ceil(m / nchunk); recompute nchunk so none is empty
     const int rpc = (m + nchunk - 1) / nchunk;
     return (m + rpc - 1) / rpc;
+}
+
+template <int NV>
+void cols_dispatch(const float *A, int m, int N, const float *R, int ldr, float *P,
+                   long long chunk_stride, const ImgState *st, int nact, hipStream_t s) {
+    const int nrc = cols_rowchunks(m, N);          // the same chunks for every NV
+    const int rpc = (m + nrc - 1) / nrc;
+    const int slots = gemv_cols_chunks(m, N);
+    const int colblocks = (N / 4 + kThreads * TVCS_COLS_VEC - 1) / (kThreads * TVCS_COLS_VEC);
+    hipLaunchKernelGGL((k_gemv_cols<NV>), dim3(colblocks, slots), dim3(kThreads),
+                       sizeof(double) * rpc * NV, s, A, m, N, R, ldr, P, chunk_stride, rpc, nrc,
+                       st, nact);
+}
+
+}  // namespace
+
+// Partial sums per column of the A^T r product: one per slot (TVCS_COLS_SLOTS > 0)
+// or one per row chunk.
+int gemv_cols_chunks(int m, int N) {
+    const int nrc = cols_rowchunks(m, N);
+    return TVCS_COLS_SLOTS > 0 ? std::min(TVCS_COLS_SLOTS, nrc) : nrc;
 }
 
 void launch_gemv_rows(const float *A, int m, int N, const float *U, int ldu, const float *F,
