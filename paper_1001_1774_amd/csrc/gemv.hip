@@ -33,8 +33,14 @@
 #ifndef TVCS_COLS_TARGET_WG
 #define TVCS_COLS_TARGET_WG 1024   // workgroups the A^T r product aims for
 #endif
-#ifndef TVCS_GEMV_NT
-#define TVCS_GEMV_NT 0        // 1: nontemporal (streaming) loads of A; 0: ordinary loads
+#ifndef TVCS_GEMV_NT_BYTES
+// A larger than this is read with nontemporal (streaming) loads, a smaller one with
+// ordinary loads (measured: ordinary loads win while A is about the size of the
+// 256 MB Infinity Cache, streaming loads for multi-GB A)
+#define TVCS_GEMV_NT_BYTES (512ull << 20)
+#endif
+#ifndef TVCS_COLS_RS
+#define TVCS_COLS_RS 1        // row phases (256 threads each) per workgroup of A^T r
 #endif
 #ifndef TVCS_COLS_SLOTS
 #define TVCS_COLS_SLOTS 0     // >0: row-chunk slots per column block of A^T r (0: one per chunk)
@@ -51,8 +57,9 @@ constexpr int kThreads = 256;
 // native 4-wide vector (the nontemporal load builtin needs a clang vector type)
 typedef float f4 __attribute__((ext_vector_type(4)));
 
+template <bool NT>
 __device__ inline f4 load_a(const f4 *p) {
-    if (TVCS_GEMV_NT) return __builtin_nontemporal_load(p);
+    if (NT) return __builtin_nontemporal_load(p);
     return *p;
 }
 
@@ -70,7 +77,7 @@ __device__ inline double dot4(f4 a, const double (&x)[4], double acc) {
     return fma((double)a.w, x[3], acc);
 }
 
-template <int NV, int ROWS>
+template <int NV, int ROWS, bool NT>
 __global__ __launch_bounds__(kThreads) void k_gemv_rows(
     const float *__restrict__ A, int m, int N, const float *__restrict__ U, int ldu,
     const float *__restrict__ F, int ldf, float *__restrict__ R, int ldr,
@@ -94,7 +101,7 @@ __global__ __launch_bounds__(kThreads) void k_gemv_rows(
     for (int j = threadIdx.x; j < N4; j += kThreads) {
         f4 a[ROWS];
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) a[r] = load_a(rowp[r] + j);
+        for (int r = 0; r < ROWS; ++r) a[r] = load_a<NT>(rowp[r] + j);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const f4 x = reinterpret_cast<const f4 *>(U + (size_t)v * ldu)[j];
@@ -131,20 +138,23 @@ __global__ __launch_bounds__(kThreads) void k_gemv_rows(
 
 // Row chunks are visited by gridDim.y slots: slot s takes chunks s, s + slots, ...
 // (counted from the last chunk when TVCS_COLS_REVERSE), accumulating all of them
-// before it writes its partial sums, so at any time the workgroups sweep one band
-// of rows.  The chunking and the slots depend on (m, N) only.
-template <int NV>
-__global__ __launch_bounds__(kThreads) void k_gemv_cols(
+// before it writes its partial sums.  A workgroup has RS row phases of 256 threads:
+// phase p takes rows p, p + RS, ... of each chunk for the same columns, and the
+// phases' sums are added in phase order at the end.  The chunking, the slots and
+// the phases depend on (m, N) only.
+template <int NV, bool NT>
+__global__ __launch_bounds__(kThreads * TVCS_COLS_RS) void k_gemv_cols(
     const float *__restrict__ A, int m, int N, const float *__restrict__ Rv, int ldr,
     float *__restrict__ P, long long chunk_stride, int rows_per_chunk, int nrowchunk,
     const ImgState *__restrict__ st, int nact) {
-    constexpr int VEC = TVCS_COLS_VEC;
+    constexpr int VEC = TVCS_COLS_VEC, RS = TVCS_COLS_RS;
     if (!any_active(st, nact)) return;
-    extern __shared__ double rs[];           // rows_per_chunk x NV coefficients
+    extern __shared__ double rs[];           // rows_per_chunk x NV coefficients, then 256 x 4
     const int N4 = N >> 2;
+    const int tl = threadIdx.x & (kThreads - 1), phase = threadIdx.x / kThreads;
     // the workgroup covers VEC * 256 consecutive float4 columns; thread t owns
     // columns t, t + 256, ... so each wave still reads contiguous 1 KiB pieces
-    const int jb = blockIdx.x * kThreads * VEC + threadIdx.x;
+    const int jb = blockIdx.x * kThreads * VEC + tl;
     double acc[VEC][NV][4];
 #pragma unroll
     for (int c = 0; c < VEC; ++c)
@@ -155,19 +165,19 @@ __global__ __launch_bounds__(kThreads) void k_gemv_cols(
         const int i0 = chunk * rows_per_chunk;
         const int rows = min(rows_per_chunk, m - i0);
         __syncthreads();   // the previous chunk's coefficients are no longer read
-        for (int t = threadIdx.x; t < rows * NV; t += kThreads) {
+        for (int t = threadIdx.x; t < rows * NV; t += kThreads * RS) {
             const int i = t / NV, v = t % NV;
             rs[t] = Rv[(size_t)v * ldr + i0 + i];
         }
         __syncthreads();
         const f4 *col = reinterpret_cast<const f4 *>(A + (size_t)i0 * N);
 #pragma unroll 8
-        for (int i = 0; i < rows; ++i) {
+        for (int i = phase; i < rows; i += RS) {
             f4 a[VEC];
 #pragma unroll
             for (int c = 0; c < VEC; ++c) {
                 const int j4 = jb + c * kThreads;
-                a[c] = j4 < N4 ? load_a(col + (size_t)i * N4 + j4) : f4{0, 0, 0, 0};
+                a[c] = j4 < N4 ? load_a<NT>(col + (size_t)i * N4 + j4) : f4{0, 0, 0, 0};
             }
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
@@ -181,6 +191,22 @@ __global__ __launch_bounds__(kThreads) void k_gemv_cols(
                 }
             }
         }
+    }
+    if (RS > 1) {   // phase 0 adds the other phases' sums, one (c, v) at a time
+        double *buf = rs + rows_per_chunk * NV;
+#pragma unroll
+        for (int c = 0; c < VEC; ++c)
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                for (int p = 1; p < RS; ++p) {
+                    __syncthreads();
+                    if (phase == p)
+                        for (int e = 0; e < 4; ++e) buf[e * kThreads + tl] = acc[c][v][e];
+                    __syncthreads();
+                    if (phase == 0)
+                        for (int e = 0; e < 4; ++e) acc[c][v][e] += buf[e * kThreads + tl];
+                }
+        if (phase != 0) return;
     }
 #pragma unroll
     for (int c = 0; c < VEC; ++c) {
@@ -198,8 +224,12 @@ void rows_dispatch(const float *A, int m, int N, const float *U, int ldu, const 
                    int ldf, float *R, int ldr, const ImgState *st, int nact, hipStream_t s) {
     constexpr int ROWS = NV <= 2 ? TVCS_GEMV_ROWS : 2;
     const int grid = (m + ROWS - 1) / ROWS;
-    hipLaunchKernelGGL((k_gemv_rows<NV, ROWS>), dim3(grid), dim3(kThreads), 0, s, A, m, N, U,
-                       ldu, F, ldf, R, ldr, st, nact);
+    if ((size_t)m * N * sizeof(float) > TVCS_GEMV_NT_BYTES)
+        hipLaunchKernelGGL((k_gemv_rows<NV, ROWS, true>), dim3(grid), dim3(kThreads), 0, s, A, m,
+                           N, U, ldu, F, ldf, R, ldr, st, nact);
+    else
+        hipLaunchKernelGGL((k_gemv_rows<NV, ROWS, false>), dim3(grid), dim3(kThreads), 0, s, A, m,
+                           N, U, ldu, F, ldf, R, ldr, st, nact);
 }
 
 // Row chunks of the A^T r product: aim for ~TVCS_COLS_TARGET_WG chunk x column
@@ -225,9 +255,14 @@ void cols_dispatch(const float *A, int m, int N, const float *R, int ldr, float 
     const int rpc = (m + nrc - 1) / nrc;
     const int slots = gemv_cols_chunks(m, N);
     const int colblocks = (N / 4 + kThreads * TVCS_COLS_VEC - 1) / (kThreads * TVCS_COLS_VEC);
-    hipLaunchKernelGGL((k_gemv_cols<NV>), dim3(colblocks, slots), dim3(kThreads),
-                       sizeof(double) * rpc * NV, s, A, m, N, R, ldr, P, chunk_stride, rpc, nrc,
-                       st, nact);
+    const size_t lds = sizeof(double) * (rpc * NV + (TVCS_COLS_RS > 1 ? 4 * kThreads : 0));
+    const dim3 block(kThreads * TVCS_COLS_RS);
+    if ((size_t)m * N * sizeof(float) > TVCS_GEMV_NT_BYTES)
+        hipLaunchKernelGGL((k_gemv_cols<NV, true>), dim3(colblocks, slots), block, lds, s, A, m, N,
+                           R, ldr, P, chunk_stride, rpc, nrc, st, nact);
+    else
+        hipLaunchKernelGGL((k_gemv_cols<NV, false>), dim3(colblocks, slots), block, lds, s, A, m,
+                           N, R, ldr, P, chunk_stride, rpc, nrc, st, nact);
 }
 
 }  // namespace
