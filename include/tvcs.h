@@ -155,6 +155,27 @@ int tvcs_solve_batch(tvcs_handle h, const float *F, int B, double mu, double bet
                      int maxit, unsigned flags, float *U, double *lambda, tvcs_stats *st);
 
 /*
+ * tvcs_solve_continuation: Algorithm 1 (FTVCS) with continuation in beta, as the
+ * paper runs it (Sec. 3.1): one FTVCS run per value of betas[0..nbeta-1] (an
+ * increasing sequence, e.g. 2^4, 2^5, 2^6, 2^7), each stage warm-started from the
+ * previous stage's u and ended by eq. (stop) with tolerance tol (0: exactly maxit
+ * iterations per stage) or by maxit.
+ *   F, B, mu, U   as for tvcs_solve_batch (U is also the warm start of the first
+ *                 stage with TVCS_WARM_START)
+ *   flags         TVCS_U0_ZERO, TVCS_WARM_START (first stage only) and
+ *                 TVCS_OBJECTIVE (after the last stage); TVCS_IADM is rejected
+ *                 (Algorithm 2 keeps beta fixed)
+ *   st            optional B stats: iters counts all stages, the other fields are
+ *                 the last stage's (ms: sum over stages)
+ * Returns TVCS_OK if every stage of every image met tol (or tol = 0), TVCS_MAXIT if
+ * some stage stopped at maxit (the next stage still runs), or an error code
+ * (TVCS_EINVAL for NULL betas, nbeta < 1 or a beta that is not positive and finite).
+ */
+int tvcs_solve_continuation(tvcs_handle h, const float *F, int B, double mu,
+                            const double *betas, int nbeta, double tol, int maxit,
+                            unsigned flags, float *U, tvcs_stats *st);
+
+/*
  * tvcs_time_products: measurement helper.  Average device time in milliseconds
  * of one forward product (r = A u - f, all images of a batch of B) and of one
  * adjoint product (A^T r, including its partial-sum reduction), over `reps`

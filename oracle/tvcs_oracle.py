@@ -36,7 +36,7 @@ import numpy as np
 __all__ = [
     "D", "Dt", "project_disc", "shrink", "dtd_eigenvalues", "solve_u", "gradient",
     "lambda_max", "default_tau", "tv", "objective_tv", "huber_objective",
-    "OracleResult", "initial_u", "ftvcs", "iadm", "bf16_rne", "split_bf16", "fp8_e4m3_values",
+    "OracleResult", "initial_u", "ftvcs", "ftvcs_continuation", "iadm", "bf16_rne", "split_bf16", "fp8_e4m3_values",
     "fp8_e4m3_rne", "fp8_rowscale_quantize", "dequantized_A",
 ]
 
@@ -245,6 +245,26 @@ def ftvcs(A, f, n, mu, beta, tau, tol=0.0, maxit=200, u0=None, record=None) -> O
         if record is not None:
             record(k, u)
     return OracleResult(u=u, iters=iters, rel_change=rel, w=w)
+
+
+def ftvcs_continuation(A, f, n, mu, betas, tau, tol=0.0, maxit=200, u0=None,
+                       record=None) -> OracleResult:
+    """FTVCS with continuation in beta (Sec. 3.1): Algorithm 1 is run for each beta of
+    the increasing sequence `betas` in turn, each stage warm-started from the previous
+    stage's u and ended by the stop rule (eq. (stop)) or `maxit`.  Returns the last
+    stage's u and w; `iters` counts the iterations of all stages.
+    `record(stage, k, u)` is called after every iteration if given.
+    """
+    f = _as_batch(f)
+    u = u0
+    total = np.zeros(f.shape[0], dtype=np.int64)
+    res = None
+    for s, beta in enumerate(betas):
+        rec = None if record is None else (lambda k, uu, s=s: record(s, k, uu))
+        res = ftvcs(A, f, n, mu, beta, tau, tol=tol, maxit=maxit, u0=u, record=rec)
+        total += res.iters
+        u = res.u
+    return OracleResult(u=res.u, iters=total, rel_change=res.rel_change, w=res.w)
 
 
 def iadm(A, f, n, mu, beta, tau, tol=0.0, maxit=200, u0=None, lam0=None, sign=+1,

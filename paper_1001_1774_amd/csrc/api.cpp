@@ -258,6 +258,46 @@ int tvcs_solve_batch(tvcs_handle h, const float *F, int B, double mu, double bet
     return guarded([&] { return solve_impl(h, F, B, mu, beta, tol, maxit, flags, U, lambda, st); });
 }
 
+int tvcs_solve_continuation(tvcs_handle h, const float *F, int B, double mu,
+                            const double *betas, int nbeta, double tol, int maxit,
+                            unsigned flags, float *U, tvcs_stats *st) {
+    return guarded([&] {
+        if (!betas || nbeta < 1) fail(TVCS_EINVAL, "betas must hold nbeta >= 1 values");
+        for (int k = 0; k < nbeta; ++k)
+            if (!(betas[k] > 0) || !std::isfinite(betas[k]))
+                fail(TVCS_EINVAL, "every beta must be positive and finite");
+        if (flags & TVCS_IADM)
+            fail(TVCS_EINVAL, "continuation in beta is defined for FTVCS (Algorithm 1)");
+        if (flags & ~(TVCS_U0_ZERO | TVCS_OBJECTIVE | TVCS_WARM_START))
+            fail(TVCS_EINVAL, "unknown flag bits");
+        if (B < 1) fail(TVCS_EINVAL, "batch size must be >= 1");
+        std::vector<tvcs_stats> stage((size_t)B);
+        std::vector<int> total((size_t)B, 0);
+        std::vector<float> ms((size_t)B, 0.f);
+        int rc = TVCS_OK;
+        for (int k = 0; k < nbeta; ++k) {
+            // first stage: the caller's start; later stages: warm start from U
+            unsigned f = k == 0 ? (flags & (TVCS_U0_ZERO | TVCS_WARM_START)) : TVCS_WARM_START;
+            if (k == nbeta - 1) f |= flags & TVCS_OBJECTIVE;
+            const int r = solve_impl(h, F, B, mu, betas[k], tol, maxit, f, U, nullptr,
+                                     stage.data());
+            if (r < 0) return r;
+            if (r == TVCS_MAXIT) rc = TVCS_MAXIT;
+            for (int b = 0; b < B; ++b) {
+                total[b] += stage[b].iters;
+                ms[b] += stage[b].ms;
+            }
+        }
+        if (st)
+            for (int b = 0; b < B; ++b) {
+                st[b] = stage[b];
+                st[b].iters = total[b];
+                st[b].ms = ms[b];
+            }
+        return rc;
+    });
+}
+
 int tvcs_time_products(tvcs_handle h, int B, int reps, float *ms_forward, float *ms_adjoint) {
     return guarded([&] {
         if (!h) fail(TVCS_EINVAL, "null handle");

@@ -74,6 +74,10 @@ _SIGS = {
                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_int, ctypes.c_uint, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p]),
+    "tvcs_solve_continuation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                               ctypes.c_double, ctypes.c_void_p, ctypes.c_int,
+                                               ctypes.c_double, ctypes.c_int, ctypes.c_uint,
+                                               ctypes.c_void_p, ctypes.c_void_p]),
     "tvcs_time_products": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_void_p, ctypes.c_void_p]),
     "tvcs_destroy": (None, [ctypes.c_void_p]),
@@ -180,6 +184,13 @@ def tvcs_solve_batch(h, F, B, mu, beta, tol, maxit, flags, U, lam=None, st=None)
     return lib().tvcs_solve_batch(h, _ptr(F, torch.float32), B, mu, beta, tol, maxit, flags,
                                   _ptr(U, torch.float32), _ptr(lam, torch.float64),
                                   st if st is not None else None)
+
+
+def tvcs_solve_continuation(h, F, B, mu, betas, nbeta, tol, maxit, flags, U, st=None):
+    """betas: a float64 numpy array (host) of nbeta values."""
+    return lib().tvcs_solve_continuation(h, _ptr(F, torch.float32), B, mu,
+                                         _ptr(betas, torch.float64), nbeta, tol, maxit, flags,
+                                         _ptr(U, torch.float32), st if st is not None else None)
 
 
 def tvcs_time_products(h, B, reps, ms_forward=None, ms_adjoint=None):
@@ -319,6 +330,28 @@ class Solver:
         if lam is not None:
             out["lam"] = lam.reshape(B, 2, self.n, self.n)
         return out
+
+    def solve_continuation(self, F, mu=1e3, betas=(16.0, 32.0, 64.0, 128.0), tol=1e-3,
+                           maxit=500, objective=False, u0=None, u0_zero=False):
+        """FTVCS with continuation in beta (one warm-started stage per beta)."""
+        F = self._as_dev(F, torch.float32)
+        if F.dim() == 1:
+            F = F[None]
+        B = F.shape[0]
+        flags = (TVCS_OBJECTIVE if objective else 0) | (TVCS_U0_ZERO if u0_zero else 0)
+        if u0 is not None:
+            U = self._as_dev(u0, torch.float32).reshape(B, self.N).clone()
+            flags |= TVCS_WARM_START
+        else:
+            U = torch.empty(B, self.N, dtype=torch.float32, device=self.device)
+        b = np.ascontiguousarray(np.asarray(betas, dtype=np.float64))
+        st = (tvcs_stats * B)()
+        rc = tvcs_solve_continuation(self.h, F, B, mu, b, len(b), tol, maxit, flags, U, st)
+        if rc < 0:
+            raise TvcsError(rc, tvcs_last_error())
+        stats = [dict(iters=s.iters, status=s.status, rel_change=s.rel_change,
+                      objective=s.objective, tau=s.tau, ms=s.ms) for s in st]
+        return dict(u=U.reshape(B, self.n, self.n), stats=stats, rc=rc)
 
     def time_products(self, B=1, reps=20):
         """Average ms per launch of the forward and adjoint products (HIP events)."""

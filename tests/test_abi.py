@@ -67,6 +67,20 @@ def test_argument_errors_without_device(clib):
     f = np.zeros(4, np.float32)
     assert T.tvcs_solve(None, f, 1.0, 1.0, 0.0, 1, 0, u) == T.TVCS_EINVAL
     assert T.tvcs_set_tau(None, 1.0) == T.TVCS_EINVAL
+    # continuation: betas and flags are checked before any device work
+    betas = np.array([16.0, 32.0])
+    U = np.zeros((1, 64), np.float32)
+    assert T.tvcs_solve_continuation(None, f, 1, 1.0, None, 2, 0.0, 1, 0, U) == T.TVCS_EINVAL
+    assert "betas" in T.tvcs_last_error()
+    assert T.tvcs_solve_continuation(None, f, 1, 1.0, betas, 0, 0.0, 1, 0, U) == T.TVCS_EINVAL
+    assert T.tvcs_solve_continuation(None, f, 1, 1.0, np.array([16.0, -1.0]), 2, 0.0, 1, 0,
+                                     U) == T.TVCS_EINVAL
+    assert "positive" in T.tvcs_last_error()
+    assert T.tvcs_solve_continuation(None, f, 1, 1.0, betas, 2, 0.0, 1, T.TVCS_IADM,
+                                     U) == T.TVCS_EINVAL
+    assert "FTVCS" in T.tvcs_last_error()
+    assert T.tvcs_solve_continuation(None, f, 1, 1.0, betas, 2, 0.0, 1, 0, U) == T.TVCS_EINVAL
+    assert "null handle" in T.tvcs_last_error()
     assert T.tvcs_get_tau(None) < 0
     T.tvcs_destroy(None)
 

@@ -238,3 +238,54 @@ def test_ftvcs_step_optimality(small):
         r = BETA * O.Dt(O.D(nxt.u) - nxt.w) + MU * O.gradient(p.A, uk, p.f) \
             + MU / tau * (nxt.u - uk)
         assert np.abs(r).max() <= 1e-9 * MU * np.abs(p.f @ p.A).max(), k
+
+
+# --- FTVCS with continuation in beta (Sec. 3.1) ------------------------------------
+BETAS = [2.0 ** 4, 2.0 ** 5, 2.0 ** 6, 2.0 ** 7]
+
+
+def test_continuation_single_beta_is_ftvcs(small):
+    p, tau = small
+    a = O.ftvcs_continuation(p.A, p.f, p.n, MU, [BETA], tau, tol=1e-4, maxit=300)
+    b = O.ftvcs(p.A, p.f, p.n, MU, BETA, tau, tol=1e-4, maxit=300)
+    assert np.array_equal(a.u, b.u) and np.array_equal(a.iters, b.iters)
+
+
+def test_continuation_descent_within_each_stage(small):
+    """Within a stage beta is fixed, so the descent bound of Thm. 1's step range
+    holds for that stage's Huber objective Psi_beta (the warm start only moves the
+    starting point)."""
+    p, tau = small
+    lmax = O.lambda_max(p.A, iters=5000, rtol=1e-14)
+    traj = {s: [] for s in range(len(BETAS))}
+    start = {}
+
+    def rec(s, k, u):
+        traj[s].append(u.copy())
+    res_prev = O.initial_u(p.A, np.atleast_2d(p.f), p.n, None).copy()
+    for s, beta in enumerate(BETAS):   # the starting point of each stage
+        start[s] = res_prev
+        res_prev = O.ftvcs(p.A, p.f, p.n, MU, beta, tau, tol=1e-3, maxit=400, u0=res_prev).u
+    out = O.ftvcs_continuation(p.A, p.f, p.n, MU, BETAS, tau, tol=1e-3, maxit=400, record=rec)
+    assert np.array_equal(out.u, res_prev)
+    for s, beta in enumerate(BETAS):
+        us = [start[s]] + traj[s]
+        psi = [O.huber_objective(u, p.A, p.f, MU, beta)[0] for u in us]
+        for k in range(len(us) - 1):
+            d2 = np.sum((us[k + 1] - us[k]) ** 2)
+            assert psi[k + 1] <= psi[k] - MU * (1.0 / tau - lmax / 2) * d2 + 1e-9 * abs(psi[k])
+
+
+def test_continuation_approaches_tv_optimum(small):
+    """Each stage converges to the minimiser of (atv) for its beta, whose (tv) value
+    approaches the optimum of (tv) as beta grows: the gap after the last stage is a
+    fraction of the gap of the first stage alone (the independent optimum comes from
+    a long Chambolle-Pock run)."""
+    p, tau = small
+    _, fc = chambolle_pock_tv(p.A, p.f[0], p.n, MU, iters=20000)
+    first = O.ftvcs(p.A, p.f, p.n, MU, BETAS[0], tau, tol=0, maxit=3000)
+    cont = O.ftvcs_continuation(p.A, p.f, p.n, MU, BETAS, tau, tol=0, maxit=3000)
+    gap1 = O.objective_tv(first.u, p.A, p.f, MU)[0] - fc
+    gap4 = O.objective_tv(cont.u, p.A, p.f, MU)[0] - fc
+    assert gap1 > 0 and gap4 > -1e-9 * fc
+    assert gap4 <= gap1 / 4
