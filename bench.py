@@ -142,6 +142,11 @@ def main():
     fwd_gbs = fwd_bytes / (ms_fwd * 1e-3) / 1e9
     adj_gbs = adj_bytes / (ms_adj * 1e-3) / 1e9
 
+    # achievable peaks on this device (streaming read of 2 GiB, MFMA chains)
+    peak_read, peak_mfma = tvcs.measure_peaks(2 << 30, 10)
+    log(f"measured peaks: HBM read {peak_read:.0f} GB/s, bf16 MFMA {peak_mfma:.0f} TFLOP/s")
+    ACHIEVABLE.update(hbm_read_gbs=peak_read, mfma_bf16_tflops=peak_mfma)
+
     # the dominant kernel is the slower of the two products (per launch)
     if ms_adj >= ms_fwd:
         dom = ("k_gemv_cols", "k_gemv_cols<1> (g = A^T r)", adj_gbs, adj_bytes)
@@ -149,7 +154,8 @@ def main():
         dom = ("k_gemv_rows", "k_gemv_rows<1,2> (r = A u - f)", fwd_gbs, fwd_bytes)
     roofline = {"bound": "hbm", "achieved": dom[2], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": dom[2] / HBM_PEAK_GBS, "traffic": measured_traffic(dom[0]),
-                "algorithmic_bytes": dom[3], "kernel": dom[1]}
+                "algorithmic_bytes": dom[3], "kernel": dom[1],
+                "achievable_peak": peak_read, "frac_of_achievable": dom[2] / peak_read}
 
     out = {
         "metric": "reconstructions/sec at <=1e-4 rel err vs FP64 (batched vs plain); GEMV GB/s",
@@ -168,6 +174,7 @@ def main():
                    "iterations": args.iters, "algorithm": args.alg.upper(), "storage": "fp32",
                    "mu": p.mu, "beta": p.beta, "tau": tau, "batch": 1, "seed_A": p.seed_A},
         "rel_err_vs_fp64_oracle": rel_err,
+        "measured_peaks": dict(ACHIEVABLE),
         "gemv_gbs": {"forward": fwd_gbs, "adjoint": adj_gbs,
                      "forward_ms": ms_fwd, "adjoint_ms": ms_adj},
         "roofline": roofline,
@@ -185,6 +192,7 @@ def main():
 
 
 MFMA_BF16_PEAK = 2.5e15   # MI355X dense bf16 MFMA, FLOP/s
+ACHIEVABLE = {}           # peaks measured on the device (filled in main)
 
 
 def product_rates(storage, m, N, B, ms_f, ms_a):
@@ -202,6 +210,10 @@ def product_rates(storage, m, N, B, ms_f, ms_a):
         out[f"gemm_{name}_hbm_frac"] = a_bytes / t / (HBM_PEAK_GBS * 1e9)
         out[f"mfma_useful_frac_{name}"] = useful / t / MFMA_BF16_PEAK
         out[f"mfma_executed_frac_{name}"] = execd * useful / t / MFMA_BF16_PEAK
+        if ACHIEVABLE:
+            out[f"gemm_{name}_frac_of_achievable_hbm"] = a_bytes / t / (ACHIEVABLE["hbm_read_gbs"] * 1e9)
+            out[f"mfma_executed_frac_of_achievable_{name}"] = (
+                execd * useful / t / (ACHIEVABLE["mfma_bf16_tflops"] * 1e12))
     return out
 
 
@@ -256,6 +268,21 @@ def bench_batched(args, np, torch, O, synth, tvcs):
             **product_rates(storage, p.m, p.N, p.B, ms_f, ms_a),
         }
         log(f"{storage} B=64: {1e3 * dt / K:.3f} ms/iter, err {err:.2e}")
+    # the products' rates as the batch grows (bf16 storage): the arithmetic intensity
+    # 2B / s_A moves the products from the HBM roofline towards the MFMA one
+    sweep = {}
+    with tvcs.Solver(A32, p.n, storage="bf16") as s:
+        for Bs in (64, 128, 256):
+            ms_f, ms_a = s.time_products(B=Bs, reps=5)
+            r = product_rates("bf16", p.m, p.N, Bs, ms_f, ms_a)
+            ai = 2.0 * Bs / 2.0                           # useful flops per A byte
+            bound = min(MFMA_BF16_PEAK, ai * HBM_PEAK_GBS * 1e9)
+            r["roofline_bound_tflops"] = bound / 1e12
+            r["frac_of_roofline_forward"] = 2.0 * p.m * p.N * Bs / (ms_f * 1e-3) / bound
+            r["frac_of_roofline_adjoint"] = 2.0 * p.m * p.N * Bs / (ms_a * 1e-3) / bound
+            sweep[f"B{Bs}"] = r
+            log(f"bf16 products B={Bs}: {ms_f:.3f} / {ms_a:.3f} ms")
+    res["bf16_batch_sweep"] = sweep
     return res
 
 

@@ -185,6 +185,17 @@ int tvcs_solve_continuation(tvcs_handle h, const float *F, int B, double mu,
  */
 int tvcs_time_products(tvcs_handle h, int B, int reps, float *ms_forward, float *ms_adjoint);
 
+/*
+ * tvcs_measure_peaks: measurement helper, independent of any handle.  Achievable
+ * HBM read bandwidth in GB/s (a streaming read of a `bytes`-byte device buffer with
+ * 16-byte loads; use >= 1 GiB so that caches do not serve it) and dense bf16 MFMA
+ * throughput in TFLOP/s (independent chains of v_mfma_f32_16x16x32_bf16 on every
+ * CU), each averaged over `reps` launches timed with HIP events.  Allocates and
+ * frees `bytes` of device memory.  Either output may be NULL.  Returns TVCS_EINVAL
+ * if bytes < 1 MiB or reps < 1.
+ */
+int tvcs_measure_peaks(size_t bytes, int reps, double *read_gbs, double *mfma_tflops);
+
 /* ---- continuous-batching request loop ------------------------------------ */
 typedef struct tvcs_server *tvcs_server_handle;
 

@@ -327,6 +327,15 @@ int tvcs_time_products(tvcs_handle h, int B, int reps, float *ms_forward, float 
     });
 }
 
+int tvcs_measure_peaks(size_t bytes, int reps, double *read_gbs, double *mfma_tflops) {
+    return guarded([&] {
+        if (bytes < ((size_t)1 << 20) || reps < 1)
+            fail(TVCS_EINVAL, "bytes must be >= 1 MiB and reps >= 1");
+        measure_peaks(bytes, reps, read_gbs, mfma_tflops);
+        return TVCS_OK;
+    });
+}
+
 void tvcs_destroy(tvcs_handle h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->work);

@@ -158,4 +158,7 @@ void lowp_apply_At(const LowpA &L, LowpWork &W, int B, const float *R, float *G,
 void lowp_autotune(const LowpA &L, LowpWork &W, int Bp, const float *U, float *R, float *G,
                    hipStream_t s);
 
+// achievable HBM read bandwidth (GB/s) and dense bf16 MFMA rate (TFLOP/s)
+void measure_peaks(size_t bytes, int reps, double *read_gbs, double *mfma_tflops);
+
 }  // namespace tvcs

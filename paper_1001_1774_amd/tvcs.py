@@ -78,6 +78,8 @@ _SIGS = {
                                                ctypes.c_double, ctypes.c_void_p, ctypes.c_int,
                                                ctypes.c_double, ctypes.c_int, ctypes.c_uint,
                                                ctypes.c_void_p, ctypes.c_void_p]),
+    "tvcs_measure_peaks": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p,
+                                          ctypes.c_void_p]),
     "tvcs_time_products": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_void_p, ctypes.c_void_p]),
     "tvcs_destroy": (None, [ctypes.c_void_p]),
@@ -198,6 +200,22 @@ def tvcs_time_products(h, B, reps, ms_forward=None, ms_adjoint=None):
     return lib().tvcs_time_products(h, B, reps,
                                     ctypes.byref(ms_forward) if ms_forward is not None else None,
                                     ctypes.byref(ms_adjoint) if ms_adjoint is not None else None)
+
+
+def tvcs_measure_peaks(nbytes, reps, read_gbs=None, mfma_tflops=None):
+    """read_gbs / mfma_tflops: ctypes.c_double objects (or None)."""
+    return lib().tvcs_measure_peaks(nbytes, reps,
+                                    ctypes.byref(read_gbs) if read_gbs is not None else None,
+                                    ctypes.byref(mfma_tflops) if mfma_tflops is not None else None)
+
+
+def measure_peaks(nbytes=2 << 30, reps=10):
+    """(HBM read GB/s, bf16 MFMA TFLOP/s) measured on the current device."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    rc = tvcs_measure_peaks(nbytes, reps, a, b)
+    if rc < 0:
+        raise TvcsError(rc, tvcs_last_error())
+    return a.value, b.value
 
 
 def tvcs_destroy(h):

@@ -81,6 +81,8 @@ def test_argument_errors_without_device(clib):
     assert "FTVCS" in T.tvcs_last_error()
     assert T.tvcs_solve_continuation(None, f, 1, 1.0, betas, 2, 0.0, 1, 0, U) == T.TVCS_EINVAL
     assert "null handle" in T.tvcs_last_error()
+    assert T.tvcs_measure_peaks(1024, 1) == T.TVCS_EINVAL
+    assert T.tvcs_measure_peaks(1 << 30, 0) == T.TVCS_EINVAL
     assert T.tvcs_get_tau(None) < 0
     T.tvcs_destroy(None)
 
