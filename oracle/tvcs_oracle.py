@@ -36,7 +36,8 @@ import numpy as np
 __all__ = [
     "D", "Dt", "project_disc", "shrink", "dtd_eigenvalues", "solve_u", "gradient",
     "lambda_max", "default_tau", "tv", "objective_tv", "huber_objective",
-    "OracleResult", "initial_u", "ftvcs", "ftvcs_continuation", "iadm", "bf16_rne", "split_bf16", "fp8_e4m3_values",
+    "OracleResult", "initial_u", "ftvcs", "ftvcs_continuation", "iadm", "bf16_rne",
+    "PartialDCT", "apply_A", "apply_At", "split_bf16", "fp8_e4m3_values",
     "fp8_e4m3_rne", "fp8_rowscale_quantize", "dequantized_A",
 ]
 
@@ -113,6 +114,51 @@ def solve_u(rhs: np.ndarray, c: float) -> np.ndarray:
     return np.real(np.fft.ifft2(spec / denom))
 
 
+class PartialDCT:
+    """A = P C as an operator: the rows `rows` (flat indices k_r * n + k_c) of the
+    orthonormal 2-D DCT-II C of n x n images, applied as fast transforms (Sec. 3.2:
+    m rows of the DCT matrix chosen at random, stored implicitly).  The rows of C are
+    orthonormal, so A A^T = I and A^T is the inverse DCT of the zero-filled
+    coefficients.  The transforms are scipy.fft.dctn / idctn (type 2, norm "ortho");
+    pinned against the DCT matrix written out from its cosine formula."""
+
+    def __init__(self, n: int, rows):
+        self.n = int(n)
+        self.rows = np.asarray(rows, dtype=np.int64)
+        self.shape = (len(self.rows), self.n * self.n)
+
+    def fwd(self, U: np.ndarray) -> np.ndarray:
+        """U (B, n^2) -> A U (B, m)."""
+        import scipy.fft
+        B, n = U.shape[0], self.n
+        X = scipy.fft.dctn(U.reshape(B, n, n), type=2, norm="ortho", axes=(1, 2))
+        return X.reshape(B, n * n)[:, self.rows]
+
+    def adj(self, R: np.ndarray) -> np.ndarray:
+        """R (B, m) -> A^T R (B, n^2)."""
+        import scipy.fft
+        B, n = R.shape[0], self.n
+        X = np.zeros((B, n * n))
+        X[:, self.rows] = R
+        return scipy.fft.idctn(X.reshape(B, n, n), type=2, norm="ortho",
+                               axes=(1, 2)).reshape(B, n * n)
+
+
+def _as_A(A):
+    """A dense matrix as FP64, or an operator object as it is."""
+    return A if isinstance(A, PartialDCT) else np.asarray(A, dtype=np.float64)
+
+
+def apply_A(A, U: np.ndarray) -> np.ndarray:
+    """A U for U (B, N): a dense product or the operator's forward transform."""
+    return A.fwd(U) if isinstance(A, PartialDCT) else U @ A.T
+
+
+def apply_At(A, R: np.ndarray) -> np.ndarray:
+    """A^T R for R (B, m)."""
+    return A.adj(R) if isinstance(A, PartialDCT) else R @ A
+
+
 def gradient(A: np.ndarray, u: np.ndarray, f: np.ndarray) -> np.ndarray:
     """g_k = A^T (A u^k - f), the gradient of 1/2 ||A u - f||^2 (eq. (line)).
 
@@ -120,8 +166,8 @@ def gradient(A: np.ndarray, u: np.ndarray, f: np.ndarray) -> np.ndarray:
     """
     B, n, _ = u.shape
     U = u.reshape(B, n * n)
-    R = U @ A.T - f            # (B, m): r_b = A u_b - f_b
-    G = R @ A                  # (B, N): g_b = A^T r_b
+    R = apply_A(A, U) - f      # (B, m): r_b = A u_b - f_b
+    G = apply_At(A, R)         # (B, N): g_b = A^T r_b
     return G.reshape(B, n, n)
 
 
@@ -135,7 +181,7 @@ def lambda_max(A: np.ndarray, iters: int = 100, rtol: float = 1e-10) -> float:
     v = np.full(N, 1.0 / np.sqrt(N))
     lam = 0.0
     for _ in range(iters):
-        w = A.T @ (A @ v)
+        w = apply_At(A, apply_A(A, v[None]))[0]
         new = float(v @ w)
         v = w / np.linalg.norm(w)
         if lam > 0 and abs(new - lam) <= rtol * new:
@@ -162,7 +208,7 @@ def tv(u: np.ndarray) -> np.ndarray:
 def objective_tv(u: np.ndarray, A: np.ndarray, f: np.ndarray, mu: float) -> np.ndarray:
     """sum_i ||D_i u|| + mu/2 ||A u - f||^2 per image (eq. (tv)); u (B,n,n), f (B,m)."""
     B, n, _ = u.shape
-    R = u.reshape(B, n * n) @ A.T - f
+    R = apply_A(A, u.reshape(B, n * n)) - f
     return tv(u) + 0.5 * mu * np.sum(R * R, axis=1)
 
 
@@ -178,7 +224,7 @@ def huber_objective(u: np.ndarray, A: np.ndarray, f: np.ndarray, mu: float,
     d = D(u)
     t = np.hypot(d[..., 0, :, :], d[..., 1, :, :])
     phi = np.where(t <= 1.0 / beta, 0.5 * beta * t * t, t - 0.5 / beta)
-    R = u.reshape(B, n * n) @ A.T - f
+    R = apply_A(A, u.reshape(B, n * n)) - f
     return phi.sum(axis=(-1, -2)) + 0.5 * mu * np.sum(R * R, axis=1)
 
 
@@ -204,7 +250,7 @@ def initial_u(A, f, n, u0):
     """u^0: A^T f by default (Alg. 1 and 2 print "u^0 = f", which has the wrong length)."""
     B = f.shape[0]
     if u0 is None:                                  # reading: u^0 = A^T f
-        return (f @ A).reshape(B, n, n)
+        return apply_At(A, f).reshape(B, n, n)
     return np.broadcast_to(np.asarray(u0, dtype=np.float64), (B, n, n)).copy()
 
 
@@ -215,7 +261,7 @@ def ftvcs(A, f, n, mu, beta, tau, tol=0.0, maxit=200, u0=None, record=None) -> O
     Each image of the batch stops on its own by the rule (eq. (stop)).
     `record(k, u)` is called after every iteration if given.
     """
-    A = np.asarray(A, dtype=np.float64)
+    A = _as_A(A)
     f = _as_batch(f)
     u = initial_u(A, f, n, u0)
     B = u.shape[0]
@@ -275,7 +321,7 @@ def iadm(A, f, n, mu, beta, tau, tol=0.0, maxit=200, u0=None, lam0=None, sign=+1
     sign=+1 uses the shrinkage centre D_i u^k + lambda_i^k / beta obtained by
     minimising (ALP) over w_i; sign=-1 uses the printed D_i u^k - lambda_i^k / beta.
     """
-    A = np.asarray(A, dtype=np.float64)
+    A = _as_A(A)
     f = _as_batch(f)
     u = initial_u(A, f, n, u0)
     B = u.shape[0]

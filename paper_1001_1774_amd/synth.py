@@ -163,6 +163,53 @@ def make_problem(name: str, n: int, ratio: float | None = None, m: int | None = 
                                             ramp=ramp))
 
 
+@dataclass
+class DctProblem:
+    """Seeded inputs for the partial-DCT operator: `rows` are the m selected flat
+    indices k_r * n + k_c of the orthonormal 2-D DCT-II of n x n images."""
+    name: str
+    n: int
+    m: int
+    rows: np.ndarray
+    ubar: np.ndarray
+    f: np.ndarray
+    sigma: np.ndarray
+    mu: float
+    beta: float
+    tau: float
+    seed_sel: int
+
+    @property
+    def N(self) -> int:
+        return self.n * self.n
+
+    @property
+    def B(self) -> int:
+        return self.f.shape[0]
+
+
+def make_dct_problem(name: str, n: int, ratio: float, batch: int = 1, seed_sel: int = 1006,
+                     n_shapes: int | None = None, sigma=1e-3, image_index0: int = 0,
+                     mu: float = 500.0, beta: float = 2.0 ** 6, tau: float = 1.9) -> DctProblem:
+    """m = round(ratio n^2) DCT coefficients chosen uniformly at random without
+    replacement (seed `seed_sel`), f = (DCT2 ubar)[rows] + sigma N(0, 1).  Defaults
+    follow the partial-DCT experiments: mu = 500, beta = 2^6, tau = 1.9."""
+    import scipy.fft
+    N = n * n
+    m = int(round(ratio * N))
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed_sel, 0xDC7])))
+    rows = np.sort(rng.choice(N, size=m, replace=False)).astype(np.int64)
+    sig = np.broadcast_to(np.asarray(sigma, dtype=np.float64), (batch,)).copy()
+    ubar = np.stack([image(n, IMAGE_SEED0 + image_index0 + i, n_shapes)
+                     for i in range(batch)])
+    X = scipy.fft.dctn(ubar, type=2, norm="ortho", axes=(1, 2)).reshape(batch, N)
+    f = X[:, rows].copy()
+    for i in range(batch):
+        f[i] += noise(m, image_index0 + i, sig[i])
+    return DctProblem(name=name, n=n, m=m, rows=rows, ubar=ubar, f=f, sigma=sig, mu=mu,
+                      beta=beta, tau=tau, seed_sel=seed_sel)
+
+
 # Named workloads (sizes of the paper's dense-A experiment range, Sec. 3.1).
 WORKLOADS = {
     # n = 32, m = 307 (30 %), 6 shapes: the small case the oracle runs in seconds.
