@@ -67,6 +67,9 @@ extern "C" {
                                    hi*x_lo + lo*x_hi on MFMA, 4 bytes/entry          */
 #define TVCS_A_FP8_ROWSCALE  3  /* s_i = max_j |A_ij| / 448 (FP32), q_ij = OCP E4M3
                                    nearest-even of A_ij / s_i; 1 byte/entry + 4/row  */
+#define TVCS_A_PARTIAL_DCT   4  /* no stored matrix: A = m rows of the orthonormal
+                                   2-D DCT-II, applied as fast transforms; only
+                                   through tvcs_create_dct                          */
 
 typedef struct tvcs_ctx *tvcs_handle;
 
@@ -106,6 +109,22 @@ tvcs_handle tvcs_create(const float *A, int m, int n);
 tvcs_handle tvcs_create_ex(const void *A, int a_is_fp64, int m, int n, int storage,
                            void *stream);
 
+/*
+ * tvcs_create_dct: the partial-DCT measurement operator of Sec. 3.2, A = P C with
+ * C the orthonormal 2-D DCT-II of n x n images (C[k_r n + k_c][r n + c] =
+ * w_{k_r} w_{k_c} cos(pi k_r (2r+1) / 2n) cos(pi k_c (2c+1) / 2n), w_0 = sqrt(1/n),
+ * w_k = sqrt(2/n)) and P the selection of the m coefficients rows[0..m-1]
+ * (host int array of flat indices k_r * n + k_c, distinct, any order; f[i]
+ * measures coefficient rows[i]).  A u and A^T r are computed as fast transforms
+ * in FP32 (no matrix is stored).  A A^T = I, so lambda_max(A^T A) = 1 exactly and
+ * the default tau is 1.9, the value of the partial-DCT experiments.  The caller
+ * keeps ownership of rows.  Storage is TVCS_A_PARTIAL_DCT.
+ * Returns NULL on error (see tvcs_last_error): rows NULL, m < 1 or m > n*n, an
+ * index outside [0, n*n) or repeated, n not a power of two in [8, 512], or out
+ * of device memory.
+ */
+tvcs_handle tvcs_create_dct(const int *rows, int m, int n, void *stream);
+
 /* Set the stream the handle's work is ordered on (hipStream_t or NULL). */
 int tvcs_set_stream(tvcs_handle h, void *stream);
 
@@ -114,7 +133,8 @@ int tvcs_set_tau(tvcs_handle h, double tau);
 
 /* Current tau and the power-iteration estimate of lambda_max(A^T A) for the
  * stored A (FP64 norms, start vector 1/sqrt(N), up to 100 steps or relative
- * Rayleigh-quotient change < 1e-10).  Return a negative value on error. */
+ * Rayleigh-quotient change < 1e-10; exactly 1 for the partial DCT).  Return a
+ * negative value on error. */
 double tvcs_get_tau(tvcs_handle h);
 double tvcs_lambda_max(tvcs_handle h);
 

@@ -146,6 +146,8 @@ tvcs_ctx *create_impl(const void *A, int a_is_fp64, int m, int n, int storage, v
     if (m < 1) fail(TVCS_EINVAL, "m must be >= 1");
     if (!pow2_in_range(n))
         fail(TVCS_EUNSUPPORTED, "n must be a power of two in [8, 512], got " + std::to_string(n));
+    if (storage == TVCS_A_PARTIAL_DCT)
+        fail(TVCS_EINVAL, "the partial-DCT operator is created with tvcs_create_dct");
     if (storage < TVCS_A_FP32 || storage > TVCS_A_FP8_ROWSCALE)
         fail(TVCS_EINVAL, "unknown storage format");
     if (storage != TVCS_A_FP32 && n < 16)
@@ -195,6 +197,47 @@ tvcs_ctx *create_impl(const void *A, int a_is_fp64, int m, int n, int storage, v
     return h.release();
 }
 
+tvcs_ctx *create_dct_impl(const int *rows, int m, int n, void *stream) {
+    if (!rows) fail(TVCS_EINVAL, "rows must not be NULL");
+    if (!pow2_in_range(n))
+        fail(TVCS_EUNSUPPORTED, "n must be a power of two in [8, 512], got " + std::to_string(n));
+    const int N = n * n;
+    if (m < 1 || m > N) fail(TVCS_EINVAL, "m must be in [1, n*n]");
+    // selT[k_c * n + k_r] = i for rows[i] = k_r * n + k_c (column-major, as the
+    // column pass reads it), -1 for coefficients that are not measured
+    std::vector<int> selT((size_t)N, -1);
+    for (int i = 0; i < m; ++i) {
+        const int p = rows[i];
+        if (p < 0 || p >= N)
+            fail(TVCS_EINVAL, "rows[" + std::to_string(i) + "] = " + std::to_string(p) +
+                                  " is outside [0, n*n)");
+        int &slot = selT[(size_t)(p % n) * n + p / n];
+        if (slot >= 0) fail(TVCS_EINVAL, "coefficient " + std::to_string(p) + " is repeated");
+        slot = i;
+    }
+    std::unique_ptr<tvcs_ctx> h(new tvcs_ctx());
+    h->m = m;
+    h->n = n;
+    h->N = N;
+    h->storage = TVCS_A_PARTIAL_DCT;
+    h->user = static_cast<hipStream_t>(stream);
+    TVCS_HIP(hipStreamCreateWithFlags(&h->work, hipStreamNonBlocking));
+    TVCS_HIP(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
+    TVCS_HIP(hipEventCreate(&h->ev_t0));
+    TVCS_HIP(hipEventCreate(&h->ev_t1));
+    h->begin_call();
+    h->selT.ensure(sizeof(int) * (size_t)N);
+    TVCS_HIP(hipMemcpyAsync(h->selT.p, selT.data(), sizeof(int) * (size_t)N, hipMemcpyHostToDevice,
+                            h->work));
+    h->dtab.ensure(sizeof(float4) * (size_t)n);
+    launch_dct_table(n, h->dtab.as<float4>(), h->work);
+    h->tw.ensure(sizeof(float2) * kMaxN);
+    launch_twiddles(h->tw.as<float2>(), h->work);
+    h->estimate_lambda_max();
+    TVCS_HIP(hipStreamSynchronize(h->work));   // selT's host copy goes out of scope
+    return h.release();
+}
+
 }  // namespace
 
 extern "C" {
@@ -208,6 +251,15 @@ tvcs_handle tvcs_create_ex(const void *A, int a_is_fp64, int m, int n, int stora
     tvcs_ctx *out = nullptr;
     const int rc = guarded([&] {
         out = create_impl(A, a_is_fp64, m, n, storage, stream);
+        return TVCS_OK;
+    });
+    return rc == TVCS_OK ? out : nullptr;
+}
+
+tvcs_handle tvcs_create_dct(const int *rows, int m, int n, void *stream) {
+    tvcs_ctx *out = nullptr;
+    const int rc = guarded([&] {
+        out = create_dct_impl(rows, m, n, stream);
         return TVCS_OK;
     });
     return rc == TVCS_OK ? out : nullptr;

@@ -1,0 +1,262 @@
+// The partial-DCT measurement operator (Sec. 3.2): A = P C, where C is the
+// orthonormal 2-D DCT-II of n x n images and P keeps m of its n^2 coefficients.
+// The rows of C are orthonormal, so A A^T = I, lambda_max(A^T A) = 1, and
+// A^T r = C^T (P^T r) is the inverse transform of the zero-filled coefficients.
+//
+// The 2-D transform is separable: X = C_n U C_n^T for the 1-D orthonormal DCT-II
+// matrix C_n.  Three passes, each a batch of 1-D transforms in LDS:
+//   rows_fwd : Y = U C_n^T (each row of u transformed), written column-major
+//              T[b][k_c][r] so that the next pass reads contiguous columns;
+//   cols     : X = C_n Y along r; the kept coefficients give r = X[sel] - f
+//              (written to R in measurement order); with the adjoint fused, the
+//              masked residual is transformed back along k_r in the same block
+//              (C_n^T along the columns), in place in T;
+//   rows_inv : G = T' C_n along each row, written row-major: g = A^T r.
+// Each 1-D DCT-II of length n is one complex FFT of length n (Makhoul, "A fast
+// cosine transform in one and multiple dimensions", IEEE TASSP 1980): reorder
+// v_j = x_{2j}, v_{n-1-j} = x_{2j+1}; V = FFT(v); X_k = w_k Re(e^{-i pi k/(2n)} V_k),
+// w_0 = sqrt(1/n), w_k = sqrt(2/n).  Its inverse rebuilds the Hermitian V from
+// V_k = e^{i pi k/(2n)} (X_k / w_k - i X_{n-k} / w_{n-k}) (X_n = 0), inverse FFT,
+// and undoes the reordering.  Two real lines share one complex transform (the
+// second line as the imaginary part), split again with the Hermitian symmetry.
+// The FFTs are the LDS Stockham FFTs of the u-step solve.
+#include "device_fft.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace tvcs {
+namespace {
+
+using namespace fftdev;
+
+// tab[k] = (w_k cos(pi k / 2n), -w_k sin(pi k / 2n), t_k cos(pi k / 2n), t_k sin(pi k / 2n))
+// with t_k = 1 / (n w_k): the forward weight w_k e^{-i pi k/(2n)} and the inverse
+// factor e^{i pi k/(2n)} / (n w_k) (the 1/n of the inverse FFT folded in).
+__global__ void k_dct_table(int n, float4 *tab) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double s, c;
+    sincospi((double)k / (2.0 * n), &s, &c);
+    const double w = k == 0 ? sqrt(1.0 / n) : sqrt(2.0 / n);
+    const double t = 1.0 / (n * w);
+    tab[k] = make_float4((float)(w * c), (float)(-w * s), (float)(t * c), (float)(t * s));
+}
+
+__device__ inline int makhoul_pos(int j, int n) {   // position of x_j in v
+    return (j & 1) ? n - 1 - (j >> 1) : (j >> 1);
+}
+__device__ inline int makhoul_src(int i, int n) {   // index j with v_i = x_j
+    return i < n / 2 ? 2 * i : 2 * (n - 1 - i) + 1;
+}
+
+struct DctLds {
+    float2 *tl;    // FFT twiddles (kMaxN)
+    float4 *dt;    // DCT table (n)
+    float2 *X, *Y; // FFT buffers, (lines / 2) * n complex each
+    float *A;      // real staging, lines * n
+};
+
+__device__ inline DctLds dct_lds(int n, int lines) {
+    extern __shared__ float2 lds[];
+    DctLds L;
+    L.tl = lds;
+    L.dt = reinterpret_cast<float4 *>(lds + kMaxN);
+    L.X = lds + kMaxN + 2 * n;
+    L.Y = L.X + (lines / 2) * n;
+    L.A = reinterpret_cast<float *>(L.Y + (lines / 2) * n);
+    return L;
+}
+
+size_t dct_lds_bytes(int n, int lines) {
+    return sizeof(float2) * (kMaxN + 2 * n + 2 * (lines / 2) * n) + sizeof(float) * lines * n;
+}
+
+__device__ inline void load_tables(const DctLds &L, int n, const float2 *tw, const float4 *tab) {
+    load_twiddles(L.tl, tw);
+    for (int k = threadIdx.x; k < n; k += kThreads) L.dt[k] = tab[k];
+}
+
+// Forward DCT-II of the `lines` real lines staged in L.X (already reordered, two
+// lines per complex transform).  Returns the FFT output buffer; the coefficient
+// k of line l is then dct_coef(Z, L, l, k).
+__device__ inline float dct_coef(const float2 *Z, const float4 *dt, int n, int l, int k) {
+    const float2 zk = Z[(l >> 1) * n + k], znk = Z[(l >> 1) * n + ((n - k) & (n - 1))];
+    float2 v;
+    if ((l & 1) == 0)   // V of the real part: (Z_k + conj Z_{n-k}) / 2
+        v = make_float2(0.5f * (zk.x + znk.x), 0.5f * (zk.y - znk.y));
+    else                // V of the imaginary part: (Z_k - conj Z_{n-k}) / (2i)
+        v = make_float2(0.5f * (zk.y + znk.y), -0.5f * (zk.x - znk.x));
+    const float4 t = dt[k];
+    return t.x * v.x - t.y * v.y;   // Re(w_k e^{-i pi k/(2n)} V_k)
+}
+
+// Inverse: coefficients of `lines` lines in L.A[l * n + k] -> spectra of the
+// reordered sequences, two lines per complex transform, in L.X; then the inverse
+// FFT.  Returns the buffer holding v (line l: component l & 1 of pair l >> 1).
+__device__ inline float2 *idct_lines(const DctLds &L, int n, int lines) {
+    const int ln = log2i(n), npair = lines >> 1;
+    for (int e = threadIdx.x; e < npair * n; e += kThreads) {
+        const int pr = e >> ln, k = e & (n - 1);
+        const float *a = L.A + (2 * pr) * n, *b = a + n;
+        const float ak = a[k], bk = b[k];
+        const float ank = k ? a[n - k] : 0.f, bnk = k ? b[n - k] : 0.f;
+        const float4 t = L.dt[k];
+        // V_a = t (a_k - i a_{n-k}), V_b likewise; Z = V_a + i V_b
+        const float2 va = make_float2(t.z * ak + t.w * ank, t.w * ak - t.z * ank);
+        const float2 vb = make_float2(t.z * bk + t.w * bnk, t.w * bk - t.z * bnk);
+        L.X[e] = make_float2(va.x - vb.y, va.y + vb.x);
+    }
+    __syncthreads();
+    return lds_fft<true>(L.X, L.Y, n, ln, npair, n, L.tl);
+}
+
+// rows_fwd: T[b][k][row] = (DCT-II of row `row` of u_b)_k, `lines` rows per block.
+__global__ __launch_bounds__(kThreads) void k_dct_rows_fwd(int n, int lines,
+                                                           const float *__restrict__ U,
+                                                           float *__restrict__ T,
+                                                           const float2 *__restrict__ tw,
+                                                           const float4 *__restrict__ tab,
+                                                           const ImgState *__restrict__ st) {
+    const int b = blockIdx.y;
+    if (st && !st[b].active) return;
+    const DctLds L = dct_lds(n, lines);
+    load_tables(L, n, tw, tab);
+    const int ln = log2i(n), N = n * n, row0 = blockIdx.x * lines;
+    const float *src = U + (size_t)b * N + (size_t)row0 * n;
+    float *Xf = reinterpret_cast<float *>(L.X);
+    for (int e = threadIdx.x; e < lines * n; e += kThreads) {
+        const int l = e >> ln, j = e & (n - 1);
+        Xf[2 * ((l >> 1) * n + makhoul_pos(j, n)) + (l & 1)] = src[e];
+    }
+    __syncthreads();
+    const float2 *Z = lds_fft<false>(L.X, L.Y, n, ln, lines >> 1, n, L.tl);
+    float *dst = T + (size_t)b * N + row0;
+    for (int e = threadIdx.x; e < lines * n; e += kThreads) {
+        const int k = e / lines, l = e - k * lines;
+        dst[(size_t)k * n + l] = dct_coef(Z, L.dt, n, l, k);
+    }
+}
+
+// cols: for the block's columns k_c of T (contiguous, indexed by r):
+//   FWD: X = DCT-II along r; for each kept coefficient (k_r, k_c), R[sel] = X - F[sel]
+//        (F may be null); without FWD the kept coefficients are read from R instead;
+//   ADJ: the zero-filled coefficients are transformed back along k_r into T.
+// selT[k_c * n + k_r] is the measurement index of coefficient k_r * n + k_c, or -1.
+template <bool FWD, bool ADJ>
+__global__ __launch_bounds__(kThreads) void k_dct_cols(int n, int lines, float *__restrict__ T,
+                                                       const int *__restrict__ selT,
+                                                       const float *__restrict__ F, int ldf,
+                                                       float *__restrict__ R, int ldr,
+                                                       const float2 *__restrict__ tw,
+                                                       const float4 *__restrict__ tab,
+                                                       const ImgState *__restrict__ st) {
+    const int b = blockIdx.y;
+    if (st && !st[b].active) return;
+    const DctLds L = dct_lds(n, lines);
+    load_tables(L, n, tw, tab);
+    const int ln = log2i(n), N = n * n, col0 = blockIdx.x * lines;
+    float *col = T + (size_t)b * N + (size_t)col0 * n;
+    const int *sel = selT + (size_t)col0 * n;
+    float *Rb = R + (size_t)b * ldr;
+    if (FWD) {
+        float *Xf = reinterpret_cast<float *>(L.X);
+        for (int e = threadIdx.x; e < lines * n; e += kThreads) {
+            const int l = e >> ln, j = e & (n - 1);
+            Xf[2 * ((l >> 1) * n + makhoul_pos(j, n)) + (l & 1)] = col[e];
+        }
+        __syncthreads();
+        const float2 *Z = lds_fft<false>(L.X, L.Y, n, ln, lines >> 1, n, L.tl);
+        const float *Fb = F ? F + (size_t)b * ldf : nullptr;
+        for (int e = threadIdx.x; e < lines * n; e += kThreads) {
+            const int l = e >> ln, k = e & (n - 1);
+            const int s = sel[e];
+            float rv = 0.f;
+            if (s >= 0) {
+                rv = dct_coef(Z, L.dt, n, l, k) - (Fb ? Fb[s] : 0.f);
+                Rb[s] = rv;
+            }
+            if (ADJ) L.A[e] = rv;
+        }
+    } else {
+        for (int e = threadIdx.x; e < lines * n; e += kThreads) {
+            const int s = sel[e];
+            L.A[e] = s >= 0 ? Rb[s] : 0.f;
+        }
+    }
+    if (!ADJ) return;
+    __syncthreads();
+    const float2 *v = idct_lines(L, n, lines);
+    for (int e = threadIdx.x; e < lines * n; e += kThreads) {
+        const int l = e >> ln, r = e & (n - 1);
+        const float2 z = v[(l >> 1) * n + makhoul_pos(r, n)];
+        col[e] = (l & 1) ? z.y : z.x;
+    }
+}
+
+// rows_inv: G[b][row][c] = (DCT-II^T along k_c of T[b][.][row])_c.
+__global__ __launch_bounds__(kThreads) void k_dct_rows_inv(int n, int lines,
+                                                           const float *__restrict__ T,
+                                                           float *__restrict__ G, int ldg,
+                                                           const float2 *__restrict__ tw,
+                                                           const float4 *__restrict__ tab,
+                                                           const ImgState *__restrict__ st) {
+    const int b = blockIdx.y;
+    if (st && !st[b].active) return;
+    const DctLds L = dct_lds(n, lines);
+    load_tables(L, n, tw, tab);
+    const int ln = log2i(n), N = n * n, row0 = blockIdx.x * lines;
+    const float *src = T + (size_t)b * N + row0;
+    for (int e = threadIdx.x; e < lines * n; e += kThreads) {
+        const int k = e / lines, l = e - k * lines;
+        L.A[l * n + k] = src[(size_t)k * n + l];
+    }
+    __syncthreads();
+    const float2 *v = idct_lines(L, n, lines);
+    float *dst = G + (size_t)b * ldg + (size_t)row0 * n;
+    for (int e = threadIdx.x; e < lines * n; e += kThreads) {
+        const int l = e >> ln, c = e & (n - 1);
+        const float2 z = v[(l >> 1) * n + makhoul_pos(c, n)];
+        dst[e] = (l & 1) ? z.y : z.x;
+    }
+}
+
+}  // namespace
+
+// Lines (rows or columns) per workgroup: 2048 values per block where the image
+// allows it, at least one pair.
+int dct_lines(int n) { return std::max(2, std::min(n, std::min(16, 2048 / n))); }
+
+void launch_dct_table(int n, float4 *tab, hipStream_t s) {
+    hipLaunchKernelGGL(k_dct_table, dim3((n + 255) / 256), dim3(256), 0, s, n, tab);
+}
+
+void launch_dct_forward(int n, int B, const float *U, float *T, const int *selT, const float *F,
+                        int ldf, float *R, int ldr, bool adjoint, const float2 *tw,
+                        const float4 *tab, const ImgState *st, hipStream_t s) {
+    const int lines = dct_lines(n);
+    const size_t lds = dct_lds_bytes(n, lines);
+    const dim3 grid(n / lines, B);
+    hipLaunchKernelGGL(k_dct_rows_fwd, grid, dim3(kThreads), lds, s, n, lines, U, T, tw, tab, st);
+    if (adjoint)
+        hipLaunchKernelGGL((k_dct_cols<true, true>), grid, dim3(kThreads), lds, s, n, lines, T,
+                           selT, F, ldf, R, ldr, tw, tab, st);
+    else
+        hipLaunchKernelGGL((k_dct_cols<true, false>), grid, dim3(kThreads), lds, s, n, lines, T,
+                           selT, F, ldf, R, ldr, tw, tab, st);
+}
+
+void launch_dct_adjoint(int n, int B, const float *R, int ldr, float *T, const int *selT,
+                        bool from_R, float *G, int ldg, const float2 *tw, const float4 *tab,
+                        const ImgState *st, hipStream_t s) {
+    const int lines = dct_lines(n);
+    const size_t lds = dct_lds_bytes(n, lines);
+    const dim3 grid(n / lines, B);
+    if (from_R)
+        hipLaunchKernelGGL((k_dct_cols<false, true>), grid, dim3(kThreads), lds, s, n, lines, T,
+                           selT, nullptr, 0, const_cast<float *>(R), ldr, tw, tab, st);
+    hipLaunchKernelGGL(k_dct_rows_inv, grid, dim3(kThreads), lds, s, n, lines, T, G, ldg, tw, tab,
+                       st);
+}
+
+}  // namespace tvcs

@@ -55,6 +55,7 @@ struct tvcs_ctx {
     hipEvent_t ev_in = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
 
     DevBuf A32;            // FP32 storage
+    DevBuf selT, dtab;     // partial DCT: measurement index per coefficient (k_c-major), DCT table
     LowpA lowp{};          // low-precision storage
     DevBuf lowp_mem;
     DevBuf tw;             // FFT twiddles
@@ -66,6 +67,7 @@ struct tvcs_ctx {
     int cap = 0, capP = 0;
     int gnv = 1;           // largest images-per-pass of the FP32 products
     DevBuf U, F, R, P, RHS, Q0, Q1, S, parts, state, obj, lowp_work, lamb, counters;
+    DevBuf DT;             // partial DCT: the half-transformed images between passes
     LowpWork lw{};
     ImgState *host_state = nullptr;   // pinned mirror for polling
     int host_state_cap = 0;
@@ -85,11 +87,16 @@ struct tvcs_ctx {
         if (work) (void)hipStreamDestroy(work);
     }
 
-    bool lowprec() const { return storage != TVCS_A_FP32; }
+    bool lowprec() const {
+        return storage == TVCS_A_BF16 || storage == TVCS_A_BF16_SPLIT ||
+               storage == TVCS_A_FP8_ROWSCALE;
+    }
+    bool dct() const { return storage == TVCS_A_PARTIAL_DCT; }
     double tau() const { return tau_user > 0 ? tau_user : 1.9 / lmax; }
 
     // padded batch: FP32 products take 1, 2, 4 or 8 vectors per pass of A
     int padded(int B) const {
+        if (dct()) return B;
         if (lowprec()) return ((B + kBTile - 1) / kBTile) * kBTile;
         if (B <= 2) return B;
         if (B <= 4) return 4;
@@ -104,8 +111,8 @@ struct tvcs_ctx {
         }
         const int Bp = padded(B);
         const size_t Nn = (size_t)N, mm = (size_t)m, h = (size_t)(n / 2 + 1);
-        gnv = lowprec() ? Bp : std::min(Bp, 8);
-        const int nchunk = lowprec() ? lowp_adj_splits(lowp) : chunks(Bp);
+        gnv = (lowprec() || dct()) ? Bp : std::min(Bp, 8);
+        const int nchunk = partial_count(Bp);
         U.ensure(sizeof(float) * Bp * Nn);
         F.ensure(sizeof(float) * Bp * mm);
         R.ensure(sizeof(float) * Bp * mm);
@@ -118,6 +125,7 @@ struct tvcs_ctx {
         state.ensure(sizeof(ImgState) * B);
         obj.ensure(sizeof(double) * B);
         counters.ensure(sizeof(int) * B);
+        if (dct()) DT.ensure(sizeof(float) * Bp * Nn);
         launch_fill(counters.as<float>(), (size_t)B, 0.f, work);   // all-zero bits
         if (lowprec()) {
             lowp_work.ensure(lowp_work_bytes(lowp, Bp));
@@ -143,22 +151,29 @@ struct tvcs_ctx {
     // every batch, so an image's g_k does not depend on the batch it is in.
     int pass_nv(int Bp) const { return std::min(Bp, 8); }
     int chunks(int /*Bp*/) const { return gemv_cols_chunks(m, N); }
+    // partial sums of A^T r the shrink pass adds (one for the DCT: its adjoint is whole)
+    int partial_count(int Bp) const {
+        return dct() ? 1 : lowprec() ? lowp_adj_splits(lowp) : chunks(Bp);
+    }
 
     // device bytes of the workspace ensure_workspace(B) allocates
     size_t workspace_bytes(int B) const {
         const int Bp = padded(B);
         const size_t Nn = (size_t)N, mm = (size_t)m, h = (size_t)(n / 2 + 1);
-        const int nchunk = lowprec() ? lowp_adj_splits(lowp) : chunks(Bp);
+        const int nchunk = partial_count(Bp);
         size_t b = sizeof(float) * Bp * (2 * Nn + 2 * mm) + sizeof(float) * (size_t)nchunk * Bp * Nn +
                    2 * sizeof(double) * 2 * B * Nn + sizeof(float2) * B * h * n +
                    sizeof(double) * 2 * B * (size_t)n + sizeof(ImgState) * B + sizeof(double) * B +
                    sizeof(int) * B;
         if (lowprec()) b += lowp_work_bytes(lowp, Bp);
+        if (dct()) b += sizeof(float) * Bp * Nn;
         return b;
     }
 
     // device bytes of A's storage and the FFT tables
-    size_t storage_bytes() const { return A32.bytes + lowp_mem.bytes + tw.bytes + invd.bytes; }
+    size_t storage_bytes() const {
+        return A32.bytes + lowp_mem.bytes + selT.bytes + dtab.bytes + tw.bytes + invd.bytes;
+    }
 
     // give the batch workspace back (the next call re-allocates what it needs)
     void release_workspace() {
@@ -167,7 +182,7 @@ struct tvcs_ctx {
             exec = nullptr;
         }
         for (DevBuf *b : {&U, &F, &R, &P, &RHS, &Q0, &Q1, &S, &parts, &state, &obj, &lowp_work, &lamb,
-                          &counters})
+                          &counters, &DT})
             b->release();
         cap = capP = 0;
     }
@@ -184,6 +199,11 @@ struct tvcs_ctx {
     // R = A U - F for the first Bp images (F may be null)
     void apply_A(int Bp, int B, const float *Uin, const float *Fin, float *Rout,
                  const ImgState *st) {
+        if (dct()) {
+            launch_dct_forward(n, B, Uin, DT.as<float>(), selT.as<int>(), Fin, m, Rout, m, false,
+                               tw.as<float2>(), dtab.as<float4>(), st, work);
+            return;
+        }
         if (lowprec()) {
             lowp_apply_A(lowp, lw, B, Uin, Fin, Rout, st, work);
             return;
@@ -201,6 +221,11 @@ struct tvcs_ctx {
 
     // partial sums of A^T Rin into P (layout described by shrink_args)
     void apply_At(int Bp, int B, const float *Rin, const ImgState *st) {
+        if (dct()) {
+            launch_dct_adjoint(n, B, Rin, m, DT.as<float>(), selT.as<int>(), true, P.as<float>(), N,
+                               tw.as<float2>(), dtab.as<float4>(), st, work);
+            return;
+        }
         if (lowprec()) {
             lowp_apply_At(lowp, lw, B, Rin, P.as<float>(), st, work);
             return;
@@ -218,6 +243,11 @@ struct tvcs_ctx {
 
     // out = A^T Rin (full sums) for the first Bp images
     void apply_At_full(int Bp, int B, const float *Rin, float *out, const ImgState *st) {
+        if (dct()) {
+            launch_dct_adjoint(n, B, Rin, m, DT.as<float>(), selT.as<int>(), true, out, N,
+                               tw.as<float2>(), dtab.as<float4>(), st, work);
+            return;
+        }
         apply_At(Bp, B, Rin, st);
         if (lowprec()) {
             launch_sum_partials(P.as<float>(), lowp_adj_splits(lowp), (long long)Bp * N, Bp, N,
@@ -237,10 +267,10 @@ struct tvcs_ctx {
         a.B = B;
         a.U = U.as<float>();
         a.G = P.as<float>();
-        if (lowprec()) {
+        if (lowprec() || dct()) {
             a.gnv = Bp;
             a.g_group_stride = 0;
-            a.nchunk = lowp_adj_splits(lowp);
+            a.nchunk = partial_count(Bp);
             a.g_chunk_stride = (long long)Bp * N;
         } else {
             const int nv = pass_nv(Bp), nchunk = chunks(Bp);
@@ -256,8 +286,18 @@ struct tvcs_ctx {
     void enqueue_iteration(int B, int parity, bool iadm, double beta, double c, double ctau) {
         const int Bp = padded(B);
         ImgState *st = state.as<ImgState>();
-        apply_A(Bp, B, U.as<float>(), F.as<float>(), R.as<float>(), st);
-        apply_At(Bp, B, R.as<float>(), st);
+        if (dct()) {
+            // forward and adjoint share the column pass: r = (C u)[sel] - f and the
+            // zero-filled residual's inverse column transform in one kernel
+            launch_dct_forward(n, B, U.as<float>(), DT.as<float>(), selT.as<int>(), F.as<float>(),
+                               m, R.as<float>(), m, true, tw.as<float2>(), dtab.as<float4>(), st,
+                               work);
+            launch_dct_adjoint(n, B, R.as<float>(), m, DT.as<float>(), selT.as<int>(), false,
+                               P.as<float>(), N, tw.as<float2>(), dtab.as<float4>(), st, work);
+        } else {
+            apply_A(Bp, B, U.as<float>(), F.as<float>(), R.as<float>(), st);
+            apply_At(Bp, B, R.as<float>(), st);
+        }
         ShrinkArgs a = shrink_args(B, Bp);
         a.beta = beta;
         a.c = c;
@@ -313,6 +353,10 @@ struct tvcs_ctx {
     }
 
     void estimate_lambda_max() {
+        if (dct()) {   // A A^T = I: the nonzero eigenvalues of A^T A are all 1
+            lmax = 1.0;
+            return;
+        }
         ensure_workspace(1);
         const int Bp = padded(1);
         ImgState *st = state.as<ImgState>();
@@ -334,7 +378,7 @@ struct tvcs_ctx {
     }
 
     size_t device_bytes() const {
-        return A32.bytes + lowp_mem.bytes + tw.bytes + invd.bytes + U.bytes + F.bytes + R.bytes +
+        return A32.bytes + lowp_mem.bytes + selT.bytes + dtab.bytes + DT.bytes + tw.bytes + invd.bytes + U.bytes + F.bytes + R.bytes +
                P.bytes + RHS.bytes + Q0.bytes + Q1.bytes + S.bytes + parts.bytes + state.bytes +
                obj.bytes + lowp_work.bytes + lamb.bytes + counters.bytes;
     }

@@ -158,6 +158,24 @@ void lowp_apply_At(const LowpA &L, LowpWork &W, int B, const float *R, float *G,
 void lowp_autotune(const LowpA &L, LowpWork &W, int Bp, const float *U, float *R, float *G,
                    hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Partial-DCT operator (dct.hip): A = rows of the orthonormal 2-D DCT-II.
+// T is a B x N work array (column-major half transforms); selT[k_c * n + k_r] is
+// the measurement index of coefficient k_r * n + k_c, or -1 when it is not kept.
+// ---------------------------------------------------------------------------
+int dct_lines(int n);                                // lines per workgroup of the passes
+void launch_dct_table(int n, float4 *tab, hipStream_t s);
+// R[b*ldr + i] = (C u_b)[sel_i] - F[b*ldf + i] (F may be null); with `adjoint`, T is
+// left holding the inverse column transform of the zero-filled residual, ready for
+// launch_dct_adjoint(..., from_R = false, ...)
+void launch_dct_forward(int n, int B, const float *U, float *T, const int *selT, const float *F,
+                        int ldf, float *R, int ldr, bool adjoint, const float2 *tw,
+                        const float4 *tab, const ImgState *st, hipStream_t s);
+// G[b*ldg + p] = (A^T r_b)_p; from_R: scatter R first, else continue from T
+void launch_dct_adjoint(int n, int B, const float *R, int ldr, float *T, const int *selT,
+                        bool from_R, float *G, int ldg, const float2 *tw, const float4 *tab,
+                        const ImgState *st, hipStream_t s);
+
 // achievable HBM read bandwidth (GB/s) and dense bf16 MFMA rate (TFLOP/s)
 void measure_peaks(size_t bytes, int reps, double *read_gbs, double *mfma_tflops);
 

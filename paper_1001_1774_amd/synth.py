@@ -191,14 +191,18 @@ class DctProblem:
 def make_dct_problem(name: str, n: int, ratio: float, batch: int = 1, seed_sel: int = 1006,
                      n_shapes: int | None = None, sigma=1e-3, image_index0: int = 0,
                      mu: float = 500.0, beta: float = 2.0 ** 6, tau: float = 1.9) -> DctProblem:
-    """m = round(ratio n^2) DCT coefficients chosen uniformly at random without
-    replacement (seed `seed_sel`), f = (DCT2 ubar)[rows] + sigma N(0, 1).  Defaults
-    follow the partial-DCT experiments: mu = 500, beta = 2^6, tau = 1.9."""
+    """m = round(ratio n^2) DCT coefficients: the DC term and m - 1 others chosen
+    uniformly at random without replacement (seed `seed_sel`), f = (DCT2 ubar)[rows]
+    + sigma N(0, 1).  Defaults follow the partial-DCT experiments: mu = 500,
+    beta = 2^6, tau = 1.9."""
     import scipy.fft
     N = n * n
     m = int(round(ratio * N))
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed_sel, 0xDC7])))
-    rows = np.sort(rng.choice(N, size=m, replace=False)).astype(np.int64)
+    # the DC coefficient is always kept: TV and the other DCT rows both vanish on
+    # constant images, so without it the image mean could not be recovered
+    rest = 1 + rng.choice(N - 1, size=m - 1, replace=False)
+    rows = np.sort(np.concatenate([[0], rest])).astype(np.int64)
     sig = np.broadcast_to(np.asarray(sigma, dtype=np.float64), (batch,)).copy()
     ubar = np.stack([image(n, IMAGE_SEED0 + image_index0 + i, n_shapes)
                      for i in range(batch)])

@@ -38,6 +38,7 @@ TVCS_A_FP32 = 0
 TVCS_A_BF16 = 1
 TVCS_A_BF16_SPLIT = 2
 TVCS_A_FP8_ROWSCALE = 3
+TVCS_A_PARTIAL_DCT = 4
 
 STORAGE = {"fp32": TVCS_A_FP32, "bf16": TVCS_A_BF16, "bf16_split": TVCS_A_BF16_SPLIT,
            "fp8_rowscale": TVCS_A_FP8_ROWSCALE}
@@ -62,6 +63,8 @@ _SIGS = {
     "tvcs_create": (ctypes.c_void_p, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "tvcs_create_ex": (ctypes.c_void_p, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
+    "tvcs_create_dct": (ctypes.c_void_p, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_void_p]),
     "tvcs_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "tvcs_set_tau": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
     "tvcs_get_tau": (ctypes.c_double, [ctypes.c_void_p]),
@@ -154,6 +157,14 @@ def tvcs_create(A, m, n):
 def tvcs_create_ex(A, a_is_fp64, m, n, storage, stream=None):
     dt = torch.float64 if a_is_fp64 else torch.float32
     return lib().tvcs_create_ex(_ptr(A, dt), int(a_is_fp64), m, n, int(storage), _stream(stream))
+
+
+def tvcs_create_dct(rows, m, n, stream=None):
+    """rows: C-contiguous int32 numpy array of m flat coefficient indices."""
+    if not (isinstance(rows, np.ndarray) and rows.dtype == np.int32 and rows.flags["C_CONTIGUOUS"]):
+        raise TypeError("rows must be a C-contiguous int32 numpy array")
+    return lib().tvcs_create_dct(ctypes.c_void_p(rows.ctypes.data), int(m), int(n),
+                                 _stream(stream))
 
 
 def tvcs_set_stream(h, stream):
@@ -288,6 +299,20 @@ class Solver:
         self.h = tvcs_create_ex(A, is64, self.m, self.n, self.storage, stream)
         if not self.h:
             raise TvcsError(-1, tvcs_last_error())
+
+    @classmethod
+    def partial_dct(cls, rows, n, device="cuda", stream=None):
+        """The partial-DCT operator: f[i] measures coefficient rows[i] = k_r * n + k_c
+        of the orthonormal 2-D DCT-II of the n x n image (no matrix is stored)."""
+        rows = np.ascontiguousarray(np.asarray(rows), dtype=np.int32)
+        self = cls.__new__(cls)
+        self.m, self.n, self.N = int(rows.shape[0]), int(n), int(n) * int(n)
+        self.device = torch.device(device)
+        self.storage = TVCS_A_PARTIAL_DCT
+        self.h = tvcs_create_dct(rows, self.m, self.n, stream)
+        if not self.h:
+            raise TvcsError(-1, tvcs_last_error())
+        return self
 
     def close(self):
         if getattr(self, "h", None):

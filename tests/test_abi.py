@@ -83,6 +83,26 @@ def test_argument_errors_without_device(clib):
     assert "null handle" in T.tvcs_last_error()
     assert T.tvcs_measure_peaks(1024, 1) == T.TVCS_EINVAL
     assert T.tvcs_measure_peaks(1 << 30, 0) == T.TVCS_EINVAL
+    # partial DCT: the coefficient list is checked on the host first
+    assert not T.tvcs_create_ex(A, 0, 4, 8, T.TVCS_A_PARTIAL_DCT, None)
+    assert "tvcs_create_dct" in T.tvcs_last_error()
+    assert not T.lib().tvcs_create_dct(None, 4, 8, None)
+    assert "rows" in T.tvcs_last_error()
+    rows = np.array([0, 5, 63], np.int32)
+    assert not T.tvcs_create_dct(rows, 3, 12)
+    assert "power of two" in T.tvcs_last_error()
+    assert not T.tvcs_create_dct(rows, 0, 8)
+    assert "m must be" in T.tvcs_last_error()
+    assert not T.tvcs_create_dct(np.zeros(65, np.int32), 65, 8)
+    assert "m must be" in T.tvcs_last_error()
+    assert not T.tvcs_create_dct(np.array([0, 64], np.int32), 2, 8)
+    assert "outside" in T.tvcs_last_error()
+    assert not T.tvcs_create_dct(np.array([3, -1], np.int32), 2, 8)
+    assert "outside" in T.tvcs_last_error()
+    assert not T.tvcs_create_dct(np.array([7, 9, 7], np.int32), 3, 8)
+    assert "repeated" in T.tvcs_last_error()
+    with pytest.raises(TypeError):
+        T.tvcs_create_dct(np.array([1, 2], np.int64), 2, 8)
     assert T.tvcs_get_tau(None) < 0
     T.tvcs_destroy(None)
 

@@ -1,0 +1,159 @@
+"""GPU parity of the partial-DCT operator (Sec. 3.2) against the FP64 oracle's
+PartialDCT (scipy's orthonormal dctn / idctn, pinned to the cosine matrix).
+
+The operator runs in FP32 on the device: each 2-D transform errs by about
+log2(n) eps32 of its input's norm, the same order as the FP32 FFT solve, so the
+bar of the dense FP32 path applies: relative iterate error <= 1e-5 after a fixed
+number of iterations, with tau = 1.9 on both sides.  A single step isolates the
+products: from a given u^k, u^{k+1} depends on A u^k and A^T (A u^k - f) through
+c tau g, so a one-step error at the 1e-6 level checks both transforms.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1001_1774_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_U = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    from paper_1001_1774_amd import tvcs
+    tvcs.lib()
+    return tvcs
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def op(p):
+    return O.PartialDCT(p.n, p.rows)
+
+
+def test_operator_constants(T):
+    p = synth.make_dct_problem("d", 32, 0.3)
+    with T.Solver.partial_dct(p.rows, p.n) as s:
+        assert s.lambda_max == 1.0
+        assert s.tau == 1.9
+        assert s.storage == T.TVCS_A_PARTIAL_DCT
+
+
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 256, 512])
+def test_one_step_products(T, n):
+    """One FTVCS step from a noisy u^k (forward and adjoint products), one from
+    u^0 = A^T f (the adjoint from R alone), and the objective (forward alone)."""
+    p = synth.make_dct_problem("d", n, 0.3, n_shapes=max(3, min(40, n // 6)))
+    A = op(p)
+    rng = np.random.default_rng(n)
+    u0 = (p.ubar[0] + 0.05 * rng.standard_normal((n, n))).astype(np.float32)
+    f32 = p.f[0].astype(np.float32)
+    say(f"case n={n} m={p.m} one step")
+    with T.Solver.partial_dct(p.rows, n) as s:
+        out = s.solve(f32, mu=p.mu, beta=p.beta, maxit=1, u0=u0, objective=True)
+        ref = O.ftvcs(A, f32.astype(np.float64)[None], n, p.mu, p.beta, p.tau, tol=0, maxit=1,
+                      u0=u0.astype(np.float64))
+        e = rel(out["u"].cpu().numpy(), ref.u[0])
+        obj = O.objective_tv(out["u"].cpu().numpy().astype(np.float64)[None], A,
+                             f32.astype(np.float64)[None], p.mu)[0]
+        eo = abs(out["stats"]["objective"] - obj) / obj
+        say(f"  warm step rel err {e:.3e}, objective rel err {eo:.3e}")
+        assert e <= 2e-6
+        assert eo <= 1e-6
+        out = s.solve(f32, mu=p.mu, beta=p.beta, maxit=1)
+        ref = O.ftvcs(A, f32.astype(np.float64)[None], n, p.mu, p.beta, p.tau, tol=0, maxit=1)
+        e = rel(out["u"].cpu().numpy(), ref.u[0])
+        say(f"  step from A^T f rel err {e:.3e}")
+        assert e <= 2e-6
+
+
+@pytest.mark.parametrize("iadm", [False, True], ids=["ftvcs", "iadm"])
+@pytest.mark.parametrize("n,ratio,K", [(8, 0.5, 60), (32, 0.3, 200), (64, 0.3, 150),
+                                       (128, 0.3, 200), (256, 0.3, 60)])
+def test_parity_fixed_iterations(T, n, ratio, K, iadm):
+    p = synth.make_dct_problem("d", n, ratio, n_shapes=max(3, min(40, n // 6)))
+    say(f"case n={n} m={p.m} K={K} iadm={iadm}")
+    f32 = p.f.astype(np.float32)
+    alg = O.iadm if iadm else O.ftvcs
+    ref = alg(op(p), f32.astype(np.float64), n, p.mu, p.beta, p.tau, tol=0, maxit=K)
+    with T.Solver.partial_dct(p.rows, n) as s:
+        out = s.solve(f32[0], mu=p.mu, beta=p.beta, maxit=K, iadm=iadm, want_lambda=iadm)
+    assert out["stats"]["iters"] == K
+    e = rel(out["u"].cpu().numpy(), ref.u[0])
+    say(f"  rel err u = {e:.3e}")
+    assert e <= TOL_U
+    if iadm:
+        el = rel(out["lam"].cpu().numpy(), ref.lam[0])
+        say(f"  rel err lambda = {el:.3e}")
+        assert el <= 1e-4
+
+
+def test_table1_setting_stop_rule(T):
+    """The partial-DCT comparison setting: 128 x 128, 30 % of the coefficients,
+    sigma = 1e-3, IADM with tau = 1.9, beta = 2^6, mu = 500, tol = 5e-5."""
+    p = synth.make_dct_problem("table1", 128, 0.3)
+    f32 = p.f.astype(np.float32)
+    ref = O.iadm(op(p), f32.astype(np.float64), p.n, p.mu, p.beta, p.tau, tol=5e-5, maxit=6000)
+    with T.Solver.partial_dct(p.rows, p.n) as s:
+        out = s.solve(f32[0], mu=p.mu, beta=p.beta, tol=5e-5, maxit=6000, iadm=True)
+    it, it_ref = out["stats"]["iters"], int(ref.iters[0])
+    e = rel(out["u"].cpu().numpy(), ref.u[0])
+    err_truth = rel(out["u"].cpu().numpy(), p.ubar[0])
+    say(f"  iterations {it} (oracle {it_ref}), rel err vs oracle {e:.3e}, vs truth {err_truth:.3e}")
+    assert out["stats"]["status"] == T.TVCS_OK
+    assert abs(it - it_ref) <= max(2, it_ref // 100)
+    assert e <= 1e-4
+
+
+def test_batch_equals_single(T):
+    p = synth.make_dct_problem("d", 64, 0.3, batch=5, sigma=[1e-3, 1e-2, 0.0, 1e-3, 5e-3])
+    f32 = p.f.astype(np.float32)
+    with T.Solver.partial_dct(p.rows, p.n) as s:
+        out = s.solve_batch(f32, mu=p.mu, beta=p.beta, tol=1e-4, maxit=400, iadm=True)
+        U = out["u"].cpu().numpy()
+        for b in (0, 3, 4):
+            alone = s.solve(f32[b], mu=p.mu, beta=p.beta, tol=1e-4, maxit=400, iadm=True)
+            assert np.array_equal(alone["u"].cpu().numpy(), U[b])
+            assert alone["stats"]["iters"] == out["stats"][b]["iters"]
+    say("  iterations per image", [st["iters"] for st in out["stats"]])
+
+
+def test_unsorted_rows_are_the_same_operator(T):
+    """f[i] measures rows[i] in whatever order the caller lists the coefficients."""
+    p = synth.make_dct_problem("d", 32, 0.3)
+    perm = np.random.default_rng(3).permutation(p.m)
+    f32 = p.f[0].astype(np.float32)
+    with T.Solver.partial_dct(p.rows, p.n) as s:
+        a = s.solve(f32, mu=p.mu, beta=p.beta, maxit=30, iadm=True)["u"].cpu().numpy()
+    with T.Solver.partial_dct(p.rows[perm], p.n) as s:
+        b = s.solve(f32[perm], mu=p.mu, beta=p.beta, maxit=30, iadm=True)["u"].cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_n512_ratio03_b16_sampled_images(T):
+    """Full size: 512 x 512, 30 % of the coefficients, 16 images in one batch; two
+    of them against the oracle after 20 IADM iterations."""
+    p = synth.make_dct_problem("n512", 512, 0.3, batch=16)
+    f32 = p.f.astype(np.float32)
+    K, sample = 20, [0, 11]
+    say(f"case n=512 m={p.m} B=16 K={K}")
+    with T.Solver.partial_dct(p.rows, p.n) as s:
+        out = s.solve_batch(f32, mu=p.mu, beta=p.beta, maxit=K, iadm=True)
+    U = out["u"].cpu().numpy()
+    ref = O.iadm(op(p), f32[sample].astype(np.float64), p.n, p.mu, p.beta, p.tau, tol=0, maxit=K)
+    for j, b in enumerate(sample):
+        e = rel(U[b], ref.u[j])
+        say(f"  image {b}: rel err {e:.3e}")
+        assert e <= TOL_U

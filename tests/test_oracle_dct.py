@@ -61,5 +61,6 @@ def test_dct_problem_measurements():
     """f = A ubar + noise with A the partial DCT; the selected rows are distinct."""
     p = synth.make_dct_problem("d16", n=16, ratio=0.3, batch=2, seed_sel=9, sigma=0.0)
     assert len(np.unique(p.rows)) == p.m == round(0.3 * 256)
+    assert p.rows[0] == 0                      # the DC coefficient is always measured
     A = dense_partial_dct(16, p.rows)
     assert np.abs(p.f - p.ubar.reshape(2, -1) @ A.T).max() <= 1e-12
