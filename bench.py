@@ -71,6 +71,7 @@ def main():
     ap.add_argument("--large", action="store_true",
                     help="add the n = 512, m = 26214, B = 128 section (FP8 vs BF16 storage)")
     ap.add_argument("--large-iters", type=int, default=300)
+    ap.add_argument("--no-dct", action="store_true", help="skip the partial-DCT section")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py measures one GPU: the method's images are "
@@ -188,6 +189,8 @@ def main():
         out["serving"] = bench_serving(args, np, synth, tvcs)
     if args.large:
         out["large_n512"] = bench_large(args, np, torch, synth, tvcs)
+    if not args.no_dct:
+        out["partial_dct"] = bench_dct(args, np, torch, O, synth, tvcs)
     print(json.dumps(out), flush=True)
 
 
@@ -364,6 +367,70 @@ def bench_large(args, np, torch, synth, tvcs):
         res[storage] = {"rec_per_s": p.B / dt, "ms_per_iter": 1e3 * dt / K,
                         **product_rates(storage, p.m, p.N, p.B, ms_f, ms_a)}
         log(f"{storage} n=512 B=128: {1e3 * dt / K:.3f} ms/iter")
+    return res
+
+
+def dct_product_bytes(n, m, B):
+    """Bytes each partial-DCT product moves per launch: every pass reads and writes
+    one n x n FP32 array per image; the column pass also reads the coefficient map
+    (4 n^2 bytes, shared by the batch) and f and writes r (forward), or reads r
+    (adjoint)."""
+    N = n * n
+    fwd = B * (8.0 * N + 8.0 * N + 8.0 * m) + 4.0 * N
+    adj = B * (4.0 * m + 4.0 * N + 8.0 * N) + 4.0 * N
+    return fwd, adj
+
+
+def bench_dct(args, np, torch, O, synth, tvcs):
+    """The partial-DCT operator (Sec. 3.2): 30 % of the orthonormal 2-D DCT-II
+    coefficients (the DC term and the rest uniformly at random), IADM with
+    tau = 1.9, beta = 2^6, mu = 500.
+      * 128 x 128, one image, tol = 5e-5 (the comparison setting): time, iterations
+        and error against the ground truth; a fixed-iteration run against the oracle;
+      * images of 128^2, 256^2 and 512^2 in batches: ms per iteration and the rate
+        of the two products (HIP events, bytes per launch as in dct_product_bytes)."""
+    res = {}
+    p = synth.make_dct_problem("dct128_r30", 128, 0.3)
+    f = torch.from_numpy(p.f[0].astype(np.float32)).cuda()
+    K = 300
+    with tvcs.Solver.partial_dct(p.rows, p.n) as s:
+        s.solve(f, mu=p.mu, beta=p.beta, tol=5e-5, maxit=6000, iadm=True)    # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = s.solve(f, mu=p.mu, beta=p.beta, tol=5e-5, maxit=6000, iadm=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        u = out["u"].cpu().numpy().astype(np.float64)
+        it = out["stats"]["iters"]
+        fixed = s.solve(f, mu=p.mu, beta=p.beta, maxit=K, iadm=True)["u"].cpu().numpy()
+    ref = O.iadm(O.PartialDCT(p.n, p.rows), p.f[:1].astype(np.float32).astype(np.float64),
+                 p.n, p.mu, p.beta, p.tau, tol=0, maxit=K)
+    res["n128_r30_tol5e-5"] = {
+        "iterations": it, "seconds": dt, "ms_per_iter": 1e3 * dt / it,
+        "rel_err_vs_truth": float(np.linalg.norm(u - p.ubar[0]) / np.linalg.norm(p.ubar[0])),
+        f"rel_err_vs_fp64_oracle_{K}_iters": float(np.linalg.norm(fixed - ref.u[0]) /
+                                                   np.linalg.norm(ref.u[0]))}
+    log(f"partial DCT 128^2 tol 5e-5: {it} iterations in {dt * 1e3:.1f} ms")
+    for n, B, Kb in ((128, 1, 500), (128, 64, 300), (256, 64, 200), (512, 16, 100),
+                     (512, 64, 100)):
+        q = synth.make_dct_problem(f"dct{n}_b{B}", n, 0.3, batch=B)
+        F = torch.from_numpy(q.f.astype(np.float32)).cuda()
+        with tvcs.Solver.partial_dct(q.rows, n) as s:
+            s.solve_batch(F, mu=q.mu, beta=q.beta, maxit=10, iadm=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.solve_batch(F, mu=q.mu, beta=q.beta, maxit=Kb, iadm=True)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ms_f, ms_a = s.time_products(B=B, reps=20)
+        bf, ba = dct_product_bytes(n, q.m, B)
+        key = f"n{n}_b{B}"
+        res[key] = {"m": q.m, "iterations": Kb, "ms_per_iter": 1e3 * dt / Kb,
+                    "image_iters_per_s": B * Kb / dt, "rec_per_s_at_300_iters": B * Kb / dt / 300,
+                    "forward_ms": ms_f, "adjoint_ms": ms_a,
+                    "forward_gbs": bf / (ms_f * 1e-3) / 1e9, "adjoint_gbs": ba / (ms_a * 1e-3) / 1e9}
+        log(f"partial DCT n={n} B={B}: {1e3 * dt / Kb:.3f} ms/iter, products "
+            f"{ms_f * 1e3:.1f} / {ms_a * 1e3:.1f} us")
     return res
 
 

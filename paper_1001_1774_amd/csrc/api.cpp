@@ -58,8 +58,7 @@ int solve_impl(tvcs_ctx *h, const float *Fin, int B, double mu, double beta, dou
     const double c = mu / (beta * tau), ctau = mu / beta;
     TVCS_HIP(hipEventRecord(h->ev_t0, h->work));
 
-    TVCS_HIP(hipMemcpyAsync(h->F.p, Fin, sizeof(float) * (size_t)B * m, hipMemcpyDefault,
-                            h->work));
+    h->load_measurements(Fin, 0, B);
     h->ensure_denominators(c);
     ImgState *st = h->state.as<ImgState>();
     launch_init_state(st, B, tol, maxit, h->work);
@@ -203,18 +202,25 @@ tvcs_ctx *create_dct_impl(const int *rows, int m, int n, void *stream) {
         fail(TVCS_EUNSUPPORTED, "n must be a power of two in [8, 512], got " + std::to_string(n));
     const int N = n * n;
     if (m < 1 || m > N) fail(TVCS_EINVAL, "m must be in [1, n*n]");
-    // selT[k_c * n + k_r] = i for rows[i] = k_r * n + k_c (column-major, as the
-    // column pass reads it), -1 for coefficients that are not measured
-    std::vector<int> selT((size_t)N, -1);
+    // which[k_c * n + k_r] = i for rows[i] = k_r * n + k_c, -1 if not measured
+    std::vector<int> which((size_t)N, -1);
     for (int i = 0; i < m; ++i) {
         const int p = rows[i];
         if (p < 0 || p >= N)
             fail(TVCS_EINVAL, "rows[" + std::to_string(i) + "] = " + std::to_string(p) +
                                   " is outside [0, n*n)");
-        int &slot = selT[(size_t)(p % n) * n + p / n];
+        int &slot = which[(size_t)(p % n) * n + p / n];
         if (slot >= 0) fail(TVCS_EINVAL, "coefficient " + std::to_string(p) + " is repeated");
         slot = i;
     }
+    // positions in the column pass's order (k_c-major): selT[q] = position of
+    // coefficient q, perm[position] = measurement index
+    std::vector<int> selT((size_t)N, -1), perm((size_t)m);
+    for (int q = 0, j = 0; q < N; ++q)
+        if (which[q] >= 0) {
+            selT[q] = j;
+            perm[j++] = which[q];
+        }
     std::unique_ptr<tvcs_ctx> h(new tvcs_ctx());
     h->m = m;
     h->n = n;
@@ -229,12 +235,15 @@ tvcs_ctx *create_dct_impl(const int *rows, int m, int n, void *stream) {
     h->selT.ensure(sizeof(int) * (size_t)N);
     TVCS_HIP(hipMemcpyAsync(h->selT.p, selT.data(), sizeof(int) * (size_t)N, hipMemcpyHostToDevice,
                             h->work));
+    h->dperm.ensure(sizeof(int) * (size_t)m);
+    TVCS_HIP(hipMemcpyAsync(h->dperm.p, perm.data(), sizeof(int) * (size_t)m,
+                            hipMemcpyHostToDevice, h->work));
     h->dtab.ensure(sizeof(float4) * (size_t)n);
     launch_dct_table(n, h->dtab.as<float4>(), h->work);
     h->tw.ensure(sizeof(float2) * kMaxN);
     launch_twiddles(h->tw.as<float2>(), h->work);
     h->estimate_lambda_max();
-    TVCS_HIP(hipStreamSynchronize(h->work));   // selT's host copy goes out of scope
+    TVCS_HIP(hipStreamSynchronize(h->work));   // the host tables go out of scope
     return h.release();
 }
 

@@ -7,8 +7,10 @@
 // matrix C_n.  Three passes, each a batch of 1-D transforms in LDS:
 //   rows_fwd : Y = U C_n^T (each row of u transformed), written column-major
 //              T[b][k_c][r] so that the next pass reads contiguous columns;
-//   cols     : X = C_n Y along r; the kept coefficients give r = X[sel] - f
-//              (written to R in measurement order); with the adjoint fused, the
+//   cols     : X = C_n Y along r; the kept coefficients give r = X[sel] - f;
+//              f and r are held in the order this pass visits the kept
+//              coefficients (k_c-major), so each workgroup reads and writes one
+//              contiguous range of them; with the adjoint fused, the
 //              masked residual is transformed back along k_r in the same block
 //              (C_n^T along the columns), in place in T;
 //   rows_inv : G = T' C_n along each row, written row-major: g = A^T r.
@@ -46,15 +48,13 @@ __global__ void k_dct_table(int n, float4 *tab) {
 __device__ inline int makhoul_pos(int j, int n) {   // position of x_j in v
     return (j & 1) ? n - 1 - (j >> 1) : (j >> 1);
 }
-__device__ inline int makhoul_src(int i, int n) {   // index j with v_i = x_j
-    return i < n / 2 ? 2 * i : 2 * (n - 1 - i) + 1;
-}
 
+// LDS of every pass: the two tables and two FFT buffers of (lines / 2) * n complex.
+// Real staging (lines * n floats) uses whichever FFT buffer is idle at the time.
 struct DctLds {
     float2 *tl;    // FFT twiddles (kMaxN)
     float4 *dt;    // DCT table (n)
-    float2 *X, *Y; // FFT buffers, (lines / 2) * n complex each
-    float *A;      // real staging, lines * n
+    float2 *X, *Y; // FFT buffers
 };
 
 __device__ inline DctLds dct_lds(int n, int lines) {
@@ -64,13 +64,13 @@ __device__ inline DctLds dct_lds(int n, int lines) {
     L.dt = reinterpret_cast<float4 *>(lds + kMaxN);
     L.X = lds + kMaxN + 2 * n;
     L.Y = L.X + (lines / 2) * n;
-    L.A = reinterpret_cast<float *>(L.Y + (lines / 2) * n);
     return L;
 }
 
 size_t dct_lds_bytes(int n, int lines) {
-    return sizeof(float2) * (kMaxN + 2 * n + 2 * (lines / 2) * n) + sizeof(float) * lines * n;
+    return sizeof(float2) * (kMaxN + 2 * n + 2 * (lines / 2) * n);
 }
+
 
 __device__ inline void load_tables(const DctLds &L, int n, const float2 *tw, const float4 *tab) {
     load_twiddles(L.tl, tw);
@@ -91,24 +91,26 @@ __device__ inline float dct_coef(const float2 *Z, const float4 *dt, int n, int l
     return t.x * v.x - t.y * v.y;   // Re(w_k e^{-i pi k/(2n)} V_k)
 }
 
-// Inverse: coefficients of `lines` lines in L.A[l * n + k] -> spectra of the
-// reordered sequences, two lines per complex transform, in L.X; then the inverse
-// FFT.  Returns the buffer holding v (line l: component l & 1 of pair l >> 1).
-__device__ inline float2 *idct_lines(const DctLds &L, int n, int lines) {
+// Inverse: coefficients of `lines` lines in A[l * n + k] -> spectra of the
+// reordered sequences, two lines per complex transform, in P; then the inverse
+// FFT with Q as the second buffer (Q may hold A).  Returns the buffer holding v
+// (line l: component l & 1 of pair l >> 1).
+__device__ inline float2 *idct_lines(const DctLds &L, int n, int lines, const float *A, float2 *P,
+                                     float2 *Q) {
     const int ln = log2i(n), npair = lines >> 1;
     for (int e = threadIdx.x; e < npair * n; e += kThreads) {
         const int pr = e >> ln, k = e & (n - 1);
-        const float *a = L.A + (2 * pr) * n, *b = a + n;
+        const float *a = A + (2 * pr) * n, *b = a + n;
         const float ak = a[k], bk = b[k];
         const float ank = k ? a[n - k] : 0.f, bnk = k ? b[n - k] : 0.f;
         const float4 t = L.dt[k];
         // V_a = t (a_k - i a_{n-k}), V_b likewise; Z = V_a + i V_b
         const float2 va = make_float2(t.z * ak + t.w * ank, t.w * ak - t.z * ank);
         const float2 vb = make_float2(t.z * bk + t.w * bnk, t.w * bk - t.z * bnk);
-        L.X[e] = make_float2(va.x - vb.y, va.y + vb.x);
+        P[e] = make_float2(va.x - vb.y, va.y + vb.x);
     }
     __syncthreads();
-    return lds_fft<true>(L.X, L.Y, n, ln, npair, n, L.tl);
+    return lds_fft<true>(P, Q, n, ln, npair, n, L.tl);
 }
 
 // rows_fwd: T[b][k][row] = (DCT-II of row `row` of u_b)_k, `lines` rows per block.
@@ -122,7 +124,7 @@ __global__ __launch_bounds__(kThreads) void k_dct_rows_fwd(int n, int lines,
     if (st && !st[b].active) return;
     const DctLds L = dct_lds(n, lines);
     load_tables(L, n, tw, tab);
-    const int ln = log2i(n), N = n * n, row0 = blockIdx.x * lines;
+    const int ln = log2i(n), N = n * n, row0 = xcd_block(blockIdx.x, gridDim.x) * lines;
     const float *src = U + (size_t)b * N + (size_t)row0 * n;
     float *Xf = reinterpret_cast<float *>(L.X);
     for (int e = threadIdx.x; e < lines * n; e += kThreads) {
@@ -159,6 +161,7 @@ __global__ __launch_bounds__(kThreads) void k_dct_cols(int n, int lines, float *
     float *col = T + (size_t)b * N + (size_t)col0 * n;
     const int *sel = selT + (size_t)col0 * n;
     float *Rb = R + (size_t)b * ldr;
+    float2 *P = L.X, *Q = L.Y;   // inverse transform: built in P from the staging in Q
     if (FWD) {
         float *Xf = reinterpret_cast<float *>(L.X);
         for (int e = threadIdx.x; e < lines * n; e += kThreads) {
@@ -168,6 +171,10 @@ __global__ __launch_bounds__(kThreads) void k_dct_cols(int n, int lines, float *
         __syncthreads();
         const float2 *Z = lds_fft<false>(L.X, L.Y, n, ln, lines >> 1, n, L.tl);
         const float *Fb = F ? F + (size_t)b * ldf : nullptr;
+        // the residual is staged in the FFT buffer that does not hold Z
+        P = const_cast<float2 *>(Z);
+        Q = (Z == L.X) ? L.Y : L.X;
+        float *A = reinterpret_cast<float *>(Q);
         for (int e = threadIdx.x; e < lines * n; e += kThreads) {
             const int l = e >> ln, k = e & (n - 1);
             const int s = sel[e];
@@ -176,17 +183,18 @@ __global__ __launch_bounds__(kThreads) void k_dct_cols(int n, int lines, float *
                 rv = dct_coef(Z, L.dt, n, l, k) - (Fb ? Fb[s] : 0.f);
                 Rb[s] = rv;
             }
-            if (ADJ) L.A[e] = rv;
+            if (ADJ) A[e] = rv;
         }
     } else {
+        float *A = reinterpret_cast<float *>(Q);
         for (int e = threadIdx.x; e < lines * n; e += kThreads) {
             const int s = sel[e];
-            L.A[e] = s >= 0 ? Rb[s] : 0.f;
+            A[e] = s >= 0 ? Rb[s] : 0.f;
         }
     }
     if (!ADJ) return;
     __syncthreads();
-    const float2 *v = idct_lines(L, n, lines);
+    const float2 *v = idct_lines(L, n, lines, reinterpret_cast<const float *>(Q), P, Q);
     for (int e = threadIdx.x; e < lines * n; e += kThreads) {
         const int l = e >> ln, r = e & (n - 1);
         const float2 z = v[(l >> 1) * n + makhoul_pos(r, n)];
@@ -205,14 +213,15 @@ __global__ __launch_bounds__(kThreads) void k_dct_rows_inv(int n, int lines,
     if (st && !st[b].active) return;
     const DctLds L = dct_lds(n, lines);
     load_tables(L, n, tw, tab);
-    const int ln = log2i(n), N = n * n, row0 = blockIdx.x * lines;
+    const int ln = log2i(n), N = n * n, row0 = xcd_block(blockIdx.x, gridDim.x) * lines;
     const float *src = T + (size_t)b * N + row0;
+    float *A = reinterpret_cast<float *>(L.Y);
     for (int e = threadIdx.x; e < lines * n; e += kThreads) {
         const int k = e / lines, l = e - k * lines;
-        L.A[l * n + k] = src[(size_t)k * n + l];
+        A[l * n + k] = src[(size_t)k * n + l];
     }
     __syncthreads();
-    const float2 *v = idct_lines(L, n, lines);
+    const float2 *v = idct_lines(L, n, lines, A, L.X, L.Y);
     float *dst = G + (size_t)b * ldg + (size_t)row0 * n;
     for (int e = threadIdx.x; e < lines * n; e += kThreads) {
         const int l = e >> ln, c = e & (n - 1);
@@ -221,11 +230,28 @@ __global__ __launch_bounds__(kThreads) void k_dct_rows_inv(int n, int lines,
     }
 }
 
+// dst[b * m + j] = src[b * m + perm[j]]
+__global__ void k_permute(int m, const int *__restrict__ perm, const float *__restrict__ src,
+                          float *__restrict__ dst) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const size_t o = (size_t)blockIdx.y * m;
+    dst[o + j] = src[o + perm[j]];
+}
+
 }  // namespace
 
 // Lines (rows or columns) per workgroup: 2048 values per block where the image
 // allows it, at least one pair.
-int dct_lines(int n) { return std::max(2, std::min(n, std::min(16, 2048 / n))); }
+#ifndef TVCS_DCT_LINE_VALUES
+#define TVCS_DCT_LINE_VALUES 2048   // values per workgroup of the DCT passes
+#endif
+int dct_lines(int n) { return std::max(2, std::min(n, std::min(16, TVCS_DCT_LINE_VALUES / n))); }
+
+void launch_dct_permute(int m, int B, const int *perm, const float *src, float *dst,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_permute, dim3((m + 255) / 256, B), dim3(256), 0, s, m, perm, src, dst);
+}
 
 void launch_dct_table(int n, float4 *tab, hipStream_t s) {
     hipLaunchKernelGGL(k_dct_table, dim3((n + 255) / 256), dim3(256), 0, s, n, tab);

@@ -79,6 +79,18 @@ __device__ float2 *lds_fft(float2 *src, float2 *dst, int L, int logL, int nf, in
 
 __device__ inline int log2i(int n) { return __ffs(n) - 1; }
 
+#ifndef TVCS_XCD_ROWS
+#define TVCS_XCD_ROWS 1   // XCD-aware row-block order in the row passes
+#endif
+// Workgroups are dealt to the 8 XCDs round-robin by linear id, so with a row-block
+// count gx that is a multiple of 8 the XCD of block x is x % 8 for every image.
+// Giving each XCD a contiguous range of row blocks keeps in one L2 the cache lines
+// of the column-major arrays that neighbouring row blocks share, and the halo rows
+// one block reads from its neighbour.
+__device__ inline int xcd_block(int x, int gx) {
+    return (!TVCS_XCD_ROWS || (gx & 7)) ? x : (x & 7) * (gx >> 3) + (x >> 3);
+}
+
 __device__ inline void load_twiddles(float2 *tl, const float2 *tw) {
     for (int t = threadIdx.x; t < kMaxN; t += kThreads) tl[t] = tw[t];
 }

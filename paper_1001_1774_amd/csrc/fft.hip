@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kThreads) void k_shrink_rows(ShrinkArgs a, int rpb,
     const int bufsz = npair * n + rpb;
     float2 *tl = lds, *X = lds + kMaxN, *Y = X + bufsz;
     load_twiddles(tl, tw);
-    const int row0 = blockIdx.x * rpb;
+    const int row0 = xcd_block(blockIdx.x, gridDim.x) * rpb;
     float *Xf = reinterpret_cast<float *>(X);
     const int total = rpb * n;
     for (int e0 = threadIdx.x; e0 < total; e0 += kThreads * PX) {
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
     const int bufsz = npair * n + rpb;
     float2 *tl = lds, *X = lds + kMaxN, *Y = X + bufsz;
     load_twiddles(tl, tw);
-    const int row0 = blockIdx.x * rpb;
+    const int blk = xcd_block(blockIdx.x, gridDim.x), row0 = blk * rpb;
     // raw half spectra of the block's rows: Y[rr * h + k]
     const float2 *srcS = S + (size_t)b * h * n + row0;
     for (int e = threadIdx.x; e < h * rpb; e += kThreads) {
@@ -241,9 +241,8 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
             c += red[1][w];
         }
         // publish this block's sums device-wide, then count the block as done
-        __hip_atomic_store(myparts + 2 * blockIdx.x, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(myparts + 2 * blockIdx.x + 1, c, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(myparts + 2 * blk, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(myparts + 2 * blk + 1, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (FUSED) {
             __threadfence();
             s_last = atomicAdd(&counters[b], 1) == (int)gridDim.x - 1;

@@ -116,15 +116,14 @@ struct tvcs_server {
             fresh.push_back(s);
         }
         if (fresh.empty()) return;
-        const int m = h->m, N = h->N, Bp = h->padded(slots);
+        const int N = h->N, Bp = h->padded(slots);
         float *F = h->F.as<float>(), *U = h->U.as<float>(), *T = h->RHS.as<float>();
         ImgState *st = h->state.as<ImgState>();
         const double t = now_ms();
         for (int s : fresh) {
             SrvRequest &r = reqs[g.slot[s]];
             r.t_admit = t;
-            TVCS_HIP(hipMemcpyAsync(F + (size_t)s * m, r.f.data(), sizeof(float) * m,
-                                    hipMemcpyHostToDevice, h->work));
+            h->load_measurements(r.f.data(), s, 1);
             h->host_state[s] = ImgState{0, 1, TVCS_OK, r.maxit, 0.0, 0.0, 0.0, r.tol};
             TVCS_HIP(hipMemcpyAsync(st + s, h->host_state + s, sizeof(ImgState),
                                     hipMemcpyHostToDevice, h->work));

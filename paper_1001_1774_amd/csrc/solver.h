@@ -55,7 +55,8 @@ struct tvcs_ctx {
     hipEvent_t ev_in = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
 
     DevBuf A32;            // FP32 storage
-    DevBuf selT, dtab;     // partial DCT: measurement index per coefficient (k_c-major), DCT table
+    DevBuf selT, dperm, dtab;   // partial DCT: coefficient -> position, position ->
+                                // measurement index, DCT table
     LowpA lowp{};          // low-precision storage
     DevBuf lowp_mem;
     DevBuf tw;             // FFT twiddles
@@ -172,7 +173,19 @@ struct tvcs_ctx {
 
     // device bytes of A's storage and the FFT tables
     size_t storage_bytes() const {
-        return A32.bytes + lowp_mem.bytes + selT.bytes + dtab.bytes + tw.bytes + invd.bytes;
+        return A32.bytes + lowp_mem.bytes + selT.bytes + dperm.bytes + dtab.bytes + tw.bytes +
+               invd.bytes;
+    }
+
+    // B measurement vectors (host or device memory, in the caller's order) into
+    // rows first .. first+B-1 of F; the partial DCT keeps them in its pass order
+    // (staged through the same rows of R, which every iteration rewrites)
+    void load_measurements(const float *Fin, int first, int B) {
+        float *dst = (dct() ? R : F).as<float>() + (size_t)first * m;
+        TVCS_HIP(hipMemcpyAsync(dst, Fin, sizeof(float) * (size_t)B * m, hipMemcpyDefault, work));
+        if (dct())
+            launch_dct_permute(m, B, dperm.as<int>(), dst, F.as<float>() + (size_t)first * m,
+                               work);
     }
 
     // give the batch workspace back (the next call re-allocates what it needs)
@@ -378,7 +391,8 @@ struct tvcs_ctx {
     }
 
     size_t device_bytes() const {
-        return A32.bytes + lowp_mem.bytes + selT.bytes + dtab.bytes + DT.bytes + tw.bytes + invd.bytes + U.bytes + F.bytes + R.bytes +
+        return A32.bytes + lowp_mem.bytes + selT.bytes + dperm.bytes + dtab.bytes + DT.bytes +
+               tw.bytes + invd.bytes + U.bytes + F.bytes + R.bytes +
                P.bytes + RHS.bytes + Q0.bytes + Q1.bytes + S.bytes + parts.bytes + state.bytes +
                obj.bytes + lowp_work.bytes + lamb.bytes + counters.bytes;
     }

@@ -161,10 +161,15 @@ void lowp_autotune(const LowpA &L, LowpWork &W, int Bp, const float *U, float *R
 // ---------------------------------------------------------------------------
 // Partial-DCT operator (dct.hip): A = rows of the orthonormal 2-D DCT-II.
 // T is a B x N work array (column-major half transforms); selT[k_c * n + k_r] is
-// the measurement index of coefficient k_r * n + k_c, or -1 when it is not kept.
+// the position of coefficient k_r * n + k_c among the kept ones, or -1 when it is
+// not kept.  Positions count the kept coefficients in k_c-major order (the order
+// the column pass visits them); F and R are held in that order on the device.
 // ---------------------------------------------------------------------------
 int dct_lines(int n);                                // lines per workgroup of the passes
 void launch_dct_table(int n, float4 *tab, hipStream_t s);
+// dst[b*m + j] = src[b*m + perm[j]] for b < B (measurement order -> pass order)
+void launch_dct_permute(int m, int B, const int *perm, const float *src, float *dst,
+                        hipStream_t s);
 // R[b*ldr + i] = (C u_b)[sel_i] - F[b*ldf + i] (F may be null); with `adjoint`, T is
 // left holding the inverse column transform of the zero-filled residual, ready for
 // launch_dct_adjoint(..., from_R = false, ...)

@@ -157,3 +157,34 @@ def test_n512_ratio03_b16_sampled_images(T):
         e = rel(U[b], ref.u[j])
         say(f"  image {b}: rel err {e:.3e}")
         assert e <= TOL_U
+
+
+def test_served_requests_match_the_oracle(T):
+    """Partial-DCT requests through the request loop, next to a dense-A group: each
+    equals its solve alone (bitwise, same iterations) and the oracle (1e-5)."""
+    from paper_1001_1774_amd import serving as S
+    pd = synth.make_dct_problem("srv", 64, 0.3, batch=5, sigma=[1e-3, 1e-2, 0.0, 1e-3, 5e-3])
+    pa = synth.make_problem("s32", n=32, m=307, batch=3, seed_A=51, n_shapes=6)
+    sd = T.Solver.partial_dct(pd.rows, pd.n)
+    sa = T.Solver(pa.A, pa.n)
+    reqs = [S.Request(matrix=0, f=pd.f[b].astype(np.float32), tol=0.0, maxit=80,
+                      arrival=0.001 * b) for b in range(pd.B)]
+    reqs += [S.Request(matrix=1, f=pa.f[b].astype(np.float32), tol=1e-4, maxit=300,
+                       arrival=0.0015 * b) for b in range(pa.B)]
+    with S.Server(slots=4, mu=pd.mu, beta=pd.beta, iadm=True) as srv:
+        srv.add_matrix(sd)
+        srv.add_matrix(sa)
+        out = S.run_arrivals(srv, reqs, keep_results=True)
+    ref = O.iadm(op(pd), pd.f.astype(np.float32).astype(np.float64), pd.n, pd.mu, pd.beta,
+                 pd.tau, tol=0, maxit=80)
+    for i, r in enumerate(reqs):
+        u_mix, st_mix = out["results"][i]
+        u_alone, st_alone = S.solve_alone(sd if r.matrix == 0 else sa, r, pd.mu, pd.beta, True)
+        assert st_mix["iters"] == st_alone["iters"]
+        assert np.array_equal(u_mix.ravel(), u_alone.ravel())
+        if r.matrix == 0:
+            e = rel(u_mix.reshape(pd.n, pd.n), ref.u[i])
+            say(f"  request {i}: rel err {e:.3e}")
+            assert e <= TOL_U
+    sd.close()
+    sa.close()
