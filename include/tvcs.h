@@ -44,7 +44,7 @@ extern "C" {
 #define TVCS_ENOMEM       -2   /* device allocation failed / HBM budget exceeded    */
 #define TVCS_EDEVICE      -3   /* HIP runtime error                                 */
 #define TVCS_ENONFINITE   -4   /* NaN or Inf appeared in an iterate                 */
-#define TVCS_EUNSUPPORTED -5   /* n not a power of two in [8, 512], or similar      */
+#define TVCS_EUNSUPPORTED -5   /* image side or storage format not supported        */
 
 /* ---- solve flags --------------------------------------------------------- */
 /* Algorithm 2 (IADM) instead of Algorithm 1 (FTVCS). */
@@ -90,8 +90,10 @@ typedef struct {
  * lambda_max(A^T A) for the default step tau = 1.9 / lambda_max (Thm. 1 needs
  * 0 < tau < 2 / lambda_max).  The caller keeps ownership of A and may free it
  * when the call returns.  Uses the default stream.
- * Returns NULL on error (see tvcs_last_error): m < 1, n not a power of two in
- * [8, 512], A NULL, or out of device memory.
+ * Image sides: n even, 8 <= n <= 512, with no prime factor other than 2, 3 and 5
+ * (e.g. 128, 450, 512); the FFTs are radix 2/3/4/5.
+ * Returns NULL on error (see tvcs_last_error): m < 1, n not such a side
+ * (TVCS_EUNSUPPORTED), A NULL, or out of device memory.
  */
 tvcs_handle tvcs_create(const float *A, int m, int n);
 
@@ -103,8 +105,9 @@ tvcs_handle tvcs_create(const float *A, int m, int n);
  *              work of this handle is ordered.
  * Storage formats other than FP32 also keep a transposed copy of A so that
  * both products read their reduction dimension contiguously (2x the bytes of
- * the format; the HBM traffic per product is unchanged), and need n >= 16
- * (TVCS_EUNSUPPORTED otherwise).
+ * the format; the HBM traffic per product is unchanged), and need n a power of
+ * two >= 16 (their MFMA tiles take 32-wide slices of n*n; TVCS_EUNSUPPORTED
+ * otherwise).
  */
 tvcs_handle tvcs_create_ex(const void *A, int a_is_fp64, int m, int n, int storage,
                            void *stream);
@@ -120,8 +123,8 @@ tvcs_handle tvcs_create_ex(const void *A, int a_is_fp64, int m, int n, int stora
  * the default tau is 1.9, the value of the partial-DCT experiments.  The caller
  * keeps ownership of rows.  Storage is TVCS_A_PARTIAL_DCT.
  * Returns NULL on error (see tvcs_last_error): rows NULL, m < 1 or m > n*n, an
- * index outside [0, n*n) or repeated, n not a power of two in [8, 512], or out
- * of device memory.
+ * index outside [0, n*n) or repeated, n not an image side tvcs_create accepts,
+ * or out of device memory.
  */
 tvcs_handle tvcs_create_dct(const int *rows, int m, int n, void *stream);
 

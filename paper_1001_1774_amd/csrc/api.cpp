@@ -33,8 +33,6 @@ thread_local std::string g_last_error;
 
 namespace {
 
-bool pow2_in_range(int n) { return n >= 8 && n <= kMaxN && (n & (n - 1)) == 0; }
-
 int solve_impl(tvcs_ctx *h, const float *Fin, int B, double mu, double beta, double tol,
                int maxit, unsigned flags, float *Uout, double *lam, tvcs_stats *stats) {
     if (!h) fail(TVCS_EINVAL, "null handle");
@@ -143,14 +141,15 @@ int solve_impl(tvcs_ctx *h, const float *Fin, int B, double mu, double beta, dou
 tvcs_ctx *create_impl(const void *A, int a_is_fp64, int m, int n, int storage, void *stream) {
     if (!A) fail(TVCS_EINVAL, "A must not be NULL");
     if (m < 1) fail(TVCS_EINVAL, "m must be >= 1");
-    if (!pow2_in_range(n))
-        fail(TVCS_EUNSUPPORTED, "n must be a power of two in [8, 512], got " + std::to_string(n));
+    if (!supported_side(n))
+        fail(TVCS_EUNSUPPORTED, "n must be even, in [8, 512], with no prime factor other than "
+                                 "2, 3 and 5, got " + std::to_string(n));
     if (storage == TVCS_A_PARTIAL_DCT)
         fail(TVCS_EINVAL, "the partial-DCT operator is created with tvcs_create_dct");
     if (storage < TVCS_A_FP32 || storage > TVCS_A_FP8_ROWSCALE)
         fail(TVCS_EINVAL, "unknown storage format");
-    if (storage != TVCS_A_FP32 && n < 16)
-        fail(TVCS_EUNSUPPORTED, "low-precision storage needs n >= 16");
+    if (storage != TVCS_A_FP32 && (n < 16 || !is_pow2(n)))
+        fail(TVCS_EUNSUPPORTED, "low-precision storage needs n a power of two >= 16");
     std::unique_ptr<tvcs_ctx> h(new tvcs_ctx());
     h->m = m;
     h->n = n;
@@ -191,15 +190,16 @@ tvcs_ctx *create_impl(const void *A, int a_is_fp64, int m, int n, int storage, v
         staging.release();
     }
     h->tw.ensure(sizeof(float2) * kMaxN);
-    launch_twiddles(h->tw.as<float2>(), h->work);
+    launch_twiddles(n, h->tw.as<float2>(), h->work);
     h->estimate_lambda_max();
     return h.release();
 }
 
 tvcs_ctx *create_dct_impl(const int *rows, int m, int n, void *stream) {
     if (!rows) fail(TVCS_EINVAL, "rows must not be NULL");
-    if (!pow2_in_range(n))
-        fail(TVCS_EUNSUPPORTED, "n must be a power of two in [8, 512], got " + std::to_string(n));
+    if (!supported_side(n))
+        fail(TVCS_EUNSUPPORTED, "n must be even, in [8, 512], with no prime factor other than "
+                                 "2, 3 and 5, got " + std::to_string(n));
     const int N = n * n;
     if (m < 1 || m > N) fail(TVCS_EINVAL, "m must be in [1, n*n]");
     // which[k_c * n + k_r] = i for rows[i] = k_r * n + k_c, -1 if not measured
@@ -241,7 +241,7 @@ tvcs_ctx *create_dct_impl(const int *rows, int m, int n, void *stream) {
     h->dtab.ensure(sizeof(float4) * (size_t)n);
     launch_dct_table(n, h->dtab.as<float4>(), h->work);
     h->tw.ensure(sizeof(float2) * kMaxN);
-    launch_twiddles(h->tw.as<float2>(), h->work);
+    launch_twiddles(n, h->tw.as<float2>(), h->work);
     h->estimate_lambda_max();
     TVCS_HIP(hipStreamSynchronize(h->work));   // the host tables go out of scope
     return h.release();

@@ -72,16 +72,18 @@ size_t dct_lds_bytes(int n, int lines) {
 }
 
 
+template <bool P2>
 __device__ inline void load_tables(const DctLds &L, int n, const float2 *tw, const float4 *tab) {
-    load_twiddles(L.tl, tw);
+    load_twiddles<P2>(L.tl, tw, n);
     for (int k = threadIdx.x; k < n; k += kThreads) L.dt[k] = tab[k];
 }
 
 // Forward DCT-II of the `lines` real lines staged in L.X (already reordered, two
 // lines per complex transform).  Returns the FFT output buffer; the coefficient
 // k of line l is then dct_coef(Z, L, l, k).
+template <bool P2>
 __device__ inline float dct_coef(const float2 *Z, const float4 *dt, int n, int l, int k) {
-    const float2 zk = Z[(l >> 1) * n + k], znk = Z[(l >> 1) * n + ((n - k) & (n - 1))];
+    const float2 zk = Z[(l >> 1) * n + k], znk = Z[(l >> 1) * n + Ring<P2>(n).neg(k)];
     float2 v;
     if ((l & 1) == 0)   // V of the real part: (Z_k + conj Z_{n-k}) / 2
         v = make_float2(0.5f * (zk.x + znk.x), 0.5f * (zk.y - znk.y));
@@ -95,11 +97,13 @@ __device__ inline float dct_coef(const float2 *Z, const float4 *dt, int n, int l
 // reordered sequences, two lines per complex transform, in P; then the inverse
 // FFT with Q as the second buffer (Q may hold A).  Returns the buffer holding v
 // (line l: component l & 1 of pair l >> 1).
+template <bool P2>
 __device__ inline float2 *idct_lines(const DctLds &L, int n, int lines, const float *A, float2 *P,
                                      float2 *Q) {
-    const int ln = log2i(n), npair = lines >> 1;
+    const Ring<P2> ring(n);
+    const int npair = lines >> 1;
     for (int e = threadIdx.x; e < npair * n; e += kThreads) {
-        const int pr = e >> ln, k = e & (n - 1);
+        const int pr = ring.div(e), k = e - ring.mul(pr);
         const float *a = A + (2 * pr) * n, *b = a + n;
         const float ak = a[k], bk = b[k];
         const float ank = k ? a[n - k] : 0.f, bnk = k ? b[n - k] : 0.f;
@@ -110,10 +114,11 @@ __device__ inline float2 *idct_lines(const DctLds &L, int n, int lines, const fl
         P[e] = make_float2(va.x - vb.y, va.y + vb.x);
     }
     __syncthreads();
-    return lds_fft<true>(P, Q, n, ln, npair, n, L.tl);
+    return lds_fft_any<true, P2>(P, Q, n, npair, n, L.tl);
 }
 
 // rows_fwd: T[b][k][row] = (DCT-II of row `row` of u_b)_k, `lines` rows per block.
+template <bool P2>
 __global__ __launch_bounds__(kThreads) void k_dct_rows_fwd(int n, int lines,
                                                            const float *__restrict__ U,
                                                            float *__restrict__ T,
@@ -123,20 +128,21 @@ __global__ __launch_bounds__(kThreads) void k_dct_rows_fwd(int n, int lines,
     const int b = blockIdx.y;
     if (st && !st[b].active) return;
     const DctLds L = dct_lds(n, lines);
-    load_tables(L, n, tw, tab);
-    const int ln = log2i(n), N = n * n, row0 = xcd_block(blockIdx.x, gridDim.x) * lines;
+    load_tables<P2>(L, n, tw, tab);
+    const Ring<P2> ring(n);
+    const int N = n * n, row0 = xcd_block(blockIdx.x, gridDim.x) * lines;
     const float *src = U + (size_t)b * N + (size_t)row0 * n;
     float *Xf = reinterpret_cast<float *>(L.X);
     for (int e = threadIdx.x; e < lines * n; e += kThreads) {
-        const int l = e >> ln, j = e & (n - 1);
+        const int l = ring.div(e), j = e - ring.mul(l);
         Xf[2 * ((l >> 1) * n + makhoul_pos(j, n)) + (l & 1)] = src[e];
     }
     __syncthreads();
-    const float2 *Z = lds_fft<false>(L.X, L.Y, n, ln, lines >> 1, n, L.tl);
+    const float2 *Z = lds_fft_any<false, P2>(L.X, L.Y, n, lines >> 1, n, L.tl);
     float *dst = T + (size_t)b * N + row0;
     for (int e = threadIdx.x; e < lines * n; e += kThreads) {
         const int k = e / lines, l = e - k * lines;
-        dst[(size_t)k * n + l] = dct_coef(Z, L.dt, n, l, k);
+        dst[(size_t)k * n + l] = dct_coef<P2>(Z, L.dt, n, l, k);
     }
 }
 
@@ -145,7 +151,7 @@ __global__ __launch_bounds__(kThreads) void k_dct_rows_fwd(int n, int lines,
 //        (F may be null); without FWD the kept coefficients are read from R instead;
 //   ADJ: the zero-filled coefficients are transformed back along k_r into T.
 // selT[k_c * n + k_r] is the measurement index of coefficient k_r * n + k_c, or -1.
-template <bool FWD, bool ADJ>
+template <bool FWD, bool ADJ, bool P2>
 __global__ __launch_bounds__(kThreads) void k_dct_cols(int n, int lines, float *__restrict__ T,
                                                        const int *__restrict__ selT,
                                                        const float *__restrict__ F, int ldf,
@@ -156,8 +162,9 @@ __global__ __launch_bounds__(kThreads) void k_dct_cols(int n, int lines, float *
     const int b = blockIdx.y;
     if (st && !st[b].active) return;
     const DctLds L = dct_lds(n, lines);
-    load_tables(L, n, tw, tab);
-    const int ln = log2i(n), N = n * n, col0 = blockIdx.x * lines;
+    load_tables<P2>(L, n, tw, tab);
+    const Ring<P2> ring(n);
+    const int N = n * n, col0 = blockIdx.x * lines;
     float *col = T + (size_t)b * N + (size_t)col0 * n;
     const int *sel = selT + (size_t)col0 * n;
     float *Rb = R + (size_t)b * ldr;
@@ -165,22 +172,22 @@ __global__ __launch_bounds__(kThreads) void k_dct_cols(int n, int lines, float *
     if (FWD) {
         float *Xf = reinterpret_cast<float *>(L.X);
         for (int e = threadIdx.x; e < lines * n; e += kThreads) {
-            const int l = e >> ln, j = e & (n - 1);
+            const int l = ring.div(e), j = e - ring.mul(l);
             Xf[2 * ((l >> 1) * n + makhoul_pos(j, n)) + (l & 1)] = col[e];
         }
         __syncthreads();
-        const float2 *Z = lds_fft<false>(L.X, L.Y, n, ln, lines >> 1, n, L.tl);
+        const float2 *Z = lds_fft_any<false, P2>(L.X, L.Y, n, lines >> 1, n, L.tl);
         const float *Fb = F ? F + (size_t)b * ldf : nullptr;
         // the residual is staged in the FFT buffer that does not hold Z
         P = const_cast<float2 *>(Z);
         Q = (Z == L.X) ? L.Y : L.X;
         float *A = reinterpret_cast<float *>(Q);
         for (int e = threadIdx.x; e < lines * n; e += kThreads) {
-            const int l = e >> ln, k = e & (n - 1);
+            const int l = ring.div(e), k = e - ring.mul(l);
             const int s = sel[e];
             float rv = 0.f;
             if (s >= 0) {
-                rv = dct_coef(Z, L.dt, n, l, k) - (Fb ? Fb[s] : 0.f);
+                rv = dct_coef<P2>(Z, L.dt, n, l, k) - (Fb ? Fb[s] : 0.f);
                 Rb[s] = rv;
             }
             if (ADJ) A[e] = rv;
@@ -194,15 +201,16 @@ __global__ __launch_bounds__(kThreads) void k_dct_cols(int n, int lines, float *
     }
     if (!ADJ) return;
     __syncthreads();
-    const float2 *v = idct_lines(L, n, lines, reinterpret_cast<const float *>(Q), P, Q);
+    const float2 *v = idct_lines<P2>(L, n, lines, reinterpret_cast<const float *>(Q), P, Q);
     for (int e = threadIdx.x; e < lines * n; e += kThreads) {
-        const int l = e >> ln, r = e & (n - 1);
+        const int l = ring.div(e), r = e - ring.mul(l);
         const float2 z = v[(l >> 1) * n + makhoul_pos(r, n)];
         col[e] = (l & 1) ? z.y : z.x;
     }
 }
 
 // rows_inv: G[b][row][c] = (DCT-II^T along k_c of T[b][.][row])_c.
+template <bool P2>
 __global__ __launch_bounds__(kThreads) void k_dct_rows_inv(int n, int lines,
                                                            const float *__restrict__ T,
                                                            float *__restrict__ G, int ldg,
@@ -212,8 +220,9 @@ __global__ __launch_bounds__(kThreads) void k_dct_rows_inv(int n, int lines,
     const int b = blockIdx.y;
     if (st && !st[b].active) return;
     const DctLds L = dct_lds(n, lines);
-    load_tables(L, n, tw, tab);
-    const int ln = log2i(n), N = n * n, row0 = xcd_block(blockIdx.x, gridDim.x) * lines;
+    load_tables<P2>(L, n, tw, tab);
+    const Ring<P2> ring(n);
+    const int N = n * n, row0 = xcd_block(blockIdx.x, gridDim.x) * lines;
     const float *src = T + (size_t)b * N + row0;
     float *A = reinterpret_cast<float *>(L.Y);
     for (int e = threadIdx.x; e < lines * n; e += kThreads) {
@@ -221,10 +230,10 @@ __global__ __launch_bounds__(kThreads) void k_dct_rows_inv(int n, int lines,
         A[l * n + k] = src[(size_t)k * n + l];
     }
     __syncthreads();
-    const float2 *v = idct_lines(L, n, lines, A, L.X, L.Y);
+    const float2 *v = idct_lines<P2>(L, n, lines, A, L.X, L.Y);
     float *dst = G + (size_t)b * ldg + (size_t)row0 * n;
     for (int e = threadIdx.x; e < lines * n; e += kThreads) {
-        const int l = e >> ln, c = e & (n - 1);
+        const int l = ring.div(e), c = e - ring.mul(l);
         const float2 z = v[(l >> 1) * n + makhoul_pos(c, n)];
         dst[e] = (l & 1) ? z.y : z.x;
     }
@@ -246,7 +255,9 @@ __global__ void k_permute(int m, const int *__restrict__ perm, const float *__re
 #ifndef TVCS_DCT_LINE_VALUES
 #define TVCS_DCT_LINE_VALUES 2048   // values per workgroup of the DCT passes
 #endif
-int dct_lines(int n) { return std::max(2, std::min(n, std::min(16, TVCS_DCT_LINE_VALUES / n))); }
+int dct_lines(int n) {
+    return even_divisor_at_most(n, std::max(2, std::min(n, std::min(16, TVCS_DCT_LINE_VALUES / n))));
+}
 
 void launch_dct_permute(int m, int B, const int *perm, const float *src, float *dst,
                         hipStream_t s) {
@@ -263,13 +274,21 @@ void launch_dct_forward(int n, int B, const float *U, float *T, const int *selT,
     const int lines = dct_lines(n);
     const size_t lds = dct_lds_bytes(n, lines);
     const dim3 grid(n / lines, B);
-    hipLaunchKernelGGL(k_dct_rows_fwd, grid, dim3(kThreads), lds, s, n, lines, U, T, tw, tab, st);
-    if (adjoint)
-        hipLaunchKernelGGL((k_dct_cols<true, true>), grid, dim3(kThreads), lds, s, n, lines, T,
-                           selT, F, ldf, R, ldr, tw, tab, st);
-    else
-        hipLaunchKernelGGL((k_dct_cols<true, false>), grid, dim3(kThreads), lds, s, n, lines, T,
-                           selT, F, ldf, R, ldr, tw, tab, st);
+#define TVCS_DCT_FWD(P2V)                                                                         \
+    hipLaunchKernelGGL(k_dct_rows_fwd<P2V>, grid, dim3(kThreads), lds, s, n, lines, U, T, tw, tab, \
+                       st);                                                                       \
+    if (adjoint)                                                                                  \
+        hipLaunchKernelGGL((k_dct_cols<true, true, P2V>), grid, dim3(kThreads), lds, s, n, lines, \
+                           T, selT, F, ldf, R, ldr, tw, tab, st);                                 \
+    else                                                                                          \
+        hipLaunchKernelGGL((k_dct_cols<true, false, P2V>), grid, dim3(kThreads), lds, s, n, lines, \
+                           T, selT, F, ldf, R, ldr, tw, tab, st)
+    if (is_pow2(n)) {
+        TVCS_DCT_FWD(true);
+    } else {
+        TVCS_DCT_FWD(false);
+    }
+#undef TVCS_DCT_FWD
 }
 
 void launch_dct_adjoint(int n, int B, const float *R, int ldr, float *T, const int *selT,
@@ -278,11 +297,18 @@ void launch_dct_adjoint(int n, int B, const float *R, int ldr, float *T, const i
     const int lines = dct_lines(n);
     const size_t lds = dct_lds_bytes(n, lines);
     const dim3 grid(n / lines, B);
-    if (from_R)
-        hipLaunchKernelGGL((k_dct_cols<false, true>), grid, dim3(kThreads), lds, s, n, lines, T,
-                           selT, nullptr, 0, const_cast<float *>(R), ldr, tw, tab, st);
-    hipLaunchKernelGGL(k_dct_rows_inv, grid, dim3(kThreads), lds, s, n, lines, T, G, ldg, tw, tab,
-                       st);
+#define TVCS_DCT_ADJ(P2V)                                                                        \
+    if (from_R)                                                                                  \
+        hipLaunchKernelGGL((k_dct_cols<false, true, P2V>), grid, dim3(kThreads), lds, s, n, lines, \
+                           T, selT, nullptr, 0, const_cast<float *>(R), ldr, tw, tab, st);        \
+    hipLaunchKernelGGL(k_dct_rows_inv<P2V>, grid, dim3(kThreads), lds, s, n, lines, T, G, ldg, tw, \
+                       tab, st)
+    if (is_pow2(n)) {
+        TVCS_DCT_ADJ(true);
+    } else {
+        TVCS_DCT_ADJ(false);
+    }
+#undef TVCS_DCT_ADJ
 }
 
 }  // namespace tvcs

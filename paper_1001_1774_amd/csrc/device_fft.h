@@ -1,9 +1,10 @@
 // Device helpers of the FFT kernels: complex arithmetic and the in-LDS Stockham
-// FFT (shared by fft.hip and the fused shrink + row-FFT pass).
+// FFTs (shared by fft.hip, dct.hip and the fused shrink + row-FFT pass).
 #pragma once
 
 #include <hip/hip_runtime.h>
 
+#include "device_index.h"
 #include "tvcs_internal.h"
 
 namespace tvcs {
@@ -79,6 +80,110 @@ __device__ float2 *lds_fft(float2 *src, float2 *dst, int L, int logL, int nf, in
 
 __device__ inline int log2i(int n) { return __ffs(n) - 1; }
 
+// ---- mixed radix: any n = 2^a 3^b 5^c ---------------------------------------
+// Stages take radix 4 while it divides the remaining length, then 2, 3 and 5.
+// Stage (radix R, Ns = product of the earlier radices, q = L / R): for j < q,
+// k = j mod Ns, the inputs x[j + r q] (r < R) are multiplied by w^{r k} with
+// w = exp(-+2 pi i / (Ns R)), transformed by a length-R DFT, and output q goes to
+// ((j / Ns) Ns R + k + q Ns): the Stockham autosort order of the radix-4 code above,
+// generalised.  Twiddles come from an L-entry table exp(-2 pi i t / L): w^{r k} is
+// entry r k L / (Ns R).
+__device__ inline int next_radix(int rest) {
+    return (rest & 3) == 0 ? 4 : (rest & 1) == 0 ? 2 : rest % 3 == 0 ? 3 : 5;
+}
+
+// -i z (forward) or +i z (inverse)
+template <bool INV>
+__device__ inline float2 rot(float2 z) {
+    return INV ? make_float2(-z.y, z.x) : make_float2(z.y, -z.x);
+}
+__device__ inline float2 scl(float a, float2 z) { return make_float2(a * z.x, a * z.y); }
+
+template <int R, bool INV>
+__device__ inline void dft_small(float2 *v) {
+    if (R == 2) {
+        const float2 a = v[0], b = v[1];
+        v[0] = a + b;
+        v[1] = a - b;
+    } else if (R == 3) {
+        constexpr float s3 = 0.866025403784438647f;   // sin(2 pi / 3)
+        const float2 t1 = v[1] + v[2], t2 = v[0] - scl(0.5f, t1);
+        const float2 t3 = rot<INV>(scl(s3, v[1] - v[2]));
+        v[0] = v[0] + t1;
+        v[1] = t2 + t3;
+        v[2] = t2 - t3;
+    } else if (R == 4) {
+        const float2 a = v[0] + v[2], b = v[0] - v[2], c = v[1] + v[3];
+        const float2 mid = rot<INV>(v[1] - v[3]);
+        v[0] = a + c;
+        v[1] = b + mid;
+        v[2] = a - c;
+        v[3] = b - mid;
+    } else {   // R == 5
+        constexpr float c1 = 0.309016994374947424f, c2 = -0.809016994374947424f;   // cos(2pi/5), cos(4pi/5)
+        constexpr float s1 = 0.951056516295153572f, s2 = 0.587785252292473129f;    // sin(2pi/5), sin(4pi/5)
+        const float2 a1 = v[1] + v[4], b1 = v[1] - v[4], a2 = v[2] + v[3], b2 = v[2] - v[3];
+        const float2 p1 = v[0] + scl(c1, a1) + scl(c2, a2), p2 = v[0] + scl(c2, a1) + scl(c1, a2);
+        const float2 q1 = rot<INV>(scl(s1, b1) + scl(s2, b2));
+        const float2 q2 = rot<INV>(scl(s2, b1) - scl(s1, b2));
+        v[0] = v[0] + a1 + a2;
+        v[1] = p1 + q1;
+        v[2] = p2 + q2;
+        v[3] = p2 - q2;
+        v[4] = p1 - q1;
+    }
+}
+
+template <bool INV, int R>
+__device__ inline void mixed_stage(const float2 *src, float2 *dst, int L, int Ns, int nf, int fs,
+                                   const float2 *tw) {
+    const int q = L / R, tstep = L / (Ns * R);
+    for (int t = threadIdx.x; t < nf * q; t += kThreads) {
+        const int f = t / q, j = t - f * q;
+        const int k = j % Ns;
+        const float2 *s = src + f * fs;
+        float2 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = s[j + r * q];
+        const int step = k * tstep;
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = INV ? cmulc(v[r], tw[r * step]) : cmul(v[r], tw[r * step]);
+        dft_small<R, INV>(v);
+        float2 *o = dst + f * fs + (j / Ns) * Ns * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) o[r * Ns] = v[r];
+    }
+}
+
+// nf transforms of length L (any 2^a 3^b 5^c) at src[f*fs ..]; tw: L-entry table.
+// Returns the buffer holding the result.  Ends with a barrier.
+template <bool INV>
+__device__ float2 *lds_fft_mixed(float2 *src, float2 *dst, int L, int nf, int fs,
+                                 const float2 *tw) {
+    for (int Ns = 1; Ns < L;) {
+        const int R = next_radix(L / Ns);   // the same for every thread
+        if (R == 4) mixed_stage<INV, 4>(src, dst, L, Ns, nf, fs, tw);
+        else if (R == 2) mixed_stage<INV, 2>(src, dst, L, Ns, nf, fs, tw);
+        else if (R == 3) mixed_stage<INV, 3>(src, dst, L, Ns, nf, fs, tw);
+        else mixed_stage<INV, 5>(src, dst, L, Ns, nf, fs, tw);
+        __syncthreads();
+        float2 *x = src;
+        src = dst;
+        dst = x;
+        Ns *= R;
+    }
+    return src;
+}
+
+// Power-of-two lengths use the radix-4 code (512-entry table), others the mixed
+// radix code (L-entry table).
+template <bool INV, bool P2>
+__device__ inline float2 *lds_fft_any(float2 *src, float2 *dst, int L, int nf, int fs,
+                                      const float2 *tw) {
+    if (P2) return lds_fft<INV>(src, dst, L, log2i(L), nf, fs, tw);
+    return lds_fft_mixed<INV>(src, dst, L, nf, fs, tw);
+}
+
 #ifndef TVCS_XCD_ROWS
 #define TVCS_XCD_ROWS 1   // XCD-aware row-block order in the row passes
 #endif
@@ -91,8 +196,11 @@ __device__ inline int xcd_block(int x, int gx) {
     return (!TVCS_XCD_ROWS || (gx & 7)) ? x : (x & 7) * (gx >> 3) + (x >> 3);
 }
 
-__device__ inline void load_twiddles(float2 *tl, const float2 *tw) {
-    for (int t = threadIdx.x; t < kMaxN; t += kThreads) tl[t] = tw[t];
+// the twiddle table of a length-n transform: 512 entries for powers of two, n otherwise
+template <bool P2>
+__device__ inline void load_twiddles(float2 *tl, const float2 *tw, int n) {
+    const int cnt = P2 ? kMaxN : n;
+    for (int t = threadIdx.x; t < cnt; t += kThreads) tl[t] = tw[t];
 }
 
 }  // namespace fftdev

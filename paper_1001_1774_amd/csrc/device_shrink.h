@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "device_index.h"
 #include "tvcs_internal.h"
 
 #ifndef TVCS_PARTIAL_LOADS
@@ -24,8 +25,6 @@ __device__ inline D2 shrink2(D2 z, double inv_beta) {
     return {z.x * s, z.y * s};
 }
 
-__device__ inline int log2i(int n) { return __ffs(n) - 1; }
-
 // Everything the right-hand side at one pixel reads from memory.  Loading several
 // pixels' inputs before computing any of them keeps many loads in flight (the
 // pass is latency-bound); the stores of q^k come after all loads of a round.
@@ -37,12 +36,13 @@ struct PixIn {
 
 // PL: partial sums loaded in flight.  For nchunk <= PL every PL gives the same
 // bits (the pairwise tree over the first nchunk slots, the rest exact zeros).
-template <bool IADM, int PL = TVCS_PARTIAL_LOADS>
+template <bool IADM, int PL, bool P2>
 __device__ inline PixIn load_pix(const ShrinkArgs &a, int b, int p) {
-    const int n = a.n, N = n * n, mask = n - 1, ln = log2i(n);
-    const int r = p >> ln, c = p & mask;
+    const int n = a.n, N = n * n;
+    const Ring<P2> ring(n);
+    const int r = ring.div(p), c = p - ring.mul(r);
     const float *u = a.U + (size_t)b * N;
-    auto U = [&](int rr, int cc) { return u[((rr & mask) << ln) | (cc & mask)]; };
+    auto U = [&](int rr, int cc) { return u[ring.mul(ring.wrap(rr)) + ring.wrap(cc)]; };
     PixIn in;
     in.u0 = U(r, c);
     in.uE = U(r, c + 1);
@@ -53,7 +53,7 @@ __device__ inline PixIn load_pix(const ShrinkArgs &a, int b, int p) {
     in.uNE = U(r - 1, c + 1);
     if (IADM) {
         const double *Q1 = a.Qold + (size_t)b * 2 * N, *Q2 = Q1 + N;
-        const int pW = (r << ln) | ((c - 1) & mask), pN = (((r - 1) & mask) << ln) | c;
+        const int pW = ring.mul(r) + ring.wrap(c - 1), pN = ring.mul(ring.wrap(r - 1)) + c;
         in.o0 = {Q1[p], Q2[p]};
         in.oW = {Q1[pW], Q2[pW]};
         in.oN = {Q1[pN], Q2[pN]};

@@ -24,15 +24,33 @@
 #include <algorithm>
 
 namespace tvcs {
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+bool supported_side(int n) {
+    if (n < 8 || n > kMaxN || (n & 1)) return false;
+    int r = n;
+    for (int p : {2, 3, 5})
+        while (r % p == 0) r /= p;
+    return r == 1;
+}
+
+int even_divisor_at_most(int n, int want) {
+    for (int d = std::max(2, want & ~1); d > 2; d -= 2)
+        if (n % d == 0) return d;
+    return 2;
+}
+
 namespace {
 
 using namespace fftdev;
 
-__global__ void k_twiddles(float2 *tw) {
+// tw[t] = exp(-2 pi i t / L), t < L (L = 512 for every power-of-two n, else L = n)
+__global__ void k_twiddles(float2 *tw, int L) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= kMaxN) return;
+    if (t >= L) return;
     double s, c;
-    sincospi(-2.0 * t / kMaxN, &s, &c);
+    sincospi(-2.0 * t / L, &s, &c);
     tw[t] = make_float2((float)c, (float)s);
 }
 
@@ -49,13 +67,15 @@ __global__ void k_denominators(int n, double c, double *inv_d) {
 
 // FFT of the block's packed row pairs in X, split into the half spectra and
 // written to S (rows row0 .. row0 + rpb - 1 of image b).
+template <bool P2>
 __device__ inline void rows_fwd_tail(int n, int rpb, float2 *X, float2 *Y, const float2 *tl,
                                      float2 *dstS) {
-    const int ln = log2i(n), npair = rpb >> 1, h = n / 2 + 1;
-    const float2 *Z = lds_fft<false>(X, Y, n, ln, npair, n, tl);
+    const Ring<P2> ring(n);
+    const int npair = rpb >> 1, h = n / 2 + 1;
+    const float2 *Z = lds_fft_any<false, P2>(X, Y, n, npair, n, tl);
     for (int e = threadIdx.x; e < h * rpb; e += kThreads) {
         const int k = e / rpb, rr = e - k * rpb, pr = rr >> 1;
-        const float2 zk = Z[pr * n + k], znk = Z[pr * n + ((n - k) & (n - 1))];
+        const float2 zk = Z[pr * n + k], znk = Z[pr * n + ring.neg(k)];
         float2 v;
         if ((rr & 1) == 0)   // X_k = (Z_k + conj Z_{n-k}) / 2
             v = make_float2(0.5f * (zk.x + znk.x), 0.5f * (zk.y - znk.y));
@@ -68,17 +88,18 @@ __device__ inline void rows_fwd_tail(int n, int rpb, float2 *X, float2 *Y, const
 // Fused shrinkage + forward row FFT: the right-hand side of the block's rows is
 // computed straight into the packed FFT input in LDS, PX pixels per thread and
 // round with all their loads issued before any of them is computed.
-template <bool IADM, int PX>
+template <bool IADM, int PX, bool P2>
 __global__ __launch_bounds__(kThreads) void k_shrink_rows(ShrinkArgs a, int rpb,
                                                           float2 *__restrict__ S,
                                                           const float2 *__restrict__ tw) {
     const int b = blockIdx.y;
     if (!a.st[b].active) return;
     extern __shared__ float2 lds[];
-    const int n = a.n, ln = log2i(n), npair = rpb >> 1, h = n / 2 + 1;
+    const int n = a.n, npair = rpb >> 1, h = n / 2 + 1;
+    const Ring<P2> ring(n);
     const int bufsz = npair * n + rpb;
     float2 *tl = lds, *X = lds + kMaxN, *Y = X + bufsz;
-    load_twiddles(tl, tw);
+    load_twiddles<P2>(tl, tw, n);
     const int row0 = xcd_block(blockIdx.x, gridDim.x) * rpb;
     float *Xf = reinterpret_cast<float *>(X);
     const int total = rpb * n;
@@ -88,22 +109,23 @@ __global__ __launch_bounds__(kThreads) void k_shrink_rows(ShrinkArgs a, int rpb,
         for (int j = 0; j < PX; ++j) {
             const int e = e0 + j * kThreads;
             if (e < total)
-                in[j] = shrinkdev::load_pix<IADM, (PX > 1 ? 4 : TVCS_PARTIAL_LOADS)>(
-                    a, b, (row0 << ln) + e);
+                in[j] = shrinkdev::load_pix<IADM, (PX > 1 ? 4 : TVCS_PARTIAL_LOADS), P2>(
+                    a, b, ring.mul(row0) + e);
         }
 #pragma unroll
         for (int j = 0; j < PX; ++j) {
             const int e = e0 + j * kThreads;
             if (e >= total) break;
-            const int rr = e >> ln, c = e & (n - 1);
-            const float v = (float)shrinkdev::finish_pix<IADM>(a, b, (row0 << ln) + e, in[j]);
+            const int rr = ring.div(e), c = e - ring.mul(rr);
+            const float v = (float)shrinkdev::finish_pix<IADM>(a, b, ring.mul(row0) + e, in[j]);
             Xf[2 * ((rr >> 1) * n + c) + (rr & 1)] = v;   // even row: real part, odd row: imaginary
         }
     }
     __syncthreads();
-    rows_fwd_tail(n, rpb, X, Y, tl, S + (size_t)b * h * n + row0);
+    rows_fwd_tail<P2>(n, rpb, X, Y, tl, S + (size_t)b * h * n + row0);
 }
 
+template <bool P2>
 __global__ __launch_bounds__(kThreads) void k_cols_solve(int n, int cpb, float2 *__restrict__ S,
                                                          const double *__restrict__ inv_d,
                                                          const float2 *__restrict__ tw,
@@ -111,15 +133,15 @@ __global__ __launch_bounds__(kThreads) void k_cols_solve(int n, int cpb, float2 
     const int b = blockIdx.y;
     if (!st[b].active) return;
     extern __shared__ float2 lds[];
-    const int ln = log2i(n), h = n / 2 + 1;
+    const int h = n / 2 + 1;
     const int k20 = blockIdx.x * cpb;
     const int nc = min(cpb, h - k20);
     float2 *tl = lds, *X = lds + kMaxN, *Y = X + cpb * n;
-    load_twiddles(tl, tw);
+    load_twiddles<P2>(tl, tw, n);
     float2 *col = S + (size_t)b * h * n + (size_t)k20 * n;
     for (int e = threadIdx.x; e < nc * n; e += kThreads) X[e] = col[e];
     __syncthreads();
-    float2 *Z = lds_fft<false>(X, Y, n, ln, nc, n, tl);
+    float2 *Z = lds_fft_any<false, P2>(X, Y, n, nc, n, tl);
     const double *id = inv_d + (size_t)k20 * n;
     for (int e = threadIdx.x; e < nc * n; e += kThreads) {
         const float2 z = Z[e];
@@ -128,7 +150,7 @@ __global__ __launch_bounds__(kThreads) void k_cols_solve(int n, int cpb, float2 
     }
     __syncthreads();
     float2 *W = (Z == X) ? Y : X;
-    const float2 *out = lds_fft<true>(Z, W, n, ln, nc, n, tl);
+    const float2 *out = lds_fft_any<true, P2>(Z, W, n, nc, n, tl);
     for (int e = threadIdx.x; e < nc * n; e += kThreads) col[e] = out[e];
 }
 
@@ -173,7 +195,7 @@ __device__ void stop_rule(ImgState *st, const double *parts, int nparts, int *co
 // finish (counted in `counters`, one zeroed int per image) also applies the stop
 // rule; this needs a device-scope fence per block, cheap for one image but not for
 // thousands of blocks, so batches use k_stop_rule instead.
-template <bool FUSED>
+template <bool FUSED, bool P2>
 __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const float2 *__restrict__ S,
                                                        float *__restrict__ U,
                                                        double *__restrict__ parts,
@@ -183,10 +205,11 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
     const int b = blockIdx.y;
     if (!st[b].active) return;
     extern __shared__ float2 lds[];
-    const int ln = log2i(n), npair = rpb >> 1, h = n / 2 + 1;
+    const int npair = rpb >> 1, h = n / 2 + 1;
+    const Ring<P2> ring(n);
     const int bufsz = npair * n + rpb;
     float2 *tl = lds, *X = lds + kMaxN, *Y = X + bufsz;
-    load_twiddles(tl, tw);
+    load_twiddles<P2>(tl, tw, n);
     const int blk = xcd_block(blockIdx.x, gridDim.x), row0 = blk * rpb;
     // raw half spectra of the block's rows: Y[rr * h + k]
     const float2 *srcS = S + (size_t)b * h * n + row0;
@@ -197,18 +220,18 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
     __syncthreads();
     // full spectrum of x + i y: Z_k = X_k + i Y_k (k <= n/2), conj(X) + i conj(Y) above
     for (int e = threadIdx.x; e < npair * n; e += kThreads) {
-        const int pr = e >> ln, k = e & (n - 1);
+        const int pr = ring.div(e), k = e - ring.mul(pr);
         const bool lo = k <= n / 2;
         const int kk = lo ? k : n - k;
         const float2 x = Y[(2 * pr) * h + kk], y = Y[(2 * pr + 1) * h + kk];
         X[e] = lo ? make_float2(x.x - y.y, x.y + y.x) : make_float2(x.x + y.y, y.x - x.y);
     }
     __syncthreads();
-    const float2 *z = lds_fft<true>(X, Y, n, ln, npair, n, tl);
+    const float2 *z = lds_fft_any<true, P2>(X, Y, n, npair, n, tl);
     float *dstU = U + (size_t)b * n * n + (size_t)row0 * n;
     double du2 = 0.0, u2 = 0.0;
     for (int e = threadIdx.x; e < npair * n; e += kThreads) {
-        const int pr = e >> ln, j = e & (n - 1);
+        const int pr = ring.div(e), j = e - ring.mul(pr);
         const float2 v = z[e];
         float *p0 = dstU + (2 * pr) * n + j, *p1 = p0 + n;
         const double o0 = *p0, o1 = *p1;
@@ -277,7 +300,7 @@ __global__ __launch_bounds__(64) void k_stop_rule(ImgState *__restrict__ st,
 #define TVCS_FFT_ROW_DIV 64    // rows per workgroup = n / TVCS_FFT_ROW_DIV (at least 2)
 #endif
 int rows_per_block(int n, int /*B*/) {
-    return std::max(2, std::min(n / TVCS_FFT_ROW_DIV, 4096 / n));
+    return even_divisor_at_most(n, std::max(2, std::min(n / TVCS_FFT_ROW_DIV, 4096 / n)));
 }
 int cols_per_block(int n, int B) {
     const int h = n / 2 + 1;
@@ -287,8 +310,9 @@ int cols_per_block(int n, int B) {
 
 }  // namespace
 
-void launch_twiddles(float2 *tw, hipStream_t s) {
-    hipLaunchKernelGGL(k_twiddles, dim3((kMaxN + 255) / 256), dim3(256), 0, s, tw);
+void launch_twiddles(int n, float2 *tw, hipStream_t s) {
+    const int L = is_pow2(n) ? kMaxN : n;
+    hipLaunchKernelGGL(k_twiddles, dim3((L + 255) / 256), dim3(256), 0, s, tw, L);
 }
 
 void launch_denominators(int n, double c, double *inv_d, hipStream_t s) {
@@ -300,22 +324,31 @@ void launch_fft_cols_solve(int n, int B, float2 *S, const double *inv_d, const f
                            const ImgState *st, hipStream_t s) {
     const int cpb = cols_per_block(n, B), h = n / 2 + 1;
     const size_t lds = sizeof(float2) * (kMaxN + 2 * cpb * n);
-    hipLaunchKernelGGL(k_cols_solve, dim3((h + cpb - 1) / cpb, B), dim3(kThreads), lds, s, n, cpb,
-                       S, inv_d, tw, st);
+    if (is_pow2(n))
+        hipLaunchKernelGGL(k_cols_solve<true>, dim3((h + cpb - 1) / cpb, B), dim3(kThreads), lds, s,
+                           n, cpb, S, inv_d, tw, st);
+    else
+        hipLaunchKernelGGL(k_cols_solve<false>, dim3((h + cpb - 1) / cpb, B), dim3(kThreads), lds, s,
+                           n, cpb, S, inv_d, tw, st);
 }
 
 void launch_fft_rows_inv(int n, int B, const float2 *S, float *U, double *parts,
                          const float2 *tw, ImgState *st, int *counters, hipStream_t s) {
     const int rpb = rows_per_block(n, B);
     const size_t lds = sizeof(float2) * (kMaxN + 2 * ((rpb / 2) * n + rpb));
+#define TVCS_ROWS_INV(FUSEDV, P2V)                                                            \
+    hipLaunchKernelGGL((k_rows_inv<FUSEDV, P2V>), dim3(n / rpb, B), dim3(kThreads), lds, s, n, rpb, \
+                       S, U, parts, tw, st, counters)
+    const bool p2 = is_pow2(n);
     if (B == 1) {
-        hipLaunchKernelGGL(k_rows_inv<true>, dim3(n / rpb, B), dim3(kThreads), lds, s, n, rpb, S, U,
-                           parts, tw, st, counters);
+        if (p2) TVCS_ROWS_INV(true, true);
+        else TVCS_ROWS_INV(true, false);
     } else {
-        hipLaunchKernelGGL(k_rows_inv<false>, dim3(n / rpb, B), dim3(kThreads), lds, s, n, rpb, S,
-                           U, parts, tw, st, counters);
+        if (p2) TVCS_ROWS_INV(false, true);
+        else TVCS_ROWS_INV(false, false);
         hipLaunchKernelGGL(k_stop_rule, dim3(B), dim3(64), 0, s, st, parts, n / rpb);
     }
+#undef TVCS_ROWS_INV
 }
 
 void launch_shrink_rows(const ShrinkArgs &a, bool iadm, float2 *S, const float2 *tw,
@@ -325,15 +358,26 @@ void launch_shrink_rows(const ShrinkArgs &a, bool iadm, float2 *S, const float2 
     // several pixels per round where the partial sums of g are few (their loads
     // would otherwise cost registers) and each thread has several pixels
     const bool multi = a.nchunk <= 4 && rpb * n >= 2 * kThreads;
-#define TVCS_SHRINK_LAUNCH(IADMV, PXV)                                                         \
-    hipLaunchKernelGGL((k_shrink_rows<IADMV, PXV>), dim3(n / rpb, a.B), dim3(kThreads), lds, s, \
-                       a, rpb, S, tw)
+#define TVCS_SHRINK_LAUNCH(IADMV, PXV, P2V)                                                    \
+    hipLaunchKernelGGL((k_shrink_rows<IADMV, PXV, P2V>), dim3(n / rpb, a.B), dim3(kThreads), lds, \
+                       s, a, rpb, S, tw)
+    const bool p2 = is_pow2(n);
     if (iadm) {
-        if (multi) TVCS_SHRINK_LAUNCH(true, TVCS_SHRINK_PX);
-        else TVCS_SHRINK_LAUNCH(true, 1);
+        if (multi) {
+            if (p2) TVCS_SHRINK_LAUNCH(true, TVCS_SHRINK_PX, true);
+            else TVCS_SHRINK_LAUNCH(true, TVCS_SHRINK_PX, false);
+        } else {
+            if (p2) TVCS_SHRINK_LAUNCH(true, 1, true);
+            else TVCS_SHRINK_LAUNCH(true, 1, false);
+        }
     } else {
-        if (multi) TVCS_SHRINK_LAUNCH(false, TVCS_SHRINK_PX);
-        else TVCS_SHRINK_LAUNCH(false, 1);
+        if (multi) {
+            if (p2) TVCS_SHRINK_LAUNCH(false, TVCS_SHRINK_PX, true);
+            else TVCS_SHRINK_LAUNCH(false, TVCS_SHRINK_PX, false);
+        } else {
+            if (p2) TVCS_SHRINK_LAUNCH(false, 1, true);
+            else TVCS_SHRINK_LAUNCH(false, 1, false);
+        }
     }
 #undef TVCS_SHRINK_LAUNCH
 }

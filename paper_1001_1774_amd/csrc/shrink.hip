@@ -36,13 +36,14 @@ using namespace shrinkdev;
 
 __global__ void k_init_q(int n, const float *__restrict__ U, const double *__restrict__ lam0,
                          double inv_beta, double *__restrict__ Q) {
-    const int b = blockIdx.y, N = n * n, mask = n - 1, ln = log2i(n);
+    const int b = blockIdx.y, N = n * n;
+    const Ring<false> ring(n);
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
-    const int r = p >> ln, c = p & mask;
+    const int r = ring.div(p), c = p - ring.mul(r);
     const float *u = U + (size_t)b * N;
-    const double u0 = u[p], uE = u[(r << ln) | ((c + 1) & mask)],
-                 uS = u[(((r + 1) & mask) << ln) | c];
+    const double u0 = u[p], uE = u[ring.mul(r) + ring.wrap(c + 1)],
+                 uS = u[ring.mul(ring.wrap(r + 1)) + c];
     double q1 = uE - u0, q2 = uS - u0;
     if (lam0) {
         q1 -= lam0[(size_t)b * 2 * N + p] * inv_beta;
@@ -55,14 +56,15 @@ __global__ void k_init_q(int n, const float *__restrict__ U, const double *__res
 __global__ void k_lambda_out(int n, const float *__restrict__ U, const double *__restrict__ Q0,
                              const double *__restrict__ Q1, const ImgState *__restrict__ st,
                              double beta, double *__restrict__ lam) {
-    const int b = blockIdx.y, N = n * n, mask = n - 1, ln = log2i(n);
+    const int b = blockIdx.y, N = n * n;
+    const Ring<false> ring(n);
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     const double *Q = (st[b].iters & 1) ? Q1 : Q0;
-    const int r = p >> ln, c = p & mask;
+    const int r = ring.div(p), c = p - ring.mul(r);
     const float *u = U + (size_t)b * N;
-    const double u0 = u[p], uE = u[(r << ln) | ((c + 1) & mask)],
-                 uS = u[(((r + 1) & mask) << ln) | c];
+    const double u0 = u[p], uE = u[ring.mul(r) + ring.wrap(c + 1)],
+                 uS = u[ring.mul(ring.wrap(r + 1)) + c];
     lam[(size_t)b * 2 * N + p] = beta * ((uE - u0) - Q[(size_t)b * 2 * N + p]);
     lam[(size_t)b * 2 * N + N + p] = beta * ((uS - u0) - Q[(size_t)b * 2 * N + N + p]);
 }
@@ -70,13 +72,14 @@ __global__ void k_lambda_out(int n, const float *__restrict__ U, const double *_
 __global__ __launch_bounds__(256) void k_objective(int n, int m, const float *__restrict__ U,
                                                    const float *__restrict__ R, int ldr,
                                                    double mu, double *__restrict__ obj) {
-    const int b = blockIdx.x, N = n * n, mask = n - 1, ln = log2i(n);
+    const int b = blockIdx.x, N = n * n;
+    const Ring<false> ring(n);
     const float *u = U + (size_t)b * N;
     double tv = 0.0, rr = 0.0;
     for (int p = threadIdx.x; p < N; p += blockDim.x) {
-        const int r = p >> ln, c = p & mask;
-        const double u0 = u[p], d1 = u[(r << ln) | ((c + 1) & mask)] - u0,
-                     d2 = u[(((r + 1) & mask) << ln) | c] - u0;
+        const int r = ring.div(p), c = p - ring.mul(r);
+        const double u0 = u[p], d1 = u[ring.mul(r) + ring.wrap(c + 1)] - u0,
+                     d2 = u[ring.mul(ring.wrap(r + 1)) + c] - u0;
         tv += sqrt(d1 * d1 + d2 * d2);
     }
     for (int i = threadIdx.x; i < m; i += blockDim.x) {

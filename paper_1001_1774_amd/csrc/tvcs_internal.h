@@ -42,6 +42,12 @@ struct ImgState {
 // Largest image side the FFT kernels handle (LDS twiddle table length).
 constexpr int kMaxN = 512;
 
+// Image sides: even, 8 <= n <= kMaxN, no prime factor other than 2, 3 and 5
+// (the FFTs are radix 2/3/4/5; two real rows share one complex transform).
+bool is_pow2(int n);
+bool supported_side(int n);
+int even_divisor_at_most(int n, int want);   // largest even divisor of n <= want (>= 2)
+
 // ---------------------------------------------------------------------------
 // FP32 dense products (gemv.hip).  A is m x N row-major FP32.
 //   rows: R[v*ldr + i] = sum_j A[i*N + j] U[v*ldu + j] - F[v*ldf + i], v < nv
@@ -109,7 +115,8 @@ void launch_objective(int n, int m, int B, const float *U, const float *R, int l
 // Spectrum S: B x (n/2+1) x n complex FP32, k2-major ([b][k2][r]).
 // inv_d: (n/2+1) x n FP64, 1 / (n^2 (4 sin^2(pi k1/n) + 4 sin^2(pi k2/n) + c)).
 // ---------------------------------------------------------------------------
-void launch_twiddles(float2 *tw, hipStream_t s);
+// tw[t] = exp(-2 pi i t / L), L = 512 for power-of-two n, else L = n (kMaxN entries)
+void launch_twiddles(int n, float2 *tw, hipStream_t s);
 void launch_denominators(int n, double c, double *inv_d, hipStream_t s);
 void launch_fft_cols_solve(int n, int B, float2 *S, const double *inv_d, const float2 *tw,
                            const ImgState *st, hipStream_t s);

@@ -55,13 +55,16 @@ def test_argument_errors_without_device(clib):
     assert "NULL" in T.tvcs_last_error()
     assert not T.tvcs_create(A, 0, 8)
     assert "m must be" in T.tvcs_last_error()
-    for n in (7, 4, 1024, 96):
+    for n in (7, 4, 1024, 98, 450 * 2, 15, 6):
         assert not T.tvcs_create(np.zeros((4, n * n), np.float32), 4, n)
-        assert "power of two" in T.tvcs_last_error()
+        assert "prime factor" in T.tvcs_last_error()
     assert not T.tvcs_create_ex(A, 0, 4, 8, 9, None)
     assert "storage" in T.tvcs_last_error()
     assert not T.tvcs_create_ex(A, 0, 4, 8, T.TVCS_A_BF16, None)
-    assert "n >= 16" in T.tvcs_last_error()
+    assert "n a power of two >= 16" in T.tvcs_last_error()
+    assert not T.tvcs_create_ex(np.zeros((4, 24 * 24), np.float32), 0, 4, 24, T.TVCS_A_BF16,
+                                None)
+    assert "n a power of two >= 16" in T.tvcs_last_error()
     # NULL handle
     u = np.zeros(64, np.float32)
     f = np.zeros(4, np.float32)
@@ -89,8 +92,8 @@ def test_argument_errors_without_device(clib):
     assert not T.lib().tvcs_create_dct(None, 4, 8, None)
     assert "rows" in T.tvcs_last_error()
     rows = np.array([0, 5, 63], np.int32)
-    assert not T.tvcs_create_dct(rows, 3, 12)
-    assert "power of two" in T.tvcs_last_error()
+    assert not T.tvcs_create_dct(rows, 3, 14)
+    assert "prime factor" in T.tvcs_last_error()
     assert not T.tvcs_create_dct(rows, 0, 8)
     assert "m must be" in T.tvcs_last_error()
     assert not T.tvcs_create_dct(np.zeros(65, np.int32), 65, 8)

@@ -24,7 +24,7 @@ def dense_partial_dct(n, rows):
     return np.kron(C1, C1)[rows]
 
 
-@pytest.mark.parametrize("n", [4, 8])
+@pytest.mark.parametrize("n", [4, 6, 8, 10])
 def test_operator_equals_the_written_out_matrix(n):
     rng = np.random.default_rng(n)
     rows = np.sort(rng.choice(n * n, size=(n * n) // 3, replace=False))

@@ -46,14 +46,15 @@ def test_dtd_eigenvalues_golden_n4():
     assert np.allclose(O.dtd_eigenvalues(4), _golden("dtd_eig_n4.txt"), atol=1e-14)
 
 
-@pytest.mark.parametrize("n", [4, 8])
+@pytest.mark.parametrize("n", [4, 6, 8, 10, 12])
 def test_dtd_eigenvalues_match_dense(n):
     D1, D2 = dense_D(n)
     ev = np.sort(np.linalg.eigvalsh(D1.T @ D1 + D2.T @ D2))
     assert np.allclose(np.sort(O.dtd_eigenvalues(n).ravel()), ev, atol=1e-11)
 
 
-@pytest.mark.parametrize("n,c", [(4, 0.3), (8, 5.0), (16, 474.0), (16, 1e-3)])
+@pytest.mark.parametrize("n,c", [(4, 0.3), (8, 5.0), (16, 474.0), (16, 1e-3), (6, 2.0),
+                                 (10, 0.7), (12, 40.0), (18, 3.0)])
 def test_solve_u_matches_dense_cholesky(n, c, rng):
     D1, D2 = dense_D(n)
     H = D1.T @ D1 + D2.T @ D2 + c * np.eye(n * n)
