@@ -387,8 +387,9 @@ def bench_dct(args, np, torch, O, synth, tvcs):
     tau = 1.9, beta = 2^6, mu = 500.
       * 128 x 128, one image, tol = 5e-5 (the comparison setting): time, iterations
         and error against the ground truth; a fixed-iteration run against the oracle;
-      * images of 128^2, 256^2 and 512^2 in batches: ms per iteration and the rate
-        of the two products (HIP events, bytes per launch as in dct_product_bytes)."""
+      * images of 128^2, 256^2, 450^2 (mixed-radix transforms) and 512^2 in batches:
+        ms per iteration and the rate of the two products (HIP events, bytes per
+        launch as in dct_product_bytes)."""
     res = {}
     p = synth.make_dct_problem("dct128_r30", 128, 0.3)
     f = torch.from_numpy(p.f[0].astype(np.float32)).cuda()
@@ -411,8 +412,8 @@ def bench_dct(args, np, torch, O, synth, tvcs):
         f"rel_err_vs_fp64_oracle_{K}_iters": float(np.linalg.norm(fixed - ref.u[0]) /
                                                    np.linalg.norm(ref.u[0]))}
     log(f"partial DCT 128^2 tol 5e-5: {it} iterations in {dt * 1e3:.1f} ms")
-    for n, B, Kb in ((128, 1, 500), (128, 64, 300), (256, 64, 200), (512, 16, 100),
-                     (512, 64, 100)):
+    for n, B, Kb in ((128, 1, 500), (128, 64, 300), (256, 64, 200), (450, 16, 100),
+                     (512, 16, 100), (512, 64, 100)):
         q = synth.make_dct_problem(f"dct{n}_b{B}", n, 0.3, batch=B)
         F = torch.from_numpy(q.f.astype(np.float32)).cuda()
         with tvcs.Solver.partial_dct(q.rows, n) as s:
