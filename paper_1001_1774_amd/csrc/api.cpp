@@ -76,7 +76,7 @@ int solve_impl(tvcs_ctx *h, const float *Fin, int B, double mu, double beta, dou
     } else {
         h->apply_At_full(Bp, B, h->F.as<float>(), U, nullptr);   // u^0 = A^T f
     }
-    if (iadm) launch_init_q(h->n, B, U, lam0, beta, h->Q0.as<double>(), h->work);
+    if (iadm) launch_init_q(h->n, B, U, lam0, beta, h->Q0.as<float2>(), h->work);
 
     h->build_graph(B, flags & TVCS_IADM, beta, c, ctau);
     const int launches = (maxit + kGraphIters - 1) / kGraphIters;
@@ -96,7 +96,7 @@ int solve_impl(tvcs_ctx *h, const float *Fin, int B, double mu, double beta, dou
         // lambda^K = beta (D u^K - q^{K-1}); q^{K-1} sits in Q0 or Q1 by the image's
         // iteration parity
         h->lamb.ensure(sizeof(double) * 2 * (size_t)B * N);
-        launch_lambda_out(h->n, B, U, h->Q0.as<double>(), h->Q1.as<double>(), st, beta,
+        launch_lambda_out(h->n, B, U, h->Q0.as<float2>(), h->Q1.as<float2>(), st, beta,
                           h->lamb.as<double>(), h->work);
         TVCS_HIP(hipMemcpyAsync(lam, h->lamb.p, sizeof(double) * 2 * (size_t)B * N,
                                 hipMemcpyDefault, h->work));

@@ -19,9 +19,12 @@ struct D2 {
     double x, y;
 };
 
+// s(z) = max(||z|| - 1/beta, 0) z / ||z|| (eq. (shrink)) as z (1 - (1/beta) / ||z||)
+// for ||z|| > 1/beta and 0 otherwise: one reciprocal square root instead of a
+// square root and a division (0 at z = 0 and at ||z|| = 1/beta; NaN propagates).
 __device__ inline D2 shrink2(D2 z, double inv_beta) {
-    const double t = sqrt(z.x * z.x + z.y * z.y);
-    const double s = t > inv_beta ? (t - inv_beta) / t : 0.0;   // 0 * (0/0) = 0
+    const double t2 = z.x * z.x + z.y * z.y;
+    const double s = t2 > inv_beta * inv_beta ? 1.0 - inv_beta * rsqrt(t2) : 0.0;
     return {z.x * s, z.y * s};
 }
 
@@ -52,11 +55,12 @@ __device__ inline PixIn load_pix(const ShrinkArgs &a, int b, int p) {
     in.uN = U(r - 1, c);
     in.uNE = U(r - 1, c + 1);
     if (IADM) {
-        const double *Q1 = a.Qold + (size_t)b * 2 * N, *Q2 = Q1 + N;
+        const float2 *Q = a.Qold + (size_t)b * N;
         const int pW = ring.mul(r) + ring.wrap(c - 1), pN = ring.mul(ring.wrap(r - 1)) + c;
-        in.o0 = {Q1[p], Q2[p]};
-        in.oW = {Q1[pW], Q2[pW]};
-        in.oN = {Q1[pN], Q2[pN]};
+        const float2 x0 = Q[p], xW = Q[pW], xN = Q[pN];
+        in.o0 = {x0.x, x0.y};
+        in.oW = {xW.x, xW.y};
+        in.oN = {xN.x, xN.y};
     }
     // g_k: fixed-order sum of the A^T r partials, PL loads in flight
     const float *g = a.G + (size_t)(b / a.gnv) * a.g_group_stride + (size_t)(b % a.gnv) * N + p;
@@ -96,9 +100,7 @@ __device__ inline double finish_pix(const ShrinkArgs &a, int b, int p, const Pix
         qW = step(dW, in.oW);
         qN = step(dN, in.oN);
         const int N = a.n * a.n;
-        double *W1 = a.Qnew + (size_t)b * 2 * N;
-        W1[p] = q0.x;
-        W1[N + p] = q0.y;
+        a.Qnew[(size_t)b * N + p] = make_float2((float)q0.x, (float)q0.y);
     } else {
         q0 = shrink2(d0, ib);
         qW = shrink2(dW, ib);

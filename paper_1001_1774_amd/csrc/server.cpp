@@ -135,7 +135,7 @@ struct tvcs_server {
                                     hipMemcpyDeviceToDevice, h->work));
             if (flags & TVCS_IADM)   // replays start on an even iteration: q is read from Q0
                 launch_init_q(h->n, 1, U + (size_t)s * N, nullptr, beta,
-                              h->Q0.as<double>() + (size_t)s * 2 * N, h->work);
+                              h->Q0.as<float2>() + (size_t)s * N, h->work);
         }
     }
 

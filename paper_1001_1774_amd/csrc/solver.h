@@ -119,8 +119,8 @@ struct tvcs_ctx {
         R.ensure(sizeof(float) * Bp * mm);
         P.ensure(sizeof(float) * (size_t)nchunk * Bp * Nn);
         RHS.ensure(sizeof(float) * Bp * Nn);
-        Q0.ensure(sizeof(double) * 2 * B * Nn);
-        Q1.ensure(sizeof(double) * 2 * B * Nn);
+        Q0.ensure(sizeof(float2) * B * Nn);
+        Q1.ensure(sizeof(float2) * B * Nn);
         S.ensure(sizeof(float2) * B * h * n);
         parts.ensure(sizeof(double) * 2 * B * (size_t)n);   // >= n / rows-per-block
         state.ensure(sizeof(ImgState) * B);
@@ -163,7 +163,7 @@ struct tvcs_ctx {
         const size_t Nn = (size_t)N, mm = (size_t)m, h = (size_t)(n / 2 + 1);
         const int nchunk = partial_count(Bp);
         size_t b = sizeof(float) * Bp * (2 * Nn + 2 * mm) + sizeof(float) * (size_t)nchunk * Bp * Nn +
-                   2 * sizeof(double) * 2 * B * Nn + sizeof(float2) * B * h * n +
+                   2 * sizeof(float2) * B * Nn + sizeof(float2) * B * h * n +
                    sizeof(double) * 2 * B * (size_t)n + sizeof(ImgState) * B + sizeof(double) * B +
                    sizeof(int) * B;
         if (lowprec()) b += lowp_work_bytes(lowp, Bp);
@@ -315,8 +315,8 @@ struct tvcs_ctx {
         a.beta = beta;
         a.c = c;
         a.ctau = ctau;
-        a.Qold = parity ? Q1.as<double>() : Q0.as<double>();
-        a.Qnew = parity ? Q0.as<double>() : Q1.as<double>();
+        a.Qold = parity ? Q1.as<float2>() : Q0.as<float2>();
+        a.Qnew = parity ? Q0.as<float2>() : Q1.as<float2>();
         const float2 *twp = tw.as<float2>();
         float2 *Sp = S.as<float2>();
         launch_shrink_rows(a, iadm, Sp, twp, work);

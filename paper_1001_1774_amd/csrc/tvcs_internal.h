@@ -95,16 +95,17 @@ struct ShrinkArgs {
     long long g_group_stride;
     int nchunk;
     long long g_chunk_stride;
-    const double *Qold;    // B x 2N (IADM)
-    double *Qnew;          // B x 2N (IADM)
+    const float2 *Qold;    // B x N pairs (q1, q2) (IADM)
+    float2 *Qnew;          // B x N pairs (IADM)
     double beta, c, ctau;  // c = mu/(beta tau), ctau = c*tau = mu/beta
     const ImgState *st;
 };
-void launch_init_q(int n, int B, const float *U, const double *lam0, double beta, double *Q,
+// q is held as FP32 pairs (q1, q2) per pixel; the arithmetic on it is FP64
+void launch_init_q(int n, int B, const float *U, const double *lam0, double beta, float2 *Q,
                    hipStream_t s);
 // lambda^K = beta (D u^K - q^{K-1}); q^{K-1} is in Q0 when the image's iteration count
 // is even and in Q1 when it is odd (the fields alternate every iteration).
-void launch_lambda_out(int n, int B, const float *U, const double *Q0, const double *Q1,
+void launch_lambda_out(int n, int B, const float *U, const float2 *Q0, const float2 *Q1,
                        const ImgState *st, double beta, double *lam, hipStream_t s);
 // obj[b] = TV(u_b) + mu/2 ||r_b||^2
 void launch_objective(int n, int m, int B, const float *U, const float *R, int ldr, double mu,
