@@ -1,6 +1,7 @@
-// The per-pixel step of the fused shrinkage: differences, 2-D shrinkage, D^T and
-// the right-hand side of the u-step (increment form), shared by k_shrink_rhs and
-// the fused shrink + row-FFT pass.  See shrink.hip for the formulas.
+// Per-pixel pieces of the fused shrinkage (see shrink.hip for the formulas): the
+// 2-D shrinkage, the q update of FTVCS / IADM, the fixed-order sum of the A^T r
+// partials, and the loads and arithmetic of the pixel-parallel form of the pass.
+// Used by the shrink + row-FFT passes in fft.hip and by shrink.hip.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,17 +29,48 @@ __device__ inline D2 shrink2(D2 z, double inv_beta) {
     return {z.x * s, z.y * s};
 }
 
+// q at one pixel from d = D u there and (IADM) the previous q there:
+//   FTVCS: q = s(d);   IADM: q = s(2 d - o) - d + o
+template <bool IADM>
+__device__ inline D2 q_of(D2 d, D2 o, double inv_beta) {
+    if (!IADM) return shrink2(d, inv_beta);
+    const D2 s = shrink2({2.0 * d.x - o.x, 2.0 * d.y - o.y}, inv_beta);
+    return {s.x - d.x + o.x, s.y - d.y + o.y};
+}
+
+// g_k at pixel p of image b: fixed-order sum of the A^T r partials, PL loads in
+// flight.  For nchunk <= PL every PL gives the same bits (the pairwise tree over
+// the first nchunk slots, the rest exact zeros).
+template <int PL>
+__device__ inline double g_at(const ShrinkArgs &a, int b, int p) {
+    const int N = a.n * a.n;
+    const float *g = a.G + (size_t)(b / a.gnv) * a.g_group_stride + (size_t)(b % a.gnv) * N + p;
+    double gs[PL];
+#pragma unroll
+    for (int j = 0; j < PL; ++j) gs[j] = 0.0;
+    int k = 0;
+    for (; k + PL <= a.nchunk; k += PL) {
+#pragma unroll
+        for (int j = 0; j < PL; ++j) gs[j] += (double)g[(size_t)(k + j) * a.g_chunk_stride];
+    }
+    for (int j = 0; k < a.nchunk; ++k, ++j) gs[j] += (double)g[(size_t)k * a.g_chunk_stride];
+#pragma unroll
+    for (int w = PL / 2; w > 0; w >>= 1)
+#pragma unroll
+        for (int j = 0; j < w; ++j) gs[j] += gs[j + w];
+    return gs[0];
+}
+
+// ---- pixel-parallel form (short row blocks): each thread takes whole pixels and
+// recomputes q at the left and upper neighbours it needs for D^T ----------------
 // Everything the right-hand side at one pixel reads from memory.  Loading several
-// pixels' inputs before computing any of them keeps many loads in flight (the
-// pass is latency-bound); the stores of q^k come after all loads of a round.
+// pixels' inputs before computing any of them keeps many loads in flight.
 struct PixIn {
     float u0, uE, uS, uW, uSW, uN, uNE;   // u at (r,c), (r,c+1), (r+1,c), (r,c-1), (r+1,c-1), (r-1,c), (r-1,c+1)
     D2 o0, oW, oN;                        // q^{k-1} at (r,c), (r,c-1), (r-1,c) (IADM)
     double gk;                            // g_k = (A^T (A u - f)) at (r,c)
 };
 
-// PL: partial sums loaded in flight.  For nchunk <= PL every PL gives the same
-// bits (the pairwise tree over the first nchunk slots, the rest exact zeros).
 template <bool IADM, int PL, bool P2>
 __device__ inline PixIn load_pix(const ShrinkArgs &a, int b, int p) {
     const int n = a.n, N = n * n;
@@ -62,22 +94,7 @@ __device__ inline PixIn load_pix(const ShrinkArgs &a, int b, int p) {
         in.oW = {xW.x, xW.y};
         in.oN = {xN.x, xN.y};
     }
-    // g_k: fixed-order sum of the A^T r partials, PL loads in flight
-    const float *g = a.G + (size_t)(b / a.gnv) * a.g_group_stride + (size_t)(b % a.gnv) * N + p;
-    double gs[PL];
-#pragma unroll
-    for (int j = 0; j < PL; ++j) gs[j] = 0.0;
-    int k = 0;
-    for (; k + PL <= a.nchunk; k += PL) {
-#pragma unroll
-        for (int j = 0; j < PL; ++j) gs[j] += (double)g[(size_t)(k + j) * a.g_chunk_stride];
-    }
-    for (int j = 0; k < a.nchunk; ++k, ++j) gs[j] += (double)g[(size_t)k * a.g_chunk_stride];
-#pragma unroll
-    for (int w = PL / 2; w > 0; w >>= 1)
-#pragma unroll
-        for (int j = 0; j < w; ++j) gs[j] += gs[j + w];
-    in.gk = gs[0];
+    in.gk = g_at<PL>(a, b, p);
     return in;
 }
 
@@ -90,21 +107,11 @@ __device__ inline double finish_pix(const ShrinkArgs &a, int b, int p, const Pix
     const D2 dW = {u0 - in.uW, (double)in.uSW - in.uW};                  // D u at (r, c-1)
     const D2 dN = {(double)in.uNE - in.uN, u0 - in.uN};                  // D u at (r-1, c)
     const double ib = 1.0 / a.beta;
-    D2 q0, qW, qN;
+    const D2 q0 = q_of<IADM>(d0, in.o0, ib), qW = q_of<IADM>(dW, in.oW, ib),
+             qN = q_of<IADM>(dN, in.oN, ib);
     if (IADM) {
-        auto step = [&](D2 d, D2 o) {
-            const D2 s = shrink2({2.0 * d.x - o.x, 2.0 * d.y - o.y}, ib);
-            return D2{s.x - d.x + o.x, s.y - d.y + o.y};
-        };
-        q0 = step(d0, in.o0);
-        qW = step(dW, in.oW);
-        qN = step(dN, in.oN);
         const int N = a.n * a.n;
         a.Qnew[(size_t)b * N + p] = make_float2((float)q0.x, (float)q0.y);
-    } else {
-        q0 = shrink2(d0, ib);
-        qW = shrink2(dW, ib);
-        qN = shrink2(dN, ib);
     }
     // D^T (q - D u) at (r, c): needs (q - D u) here, at (r, c-1) and at (r-1, c)
     const double dtq = ((qW.x - dW.x) - (q0.x - d0.x)) + ((qN.y - dN.y) - (q0.y - d0.y));

@@ -85,13 +85,14 @@ __device__ inline void rows_fwd_tail(int n, int rpb, float2 *X, float2 *Y, const
     }
 }
 
-// Fused shrinkage + forward row FFT: the right-hand side of the block's rows is
-// computed straight into the packed FFT input in LDS, PX pixels per thread and
-// round with all their loads issued before any of them is computed.
-template <bool IADM, int PX, bool P2>
-__global__ __launch_bounds__(kThreads) void k_shrink_rows(ShrinkArgs a, int rpb,
-                                                          float2 *__restrict__ S,
-                                                          const float2 *__restrict__ tw) {
+// Fused shrinkage + forward row FFT for short row blocks (fewer than 4 rows: small
+// n, one image spread over the chip): threads take whole pixels, PX per thread and
+// round with all their loads issued before any is computed, and each recomputes
+// q at its left and upper neighbours (formulas in shrink.hip).
+template <bool IADM, int PX, bool P2, int PL>
+__global__ __launch_bounds__(kThreads) void k_shrink_pix(ShrinkArgs a, int rpb,
+                                                         float2 *__restrict__ S,
+                                                         const float2 *__restrict__ tw) {
     const int b = blockIdx.y;
     if (!a.st[b].active) return;
     extern __shared__ float2 lds[];
@@ -108,9 +109,7 @@ __global__ __launch_bounds__(kThreads) void k_shrink_rows(ShrinkArgs a, int rpb,
 #pragma unroll
         for (int j = 0; j < PX; ++j) {
             const int e = e0 + j * kThreads;
-            if (e < total)
-                in[j] = shrinkdev::load_pix<IADM, (PX > 1 ? 4 : TVCS_PARTIAL_LOADS), P2>(
-                    a, b, ring.mul(row0) + e);
+            if (e < total) in[j] = shrinkdev::load_pix<IADM, PL, P2>(a, b, ring.mul(row0) + e);
         }
 #pragma unroll
         for (int j = 0; j < PX; ++j) {
@@ -120,6 +119,123 @@ __global__ __launch_bounds__(kThreads) void k_shrink_rows(ShrinkArgs a, int rpb,
             const float v = (float)shrinkdev::finish_pix<IADM>(a, b, ring.mul(row0) + e, in[j]);
             Xf[2 * ((rr >> 1) * n + c) + (rr & 1)] = v;   // even row: real part, odd row: imaginary
         }
+    }
+    __syncthreads();
+    rows_fwd_tail<P2>(n, rpb, X, Y, tl, S + (size_t)b * h * n + row0);
+}
+
+// Fused shrinkage + forward row FFT for row blocks of 4 rows or more (formulas in
+// shrink.hip).  Each pixel's q,
+// and z = q - D u, is computed once: thread t owns column t (and t + kThreads) of
+// its row group and walks the group's rows downwards, starting one row above them.
+// D^T z at (r, c) takes z_y of (r-1, c) from the walk's previous step (a register)
+// and z_x of (r, c-1) from that step's row of z_x in LDS (double-buffered: one
+// barrier per row).  The right-hand side goes straight into the packed FFT input.
+// Row groups: `groups` groups of n threads when n < kThreads, else one group.
+template <bool IADM, bool P2, int PL>
+__global__ __launch_bounds__(kThreads) void k_shrink_walk(ShrinkArgs a, int rpb, int groups,
+                                                          float2 *__restrict__ S,
+                                                          const float2 *__restrict__ tw) {
+    constexpr int kCols = kMaxN / kThreads;   // columns per thread when n >= kThreads
+    const int b = blockIdx.y;
+    if (!a.st[b].active) return;
+    extern __shared__ float2 lds[];
+    const int n = a.n, N = n * n, h = n / 2 + 1;
+    const Ring<P2> ring(n);
+    const int bufsz = (rpb >> 1) * n + rpb;
+    float2 *tl = lds, *X = lds + kMaxN, *Y = X + bufsz;
+    double *zx = reinterpret_cast<double *>(Y);   // 2 x groups x n, before the FFT uses Y
+    load_twiddles<P2>(tl, tw, n);
+    const int row0 = xcd_block(blockIdx.x, gridDim.x) * rpb;
+    const int rg = rpb / groups;   // own rows per group
+    const int t = threadIdx.x;
+    // threads past groups * n (n < kThreads) own no column and only join barriers
+    const int g = groups > 1 ? min(t / n, groups - 1) : 0;
+    int c[kCols];
+    bool has[kCols];
+#pragma unroll
+    for (int j = 0; j < kCols; ++j) {
+        const int cc = groups > 1 ? t - g * n : t + j * kThreads;
+        has[j] = groups > 1 ? (j == 0 && cc < n) : cc < n;
+        c[j] = has[j] ? cc : 0;
+    }
+    const float *u = a.U + (size_t)b * N;
+    const float2 *qold = a.Qold + (size_t)b * N;
+    float2 *qnew = a.Qnew + (size_t)b * N;
+    const double ib = 1.0 / a.beta;
+    float *Xf = reinterpret_cast<float *>(X);
+    double zy[kCols];
+    float ucur[kCols];
+    // loads of the next step, issued one step ahead: u east and south, q^{k-1}
+    float nE[kCols], nS[kCols];
+    float2 nq[kCols];
+    int r = ring.wrap(row0 + g * rg - 1);
+    auto prefetch = [&](int rr_) {
+        const int rs = ring.wrap(rr_ + 1);
+#pragma unroll
+        for (int j = 0; j < kCols; ++j) {
+            if (!has[j]) continue;
+            nE[j] = u[ring.mul(rr_) + ring.wrap(c[j] + 1)];
+            nS[j] = u[ring.mul(rs) + c[j]];
+            if (IADM) nq[j] = qold[ring.mul(rr_) + c[j]];
+        }
+    };
+#pragma unroll
+    for (int j = 0; j < kCols; ++j) {
+        zy[j] = 0.0;
+        ucur[j] = has[j] ? u[ring.mul(r) + c[j]] : 0.f;
+        nE[j] = nS[j] = 0.f;
+        nq[j] = make_float2(0.f, 0.f);
+    }
+    prefetch(r);
+    for (int s = 0; s <= rg; ++s) {
+        const int rn = ring.wrap(r + 1);
+        float uE[kCols], uS[kCols];
+        float2 qo[kCols];
+#pragma unroll
+        for (int j = 0; j < kCols; ++j) {
+            uE[j] = nE[j];
+            uS[j] = nS[j];
+            qo[j] = nq[j];
+        }
+        if (s < rg) prefetch(rn);
+        double gk[kCols];
+#pragma unroll
+        for (int j = 0; j < kCols; ++j)
+            gk[j] = (s > 0 && has[j]) ? shrinkdev::g_at<PL>(a, b, ring.mul(r) + c[j]) : 0.0;
+        double zxv[kCols], zyv[kCols];
+#pragma unroll
+        for (int j = 0; j < kCols; ++j) {
+            zxv[j] = zyv[j] = 0.0;
+            if (!has[j]) continue;
+            const int p = ring.mul(r) + c[j];
+            const shrinkdev::D2 d = {(double)uE[j] - ucur[j], (double)uS[j] - ucur[j]};
+            const shrinkdev::D2 o = {(double)qo[j].x, (double)qo[j].y};
+            const shrinkdev::D2 q = shrinkdev::q_of<IADM>(d, o, ib);
+            if (IADM && s > 0) qnew[p] = make_float2((float)q.x, (float)q.y);
+            zxv[j] = q.x - d.x;
+            zyv[j] = q.y - d.y;
+            ucur[j] = uS[j];
+        }
+        if (s > 0) {   // the same for every thread
+            double *zrow = zx + ((s & 1) * groups + g) * n;
+#pragma unroll
+            for (int j = 0; j < kCols; ++j)
+                if (has[j]) zrow[c[j]] = zxv[j];
+            __syncthreads();
+            const int rr = g * rg + s - 1;   // row within the block
+#pragma unroll
+            for (int j = 0; j < kCols; ++j) {
+                if (!has[j]) continue;
+                const double zw = zrow[ring.wrap(c[j] - 1)];
+                // D^T z at (r, c) - c tau g_k: the right side of the increment
+                const double rhs = (zw - zxv[j]) + (zy[j] - zyv[j]) - a.ctau * gk[j];
+                Xf[2 * ((rr >> 1) * n + c[j]) + (rr & 1)] = (float)rhs;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kCols; ++j) zy[j] = zyv[j];
+        r = rn;
     }
     __syncthreads();
     rows_fwd_tail<P2>(n, rpb, X, Y, tl, S + (size_t)b * h * n + row0);
@@ -293,9 +409,6 @@ __global__ __launch_bounds__(64) void k_stop_rule(ImgState *__restrict__ st,
 // cpb * n <= 2048 complex per buffer).  The row blocking fixes the order in which
 // the stop-rule norms are summed, so it depends on n only: an image's iterates and
 // stop decisions are then the same whatever batch it is solved in.
-#ifndef TVCS_SHRINK_PX
-#define TVCS_SHRINK_PX 4       // pixels per thread and round of the batched shrink pass
-#endif
 #ifndef TVCS_FFT_ROW_DIV
 #define TVCS_FFT_ROW_DIV 64    // rows per workgroup = n / TVCS_FFT_ROW_DIV (at least 2)
 #endif
@@ -351,35 +464,68 @@ void launch_fft_rows_inv(int n, int B, const float2 *S, float *U, double *parts,
 #undef TVCS_ROWS_INV
 }
 
+#ifndef TVCS_SHRINK_PX
+#define TVCS_SHRINK_PX 4       // pixels per thread and round of the pixel-parallel pass
+#endif
+#ifndef TVCS_SHRINK_WALK_ROWS
+#define TVCS_SHRINK_WALK_ROWS 4   // row blocks at least this tall use the column walk
+#endif
 void launch_shrink_rows(const ShrinkArgs &a, bool iadm, float2 *S, const float2 *tw,
                         hipStream_t s) {
     const int n = a.n, rpb = rows_per_block(n, a.B);
-    const size_t lds = sizeof(float2) * (kMaxN + 2 * ((rpb / 2) * n + rpb));
-    // several pixels per round where the partial sums of g are few (their loads
-    // would otherwise cost registers) and each thread has several pixels
-    const bool multi = a.nchunk <= 4 && rpb * n >= 2 * kThreads;
-#define TVCS_SHRINK_LAUNCH(IADMV, PXV, P2V)                                                    \
-    hipLaunchKernelGGL((k_shrink_rows<IADMV, PXV, P2V>), dim3(n / rpb, a.B), dim3(kThreads), lds, \
-                       s, a, rpb, S, tw)
+    const dim3 grid(n / rpb, a.B);
+    const size_t bufsz = (size_t)(rpb / 2) * n + rpb;
     const bool p2 = is_pow2(n);
-    if (iadm) {
-        if (multi) {
-            if (p2) TVCS_SHRINK_LAUNCH(true, TVCS_SHRINK_PX, true);
-            else TVCS_SHRINK_LAUNCH(true, TVCS_SHRINK_PX, false);
+    // few partial sums of g: fewer loads in flight, fewer registers (same bits)
+    const bool few = a.nchunk <= 4;
+    if (rpb < TVCS_SHRINK_WALK_ROWS) {
+        const size_t lds = sizeof(float2) * (kMaxN + 2 * bufsz);
+        // several pixels per round where the partial sums of g are few (their loads
+        // would otherwise cost registers) and each thread has several pixels
+        const bool multi = few && rpb * n >= 2 * kThreads;
+#define TVCS_PIX(IADMV, PXV, PLV)                                                          \
+    do {                                                                                   \
+        if (p2)                                                                            \
+            hipLaunchKernelGGL((k_shrink_pix<IADMV, PXV, true, PLV>), grid, dim3(kThreads), \
+                               lds, s, a, rpb, S, tw);                                     \
+        else                                                                               \
+            hipLaunchKernelGGL((k_shrink_pix<IADMV, PXV, false, PLV>), grid, dim3(kThreads), \
+                               lds, s, a, rpb, S, tw);                                     \
+    } while (0)
+        if (iadm) {
+            if (multi) TVCS_PIX(true, TVCS_SHRINK_PX, 4);
+            else if (few) TVCS_PIX(true, 1, 4);
+            else TVCS_PIX(true, 1, TVCS_PARTIAL_LOADS);
         } else {
-            if (p2) TVCS_SHRINK_LAUNCH(true, 1, true);
-            else TVCS_SHRINK_LAUNCH(true, 1, false);
+            if (multi) TVCS_PIX(false, TVCS_SHRINK_PX, 4);
+            else if (few) TVCS_PIX(false, 1, 4);
+            else TVCS_PIX(false, 1, TVCS_PARTIAL_LOADS);
         }
-    } else {
-        if (multi) {
-            if (p2) TVCS_SHRINK_LAUNCH(false, TVCS_SHRINK_PX, true);
-            else TVCS_SHRINK_LAUNCH(false, TVCS_SHRINK_PX, false);
-        } else {
-            if (p2) TVCS_SHRINK_LAUNCH(false, 1, true);
-            else TVCS_SHRINK_LAUNCH(false, 1, false);
-        }
+#undef TVCS_PIX
+        return;
     }
-#undef TVCS_SHRINK_LAUNCH
+    // column walk: as many row groups of n threads as fit, dividing the block's rows
+    int groups = std::max(1, std::min(rpb, kThreads / n));
+    while (rpb % groups) --groups;
+    const size_t ybytes = std::max(sizeof(float2) * bufsz, sizeof(double) * 2 * groups * n);
+    const size_t lds = sizeof(float2) * (kMaxN + bufsz) + ybytes;
+#define TVCS_WALK(IADMV, P2V, PLV)                                                           \
+    hipLaunchKernelGGL((k_shrink_walk<IADMV, P2V, PLV>), grid, dim3(kThreads), lds, s, a, rpb, \
+                       groups, S, tw)
+#define TVCS_WALK_PL(IADMV, P2V)                                 \
+    do {                                                         \
+        if (few) TVCS_WALK(IADMV, P2V, 4);                       \
+        else TVCS_WALK(IADMV, P2V, TVCS_PARTIAL_LOADS);          \
+    } while (0)
+    if (iadm) {
+        if (p2) TVCS_WALK_PL(true, true);
+        else TVCS_WALK_PL(true, false);
+    } else {
+        if (p2) TVCS_WALK_PL(false, true);
+        else TVCS_WALK_PL(false, false);
+    }
+#undef TVCS_WALK_PL
+#undef TVCS_WALK
 }
 
 }  // namespace tvcs

@@ -27,9 +27,10 @@
 //
 // D is the periodic forward difference: (D u)[r,c] = (u[r,c+1] - u[r,c],
 // u[r+1,c] - u[r,c]); (D^T q)[r,c] = q1[r,c-1] - q1[r,c] + q2[r-1,c] - q2[r,c].
-// Each thread owns one pixel and recomputes q at its left and upper neighbours,
-// so no LDS halo exchange or second pass is needed; the neighbours' u and q come
-// from L1/L2.  All per-pixel arithmetic is FP64; rhs is rounded to FP32 for the FFT.
+// The fused pass (k_shrink_rows in fft.hip) computes each pixel's q once: threads
+// walk down columns, keep z = q - D u of the row above in a register and exchange
+// the left neighbour's z through LDS.  All per-pixel arithmetic is FP64; rhs is
+// rounded to FP32 for the FFT.
 #include "device_shrink.h"
 
 namespace tvcs {
