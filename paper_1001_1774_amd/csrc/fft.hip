@@ -412,12 +412,27 @@ __global__ __launch_bounds__(64) void k_stop_rule(ImgState *__restrict__ st,
 #ifndef TVCS_FFT_ROW_DIV
 #define TVCS_FFT_ROW_DIV 64    // rows per workgroup = n / TVCS_FFT_ROW_DIV (at least 2)
 #endif
+#ifndef TVCS_FFT_ROW_MAX
+#define TVCS_FFT_ROW_MAX 4     // at most this many rows per workgroup (measured best at 512)
+#endif
 int rows_per_block(int n, int /*B*/) {
-    return even_divisor_at_most(n, std::max(2, std::min(n / TVCS_FFT_ROW_DIV, 4096 / n)));
+    const int want =
+        std::max(2, std::min(std::min(n / TVCS_FFT_ROW_DIV, 4096 / n), TVCS_FFT_ROW_MAX));
+    int d = even_divisor_at_most(n, want);
+    if (d < want)   // sides with factors 3 and 5: the nearest even divisor above, within 2x
+        for (int e = want + (want & 1); e <= 2 * want && e <= n; e += 2)
+            if (n % e == 0) {
+                d = e;
+                break;
+            }
+    return d;
 }
+#ifndef TVCS_FFT_COLS_BATCH
+#define TVCS_FFT_COLS_BATCH 2   // columns per workgroup of the batched column pass
+#endif
 int cols_per_block(int n, int B) {
     const int h = n / 2 + 1;
-    int cpb = B == 1 ? std::max(1, h / 32) : 8;
+    int cpb = B == 1 ? std::max(1, h / 32) : TVCS_FFT_COLS_BATCH;
     return std::max(1, std::min(std::min(cpb, 2048 / n), h));
 }
 
