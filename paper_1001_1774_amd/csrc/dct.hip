@@ -140,8 +140,9 @@ __global__ __launch_bounds__(kThreads) void k_dct_rows_fwd(int n, int lines,
     __syncthreads();
     const float2 *Z = lds_fft_any<false, P2>(L.X, L.Y, n, lines >> 1, n, L.tl);
     float *dst = T + (size_t)b * N + row0;
+    const float rlines = 1.0f / (float)lines;
     for (int e = threadIdx.x; e < lines * n; e += kThreads) {
-        const int k = e / lines, l = e - k * lines;
+        const int k = div_by(e, lines, rlines), l = e - k * lines;
         dst[(size_t)k * n + l] = dct_coef<P2>(Z, L.dt, n, l, k);
     }
 }
@@ -225,8 +226,9 @@ __global__ __launch_bounds__(kThreads) void k_dct_rows_inv(int n, int lines,
     const int N = n * n, row0 = xcd_block(blockIdx.x, gridDim.x) * lines;
     const float *src = T + (size_t)b * N + row0;
     float *A = reinterpret_cast<float *>(L.Y);
+    const float rlines = 1.0f / (float)lines;
     for (int e = threadIdx.x; e < lines * n; e += kThreads) {
-        const int k = e / lines, l = e - k * lines;
+        const int k = div_by(e, lines, rlines), l = e - k * lines;
         A[l * n + k] = src[(size_t)k * n + l];
     }
     __syncthreads();

@@ -81,15 +81,25 @@ __device__ float2 *lds_fft(float2 *src, float2 *dst, int L, int logL, int nf, in
 __device__ inline int log2i(int n) { return __ffs(n) - 1; }
 
 // ---- mixed radix: any n = 2^a 3^b 5^c ---------------------------------------
-// Stages take radix 4 while it divides the remaining length, then 2, 3 and 5.
+#ifndef TVCS_FFT_R8
+#define TVCS_FFT_R8 0   // radix-8 stages (and powers of two through this code): measured
+#endif                  // slower than radix 4 (0.478 vs 0.465 ms per 512^2 x 64 DCT iteration)
+// Stages take radix 4 while it divides the remaining length (8 first with
+// TVCS_FFT_R8), then 2, 3 and 5.
 // Stage (radix R, Ns = product of the earlier radices, q = L / R): for j < q,
 // k = j mod Ns, the inputs x[j + r q] (r < R) are multiplied by w^{r k} with
 // w = exp(-+2 pi i / (Ns R)), transformed by a length-R DFT, and output q goes to
 // ((j / Ns) Ns R + k + q Ns): the Stockham autosort order of the radix-4 code above,
-// generalised.  Twiddles come from an L-entry table exp(-2 pi i t / L): w^{r k} is
-// entry r k L / (Ns R).
+// generalised.  Twiddles come from a table exp(-2 pi i t / TL) with TL = L * tscale
+// (the 512-entry table for powers of two, an L-entry table otherwise): w^{r k} is
+// entry r k tscale L / (Ns R).  Fewer, wider stages mean fewer LDS round trips and
+// barriers.
 __device__ inline int next_radix(int rest) {
-    return (rest & 3) == 0 ? 4 : (rest & 1) == 0 ? 2 : rest % 3 == 0 ? 3 : 5;
+    return (TVCS_FFT_R8 && (rest & 7) == 0) ? 8
+           : (rest & 3) == 0                ? 4
+           : (rest & 1) == 0                ? 2
+           : rest % 3 == 0                  ? 3
+                                            : 5;
 }
 
 // -i z (forward) or +i z (inverse)
@@ -119,6 +129,25 @@ __device__ inline void dft_small(float2 *v) {
         v[1] = b + mid;
         v[2] = a - c;
         v[3] = b - mid;
+    } else if (R == 8) {   // two length-4 DFTs (even, odd inputs) and a radix-2 step
+        float2 e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+        dft_small<4, INV>(e);
+        dft_small<4, INV>(o);
+        constexpr float r2 = 0.707106781186547524f;   // 1 / sqrt(2)
+        // o_q times w8^q, w8 = exp(-+ i pi / 4)
+        const float2 t1 = INV ? make_float2(r2 * (o[1].x - o[1].y), r2 * (o[1].x + o[1].y))
+                              : make_float2(r2 * (o[1].x + o[1].y), r2 * (o[1].y - o[1].x));
+        const float2 t2 = rot<INV>(o[2]);
+        const float2 t3 = INV ? make_float2(-r2 * (o[3].x + o[3].y), r2 * (o[3].x - o[3].y))
+                              : make_float2(r2 * (o[3].y - o[3].x), -r2 * (o[3].x + o[3].y));
+        v[0] = e[0] + o[0];
+        v[4] = e[0] - o[0];
+        v[1] = e[1] + t1;
+        v[5] = e[1] - t1;
+        v[2] = e[2] + t2;
+        v[6] = e[2] - t2;
+        v[3] = e[3] + t3;
+        v[7] = e[3] - t3;
     } else {   // R == 5
         constexpr float c1 = 0.309016994374947424f, c2 = -0.809016994374947424f;   // cos(2pi/5), cos(4pi/5)
         constexpr float s1 = 0.951056516295153572f, s2 = 0.587785252292473129f;    // sin(2pi/5), sin(4pi/5)
@@ -134,13 +163,16 @@ __device__ inline void dft_small(float2 *v) {
     }
 }
 
-template <bool INV, int R>
+// P2: L and Ns are powers of two, so the index arithmetic is shifts and masks.
+template <bool INV, int R, bool P2>
 __device__ inline void mixed_stage(const float2 *src, float2 *dst, int L, int Ns, int nf, int fs,
-                                   const float2 *tw) {
-    const int q = L / R, tstep = L / (Ns * R);
+                                   const float2 *tw, int tscale) {
+    const int q = L / R, tstep = (L / (Ns * R)) * tscale;
+    const int lq = P2 ? __ffs(q) - 1 : 0, lNs = P2 ? __ffs(Ns) - 1 : 0;
+    const float rq = P2 ? 0.f : 1.0f / (float)q, rNs = P2 ? 0.f : 1.0f / (float)Ns;
     for (int t = threadIdx.x; t < nf * q; t += kThreads) {
-        const int f = t / q, j = t - f * q;
-        const int k = j % Ns;
+        const int f = P2 ? t >> lq : div_by(t, q, rq), j = t - f * q;
+        const int jn = P2 ? j >> lNs : div_by(j, Ns, rNs), k = j - jn * Ns;
         const float2 *s = src + f * fs;
         float2 v[R];
 #pragma unroll
@@ -149,7 +181,7 @@ __device__ inline void mixed_stage(const float2 *src, float2 *dst, int L, int Ns
 #pragma unroll
         for (int r = 1; r < R; ++r) v[r] = INV ? cmulc(v[r], tw[r * step]) : cmul(v[r], tw[r * step]);
         dft_small<R, INV>(v);
-        float2 *o = dst + f * fs + (j / Ns) * Ns * R + k;
+        float2 *o = dst + f * fs + jn * Ns * R + k;
 #pragma unroll
         for (int r = 0; r < R; ++r) o[r * Ns] = v[r];
     }
@@ -157,15 +189,17 @@ __device__ inline void mixed_stage(const float2 *src, float2 *dst, int L, int Ns
 
 // nf transforms of length L (any 2^a 3^b 5^c) at src[f*fs ..]; tw: L-entry table.
 // Returns the buffer holding the result.  Ends with a barrier.
-template <bool INV>
+template <bool INV, bool P2>
 __device__ float2 *lds_fft_mixed(float2 *src, float2 *dst, int L, int nf, int fs,
-                                 const float2 *tw) {
+                                 const float2 *tw, int tscale) {
     for (int Ns = 1; Ns < L;) {
         const int R = next_radix(L / Ns);   // the same for every thread
-        if (R == 4) mixed_stage<INV, 4>(src, dst, L, Ns, nf, fs, tw);
-        else if (R == 2) mixed_stage<INV, 2>(src, dst, L, Ns, nf, fs, tw);
-        else if (R == 3) mixed_stage<INV, 3>(src, dst, L, Ns, nf, fs, tw);
-        else mixed_stage<INV, 5>(src, dst, L, Ns, nf, fs, tw);
+        if (R == 8) mixed_stage<INV, 8, P2>(src, dst, L, Ns, nf, fs, tw, tscale);
+        else if (R == 4) mixed_stage<INV, 4, P2>(src, dst, L, Ns, nf, fs, tw, tscale);
+        else if (R == 2) mixed_stage<INV, 2, P2>(src, dst, L, Ns, nf, fs, tw, tscale);
+        else if (P2) __builtin_unreachable();
+        else if (R == 3) mixed_stage<INV, 3, false>(src, dst, L, Ns, nf, fs, tw, tscale);
+        else mixed_stage<INV, 5, false>(src, dst, L, Ns, nf, fs, tw, tscale);
         __syncthreads();
         float2 *x = src;
         src = dst;
@@ -175,13 +209,12 @@ __device__ float2 *lds_fft_mixed(float2 *src, float2 *dst, int L, int nf, int fs
     return src;
 }
 
-// Power-of-two lengths use the radix-4 code (512-entry table), others the mixed
-// radix code (L-entry table).
+// Powers of two use the 512-entry table, other lengths an L-entry table.
 template <bool INV, bool P2>
 __device__ inline float2 *lds_fft_any(float2 *src, float2 *dst, int L, int nf, int fs,
                                       const float2 *tw) {
-    if (P2) return lds_fft<INV>(src, dst, L, log2i(L), nf, fs, tw);
-    return lds_fft_mixed<INV>(src, dst, L, nf, fs, tw);
+    if (P2 && !TVCS_FFT_R8) return lds_fft<INV>(src, dst, L, log2i(L), nf, fs, tw);
+    return lds_fft_mixed<INV, P2>(src, dst, L, nf, fs, tw, P2 ? kMaxN / L : 1);
 }
 
 #ifndef TVCS_XCD_ROWS

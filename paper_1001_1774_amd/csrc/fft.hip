@@ -73,8 +73,9 @@ __device__ inline void rows_fwd_tail(int n, int rpb, float2 *X, float2 *Y, const
     const Ring<P2> ring(n);
     const int npair = rpb >> 1, h = n / 2 + 1;
     const float2 *Z = lds_fft_any<false, P2>(X, Y, n, npair, n, tl);
+    const float rrpb = 1.0f / (float)rpb;
     for (int e = threadIdx.x; e < h * rpb; e += kThreads) {
-        const int k = e / rpb, rr = e - k * rpb, pr = rr >> 1;
+        const int k = div_by(e, rpb, rrpb), rr = e - k * rpb, pr = rr >> 1;
         const float2 zk = Z[pr * n + k], znk = Z[pr * n + ring.neg(k)];
         float2 v;
         if ((rr & 1) == 0)   // X_k = (Z_k + conj Z_{n-k}) / 2
@@ -329,8 +330,9 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
     const int blk = xcd_block(blockIdx.x, gridDim.x), row0 = blk * rpb;
     // raw half spectra of the block's rows: Y[rr * h + k]
     const float2 *srcS = S + (size_t)b * h * n + row0;
+    const float rrpb = 1.0f / (float)rpb;
     for (int e = threadIdx.x; e < h * rpb; e += kThreads) {
-        const int k = e / rpb, rr = e - k * rpb;
+        const int k = div_by(e, rpb, rrpb), rr = e - k * rpb;
         Y[rr * h + k] = srcS[(size_t)k * n + rr];
     }
     __syncthreads();
