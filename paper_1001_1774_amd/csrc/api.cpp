@@ -77,6 +77,7 @@ int solve_impl(tvcs_ctx *h, const float *Fin, int B, double mu, double beta, dou
         h->apply_At_full(Bp, B, h->F.as<float>(), U, nullptr);   // u^0 = A^T f
     }
     if (iadm) launch_init_q(h->n, B, U, lam0, beta, h->Q0.as<float2>(), h->work);
+    h->seed_dct_rows(B);
 
     h->build_graph(B, flags & TVCS_IADM, beta, c, ctau);
     const int launches = (maxit + kGraphIters - 1) / kGraphIters;

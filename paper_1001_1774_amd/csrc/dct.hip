@@ -45,10 +45,6 @@ __global__ void k_dct_table(int n, float4 *tab) {
     tab[k] = make_float4((float)(w * c), (float)(-w * s), (float)(t * c), (float)(t * s));
 }
 
-__device__ inline int makhoul_pos(int j, int n) {   // position of x_j in v
-    return (j & 1) ? n - 1 - (j >> 1) : (j >> 1);
-}
-
 // LDS of every pass: the two tables and two FFT buffers of (lines / 2) * n complex.
 // Real staging (lines * n floats) uses whichever FFT buffer is idle at the time.
 struct DctLds {
@@ -76,21 +72,6 @@ template <bool P2>
 __device__ inline void load_tables(const DctLds &L, int n, const float2 *tw, const float4 *tab) {
     load_twiddles<P2>(L.tl, tw, n);
     for (int k = threadIdx.x; k < n; k += kThreads) L.dt[k] = tab[k];
-}
-
-// Forward DCT-II of the `lines` real lines staged in L.X (already reordered, two
-// lines per complex transform).  Returns the FFT output buffer; the coefficient
-// k of line l is then dct_coef(Z, L, l, k).
-template <bool P2>
-__device__ inline float dct_coef(const float2 *Z, const float4 *dt, int n, int l, int k) {
-    const float2 zk = Z[(l >> 1) * n + k], znk = Z[(l >> 1) * n + Ring<P2>(n).neg(k)];
-    float2 v;
-    if ((l & 1) == 0)   // V of the real part: (Z_k + conj Z_{n-k}) / 2
-        v = make_float2(0.5f * (zk.x + znk.x), 0.5f * (zk.y - znk.y));
-    else                // V of the imaginary part: (Z_k - conj Z_{n-k}) / (2i)
-        v = make_float2(0.5f * (zk.y + znk.y), -0.5f * (zk.x - znk.x));
-    const float4 t = dt[k];
-    return t.x * v.x - t.y * v.y;   // Re(w_k e^{-i pi k/(2n)} V_k)
 }
 
 // Inverse: coefficients of `lines` lines in A[l * n + k] -> spectra of the
@@ -255,7 +236,7 @@ __global__ void k_permute(int m, const int *__restrict__ perm, const float *__re
 // Lines (rows or columns) per workgroup: 2048 values per block where the image
 // allows it, at least one pair.
 #ifndef TVCS_DCT_LINE_VALUES
-#define TVCS_DCT_LINE_VALUES 2048   // values per workgroup of the DCT passes
+#define TVCS_DCT_LINE_VALUES 1024   // values per workgroup of the DCT passes
 #endif
 int dct_lines(int n) {
     return even_divisor_at_most(n, std::max(2, std::min(n, std::min(16, TVCS_DCT_LINE_VALUES / n))));
@@ -270,15 +251,26 @@ void launch_dct_table(int n, float4 *tab, hipStream_t s) {
     hipLaunchKernelGGL(k_dct_table, dim3((n + 255) / 256), dim3(256), 0, s, n, tab);
 }
 
-void launch_dct_forward(int n, int B, const float *U, float *T, const int *selT, const float *F,
-                        int ldf, float *R, int ldr, bool adjoint, const float2 *tw,
-                        const float4 *tab, const ImgState *st, hipStream_t s) {
+void launch_dct_rows_fwd(int n, int B, const float *U, float *T, const float2 *tw,
+                         const float4 *tab, const ImgState *st, hipStream_t s) {
     const int lines = dct_lines(n);
     const size_t lds = dct_lds_bytes(n, lines);
     const dim3 grid(n / lines, B);
-#define TVCS_DCT_FWD(P2V)                                                                         \
-    hipLaunchKernelGGL(k_dct_rows_fwd<P2V>, grid, dim3(kThreads), lds, s, n, lines, U, T, tw, tab, \
-                       st);                                                                       \
+    if (is_pow2(n))
+        hipLaunchKernelGGL(k_dct_rows_fwd<true>, grid, dim3(kThreads), lds, s, n, lines, U, T, tw,
+                           tab, st);
+    else
+        hipLaunchKernelGGL(k_dct_rows_fwd<false>, grid, dim3(kThreads), lds, s, n, lines, U, T, tw,
+                           tab, st);
+}
+
+void launch_dct_cols_fwd(int n, int B, float *T, const int *selT, const float *F, int ldf,
+                         float *R, int ldr, bool adjoint, const float2 *tw, const float4 *tab,
+                         const ImgState *st, hipStream_t s) {
+    const int lines = dct_lines(n);
+    const size_t lds = dct_lds_bytes(n, lines);
+    const dim3 grid(n / lines, B);
+#define TVCS_DCT_COLS(P2V)                                                                        \
     if (adjoint)                                                                                  \
         hipLaunchKernelGGL((k_dct_cols<true, true, P2V>), grid, dim3(kThreads), lds, s, n, lines, \
                            T, selT, F, ldf, R, ldr, tw, tab, st);                                 \
@@ -286,11 +278,18 @@ void launch_dct_forward(int n, int B, const float *U, float *T, const int *selT,
         hipLaunchKernelGGL((k_dct_cols<true, false, P2V>), grid, dim3(kThreads), lds, s, n, lines, \
                            T, selT, F, ldf, R, ldr, tw, tab, st)
     if (is_pow2(n)) {
-        TVCS_DCT_FWD(true);
+        TVCS_DCT_COLS(true);
     } else {
-        TVCS_DCT_FWD(false);
+        TVCS_DCT_COLS(false);
     }
-#undef TVCS_DCT_FWD
+#undef TVCS_DCT_COLS
+}
+
+void launch_dct_forward(int n, int B, const float *U, float *T, const int *selT, const float *F,
+                        int ldf, float *R, int ldr, bool adjoint, const float2 *tw,
+                        const float4 *tab, const ImgState *st, hipStream_t s) {
+    launch_dct_rows_fwd(n, B, U, T, tw, tab, st, s);
+    launch_dct_cols_fwd(n, B, T, selT, F, ldf, R, ldr, adjoint, tw, tab, st, s);
 }
 
 void launch_dct_adjoint(int n, int B, const float *R, int ldr, float *T, const int *selT,

@@ -229,6 +229,28 @@ __device__ inline int xcd_block(int x, int gx) {
     return (!TVCS_XCD_ROWS || (gx & 7)) ? x : (x & 7) * (gx >> 3) + (x >> 3);
 }
 
+// ---- DCT-II of real lines through one complex FFT (Makhoul): shared by the
+// partial-DCT passes and the inverse row FFT that produces the next iteration's
+// row transforms -------------------------------------------------------------------
+__device__ inline int makhoul_pos(int j, int n) {   // position of x_j in the reordered v
+    return (j & 1) ? n - 1 - (j >> 1) : (j >> 1);
+}
+
+// Coefficient k of line l after the FFT of the reordered lines (two per complex
+// transform: line l is component l & 1 of pair l >> 1); dt[k] = (w_k cos, -w_k sin,
+// ...) of pi k / 2n.
+template <bool P2>
+__device__ inline float dct_coef(const float2 *Z, const float4 *dt, int n, int l, int k) {
+    const float2 zk = Z[(l >> 1) * n + k], znk = Z[(l >> 1) * n + Ring<P2>(n).neg(k)];
+    float2 v;
+    if ((l & 1) == 0)   // V of the real part: (Z_k + conj Z_{n-k}) / 2
+        v = make_float2(0.5f * (zk.x + znk.x), 0.5f * (zk.y - znk.y));
+    else                // V of the imaginary part: (Z_k - conj Z_{n-k}) / (2i)
+        v = make_float2(0.5f * (zk.y + znk.y), -0.5f * (zk.x - znk.x));
+    const float4 t = dt[k];
+    return t.x * v.x - t.y * v.y;   // Re(w_k e^{-i pi k/(2n)} V_k)
+}
+
 // the twiddle table of a length-n transform: 512 entries for powers of two, n otherwise
 template <bool P2>
 __device__ inline void load_twiddles(float2 *tl, const float2 *tw, int n) {

@@ -312,13 +312,18 @@ __device__ void stop_rule(ImgState *st, const double *parts, int nparts, int *co
 // finish (counted in `counters`, one zeroed int per image) also applies the stop
 // rule; this needs a device-scope fence per block, cheap for one image but not for
 // thousands of blocks, so batches use k_stop_rule instead.
+// With T non-null (the partial-DCT operator) the block also transforms its new
+// rows of u (DCT-II along each row, the first pass of the next iteration's
+// forward product) and writes them column-major to T, as the DCT row pass does.
 template <bool FUSED, bool P2>
 __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const float2 *__restrict__ S,
                                                        float *__restrict__ U,
                                                        double *__restrict__ parts,
                                                        const float2 *__restrict__ tw,
                                                        ImgState *__restrict__ st,
-                                                       int *__restrict__ counters) {
+                                                       int *__restrict__ counters,
+                                                       float *__restrict__ T,
+                                                       const float4 *__restrict__ dtab) {
     const int b = blockIdx.y;
     if (!st[b].active) return;
     extern __shared__ float2 lds[];
@@ -326,7 +331,10 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
     const Ring<P2> ring(n);
     const int bufsz = npair * n + rpb;
     float2 *tl = lds, *X = lds + kMaxN, *Y = X + bufsz;
+    float4 *dt = reinterpret_cast<float4 *>(Y + bufsz);   // DCT table (T non-null)
     load_twiddles<P2>(tl, tw, n);
+    if (T)
+        for (int k = threadIdx.x; k < n; k += kThreads) dt[k] = dtab[k];
     const int blk = xcd_block(blockIdx.x, gridDim.x), row0 = blk * rpb;
     // raw half spectra of the block's rows: Y[rr * h + k]
     const float2 *srcS = S + (size_t)b * h * n + row0;
@@ -345,7 +353,9 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
         X[e] = lo ? make_float2(x.x - y.y, x.y + y.x) : make_float2(x.x + y.y, y.x - x.y);
     }
     __syncthreads();
-    const float2 *z = lds_fft_any<true, P2>(X, Y, n, npair, n, tl);
+    float2 *z = lds_fft_any<true, P2>(X, Y, n, npair, n, tl);
+    float2 *W = (z == X) ? Y : X;   // free: receives the new rows for the DCT
+    float *Wf = reinterpret_cast<float *>(W);
     float *dstU = U + (size_t)b * n * n + (size_t)row0 * n;
     double du2 = 0.0, u2 = 0.0;
     for (int e = threadIdx.x; e < npair * n; e += kThreads) {
@@ -359,6 +369,21 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
         u2 += o0 * o0 + o1 * o1;
         *p0 = n0;
         *p1 = n1;
+        if (T) {   // rows 2 pr and 2 pr + 1, reordered, as one complex line pair
+            const int q = 2 * (pr * n + makhoul_pos(j, n));
+            Wf[q] = n0;
+            Wf[q + 1] = n1;
+        }
+    }
+    if (T) {   // the same for every thread
+        __syncthreads();
+        const float2 *Z = lds_fft_any<false, P2>(W, z, n, npair, n, tl);
+        float *dstT = T + (size_t)b * n * n + row0;
+        const float rrpb = 1.0f / (float)rpb;
+        for (int e = threadIdx.x; e < rpb * n; e += kThreads) {
+            const int k = div_by(e, rpb, rrpb), l = e - k * rpb;
+            dstT[(size_t)k * n + l] = dct_coef<P2>(Z, dt, n, l, k);
+        }
     }
     // block reduction in a fixed order
 #pragma unroll
@@ -463,12 +488,14 @@ void launch_fft_cols_solve(int n, int B, float2 *S, const double *inv_d, const f
 }
 
 void launch_fft_rows_inv(int n, int B, const float2 *S, float *U, double *parts,
-                         const float2 *tw, ImgState *st, int *counters, hipStream_t s) {
+                         const float2 *tw, ImgState *st, int *counters, hipStream_t s, float *T,
+                         const float4 *dtab) {
     const int rpb = rows_per_block(n, B);
-    const size_t lds = sizeof(float2) * (kMaxN + 2 * ((rpb / 2) * n + rpb));
+    const size_t lds = sizeof(float2) * (kMaxN + 2 * ((rpb / 2) * n + rpb)) +
+                       (T ? sizeof(float4) * n : 0);
 #define TVCS_ROWS_INV(FUSEDV, P2V)                                                            \
     hipLaunchKernelGGL((k_rows_inv<FUSEDV, P2V>), dim3(n / rpb, B), dim3(kThreads), lds, s, n, rpb, \
-                       S, U, parts, tw, st, counters)
+                       S, U, parts, tw, st, counters, T, dtab)
     const bool p2 = is_pow2(n);
     if (B == 1) {
         if (p2) TVCS_ROWS_INV(true, true);

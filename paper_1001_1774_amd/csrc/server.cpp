@@ -137,6 +137,7 @@ struct tvcs_server {
                 launch_init_q(h->n, 1, U + (size_t)s * N, nullptr, beta,
                               h->Q0.as<float2>() + (size_t)s * N, h->work);
         }
+        h->seed_dct_rows(slots);   // partial DCT: row transforms of every slot's u
     }
 
     int step() {

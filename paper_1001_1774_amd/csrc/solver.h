@@ -274,6 +274,14 @@ struct tvcs_ctx {
                                 out + (size_t)g * nv * N, N, work);
     }
 
+    // partial DCT: the row pass of C u for the first B images (the iteration loop
+    // expects it in DT on entry; call after any change of U outside the loop)
+    void seed_dct_rows(int B) {
+        if (dct())
+            launch_dct_rows_fwd(n, B, U.as<float>(), DT.as<float>(), tw.as<float2>(),
+                                dtab.as<float4>(), nullptr, work);
+    }
+
     ShrinkArgs shrink_args(int B, int Bp) const {
         ShrinkArgs a{};
         a.n = n;
@@ -301,10 +309,12 @@ struct tvcs_ctx {
         ImgState *st = state.as<ImgState>();
         if (dct()) {
             // forward and adjoint share the column pass: r = (C u)[sel] - f and the
-            // zero-filled residual's inverse column transform in one kernel
-            launch_dct_forward(n, B, U.as<float>(), DT.as<float>(), selT.as<int>(), F.as<float>(),
-                               m, R.as<float>(), m, true, tw.as<float2>(), dtab.as<float4>(), st,
-                               work);
+            // zero-filled residual's inverse column transform in one kernel; the row
+            // pass of C u came from the previous iteration's inverse row FFT (or
+            // seed_dct_rows before the first)
+            launch_dct_cols_fwd(n, B, DT.as<float>(), selT.as<int>(), F.as<float>(), m,
+                                R.as<float>(), m, true, tw.as<float2>(), dtab.as<float4>(), st,
+                                work);
             launch_dct_adjoint(n, B, R.as<float>(), m, DT.as<float>(), selT.as<int>(), false,
                                P.as<float>(), N, tw.as<float2>(), dtab.as<float4>(), st, work);
         } else {
@@ -322,7 +332,8 @@ struct tvcs_ctx {
         launch_shrink_rows(a, iadm, Sp, twp, work);
         launch_fft_cols_solve(n, B, Sp, invd.as<double>(), twp, st, work);
         launch_fft_rows_inv(n, B, Sp, U.as<float>(), parts.as<double>(), twp, st,
-                            counters.as<int>(), work);
+                            counters.as<int>(), work, dct() ? DT.as<float>() : nullptr,
+                            dct() ? dtab.as<float4>() : nullptr);
     }
 
     void build_graph(int B, unsigned flags, double beta, double c, double ctau) {

@@ -123,8 +123,11 @@ void launch_fft_cols_solve(int n, int B, float2 *S, const double *inv_d, const f
                            const ImgState *st, hipStream_t s);
 // inverse row pass, u += increment, and the stop rule of every image (the last
 // workgroup of an image sums the norm partials; counters: one zeroed int per image)
+// T, dtab (partial DCT): also write the DCT-II of the new rows of u to T, as
+// launch_dct_rows_fwd does (null: not)
 void launch_fft_rows_inv(int n, int B, const float2 *S, float *U, double *parts,
-                         const float2 *tw, ImgState *st, int *counters, hipStream_t s);
+                         const float2 *tw, ImgState *st, int *counters, hipStream_t s,
+                         float *T = nullptr, const float4 *dtab = nullptr);
 // shrinkage + right-hand side fused with the forward row FFT
 void launch_shrink_rows(const ShrinkArgs &a, bool iadm, float2 *S, const float2 *tw,
                         hipStream_t s);
@@ -184,6 +187,12 @@ void launch_dct_permute(int m, int B, const int *perm, const float *src, float *
 void launch_dct_forward(int n, int B, const float *U, float *T, const int *selT, const float *F,
                         int ldf, float *R, int ldr, bool adjoint, const float2 *tw,
                         const float4 *tab, const ImgState *st, hipStream_t s);
+// the row pass alone (T from U), and the column pass alone (continuing from T)
+void launch_dct_rows_fwd(int n, int B, const float *U, float *T, const float2 *tw,
+                         const float4 *tab, const ImgState *st, hipStream_t s);
+void launch_dct_cols_fwd(int n, int B, float *T, const int *selT, const float *F, int ldf,
+                         float *R, int ldr, bool adjoint, const float2 *tw, const float4 *tab,
+                         const ImgState *st, hipStream_t s);
 // G[b*ldg + p] = (A^T r_b)_p; from_R: scatter R first, else continue from T
 void launch_dct_adjoint(int n, int B, const float *R, int ldr, float *T, const int *selT,
                         bool from_R, float *G, int ldg, const float2 *tw, const float4 *tab,
