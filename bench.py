@@ -279,8 +279,11 @@ def bench_batched(args, np, torch, O, synth, tvcs):
             ms_f, ms_a = s.time_products(B=Bs, reps=5)
             r = product_rates("bf16", p.m, p.N, Bs, ms_f, ms_a)
             ai = 2.0 * Bs / 2.0                           # useful flops per A byte
-            bound = min(MFMA_BF16_PEAK, ai * HBM_PEAK_GBS * 1e9)
+            # useful-flop bound: HBM x intensity, or the MFMA peak divided by the 2
+            # bf16 products executed per useful one (batch operand hi + lo)
+            bound = min(MFMA_BF16_PEAK / 2.0, ai * HBM_PEAK_GBS * 1e9)
             r["roofline_bound_tflops"] = bound / 1e12
+            r["roofline_bound"] = "mfma" if MFMA_BF16_PEAK / 2.0 < ai * HBM_PEAK_GBS * 1e9 else "hbm"
             r["frac_of_roofline_forward"] = 2.0 * p.m * p.N * Bs / (ms_f * 1e-3) / bound
             r["frac_of_roofline_adjoint"] = 2.0 * p.m * p.N * Bs / (ms_a * 1e-3) / bound
             sweep[f"B{Bs}"] = r
