@@ -14,6 +14,10 @@
 //              masked residual is transformed back along k_r in the same block
 //              (C_n^T along the columns), in place in T;
 //   rows_inv : G = T' C_n along each row, written row-major: g = A^T r.
+// In the iteration loop only the column pass runs as its own kernel: the row pass
+// of u^{k+1} is done by the inverse row FFT that produces those rows, and the
+// inverse row pass by the shrink pass that consumes g (both already hold the rows
+// in LDS).  The standalone row kernels serve set-up, the objective and timing.
 // Each 1-D DCT-II of length n is one complex FFT of length n (Makhoul, "A fast
 // cosine transform in one and multiple dimensions", IEEE TASSP 1980): reorder
 // v_j = x_{2j}, v_{n-1-j} = x_{2j+1}; V = FFT(v); X_k = w_k Re(e^{-i pi k/(2n)} V_k),
@@ -59,12 +63,12 @@ __device__ inline DctLds dct_lds(int n, int lines) {
     L.tl = lds;
     L.dt = reinterpret_cast<float4 *>(lds + kMaxN);
     L.X = lds + kMaxN + 2 * n;
-    L.Y = L.X + (lines / 2) * n;
+    L.Y = L.X + lp_size((lines / 2) * n);
     return L;
 }
 
 size_t dct_lds_bytes(int n, int lines) {
-    return sizeof(float2) * (kMaxN + 2 * n + 2 * (lines / 2) * n);
+    return sizeof(float2) * (kMaxN + 2 * n + 2 * lp_size((lines / 2) * n));
 }
 
 
@@ -74,28 +78,10 @@ __device__ inline void load_tables(const DctLds &L, int n, const float2 *tw, con
     for (int k = threadIdx.x; k < n; k += kThreads) L.dt[k] = tab[k];
 }
 
-// Inverse: coefficients of `lines` lines in A[l * n + k] -> spectra of the
-// reordered sequences, two lines per complex transform, in P; then the inverse
-// FFT with Q as the second buffer (Q may hold A).  Returns the buffer holding v
-// (line l: component l & 1 of pair l >> 1).
 template <bool P2>
 __device__ inline float2 *idct_lines(const DctLds &L, int n, int lines, const float *A, float2 *P,
                                      float2 *Q) {
-    const Ring<P2> ring(n);
-    const int npair = lines >> 1;
-    for (int e = threadIdx.x; e < npair * n; e += kThreads) {
-        const int pr = ring.div(e), k = e - ring.mul(pr);
-        const float *a = A + (2 * pr) * n, *b = a + n;
-        const float ak = a[k], bk = b[k];
-        const float ank = k ? a[n - k] : 0.f, bnk = k ? b[n - k] : 0.f;
-        const float4 t = L.dt[k];
-        // V_a = t (a_k - i a_{n-k}), V_b likewise; Z = V_a + i V_b
-        const float2 va = make_float2(t.z * ak + t.w * ank, t.w * ak - t.z * ank);
-        const float2 vb = make_float2(t.z * bk + t.w * bnk, t.w * bk - t.z * bnk);
-        P[e] = make_float2(va.x - vb.y, va.y + vb.x);
-    }
-    __syncthreads();
-    return lds_fft_any<true, P2>(P, Q, n, npair, n, L.tl);
+    return idct_lines_lds<P2>(L.tl, L.dt, n, lines, A, P, Q);
 }
 
 // rows_fwd: T[b][k][row] = (DCT-II of row `row` of u_b)_k, `lines` rows per block.
@@ -116,7 +102,7 @@ __global__ __launch_bounds__(kThreads) void k_dct_rows_fwd(int n, int lines,
     float *Xf = reinterpret_cast<float *>(L.X);
     for (int e = threadIdx.x; e < lines * n; e += kThreads) {
         const int l = ring.div(e), j = e - ring.mul(l);
-        Xf[2 * ((l >> 1) * n + makhoul_pos(j, n)) + (l & 1)] = src[e];
+        Xf[2 * lp((l >> 1) * n + makhoul_pos(j, n)) + (l & 1)] = src[e];
     }
     __syncthreads();
     const float2 *Z = lds_fft_any<false, P2>(L.X, L.Y, n, lines >> 1, n, L.tl);
@@ -155,7 +141,7 @@ __global__ __launch_bounds__(kThreads) void k_dct_cols(int n, int lines, float *
         float *Xf = reinterpret_cast<float *>(L.X);
         for (int e = threadIdx.x; e < lines * n; e += kThreads) {
             const int l = ring.div(e), j = e - ring.mul(l);
-            Xf[2 * ((l >> 1) * n + makhoul_pos(j, n)) + (l & 1)] = col[e];
+            Xf[2 * lp((l >> 1) * n + makhoul_pos(j, n)) + (l & 1)] = col[e];
         }
         __syncthreads();
         const float2 *Z = lds_fft_any<false, P2>(L.X, L.Y, n, lines >> 1, n, L.tl);
@@ -186,7 +172,7 @@ __global__ __launch_bounds__(kThreads) void k_dct_cols(int n, int lines, float *
     const float2 *v = idct_lines<P2>(L, n, lines, reinterpret_cast<const float *>(Q), P, Q);
     for (int e = threadIdx.x; e < lines * n; e += kThreads) {
         const int l = ring.div(e), r = e - ring.mul(l);
-        const float2 z = v[(l >> 1) * n + makhoul_pos(r, n)];
+        const float2 z = v[lp((l >> 1) * n + makhoul_pos(r, n))];
         col[e] = (l & 1) ? z.y : z.x;
     }
 }
@@ -217,7 +203,7 @@ __global__ __launch_bounds__(kThreads) void k_dct_rows_inv(int n, int lines,
     float *dst = G + (size_t)b * ldg + (size_t)row0 * n;
     for (int e = threadIdx.x; e < lines * n; e += kThreads) {
         const int l = ring.div(e), c = e - ring.mul(l);
-        const float2 z = v[(l >> 1) * n + makhoul_pos(c, n)];
+        const float2 z = v[lp((l >> 1) * n + makhoul_pos(c, n))];
         dst[e] = (l & 1) ? z.y : z.x;
     }
 }

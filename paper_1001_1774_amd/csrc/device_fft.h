@@ -12,6 +12,19 @@ namespace fftdev {
 
 constexpr int kThreads = 256;   // every FFT kernel runs 256-thread workgroups
 
+#ifndef TVCS_LDS_PAD
+#define TVCS_LDS_PAD 0   // pad the FFT buffers in LDS against bank conflicts (measured slower)
+#endif
+// LDS slot of complex element i of an FFT buffer: one pad slot after every 4
+// elements.  The early Stockham stages write with strides of 4 and 16 elements
+// (32 and 128 bytes), which put 4 lanes of every 16 on one bank pair; with the pad
+// the stride becomes 5 elements and the 16 lanes of a pass hit distinct banks.
+__host__ __device__ inline int lp(int i) { return TVCS_LDS_PAD ? i + (i >> 2) : i; }
+// slots a buffer of cnt elements occupies (even, so later regions stay 16-byte aligned)
+__host__ __device__ inline int lp_size(int cnt) {
+    return TVCS_LDS_PAD ? ((cnt + (cnt >> 2) + 2) & ~1) : ((cnt + 1) & ~1);
+}
+
 __device__ inline float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -32,9 +45,9 @@ __device__ float2 *lds_fft(float2 *src, float2 *dst, int L, int logL, int nf, in
         const int h = L >> 1;
         for (int t = tid; t < nf * h; t += kThreads) {
             const int f = t >> (logL - 1), j = t & (h - 1);
-            const float2 v0 = src[f * fs + j], v1 = src[f * fs + j + h];
-            dst[f * fs + 2 * j] = v0 + v1;
-            dst[f * fs + 2 * j + 1] = v0 - v1;
+            const float2 v0 = src[lp(f * fs + j)], v1 = src[lp(f * fs + j + h)];
+            dst[lp(f * fs + 2 * j)] = v0 + v1;
+            dst[lp(f * fs + 2 * j + 1)] = v0 - v1;
         }
         __syncthreads();
         float2 *x = src;
@@ -48,8 +61,9 @@ __device__ float2 *lds_fft(float2 *src, float2 *dst, int L, int logL, int nf, in
         for (int t = tid; t < nf * q; t += kThreads) {
             const int f = t >> (logL - 2), j = t & (q - 1);
             const int k = j & (Ns - 1);
-            const float2 *s = src + f * fs;
-            float2 v0 = s[j], v1 = s[j + q], v2 = s[j + 2 * q], v3 = s[j + 3 * q];
+            const int sb = f * fs + j;
+            float2 v0 = src[lp(sb)], v1 = src[lp(sb + q)], v2 = src[lp(sb + 2 * q)],
+                   v3 = src[lp(sb + 3 * q)];
             // twiddle exp(-+2 pi i k r / (4 Ns)) = table[k r 128 / Ns]
             const int step = (k << 7) >> lNs;
             if (INV) {
@@ -64,11 +78,11 @@ __device__ float2 *lds_fft(float2 *src, float2 *dst, int L, int logL, int nf, in
             const float2 a = v0 + v2, bb = v0 - v2, c = v1 + v3, d = v1 - v3;
             // -i d = (d.y, -d.x); +i d = (-d.y, d.x)
             const float2 mid = INV ? make_float2(-d.y, d.x) : make_float2(d.y, -d.x);
-            float2 *o = dst + f * fs + ((j >> lNs) << (lNs + 2)) + k;
-            o[0] = a + c;
-            o[Ns] = bb + mid;
-            o[2 * Ns] = a - c;
-            o[3 * Ns] = bb - mid;
+            const int ob = f * fs + ((j >> lNs) << (lNs + 2)) + k;
+            dst[lp(ob)] = a + c;
+            dst[lp(ob + Ns)] = bb + mid;
+            dst[lp(ob + 2 * Ns)] = a - c;
+            dst[lp(ob + 3 * Ns)] = bb - mid;
         }
         __syncthreads();
         float2 *x = src;
@@ -173,17 +187,17 @@ __device__ inline void mixed_stage(const float2 *src, float2 *dst, int L, int Ns
     for (int t = threadIdx.x; t < nf * q; t += kThreads) {
         const int f = P2 ? t >> lq : div_by(t, q, rq), j = t - f * q;
         const int jn = P2 ? j >> lNs : div_by(j, Ns, rNs), k = j - jn * Ns;
-        const float2 *s = src + f * fs;
+        const int sb = f * fs + j;
         float2 v[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = s[j + r * q];
+        for (int r = 0; r < R; ++r) v[r] = src[lp(sb + r * q)];
         const int step = k * tstep;
 #pragma unroll
         for (int r = 1; r < R; ++r) v[r] = INV ? cmulc(v[r], tw[r * step]) : cmul(v[r], tw[r * step]);
         dft_small<R, INV>(v);
-        float2 *o = dst + f * fs + jn * Ns * R + k;
+        const int ob = f * fs + jn * Ns * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) o[r * Ns] = v[r];
+        for (int r = 0; r < R; ++r) dst[lp(ob + r * Ns)] = v[r];
     }
 }
 
@@ -241,7 +255,7 @@ __device__ inline int makhoul_pos(int j, int n) {   // position of x_j in the re
 // ...) of pi k / 2n.
 template <bool P2>
 __device__ inline float dct_coef(const float2 *Z, const float4 *dt, int n, int l, int k) {
-    const float2 zk = Z[(l >> 1) * n + k], znk = Z[(l >> 1) * n + Ring<P2>(n).neg(k)];
+    const float2 zk = Z[lp((l >> 1) * n + k)], znk = Z[lp((l >> 1) * n + Ring<P2>(n).neg(k))];
     float2 v;
     if ((l & 1) == 0)   // V of the real part: (Z_k + conj Z_{n-k}) / 2
         v = make_float2(0.5f * (zk.x + znk.x), 0.5f * (zk.y - znk.y));
@@ -249,6 +263,32 @@ __device__ inline float dct_coef(const float2 *Z, const float4 *dt, int n, int l
         v = make_float2(0.5f * (zk.y + znk.y), -0.5f * (zk.x - znk.x));
     const float4 t = dt[k];
     return t.x * v.x - t.y * v.y;   // Re(w_k e^{-i pi k/(2n)} V_k)
+}
+
+// Inverse DCT-II (C_n^T) of `lines` lines whose coefficients are in A[l * n + k]:
+// the spectra of the reordered sequences, two lines per complex transform, are
+// built in P, V_k = e^{i pi k/(2n)} (X_k / w_k - i X_{n-k} / w_{n-k}) (X_n = 0, the
+// factors in dt[k].zw with the 1/n of the inverse FFT), then inverse-transformed
+// with Q as the second buffer (Q may hold A).  Returns the buffer holding v: x_j of
+// line l is component l & 1 of v[(l >> 1) * n + makhoul_pos(j, n)].
+template <bool P2>
+__device__ inline float2 *idct_lines_lds(const float2 *tl, const float4 *dt, int n, int lines,
+                                         const float *A, float2 *P, float2 *Q) {
+    const Ring<P2> ring(n);
+    const int npair = lines >> 1;
+    for (int e = threadIdx.x; e < npair * n; e += kThreads) {
+        const int pr = ring.div(e), k = e - ring.mul(pr);
+        const float *a = A + (2 * pr) * n, *b = a + n;
+        const float ak = a[k], bk = b[k];
+        const float ank = k ? a[n - k] : 0.f, bnk = k ? b[n - k] : 0.f;
+        const float4 t = dt[k];
+        // V_a = t (a_k - i a_{n-k}), V_b likewise; Z = V_a + i V_b
+        const float2 va = make_float2(t.z * ak + t.w * ank, t.w * ak - t.z * ank);
+        const float2 vb = make_float2(t.z * bk + t.w * bnk, t.w * bk - t.z * bnk);
+        P[lp(e)] = make_float2(va.x - vb.y, va.y + vb.x);
+    }
+    __syncthreads();
+    return lds_fft_any<true, P2>(P, Q, n, npair, n, tl);
 }
 
 // the twiddle table of a length-n transform: 512 entries for powers of two, n otherwise

@@ -72,7 +72,7 @@ struct PixIn {
 };
 
 template <bool IADM, int PL, bool P2>
-__device__ inline PixIn load_pix(const ShrinkArgs &a, int b, int p) {
+__device__ inline PixIn load_pix(const ShrinkArgs &a, int b, int p, bool with_g) {
     const int n = a.n, N = n * n;
     const Ring<P2> ring(n);
     const int r = ring.div(p), c = p - ring.mul(r);
@@ -94,7 +94,7 @@ __device__ inline PixIn load_pix(const ShrinkArgs &a, int b, int p) {
         in.oW = {xW.x, xW.y};
         in.oN = {xN.x, xN.y};
     }
-    in.gk = g_at<PL>(a, b, p);
+    in.gk = with_g ? g_at<PL>(a, b, p) : 0.0;
     return in;
 }
 

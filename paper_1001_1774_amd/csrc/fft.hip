@@ -65,6 +65,36 @@ __global__ void k_denominators(int n, double c, double *inv_d) {
     inv_d[e] = 1.0 / ((double)n * (double)n * d);
 }
 
+// Partial DCT: g of the block's rows (rows row0 .. row0 + rpb - 1 of image b) from
+// T, computed in the shrink pass: the rows' coefficients (column-major in T) are
+// staged in Y, inverse-transformed (C_n^T along each row) with X and Y as the FFT
+// buffers, and left in gl[rr * n + c].  gl first holds the DCT table.  Needs
+// max(rpb * n floats, n float4) at gl; ends with a barrier.
+template <bool P2>
+__device__ inline void shrink_g_from_T(const ShrinkArgs &a, int b, int row0, int rpb,
+                                       const float2 *tl, float2 *X, float2 *Y, float *gl) {
+    const int n = a.n;
+    float4 *dt = reinterpret_cast<float4 *>(gl);
+    for (int k = threadIdx.x; k < n; k += kThreads) dt[k] = a.dtab[k];
+    float *A = reinterpret_cast<float *>(Y);
+    const float *src = a.T + (size_t)b * n * n + row0;
+    const float rrpb = 1.0f / (float)rpb;
+    for (int e = threadIdx.x; e < rpb * n; e += kThreads) {
+        const int k = div_by(e, rpb, rrpb), l = e - k * rpb;
+        A[l * n + k] = src[(size_t)k * n + l];
+    }
+    __syncthreads();
+    const float2 *v = idct_lines_lds<P2>(tl, dt, n, rpb, A, X, Y);
+    // (the transform ended with a barrier: the table is no longer read)
+    const Ring<P2> ring(n);
+    for (int e = threadIdx.x; e < rpb * n; e += kThreads) {
+        const int l = ring.div(e), c = e - ring.mul(l);
+        const float2 z = v[lp((l >> 1) * n + makhoul_pos(c, n))];
+        gl[e] = (l & 1) ? z.y : z.x;
+    }
+    __syncthreads();
+}
+
 // FFT of the block's packed row pairs in X, split into the half spectra and
 // written to S (rows row0 .. row0 + rpb - 1 of image b).
 template <bool P2>
@@ -76,7 +106,7 @@ __device__ inline void rows_fwd_tail(int n, int rpb, float2 *X, float2 *Y, const
     const float rrpb = 1.0f / (float)rpb;
     for (int e = threadIdx.x; e < h * rpb; e += kThreads) {
         const int k = div_by(e, rpb, rrpb), rr = e - k * rpb, pr = rr >> 1;
-        const float2 zk = Z[pr * n + k], znk = Z[pr * n + ring.neg(k)];
+        const float2 zk = Z[lp(pr * n + k)], znk = Z[lp(pr * n + ring.neg(k))];
         float2 v;
         if ((rr & 1) == 0)   // X_k = (Z_k + conj Z_{n-k}) / 2
             v = make_float2(0.5f * (zk.x + znk.x), 0.5f * (zk.y - znk.y));
@@ -100,9 +130,11 @@ __global__ __launch_bounds__(kThreads) void k_shrink_pix(ShrinkArgs a, int rpb,
     const int n = a.n, npair = rpb >> 1, h = n / 2 + 1;
     const Ring<P2> ring(n);
     const int bufsz = npair * n + rpb;
-    float2 *tl = lds, *X = lds + kMaxN, *Y = X + bufsz;
+    float2 *tl = lds, *X = lds + kMaxN, *Y = X + lp_size(bufsz);
+    float *gl = reinterpret_cast<float *>(Y + lp_size(bufsz));   // partial DCT: g rows
     load_twiddles<P2>(tl, tw, n);
     const int row0 = xcd_block(blockIdx.x, gridDim.x) * rpb;
+    if (a.T) shrink_g_from_T<P2>(a, b, row0, rpb, tl, X, Y, gl);
     float *Xf = reinterpret_cast<float *>(X);
     const int total = rpb * n;
     for (int e0 = threadIdx.x; e0 < total; e0 += kThreads * PX) {
@@ -110,7 +142,10 @@ __global__ __launch_bounds__(kThreads) void k_shrink_pix(ShrinkArgs a, int rpb,
 #pragma unroll
         for (int j = 0; j < PX; ++j) {
             const int e = e0 + j * kThreads;
-            if (e < total) in[j] = shrinkdev::load_pix<IADM, PL, P2>(a, b, ring.mul(row0) + e);
+            if (e < total) {
+                in[j] = shrinkdev::load_pix<IADM, PL, P2>(a, b, ring.mul(row0) + e, !a.T);
+                if (a.T) in[j].gk = gl[e];
+            }
         }
 #pragma unroll
         for (int j = 0; j < PX; ++j) {
@@ -118,7 +153,7 @@ __global__ __launch_bounds__(kThreads) void k_shrink_pix(ShrinkArgs a, int rpb,
             if (e >= total) break;
             const int rr = ring.div(e), c = e - ring.mul(rr);
             const float v = (float)shrinkdev::finish_pix<IADM>(a, b, ring.mul(row0) + e, in[j]);
-            Xf[2 * ((rr >> 1) * n + c) + (rr & 1)] = v;   // even row: real part, odd row: imaginary
+            Xf[2 * lp((rr >> 1) * n + c) + (rr & 1)] = v;   // even row: real part, odd row: imaginary
         }
     }
     __syncthreads();
@@ -144,10 +179,14 @@ __global__ __launch_bounds__(kThreads) void k_shrink_walk(ShrinkArgs a, int rpb,
     const int n = a.n, N = n * n, h = n / 2 + 1;
     const Ring<P2> ring(n);
     const int bufsz = (rpb >> 1) * n + rpb;
-    float2 *tl = lds, *X = lds + kMaxN, *Y = X + bufsz;
+    float2 *tl = lds, *X = lds + kMaxN, *Y = X + lp_size(bufsz);
     double *zx = reinterpret_cast<double *>(Y);   // 2 x groups x n, before the FFT uses Y
+    // partial DCT: g rows after the Y region (the larger of the FFT buffer and zx)
+    const int ybytes = max((int)sizeof(float2) * lp_size(bufsz), (int)sizeof(double) * 2 * groups * n);
+    float *gl = reinterpret_cast<float *>(reinterpret_cast<char *>(Y) + ybytes);
     load_twiddles<P2>(tl, tw, n);
     const int row0 = xcd_block(blockIdx.x, gridDim.x) * rpb;
+    if (a.T) shrink_g_from_T<P2>(a, b, row0, rpb, tl, X, Y, gl);
     const int rg = rpb / groups;   // own rows per group
     const int t = threadIdx.x;
     // threads past groups * n (n < kThreads) own no column and only join barriers
@@ -203,7 +242,10 @@ __global__ __launch_bounds__(kThreads) void k_shrink_walk(ShrinkArgs a, int rpb,
         double gk[kCols];
 #pragma unroll
         for (int j = 0; j < kCols; ++j)
-            gk[j] = (s > 0 && has[j]) ? shrinkdev::g_at<PL>(a, b, ring.mul(r) + c[j]) : 0.0;
+            gk[j] = (s > 0 && has[j])
+                        ? (a.T ? (double)gl[(g * rg + s - 1) * n + c[j]]
+                               : shrinkdev::g_at<PL>(a, b, ring.mul(r) + c[j]))
+                        : 0.0;
         double zxv[kCols], zyv[kCols];
 #pragma unroll
         for (int j = 0; j < kCols; ++j) {
@@ -231,7 +273,7 @@ __global__ __launch_bounds__(kThreads) void k_shrink_walk(ShrinkArgs a, int rpb,
                 const double zw = zrow[ring.wrap(c[j] - 1)];
                 // D^T z at (r, c) - c tau g_k: the right side of the increment
                 const double rhs = (zw - zxv[j]) + (zy[j] - zyv[j]) - a.ctau * gk[j];
-                Xf[2 * ((rr >> 1) * n + c[j]) + (rr & 1)] = (float)rhs;
+                Xf[2 * lp((rr >> 1) * n + c[j]) + (rr & 1)] = (float)rhs;
             }
         }
 #pragma unroll
@@ -253,22 +295,22 @@ __global__ __launch_bounds__(kThreads) void k_cols_solve(int n, int cpb, float2 
     const int h = n / 2 + 1;
     const int k20 = blockIdx.x * cpb;
     const int nc = min(cpb, h - k20);
-    float2 *tl = lds, *X = lds + kMaxN, *Y = X + cpb * n;
+    float2 *tl = lds, *X = lds + kMaxN, *Y = X + lp_size(cpb * n);
     load_twiddles<P2>(tl, tw, n);
     float2 *col = S + (size_t)b * h * n + (size_t)k20 * n;
-    for (int e = threadIdx.x; e < nc * n; e += kThreads) X[e] = col[e];
+    for (int e = threadIdx.x; e < nc * n; e += kThreads) X[lp(e)] = col[e];
     __syncthreads();
     float2 *Z = lds_fft_any<false, P2>(X, Y, n, nc, n, tl);
     const double *id = inv_d + (size_t)k20 * n;
     for (int e = threadIdx.x; e < nc * n; e += kThreads) {
-        const float2 z = Z[e];
+        const float2 z = Z[lp(e)];
         const double d = id[e];
-        Z[e] = make_float2((float)(z.x * d), (float)(z.y * d));
+        Z[lp(e)] = make_float2((float)(z.x * d), (float)(z.y * d));
     }
     __syncthreads();
     float2 *W = (Z == X) ? Y : X;
     const float2 *out = lds_fft_any<true, P2>(Z, W, n, nc, n, tl);
-    for (int e = threadIdx.x; e < nc * n; e += kThreads) col[e] = out[e];
+    for (int e = threadIdx.x; e < nc * n; e += kThreads) col[e] = out[lp(e)];
 }
 
 // The stop rule of eq. (stop), ||u^{k+1} - u^k|| <= tol ||u^k|| (inclusive, FP64),
@@ -330,8 +372,8 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
     const int npair = rpb >> 1, h = n / 2 + 1;
     const Ring<P2> ring(n);
     const int bufsz = npair * n + rpb;
-    float2 *tl = lds, *X = lds + kMaxN, *Y = X + bufsz;
-    float4 *dt = reinterpret_cast<float4 *>(Y + bufsz);   // DCT table (T non-null)
+    float2 *tl = lds, *X = lds + kMaxN, *Y = X + lp_size(bufsz);
+    float4 *dt = reinterpret_cast<float4 *>(Y + lp_size(bufsz));   // DCT table (T non-null)
     load_twiddles<P2>(tl, tw, n);
     if (T)
         for (int k = threadIdx.x; k < n; k += kThreads) dt[k] = dtab[k];
@@ -350,7 +392,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
         const bool lo = k <= n / 2;
         const int kk = lo ? k : n - k;
         const float2 x = Y[(2 * pr) * h + kk], y = Y[(2 * pr + 1) * h + kk];
-        X[e] = lo ? make_float2(x.x - y.y, x.y + y.x) : make_float2(x.x + y.y, y.x - x.y);
+        X[lp(e)] = lo ? make_float2(x.x - y.y, x.y + y.x) : make_float2(x.x + y.y, y.x - x.y);
     }
     __syncthreads();
     float2 *z = lds_fft_any<true, P2>(X, Y, n, npair, n, tl);
@@ -360,7 +402,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
     double du2 = 0.0, u2 = 0.0;
     for (int e = threadIdx.x; e < npair * n; e += kThreads) {
         const int pr = ring.div(e), j = e - ring.mul(pr);
-        const float2 v = z[e];
+        const float2 v = z[lp(e)];
         float *p0 = dstU + (2 * pr) * n + j, *p1 = p0 + n;
         const double o0 = *p0, o1 = *p1;
         const float n0 = (float)(o0 + (double)v.x), n1 = (float)(o1 + (double)v.y);
@@ -370,7 +412,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
         *p0 = n0;
         *p1 = n1;
         if (T) {   // rows 2 pr and 2 pr + 1, reordered, as one complex line pair
-            const int q = 2 * (pr * n + makhoul_pos(j, n));
+            const int q = 2 * lp(pr * n + makhoul_pos(j, n));
             Wf[q] = n0;
             Wf[q + 1] = n1;
         }
@@ -478,7 +520,7 @@ void launch_denominators(int n, double c, double *inv_d, hipStream_t s) {
 void launch_fft_cols_solve(int n, int B, float2 *S, const double *inv_d, const float2 *tw,
                            const ImgState *st, hipStream_t s) {
     const int cpb = cols_per_block(n, B), h = n / 2 + 1;
-    const size_t lds = sizeof(float2) * (kMaxN + 2 * cpb * n);
+    const size_t lds = sizeof(float2) * (kMaxN + 2 * lp_size(cpb * n));
     if (is_pow2(n))
         hipLaunchKernelGGL(k_cols_solve<true>, dim3((h + cpb - 1) / cpb, B), dim3(kThreads), lds, s,
                            n, cpb, S, inv_d, tw, st);
@@ -491,7 +533,7 @@ void launch_fft_rows_inv(int n, int B, const float2 *S, float *U, double *parts,
                          const float2 *tw, ImgState *st, int *counters, hipStream_t s, float *T,
                          const float4 *dtab) {
     const int rpb = rows_per_block(n, B);
-    const size_t lds = sizeof(float2) * (kMaxN + 2 * ((rpb / 2) * n + rpb)) +
+    const size_t lds = sizeof(float2) * (kMaxN + 2 * lp_size((rpb / 2) * n + rpb)) +
                        (T ? sizeof(float4) * n : 0);
 #define TVCS_ROWS_INV(FUSEDV, P2V)                                                            \
     hipLaunchKernelGGL((k_rows_inv<FUSEDV, P2V>), dim3(n / rpb, B), dim3(kThreads), lds, s, n, rpb, \
@@ -522,8 +564,11 @@ void launch_shrink_rows(const ShrinkArgs &a, bool iadm, float2 *S, const float2 
     const bool p2 = is_pow2(n);
     // few partial sums of g: fewer loads in flight, fewer registers (same bits)
     const bool few = a.nchunk <= 4;
+    // partial DCT: the g rows (or, first, the DCT table) after the FFT buffers
+    const size_t gbytes =
+        a.T ? std::max(sizeof(float) * (size_t)rpb * n, sizeof(float4) * (size_t)n) : 0;
     if (rpb < TVCS_SHRINK_WALK_ROWS) {
-        const size_t lds = sizeof(float2) * (kMaxN + 2 * bufsz);
+        const size_t lds = sizeof(float2) * (kMaxN + 2 * lp_size((int)bufsz)) + gbytes;
         // several pixels per round where the partial sums of g are few (their loads
         // would otherwise cost registers) and each thread has several pixels
         const bool multi = few && rpb * n >= 2 * kThreads;
@@ -551,8 +596,9 @@ void launch_shrink_rows(const ShrinkArgs &a, bool iadm, float2 *S, const float2 
     // column walk: as many row groups of n threads as fit, dividing the block's rows
     int groups = std::max(1, std::min(rpb, kThreads / n));
     while (rpb % groups) --groups;
-    const size_t ybytes = std::max(sizeof(float2) * bufsz, sizeof(double) * 2 * groups * n);
-    const size_t lds = sizeof(float2) * (kMaxN + bufsz) + ybytes;
+    const size_t ybytes =
+        std::max(sizeof(float2) * lp_size((int)bufsz), sizeof(double) * 2 * groups * n);
+    const size_t lds = sizeof(float2) * (kMaxN + lp_size((int)bufsz)) + ybytes + gbytes;
 #define TVCS_WALK(IADMV, P2V, PLV)                                                           \
     hipLaunchKernelGGL((k_shrink_walk<IADMV, P2V, PLV>), grid, dim3(kThreads), lds, s, a, rpb, \
                        groups, S, tw)

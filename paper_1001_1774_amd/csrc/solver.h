@@ -315,13 +315,16 @@ struct tvcs_ctx {
             launch_dct_cols_fwd(n, B, DT.as<float>(), selT.as<int>(), F.as<float>(), m,
                                 R.as<float>(), m, true, tw.as<float2>(), dtab.as<float4>(), st,
                                 work);
-            launch_dct_adjoint(n, B, R.as<float>(), m, DT.as<float>(), selT.as<int>(), false,
-                               P.as<float>(), N, tw.as<float2>(), dtab.as<float4>(), st, work);
+            // the inverse row transform (g = A^T r) is computed by the shrink pass
         } else {
             apply_A(Bp, B, U.as<float>(), F.as<float>(), R.as<float>(), st);
             apply_At(Bp, B, R.as<float>(), st);
         }
         ShrinkArgs a = shrink_args(B, Bp);
+        if (dct()) {
+            a.T = DT.as<float>();
+            a.dtab = dtab.as<float4>();
+        }
         a.beta = beta;
         a.c = c;
         a.ctau = ctau;

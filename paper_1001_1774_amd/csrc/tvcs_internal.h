@@ -99,6 +99,10 @@ struct ShrinkArgs {
     float2 *Qnew;          // B x N pairs (IADM)
     double beta, c, ctau;  // c = mu/(beta tau), ctau = c*tau = mu/beta
     const ImgState *st;
+    // partial DCT: g is the inverse row DCT of T (the column pass's output,
+    // column-major per image), computed in the pass; G is then unused
+    const float *T;
+    const float4 *dtab;
 };
 // q is held as FP32 pairs (q1, q2) per pixel; the arithmetic on it is FP64
 void launch_init_q(int n, int B, const float *U, const double *lam0, double beta, float2 *Q,
