@@ -39,6 +39,13 @@ def measured_traffic(kernel):
     return None
 
 
+def psnr_db(u, ref):
+    """PSNR of u against the FP64 reference: 20 log10(max |ref| / RMS(u - ref))."""
+    import numpy as np
+    rms = float(np.sqrt(np.mean((np.asarray(u, np.float64) - ref) ** 2)))
+    return float("inf") if rms == 0.0 else float(20.0 * np.log10(np.abs(ref).max() / rms))
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -130,10 +137,11 @@ def main():
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
     rec_s = args.steps / elapsed
-    rel_err = None
+    rel_err = psnr = None
     if ref_u is not None:
         ug = u.cpu().numpy().astype(np.float64).reshape(p.n, p.n)
         rel_err = float(np.linalg.norm(ug - ref_u) / np.linalg.norm(ref_u))
+        psnr = psnr_db(ug, ref_u)
 
     # ---- roofline of the products (HIP events on the solver's stream) -------------
     ms_fwd, ms_adj = solver.time_products(B=1, reps=20)
@@ -175,6 +183,7 @@ def main():
                    "iterations": args.iters, "algorithm": args.alg.upper(), "storage": "fp32",
                    "mu": p.mu, "beta": p.beta, "tau": tau, "batch": 1, "seed_A": p.seed_A},
         "rel_err_vs_fp64_oracle": rel_err,
+        "psnr_db_vs_fp64_oracle": psnr,
         "measured_peaks": dict(ACHIEVABLE),
         "gemv_gbs": {"forward": fwd_gbs, "adjoint": adj_gbs,
                      "forward_ms": ms_fwd, "adjoint_ms": ms_adj},
@@ -267,7 +276,8 @@ def bench_batched(args, np, torch, O, synth, tvcs):
         res[storage] = {
             "rec_per_s": p.B / dt, "ms_per_iter": 1e3 * dt / K,
             "speedup_vs_plain_fp32": (p.B / dt) / res["plain_fp32"]["rec_per_s"],
-            "rel_err_vs_fp64_oracle_image0": err, "oracle_check_iterations": KC,
+            "rel_err_vs_fp64_oracle_image0": err,
+            "psnr_db_vs_fp64_oracle_image0": psnr_db(u0, ref.u[0]), "oracle_check_iterations": KC,
             **product_rates(storage, p.m, p.N, p.B, ms_f, ms_a),
         }
         log(f"{storage} B=64: {1e3 * dt / K:.3f} ms/iter, err {err:.2e}")
