@@ -188,3 +188,20 @@ def test_served_requests_match_the_oracle(T):
             assert e <= TOL_U
     sd.close()
     sa.close()
+
+
+def test_continuation_in_beta_on_the_operator(T):
+    """FTVCS with continuation in beta (warm-started stages) on the partial DCT: each
+    stage re-enters the loop from the previous stage's u, which the loop's row
+    transforms must follow; fixed iterations per stage against the oracle."""
+    p = synth.make_dct_problem("cont", 64, 0.3)
+    f32 = p.f.astype(np.float32)
+    betas, K = (16.0, 32.0, 64.0), 40
+    ref = O.ftvcs_continuation(op(p), f32.astype(np.float64), p.n, p.mu, betas, p.tau, tol=0,
+                               maxit=K)
+    with T.Solver.partial_dct(p.rows, p.n) as s:
+        out = s.solve_continuation(f32[0], mu=p.mu, betas=betas, tol=0, maxit=K)
+    assert out["stats"][0]["iters"] == K * len(betas)
+    e = rel(out["u"].cpu().numpy()[0], ref.u[0])
+    say(f"  continuation rel err {e:.3e}")
+    assert e <= TOL_U
