@@ -43,8 +43,14 @@
 #include <algorithm>
 
 // Tile parameters (compile-time; the defaults are the measured best on MI355X)
+#ifndef TVCS_GEMM_NT_MAX
+#define TVCS_GEMM_NT_MAX 16    // image tiles per workgroup of split storage at most (16: 256 images)
+#endif
+#ifndef TVCS_GEMM_KF_NT16
+#define TVCS_GEMM_KF_NT16 1    // 32-wide k tiles per pipeline step for 256-image groups
+#endif
 #ifndef TVCS_GEMM_KF_NT8
-#define TVCS_GEMM_KF_NT8 1     // 32-wide k tiles per pipeline step for 128-image groups
+#define TVCS_GEMM_KF_NT8 1     // ... 128-image groups
 #endif
 #ifndef TVCS_GEMM_KF_NT4
 #define TVCS_GEMM_KF_NT4 2     // ... 64-image groups
@@ -510,7 +516,17 @@ void gemm_dispatch(int NT, const void *Xhi, const void *Xlo, long long ldx, cons
         TVCS_GEMM_CASE(2, TVCS_GEMM_KF_NT2)
         TVCS_GEMM_CASE(4, TVCS_GEMM_KF_NT4)
         TVCS_GEMM_CASE(8, TVCS_GEMM_KF_NT8)
-        default: fail(TVCS_EUNSUPPORTED, "MFMA product: padded batch must be 16, 32, 64 or 128");
+#if TVCS_GEMM_NT_MAX >= 16
+        case 16:   // 2 row tiles per wave only (the accumulators of 4 do not fit)
+            if constexpr (RT == 2) {
+                hipLaunchKernelGGL((k_gemm<MODE, 2, 16, TVCS_GEMM_KF_NT16>), grid, dim3(kThreads), 0,
+                                   s, Xhi, Xlo, ldx >> 5, Yhi, Ylo, yimg, ytile, M, kspan, RB, KS,
+                                   out, split_stride, ldo, st, nact);
+                break;
+            }
+            fail(TVCS_EUNSUPPORTED, "MFMA product: 256-image groups take 2 row tiles per wave");
+#endif
+        default: fail(TVCS_EUNSUPPORTED, "MFMA product: image groups of 16, 32, 64, 128 or 256");
     }
 #undef TVCS_GEMM_CASE
 }
@@ -541,6 +557,7 @@ void gemm_any(int RT, int mode, int NT, const void *Xhi, const void *Xlo, long l
               int KS,
               float *out, long long split_stride, long long ldo, const ImgState *st, int nact,
               hipStream_t s) {
+    if (NT == 16) RT = 2;
     const int RB = (M + 4 * RT * 16 - 1) / (4 * RT * 16);
     if (RT == 4)
         gemm_mode<4>(mode, NT, Xhi, Xlo, ldx, Yhi, Ylo, yimg, ytile, M, kspan, RB, KS, out, split_stride,
@@ -576,13 +593,18 @@ void y_strides(long long K, int Bp, long long &yimg, long long &ytile) {
     }
 }
 
-// Cover the padded batch with image groups of 16 * nt, nt in {8, 4, 2, 1}; groups
-// holding only padding images are skipped.  fn(first image, nt, real images).
+// Image tiles per group: up to 16 (256 images, A streamed once for them) for split
+// storage, whose products then run 10-15 % faster at 256 images; 8 for BF16 and
+// FP8, which run as fast (BF16) or 17 % slower (FP8) with 16.
+int nt_max(int mode) { return mode == M_SPLIT ? TVCS_GEMM_NT_MAX : std::min(8, TVCS_GEMM_NT_MAX); }
+
+// Cover the padded batch with image groups of 16 * nt, nt in {ntmax, ..., 2, 1};
+// groups holding only padding images are skipped.  fn(first image, nt, real images).
 template <class Fn>
-void for_each_group(int Bp, int B, Fn &&fn) {
+void for_each_group(int Bp, int B, int ntmax, Fn &&fn) {
     int tiles = Bp / 16, img0 = 0;
     while (tiles > 0) {
-        int nt = 8;
+        int nt = ntmax;
         while (nt > tiles) nt >>= 1;
         const int nact = std::min(16 * nt, B - img0);
         if (nact > 0) fn(img0, nt, nact);
@@ -733,7 +755,7 @@ void lowp_apply_A(const LowpA &L, LowpWork &W, int B, const float *U, const floa
                        L.N, Bp, nullptr, (u16 *)W.Ubf_hi, (u16 *)W.Ubf_lo, yimg, ytile);
     const int KS = fwd_splits(L);
     const long long split_stride = (long long)Bp * L.mp;
-    for_each_group(Bp, B, [&](int img0, int nt, int nact) {
+    for_each_group(Bp, B, nt_max(mode), [&](int img0, int nt, int nact) {
         gemm_any(W.fwd_rt, mode, nt, L.X_hi, L.X_lo, L.N,
                  (const u16 *)W.Ubf_hi + (img0 / 16) * yimg,
                  (const u16 *)W.Ubf_lo + (img0 / 16) * yimg, yimg, ytile, L.mp, L.N / KS, KS,
@@ -755,7 +777,7 @@ void lowp_apply_At(const LowpA &L, LowpWork &W, int B, const float *R, float *G,
                        L.mp, Bp, L.scale, (u16 *)W.Rbf_hi, (u16 *)W.Rbf_lo, yimg, ytile);
     const int KS = lowp_adj_splits(L);
     const long long split_stride = (long long)Bp * L.N;
-    for_each_group(Bp, B, [&](int img0, int nt, int nact) {
+    for_each_group(Bp, B, nt_max(mode), [&](int img0, int nt, int nact) {
         gemm_any(W.adj_rt, mode, nt, L.XT_hi, L.XT_lo, L.mp,
                  (const u16 *)W.Rbf_hi + (img0 / 16) * yimg,
                  (const u16 *)W.Rbf_lo + (img0 / 16) * yimg, yimg, ytile, L.N, L.mp / KS, KS,

@@ -143,9 +143,10 @@ def test_lowp_stop_rule_per_image(T, batch64):
     assert len(set(it_gpu.tolist())) > 1     # images really stop at different counts
 
 
-@pytest.mark.parametrize("B", [1, 16, 33, 130])
+@pytest.mark.parametrize("B", [1, 16, 33, 130, 300])
 def test_lowp_batch_sizes(T, B):
-    """Padded batches (1 -> 16, 33 -> 48, 130 -> 144) run and agree with the oracle."""
+    """Padded batches (1 -> 16, 33 -> 48, 130 -> 144, 300 -> 304: image groups of
+    256, 32 and 16) run and agree with the oracle."""
     p = synth.make_problem("bs", n=32, m=307, batch=B, seed_A=41, n_shapes=6)
     tau = tau_for(p.A)
     ref = O.ftvcs(p.A, p.f, p.n, p.mu, p.beta, tau, tol=0, maxit=40)
@@ -156,3 +157,18 @@ def test_lowp_batch_sizes(T, B):
     e = max(rel(U[b], ref.u[b]) for b in range(B))
     say(f"  B={B}: max rel err {e:.3e}")
     assert e <= 1e-4
+
+
+@pytest.mark.parametrize("storage", ["bf16", "bf16_split", "fp8_rowscale"])
+def test_lowp_256_image_groups_are_batch_invariant(T, storage):
+    """A batch of 272 images runs as one 256-image group (split storage) or two
+    128-image groups (BF16, FP8), and one 16-image group; an image gives the same
+    bits there as alone (a 16-image group), in each storage."""
+    p = synth.make_problem("g256", n=32, m=307, batch=272, seed_A=43, n_shapes=6)
+    F = p.f.astype(np.float32)
+    with T.Solver(p.A, p.n, storage=storage) as s:
+        rb = s.solve_batch(F, mu=p.mu, beta=p.beta, maxit=30, iadm=True)
+        for b in (0, 137, 255, 271):
+            r1 = s.solve(F[b], mu=p.mu, beta=p.beta, maxit=30, iadm=True)
+            assert np.array_equal(r1["u"].cpu().numpy(), rb["u"][b].cpu().numpy()), b
+    say(f"  {storage}: images 0, 137, 255, 271 equal alone and in the batch of 272")
