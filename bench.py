@@ -299,6 +299,12 @@ def bench_batched(args, np, torch, O, synth, tvcs):
             sweep[f"B{Bs}"] = r
             log(f"bf16 products B={Bs}: {ms_f:.3f} / {ms_a:.3f} ms")
     res["bf16_batch_sweep"] = sweep
+    # split storage at 256 images (one 256-image group per workgroup): the MFMA
+    # pipes execute 3 bf16 products per useful one
+    with tvcs.Solver(A32, p.n, storage="bf16_split") as s:
+        ms_f, ms_a = s.time_products(B=256, reps=5)
+        res["bf16_split_products_B256"] = product_rates("bf16_split", p.m, p.N, 256, ms_f, ms_a)
+        log(f"split products B=256: {ms_f:.3f} / {ms_a:.3f} ms")
     return res
 
 
