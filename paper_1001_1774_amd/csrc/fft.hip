@@ -352,8 +352,8 @@ __device__ void stop_rule(ImgState *st, const double *parts, int nparts, int *co
 
 // Inverse row pass (see the file header).  FUSED: the last block of each image to
 // finish (counted in `counters`, one zeroed int per image) also applies the stop
-// rule; this needs a device-scope fence per block, cheap for one image but not for
-// thousands of blocks, so batches use k_stop_rule instead.
+// rule; this needs a device-scope fence per block.  Off by default: a separate
+// k_stop_rule pass is faster even for one image (TVCS_FUSED_STOP).
 // With T non-null (the partial-DCT operator) the block also transforms its new
 // rows of u (DCT-II along each row, the first pass of the next iteration's
 // forward product) and writes them column-major to T, as the DCT row pass does.
@@ -499,9 +499,12 @@ int rows_per_block(int n, int /*B*/) {
 #ifndef TVCS_FFT_COLS_BATCH
 #define TVCS_FFT_COLS_BATCH 2   // columns per workgroup of the batched column pass
 #endif
+#ifndef TVCS_FFT_COLS_SINGLE_DIV
+#define TVCS_FFT_COLS_SINGLE_DIV 32   // one image: columns per workgroup = (n/2 + 1) / this (at least 1)
+#endif
 int cols_per_block(int n, int B) {
     const int h = n / 2 + 1;
-    int cpb = B == 1 ? std::max(1, h / 32) : TVCS_FFT_COLS_BATCH;
+    int cpb = B == 1 ? std::max(1, h / TVCS_FFT_COLS_SINGLE_DIV) : TVCS_FFT_COLS_BATCH;
     return std::max(1, std::min(std::min(cpb, 2048 / n), h));
 }
 
@@ -529,6 +532,9 @@ void launch_fft_cols_solve(int n, int B, float2 *S, const double *inv_d, const f
                            n, cpb, S, inv_d, tw, st);
 }
 
+#ifndef TVCS_FUSED_STOP
+#define TVCS_FUSED_STOP 0   // 1: for one image the inverse row pass applies the stop rule itself
+#endif
 void launch_fft_rows_inv(int n, int B, const float2 *S, float *U, double *parts,
                          const float2 *tw, ImgState *st, int *counters, hipStream_t s, float *T,
                          const float4 *dtab) {
@@ -539,7 +545,7 @@ void launch_fft_rows_inv(int n, int B, const float2 *S, float *U, double *parts,
     hipLaunchKernelGGL((k_rows_inv<FUSEDV, P2V>), dim3(n / rpb, B), dim3(kThreads), lds, s, n, rpb, \
                        S, U, parts, tw, st, counters, T, dtab)
     const bool p2 = is_pow2(n);
-    if (B == 1) {
+    if (TVCS_FUSED_STOP && B == 1) {
         if (p2) TVCS_ROWS_INV(true, true);
         else TVCS_ROWS_INV(true, false);
     } else {
