@@ -209,7 +209,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int row_wave = rb * (4 * RT * 16) + wave * RT * 16;
     const int kt_begin = (ks * kspan) >> 5;
-    const int steps = kspan / (32 * KF);
+    // the last K slice may be shorter (slices are multiples of 4 k tiles, so of KF)
+    const int steps = min(kspan, (int)(xkt << 5) - ks * kspan) / (32 * KF);
 
     f32x4 acc[RT][NT];
 #pragma unroll
@@ -569,15 +570,55 @@ void gemm_any(int RT, int mode, int NT, const void *Xhi, const void *Xlo, long l
 
 size_t elem_bytes(int mode) { return mode == M_FP8 ? 1 : 2; }
 
-// K slices of the forward product: enough workgroups to fill the chip, slices a
-// multiple of KMAX long.  Depends on (m, N) only, so the order of every sum, and
-// with it each image's result, is the same for every batch size and tile choice.
-int fwd_splits(const LowpA &L) {
+// K slices of the forward product.  Depends on (m, N) only, so the order of every
+// sum, and with it each image's result, is the same for every batch size and tile
+// choice.  The RB x KS tiles of a launch run in rounds of 256 (one per CU; two per
+// CU with twice the tiles at 2 row tiles per wave), and a tile's time is about its
+// slice length plus a fixed cost (pipeline fill, partial results) of ~2 quanta of
+// KMAX: the slice count is the smallest of 1 .. 64 (slices of at least 4 quanta)
+// whose rounds x (length + 2) is within 3 % of the best.  At n = 256, m = 13107
+// (RB = 52): 9 slices of 57 quanta in 2 nearly full rounds of 468 tiles, where 8
+// leave 96 CUs idle in the second round.  The last slice may be shorter.
+// TVCS_FWD_BALANCE 0: powers of two until RB x KS >= TVCS_FWD_TARGET_WG.
+#ifndef TVCS_FWD_BALANCE
+#define TVCS_FWD_BALANCE 1
+#endif
+void fwd_split(const LowpA &L, int &KS, int &kspan) {
     const int RB = L.mp / kRowsRT4;
-    int KS = 1;
-    while (RB * KS < TVCS_FWD_TARGET_WG && (L.N / (KS * 2)) % KMAX == 0 &&
-           L.N / (KS * 2) >= 4 * KMAX)
-        KS *= 2;
+    if (!TVCS_FWD_BALANCE) {
+        KS = 1;
+        while (RB * KS < TVCS_FWD_TARGET_WG && (L.N / (KS * 2)) % KMAX == 0 &&
+               L.N / (KS * 2) >= 4 * KMAX)
+            KS *= 2;
+        kspan = L.N / KS;
+        return;
+    }
+    const int kq = L.N / KMAX;   // k quanta (the reduction step of every KF)
+    constexpr int kMaxSlices = 64;
+    long long cost[kMaxSlices + 1];
+    int span[kMaxSlices + 1], nsl[kMaxSlices + 1];
+    long long best = -1;
+    int last = 1;
+    for (int k = 1; k <= kMaxSlices; ++k) {
+        span[k] = (kq + k - 1) / k;                 // quanta per slice
+        if (k > 1 && span[k] < 4) break;
+        nsl[k] = (kq + span[k] - 1) / span[k];      // slices actually used
+        const long long rounds = ((long long)RB * nsl[k] + 255) / 256;
+        cost[k] = rounds * (span[k] + 2);
+        if (best < 0 || cost[k] < best) best = cost[k];
+        last = k;
+    }
+    for (int k = 1; k <= last; ++k)
+        if (cost[k] * 100 <= best * 103) {
+            KS = nsl[k];
+            kspan = span[k] * KMAX;
+            return;
+        }
+}
+
+int fwd_splits(const LowpA &L) {
+    int KS, kspan;
+    fwd_split(L, KS, kspan);
     return KS;
 }
 
@@ -753,12 +794,13 @@ void lowp_apply_A(const LowpA &L, LowpWork &W, int B, const float *U, const floa
     y_strides(L.N, Bp, yimg, ytile);
     hipLaunchKernelGGL(k_split_frag, dim3(grid1d((size_t)Bp * L.N / 8)), dim3(256), 0, s, U, L.N,
                        L.N, Bp, nullptr, (u16 *)W.Ubf_hi, (u16 *)W.Ubf_lo, yimg, ytile);
-    const int KS = fwd_splits(L);
+    int KS, kspan;
+    fwd_split(L, KS, kspan);
     const long long split_stride = (long long)Bp * L.mp;
     for_each_group(Bp, B, nt_max(mode), [&](int img0, int nt, int nact) {
         gemm_any(W.fwd_rt, mode, nt, L.X_hi, L.X_lo, L.N,
                  (const u16 *)W.Ubf_hi + (img0 / 16) * yimg,
-                 (const u16 *)W.Ubf_lo + (img0 / 16) * yimg, yimg, ytile, L.mp, L.N / KS, KS,
+                 (const u16 *)W.Ubf_lo + (img0 / 16) * yimg, yimg, ytile, L.mp, kspan, KS,
                  W.Rpart + (size_t)img0 * L.mp, split_stride, L.mp, st ? st + img0 : nullptr,
                  nact, s);
     });
