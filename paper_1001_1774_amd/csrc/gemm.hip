@@ -583,23 +583,18 @@ size_t elem_bytes(int mode) { return mode == M_FP8 ? 1 : 2; }
 #ifndef TVCS_FWD_BALANCE
 #define TVCS_FWD_BALANCE 1
 #endif
-void fwd_split(const LowpA &L, int &KS, int &kspan) {
-    const int RB = L.mp / kRowsRT4;
-    if (!TVCS_FWD_BALANCE) {
-        KS = 1;
-        while (RB * KS < TVCS_FWD_TARGET_WG && (L.N / (KS * 2)) % KMAX == 0 &&
-               L.N / (KS * 2) >= 4 * KMAX)
-            KS *= 2;
-        kspan = L.N / KS;
-        return;
-    }
-    const int kq = L.N / KMAX;   // k quanta (the reduction step of every KF)
+// Slice count of a reduction of length K over RB row blocks of 256, at most maxk
+// slices of at least 4 quanta: the smallest whose rounds x (length + 2) is within
+// 3 % of the best (see above).
+void balanced_split(int RB, int K, int maxk, int &KS, int &kspan) {
+    const int kq = K / KMAX;   // k quanta (the reduction step of every KF)
     constexpr int kMaxSlices = 64;
+    maxk = std::min(maxk, kMaxSlices);
     long long cost[kMaxSlices + 1];
     int span[kMaxSlices + 1], nsl[kMaxSlices + 1];
     long long best = -1;
     int last = 1;
-    for (int k = 1; k <= kMaxSlices; ++k) {
+    for (int k = 1; k <= maxk; ++k) {
         span[k] = (kq + k - 1) / k;                 // quanta per slice
         if (k > 1 && span[k] < 4) break;
         nsl[k] = (kq + span[k] - 1) / span[k];      // slices actually used
@@ -614,6 +609,19 @@ void fwd_split(const LowpA &L, int &KS, int &kspan) {
             kspan = span[k] * KMAX;
             return;
         }
+}
+
+void fwd_split(const LowpA &L, int &KS, int &kspan) {
+    const int RB = L.mp / kRowsRT4;
+    if (!TVCS_FWD_BALANCE) {
+        KS = 1;
+        while (RB * KS < TVCS_FWD_TARGET_WG && (L.N / (KS * 2)) % KMAX == 0 &&
+               L.N / (KS * 2) >= 4 * KMAX)
+            KS *= 2;
+        kspan = L.N / KS;
+        return;
+    }
+    balanced_split(RB, L.N, 64, KS, kspan);
 }
 
 int fwd_splits(const LowpA &L) {
@@ -658,9 +666,31 @@ int grid1d(size_t count) { return (int)std::min<size_t>((count + 255) / 256, 163
 
 }  // namespace
 
+// K slices of the adjoint product: TVCS_ADJ_SPLIT, or with TVCS_ADJ_BALANCE the
+// balanced count of at most TVCS_ADJ_SPLIT_MAX slices (the shrink pass adds the
+// slices' partials per pixel, so they stay few; measured: 1 slice instead of 2 at
+// n = 256 makes the adjoint 6-7 % faster, while 3-4 slices at n = 128 are slower
+// than 2, the model's fixed cost per tile being too small for such short tiles).
+// Depends on (m, N) only.
+#ifndef TVCS_ADJ_BALANCE
+#define TVCS_ADJ_BALANCE 1
+#endif
+#ifndef TVCS_ADJ_SPLIT_MAX
+#define TVCS_ADJ_SPLIT_MAX 2
+#endif
+void adj_split(const LowpA &L, int &KS, int &kspan) {
+    if (!TVCS_ADJ_BALANCE) {
+        KS = 1;
+        while (KS < TVCS_ADJ_SPLIT && (L.mp / (KS * 2)) % KMAX == 0) KS *= 2;
+        kspan = L.mp / KS;
+        return;
+    }
+    balanced_split(L.N / kRowsRT4, L.mp, TVCS_ADJ_SPLIT_MAX, KS, kspan);
+}
+
 int lowp_adj_splits(const LowpA &L) {
-    int KS = 1;
-    while (KS < TVCS_ADJ_SPLIT && (L.mp / (KS * 2)) % KMAX == 0) KS *= 2;
+    int KS, kspan;
+    adj_split(L, KS, kspan);
     return KS;
 }
 
@@ -817,12 +847,13 @@ void lowp_apply_At(const LowpA &L, LowpWork &W, int B, const float *R, float *G,
     y_strides(L.mp, Bp, yimg, ytile);
     hipLaunchKernelGGL(k_split_frag, dim3(grid1d((size_t)Bp * L.mp / 8)), dim3(256), 0, s, R, L.m,
                        L.mp, Bp, L.scale, (u16 *)W.Rbf_hi, (u16 *)W.Rbf_lo, yimg, ytile);
-    const int KS = lowp_adj_splits(L);
+    int KS, kspan;
+    adj_split(L, KS, kspan);
     const long long split_stride = (long long)Bp * L.N;
     for_each_group(Bp, B, nt_max(mode), [&](int img0, int nt, int nact) {
         gemm_any(W.adj_rt, mode, nt, L.XT_hi, L.XT_lo, L.mp,
                  (const u16 *)W.Rbf_hi + (img0 / 16) * yimg,
-                 (const u16 *)W.Rbf_lo + (img0 / 16) * yimg, yimg, ytile, L.N, L.mp / KS, KS,
+                 (const u16 *)W.Rbf_lo + (img0 / 16) * yimg, yimg, ytile, L.N, kspan, KS,
                  G + (size_t)img0 * L.N, split_stride, L.N, st ? st + img0 : nullptr, nact, s);
     });
 }
