@@ -53,7 +53,7 @@
 #define TVCS_GEMM_KF_NT8 1     // ... 128-image groups
 #endif
 #ifndef TVCS_GEMM_KF_NT4
-#define TVCS_GEMM_KF_NT4 2     // ... 64-image groups
+#define TVCS_GEMM_KF_NT4 4     // ... 64-image groups
 #endif
 #ifndef TVCS_GEMM_KF_NT2
 #define TVCS_GEMM_KF_NT2 4     // ... 32-image groups
