@@ -583,6 +583,9 @@ size_t elem_bytes(int mode) { return mode == M_FP8 ? 1 : 2; }
 #ifndef TVCS_FWD_BALANCE
 #define TVCS_FWD_BALANCE 1
 #endif
+#ifndef TVCS_SPLIT_FIXED
+#define TVCS_SPLIT_FIXED 2   // fixed cost of a tile in the slice-count model, in quanta of KMAX
+#endif
 // Slice count of a reduction of length K over RB row blocks of 256, at most maxk
 // slices of at least 4 quanta: the smallest whose rounds x (length + 2) is within
 // 3 % of the best (see above).
@@ -599,7 +602,7 @@ void balanced_split(int RB, int K, int maxk, int &KS, int &kspan) {
         if (k > 1 && span[k] < 4) break;
         nsl[k] = (kq + span[k] - 1) / span[k];      // slices actually used
         const long long rounds = ((long long)RB * nsl[k] + 255) / 256;
-        cost[k] = rounds * (span[k] + 2);
+        cost[k] = rounds * (span[k] + TVCS_SPLIT_FIXED);
         if (best < 0 || cost[k] < best) best = cost[k];
         last = k;
     }
