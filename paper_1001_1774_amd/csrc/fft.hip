@@ -20,6 +20,7 @@
 // Twiddles come from a 512-entry table of exp(-2 pi i t / 512) computed in FP64.
 #include "device_fft.h"
 #include "device_shrink.h"
+#include "device_stop.h"
 
 #include <algorithm>
 
@@ -313,42 +314,6 @@ __global__ __launch_bounds__(kThreads) void k_cols_solve(int n, int cpb, float2 
     for (int e = threadIdx.x; e < nc * n; e += kThreads) col[e] = out[lp(e)];
 }
 
-// The stop rule of eq. (stop), ||u^{k+1} - u^k|| <= tol ||u^k|| (inclusive, FP64),
-// for one image from its row blocks' partial sums (added in block order by one
-// 64-lane wave, so the result does not depend on how the pass was launched).
-__device__ void stop_rule(ImgState *st, const double *parts, int nparts, int *counter) {
-    const int lane = threadIdx.x & 63;
-    double sd = 0.0, su = 0.0;
-    for (int p = lane; p < nparts; p += 64) {
-        sd += __hip_atomic_load(parts + 2 * p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        su += __hip_atomic_load(parts + 2 * p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        sd += __shfl_xor(sd, off, 64);
-        su += __shfl_xor(su, off, 64);
-    }
-    if (lane == 0) {
-        ImgState s = *st;
-        s.iters += 1;
-        s.du2 = sd;
-        s.u2 = su;
-        const double du = sqrt(sd), nu = sqrt(su);
-        s.rel = nu > 0.0 ? du / nu : (du > 0.0 ? INFINITY : 0.0);
-        if (!isfinite(sd) || !isfinite(su)) {
-            s.status = TVCS_ENONFINITE;
-            s.active = 0;
-        } else if (s.tol > 0.0 && du <= s.tol * nu) {
-            s.status = TVCS_OK;
-            s.active = 0;
-        } else if (s.iters >= s.maxit) {
-            s.status = s.tol > 0.0 ? TVCS_MAXIT : TVCS_OK;
-            s.active = 0;
-        }
-        *st = s;
-        if (counter) *counter = 0;   // ready for the next pass
-    }
-}
 
 // Inverse row pass (see the file header).  FUSED: the last block of each image to
 // finish (counted in `counters`, one zeroed int per image) also applies the stop
@@ -535,9 +500,11 @@ void launch_fft_cols_solve(int n, int B, float2 *S, const double *inv_d, const f
 #ifndef TVCS_FUSED_STOP
 #define TVCS_FUSED_STOP 0   // 1: for one image the inverse row pass applies the stop rule itself
 #endif
+int stop_parts(int n, int B) { return n / rows_per_block(n, B); }
+
 void launch_fft_rows_inv(int n, int B, const float2 *S, float *U, double *parts,
                          const float2 *tw, ImgState *st, int *counters, hipStream_t s, float *T,
-                         const float4 *dtab) {
+                         const float4 *dtab, bool stop_pass) {
     const int rpb = rows_per_block(n, B);
     const size_t lds = sizeof(float2) * (kMaxN + 2 * lp_size((rpb / 2) * n + rpb)) +
                        (T ? sizeof(float4) * n : 0);
@@ -545,13 +512,13 @@ void launch_fft_rows_inv(int n, int B, const float2 *S, float *U, double *parts,
     hipLaunchKernelGGL((k_rows_inv<FUSEDV, P2V>), dim3(n / rpb, B), dim3(kThreads), lds, s, n, rpb, \
                        S, U, parts, tw, st, counters, T, dtab)
     const bool p2 = is_pow2(n);
-    if (TVCS_FUSED_STOP && B == 1) {
+    if (TVCS_FUSED_STOP && B == 1 && stop_pass) {
         if (p2) TVCS_ROWS_INV(true, true);
         else TVCS_ROWS_INV(true, false);
     } else {
         if (p2) TVCS_ROWS_INV(false, true);
         else TVCS_ROWS_INV(false, false);
-        hipLaunchKernelGGL(k_stop_rule, dim3(B), dim3(64), 0, s, st, parts, n / rpb);
+        if (stop_pass) hipLaunchKernelGGL(k_stop_rule, dim3(B), dim3(64), 0, s, st, parts, n / rpb);
     }
 #undef TVCS_ROWS_INV
 }

@@ -16,6 +16,7 @@
 // exact).  r = A u - f is a small residual of O(1) terms, so FP32 accumulation
 // would put an error of ~sqrt(N) eps |A||u| into it; the FP64 units have an
 // order of magnitude more throughput than this HBM-bound loop needs.
+#include "device_stop.h"
 #include "tvcs_internal.h"
 
 #include <algorithm>
@@ -83,11 +84,20 @@ __device__ inline double dot4(f4 a, const double (&x)[4], double acc) {
     return fma((double)a.w, x[3], acc);
 }
 
+// stw (one image, non-null): workgroup 0 first applies the stop rule of the
+// previous iteration to stw from its nparts norm partials (as k_stop_rule would
+// after the inverse row pass).  The other workgroups may read the flag before or
+// after that update: when the rule stops the image, some of them still write R,
+// which no later pass of a stopped image reads.
 template <int NV, int ROWS, bool NT>
 __global__ __launch_bounds__(kThreads) void k_gemv_rows(
     const float *__restrict__ A, int m, int N, const float *__restrict__ U, int ldu,
     const float *__restrict__ F, int ldf, float *__restrict__ R, int ldr,
-    const ImgState *__restrict__ st, int nact) {
+    const ImgState *st, int nact, ImgState *stw, const double *parts, int nparts) {
+    if (stw && blockIdx.x == 0) {
+        if (threadIdx.x < 64 && stw->active) stop_rule(stw, parts, nparts, nullptr);
+        __syncthreads();
+    }
     if (!any_active(st, nact)) return;
     // Workgroups take row pairs from the last to the first (TVCS_GEMV_ROWS_REVERSE):
     // measured 0.4 % faster per 500-iteration solve at n = 128 (A of 256 MiB, about
@@ -230,15 +240,16 @@ __global__ __launch_bounds__(kThreads * TVCS_COLS_RS) void k_gemv_cols(
 
 template <int NV>
 void rows_dispatch(const float *A, int m, int N, const float *U, int ldu, const float *F,
-                   int ldf, float *R, int ldr, const ImgState *st, int nact, hipStream_t s) {
+                   int ldf, float *R, int ldr, const ImgState *st, int nact, ImgState *stw,
+                   const double *parts, int nparts, hipStream_t s) {
     constexpr int ROWS = NV <= 2 ? TVCS_GEMV_ROWS : 2;
     const int grid = (m + ROWS - 1) / ROWS;
     if ((size_t)m * N * sizeof(float) > TVCS_GEMV_NT_BYTES)
         hipLaunchKernelGGL((k_gemv_rows<NV, ROWS, true>), dim3(grid), dim3(kThreads), 0, s, A, m,
-                           N, U, ldu, F, ldf, R, ldr, st, nact);
+                           N, U, ldu, F, ldf, R, ldr, st, nact, stw, parts, nparts);
     else
         hipLaunchKernelGGL((k_gemv_rows<NV, ROWS, false>), dim3(grid), dim3(kThreads), 0, s, A, m,
-                           N, U, ldu, F, ldf, R, ldr, st, nact);
+                           N, U, ldu, F, ldf, R, ldr, st, nact, stw, parts, nparts);
 }
 
 // Row chunks of the A^T r product: aim for ~TVCS_COLS_TARGET_WG chunk x column
@@ -285,12 +296,14 @@ int gemv_cols_chunks(int m, int N) {
 
 void launch_gemv_rows(const float *A, int m, int N, const float *U, int ldu, const float *F,
                       int ldf, float *R, int ldr, int nv, const ImgState *st, int nact,
-                      hipStream_t s) {
+                      hipStream_t s, ImgState *stw, const double *parts, int nparts) {
+    if (stw && (nv != 1 || nact != 1 || st != stw || !parts || nparts < 1))
+        fail(TVCS_EINVAL, "gemv_rows: the stop rule is folded in for one image only");
     switch (nv) {
-        case 1: rows_dispatch<1>(A, m, N, U, ldu, F, ldf, R, ldr, st, nact, s); break;
-        case 2: rows_dispatch<2>(A, m, N, U, ldu, F, ldf, R, ldr, st, nact, s); break;
-        case 4: rows_dispatch<4>(A, m, N, U, ldu, F, ldf, R, ldr, st, nact, s); break;
-        case 8: rows_dispatch<8>(A, m, N, U, ldu, F, ldf, R, ldr, st, nact, s); break;
+        case 1: rows_dispatch<1>(A, m, N, U, ldu, F, ldf, R, ldr, st, nact, stw, parts, nparts, s); break;
+        case 2: rows_dispatch<2>(A, m, N, U, ldu, F, ldf, R, ldr, st, nact, stw, parts, nparts, s); break;
+        case 4: rows_dispatch<4>(A, m, N, U, ldu, F, ldf, R, ldr, st, nact, stw, parts, nparts, s); break;
+        case 8: rows_dispatch<8>(A, m, N, U, ldu, F, ldf, R, ldr, st, nact, stw, parts, nparts, s); break;
         default: fail(TVCS_EINVAL, "gemv_rows: nv must be 1, 2, 4 or 8");
     }
 }

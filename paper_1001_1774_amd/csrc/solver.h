@@ -41,6 +41,9 @@ struct DevBuf {
 };
 
 constexpr int kGraphIters = 10;   // iterations per captured graph (even: q ping-pong)
+#ifndef TVCS_FOLD_STOP
+#define TVCS_FOLD_STOP 1          // one image, FP32 A: stop rule folded into the next A u product
+#endif
 constexpr int kPowerIters = 100;
 constexpr double kPowerRtol = 1e-10;
 
@@ -304,10 +307,23 @@ struct tvcs_ctx {
         return a;
     }
 
-    void enqueue_iteration(int B, int parity, bool iadm, double beta, double c, double ctau) {
+    // One image with FP32 A: the stop rule of an iteration is applied by the first
+    // workgroup of the next iteration's A u product (fold_prev), and only the last
+    // iteration of a captured graph ends with its own stop-rule pass (stop_here).
+    bool fold_stop(int B) const {
+        return TVCS_FOLD_STOP && !dct() && !lowprec() && B == 1 && pass_nv(padded(B)) == 1;
+    }
+
+    void enqueue_iteration(int B, int parity, bool iadm, double beta, double c, double ctau,
+                           bool fold_prev = false, bool stop_here = true) {
         const int Bp = padded(B);
         ImgState *st = state.as<ImgState>();
-        if (dct()) {
+        if (fold_prev) {
+            launch_gemv_rows(A32.as<float>(), m, N, U.as<float>(), N, F.as<float>(), m,
+                             R.as<float>(), m, 1, st, 1, work, st, parts.as<double>(),
+                             stop_parts(n, B));
+            apply_At(Bp, B, R.as<float>(), st);
+        } else if (dct()) {
             // forward and adjoint share the column pass: r = (C u)[sel] - f and the
             // zero-filled residual's inverse column transform in one kernel; the row
             // pass of C u came from the previous iteration's inverse row FFT (or
@@ -336,7 +352,7 @@ struct tvcs_ctx {
         launch_fft_cols_solve(n, B, Sp, invd.as<double>(), twp, st, work);
         launch_fft_rows_inv(n, B, Sp, U.as<float>(), parts.as<double>(), twp, st,
                             counters.as<int>(), work, dct() ? DT.as<float>() : nullptr,
-                            dct() ? dtab.as<float4>() : nullptr);
+                            dct() ? dtab.as<float4>() : nullptr, stop_here);
     }
 
     void build_graph(int B, unsigned flags, double beta, double c, double ctau) {
@@ -349,8 +365,10 @@ struct tvcs_ctx {
         hipGraph_t graph = nullptr;
         TVCS_HIP(hipStreamBeginCapture(work, hipStreamCaptureModeRelaxed));
         try {
+            const bool fold = fold_stop(B);
             for (int i = 0; i < kGraphIters; ++i)
-                enqueue_iteration(B, i & 1, (flags & TVCS_IADM) != 0, beta, c, ctau);
+                enqueue_iteration(B, i & 1, (flags & TVCS_IADM) != 0, beta, c, ctau,
+                                  fold && i > 0, !fold || i == kGraphIters - 1);
         } catch (...) {
             (void)hipStreamEndCapture(work, &graph);
             if (graph) (void)hipGraphDestroy(graph);

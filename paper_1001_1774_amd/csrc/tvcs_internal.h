@@ -54,9 +54,13 @@ int even_divisor_at_most(int n, int want);   // largest even divisor of n <= wan
 //   cols: P[c*chunk_stride + v*N + j] = sum_{i in chunk c} A[i*N + j] R[v*ldr + i]
 // Both return at entry when `active` is given and none of its `nact` flags is set.
 // ---------------------------------------------------------------------------
+// stw, parts, nparts (one image, nv = nact = 1, stw == active): workgroup 0 first
+// applies the previous iteration's stop rule to stw from the inverse row pass's
+// nparts norm partials (launch_fft_rows_inv with stop_pass = false)
 void launch_gemv_rows(const float *A, int m, int N, const float *U, int ldu, const float *F,
                       int ldf, float *R, int ldr, int nv, const ImgState *active, int nact,
-                      hipStream_t s);
+                      hipStream_t s, ImgState *stw = nullptr, const double *parts = nullptr,
+                      int nparts = 0);
 int gemv_cols_chunks(int m, int N);   // row chunks of the A^T r partial sums
 // chunk c of vector v goes to P[c*chunk_stride + v*N + j]
 void launch_gemv_cols(const float *A, int m, int N, const float *R, int ldr, float *P,
@@ -129,9 +133,13 @@ void launch_fft_cols_solve(int n, int B, float2 *S, const double *inv_d, const f
 // workgroup of an image sums the norm partials; counters: one zeroed int per image)
 // T, dtab (partial DCT): also write the DCT-II of the new rows of u to T, as
 // launch_dct_rows_fwd does (null: not)
+// stop_pass = false: no k_stop_rule after the pass (the caller applies the rule
+// later, e.g. folded into the next A u product); stop_parts(n, B) partials per image
 void launch_fft_rows_inv(int n, int B, const float2 *S, float *U, double *parts,
                          const float2 *tw, ImgState *st, int *counters, hipStream_t s,
-                         float *T = nullptr, const float4 *dtab = nullptr);
+                         float *T = nullptr, const float4 *dtab = nullptr,
+                         bool stop_pass = true);
+int stop_parts(int n, int B);
 // shrinkage + right-hand side fused with the forward row FFT
 void launch_shrink_rows(const ShrinkArgs &a, bool iadm, float2 *S, const float2 *tw,
                         hipStream_t s);
