@@ -27,6 +27,7 @@
 // second line as the imaginary part), split again with the Hermitian symmetry.
 // The FFTs are the LDS Stockham FFTs of the u-step solve.
 #include "device_fft.h"
+#include "device_stop.h"
 
 #include <algorithm>
 #include <cmath>
@@ -126,8 +127,16 @@ __global__ __launch_bounds__(kThreads) void k_dct_cols(int n, int lines, float *
                                                        float *__restrict__ R, int ldr,
                                                        const float2 *__restrict__ tw,
                                                        const float4 *__restrict__ tab,
-                                                       const ImgState *__restrict__ st) {
+                                                       const ImgState *st, ImgState *stw,
+                                                       const double *parts, int nparts) {
     const int b = blockIdx.y;
+    // stw (one image): workgroup 0 first applies the previous iteration's stop rule,
+    // as in the A u product of FP32 storage (the other workgroups may read the flag
+    // before or after; a stopped image's r and transformed residual are not read)
+    if (stw && blockIdx.x == 0) {
+        if (threadIdx.x < 64 && stw->active) stop_rule(stw, parts, nparts, nullptr);
+        __syncthreads();
+    }
     if (st && !st[b].active) return;
     const DctLds L = dct_lds(n, lines);
     load_tables<P2>(L, n, tw, tab);
@@ -252,17 +261,20 @@ void launch_dct_rows_fwd(int n, int B, const float *U, float *T, const float2 *t
 
 void launch_dct_cols_fwd(int n, int B, float *T, const int *selT, const float *F, int ldf,
                          float *R, int ldr, bool adjoint, const float2 *tw, const float4 *tab,
-                         const ImgState *st, hipStream_t s) {
+                         const ImgState *st, hipStream_t s, ImgState *stw, const double *parts,
+                         int nparts) {
+    if (stw && (B != 1 || st != stw || !parts || nparts < 1))
+        fail(TVCS_EINVAL, "dct_cols: the stop rule is folded in for one image only");
     const int lines = dct_lines(n);
     const size_t lds = dct_lds_bytes(n, lines);
     const dim3 grid(n / lines, B);
 #define TVCS_DCT_COLS(P2V)                                                                        \
     if (adjoint)                                                                                  \
         hipLaunchKernelGGL((k_dct_cols<true, true, P2V>), grid, dim3(kThreads), lds, s, n, lines, \
-                           T, selT, F, ldf, R, ldr, tw, tab, st);                                 \
+                           T, selT, F, ldf, R, ldr, tw, tab, st, stw, parts, nparts);             \
     else                                                                                          \
         hipLaunchKernelGGL((k_dct_cols<true, false, P2V>), grid, dim3(kThreads), lds, s, n, lines, \
-                           T, selT, F, ldf, R, ldr, tw, tab, st)
+                           T, selT, F, ldf, R, ldr, tw, tab, st, stw, parts, nparts)
     if (is_pow2(n)) {
         TVCS_DCT_COLS(true);
     } else {
@@ -287,7 +299,8 @@ void launch_dct_adjoint(int n, int B, const float *R, int ldr, float *T, const i
 #define TVCS_DCT_ADJ(P2V)                                                                        \
     if (from_R)                                                                                  \
         hipLaunchKernelGGL((k_dct_cols<false, true, P2V>), grid, dim3(kThreads), lds, s, n, lines, \
-                           T, selT, nullptr, 0, const_cast<float *>(R), ldr, tw, tab, st);        \
+                           T, selT, nullptr, 0, const_cast<float *>(R), ldr, tw, tab, st, nullptr, \
+                           nullptr, 0);                                                          \
     hipLaunchKernelGGL(k_dct_rows_inv<P2V>, grid, dim3(kThreads), lds, s, n, lines, T, G, ldg, tw, \
                        tab, st)
     if (is_pow2(n)) {

@@ -307,31 +307,34 @@ struct tvcs_ctx {
         return a;
     }
 
-    // One image with FP32 A: the stop rule of an iteration is applied by the first
-    // workgroup of the next iteration's A u product (fold_prev), and only the last
-    // iteration of a captured graph ends with its own stop-rule pass (stop_here).
+    // One image with FP32 A or the partial DCT: the stop rule of an iteration is
+    // applied by the first workgroup of the next iteration's A u product (fold_prev),
+    // and only the last iteration of a captured graph ends with its own stop-rule
+    // pass (stop_here).
     bool fold_stop(int B) const {
-        return TVCS_FOLD_STOP && !dct() && !lowprec() && B == 1 && pass_nv(padded(B)) == 1;
+        return TVCS_FOLD_STOP && !lowprec() && B == 1 && (dct() || pass_nv(padded(B)) == 1);
     }
 
     void enqueue_iteration(int B, int parity, bool iadm, double beta, double c, double ctau,
                            bool fold_prev = false, bool stop_here = true) {
         const int Bp = padded(B);
         ImgState *st = state.as<ImgState>();
-        if (fold_prev) {
-            launch_gemv_rows(A32.as<float>(), m, N, U.as<float>(), N, F.as<float>(), m,
-                             R.as<float>(), m, 1, st, 1, work, st, parts.as<double>(),
-                             stop_parts(n, B));
-            apply_At(Bp, B, R.as<float>(), st);
-        } else if (dct()) {
+        if (dct()) {
             // forward and adjoint share the column pass: r = (C u)[sel] - f and the
             // zero-filled residual's inverse column transform in one kernel; the row
             // pass of C u came from the previous iteration's inverse row FFT (or
             // seed_dct_rows before the first)
             launch_dct_cols_fwd(n, B, DT.as<float>(), selT.as<int>(), F.as<float>(), m,
                                 R.as<float>(), m, true, tw.as<float2>(), dtab.as<float4>(), st,
-                                work);
+                                work, fold_prev ? st : nullptr,
+                                fold_prev ? parts.as<double>() : nullptr,
+                                fold_prev ? stop_parts(n, B) : 0);
             // the inverse row transform (g = A^T r) is computed by the shrink pass
+        } else if (fold_prev) {
+            launch_gemv_rows(A32.as<float>(), m, N, U.as<float>(), N, F.as<float>(), m,
+                             R.as<float>(), m, 1, st, 1, work, st, parts.as<double>(),
+                             stop_parts(n, B));
+            apply_At(Bp, B, R.as<float>(), st);
         } else {
             apply_A(Bp, B, U.as<float>(), F.as<float>(), R.as<float>(), st);
             apply_At(Bp, B, R.as<float>(), st);

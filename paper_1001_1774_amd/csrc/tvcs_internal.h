@@ -202,9 +202,12 @@ void launch_dct_forward(int n, int B, const float *U, float *T, const int *selT,
 // the row pass alone (T from U), and the column pass alone (continuing from T)
 void launch_dct_rows_fwd(int n, int B, const float *U, float *T, const float2 *tw,
                          const float4 *tab, const ImgState *st, hipStream_t s);
+// stw, parts, nparts (one image, stw == st): workgroup 0 first applies the previous
+// iteration's stop rule, as launch_gemv_rows does
 void launch_dct_cols_fwd(int n, int B, float *T, const int *selT, const float *F, int ldf,
                          float *R, int ldr, bool adjoint, const float2 *tw, const float4 *tab,
-                         const ImgState *st, hipStream_t s);
+                         const ImgState *st, hipStream_t s, ImgState *stw = nullptr,
+                         const double *parts = nullptr, int nparts = 0);
 // G[b*ldg + p] = (A^T r_b)_p; from_R: scatter R first, else continue from T
 void launch_dct_adjoint(int n, int B, const float *R, int ldr, float *T, const int *selT,
                         bool from_R, float *G, int ldg, const float2 *tw, const float4 *tab,
