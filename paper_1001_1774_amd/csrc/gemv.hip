@@ -52,6 +52,9 @@
 #ifndef TVCS_COLS_SLOTS
 #define TVCS_COLS_SLOTS 0     // >0: row-chunk slots per column block of A^T r (0: one per chunk)
 #endif
+#ifndef TVCS_COLS_R_LDS
+#define TVCS_COLS_R_LDS 0     // 1: a chunk's r coefficients are staged in LDS first
+#endif
 #ifndef TVCS_COLS_REVERSE
 #define TVCS_COLS_REVERSE 0   // 1: sweep row chunks last-to-first (after A u read first-to-last)
 #endif
@@ -183,12 +186,14 @@ __global__ __launch_bounds__(kThreads * TVCS_COLS_RS) void k_gemv_cols(
         const int chunk = TVCS_COLS_REVERSE ? nrowchunk - 1 - idx : idx;
         const int i0 = chunk * rows_per_chunk;
         const int rows = min(rows_per_chunk, m - i0);
-        __syncthreads();   // the previous chunk's coefficients are no longer read
-        for (int t = threadIdx.x; t < rows * NV; t += kThreads * RS) {
-            const int i = t / NV, v = t % NV;
-            rs[t] = Rv[(size_t)v * ldr + i0 + i];
+        if (TVCS_COLS_R_LDS) {
+            __syncthreads();   // the previous chunk's coefficients are no longer read
+            for (int t = threadIdx.x; t < rows * NV; t += kThreads * RS) {
+                const int i = t / NV, v = t % NV;
+                rs[t] = Rv[(size_t)v * ldr + i0 + i];
+            }
+            __syncthreads();
         }
-        __syncthreads();
         const f4 *col = reinterpret_cast<const f4 *>(A + (size_t)i0 * N);
 #pragma unroll 8
         for (int i = phase; i < rows; i += RS) {
@@ -200,7 +205,9 @@ __global__ __launch_bounds__(kThreads * TVCS_COLS_RS) void k_gemv_cols(
             }
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double r = rs[i * NV + v];
+                // the row's coefficient: staged in LDS, or read where it is used (one
+                // address for the whole workgroup, no barrier before the A stream)
+                const double r = TVCS_COLS_R_LDS ? rs[i * NV + v] : (double)Rv[(size_t)v * ldr + i0 + i];
 #pragma unroll
                 for (int c = 0; c < VEC; ++c) {
                     acc[c][v][0] = fma((double)a[c].x, r, acc[c][v][0]);
@@ -212,7 +219,7 @@ __global__ __launch_bounds__(kThreads * TVCS_COLS_RS) void k_gemv_cols(
         }
     }
     if (RS > 1) {   // phase 0 adds the other phases' sums, one (c, v) at a time
-        double *buf = rs + rows_per_chunk * NV;
+        double *buf = rs + (TVCS_COLS_R_LDS ? rows_per_chunk * NV : 0);
 #pragma unroll
         for (int c = 0; c < VEC; ++c)
 #pragma unroll
@@ -275,7 +282,8 @@ void cols_dispatch(const float *A, int m, int N, const float *R, int ldr, float 
     const int rpc = (m + nrc - 1) / nrc;
     const int slots = gemv_cols_chunks(m, N);
     const int colblocks = (N / 4 + kThreads * TVCS_COLS_VEC - 1) / (kThreads * TVCS_COLS_VEC);
-    const size_t lds = sizeof(double) * (rpc * NV + (TVCS_COLS_RS > 1 ? 4 * kThreads : 0));
+    const size_t lds =
+        sizeof(double) * ((TVCS_COLS_R_LDS ? rpc * NV : 0) + (TVCS_COLS_RS > 1 ? 4 * kThreads : 0));
     const dim3 block(kThreads * TVCS_COLS_RS);
     if ((size_t)m * N * sizeof(float) > TVCS_COLS_NT_BYTES)
         hipLaunchKernelGGL((k_gemv_cols<NV, true>), dim3(colblocks, slots), block, lds, s, A, m, N,
