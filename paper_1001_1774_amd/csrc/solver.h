@@ -42,7 +42,7 @@ struct DevBuf {
 
 constexpr int kGraphIters = 10;   // iterations per captured graph (even: q ping-pong)
 #ifndef TVCS_FOLD_STOP
-#define TVCS_FOLD_STOP 1          // one image, FP32 A: stop rule folded into the next A u product
+#define TVCS_FOLD_STOP 1          // one image (FP32 A, partial DCT): stop rule folded into the next A u pass
 #endif
 constexpr int kPowerIters = 100;
 constexpr double kPowerRtol = 1e-10;
