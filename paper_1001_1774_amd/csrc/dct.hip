@@ -130,11 +130,13 @@ __global__ __launch_bounds__(kThreads) void k_dct_cols(int n, int lines, float *
                                                        const ImgState *st, ImgState *stw,
                                                        const double *parts, int nparts) {
     const int b = blockIdx.y;
-    // stw (one image): workgroup 0 first applies the previous iteration's stop rule,
-    // as in the A u product of FP32 storage (the other workgroups may read the flag
-    // before or after; a stopped image's r and transformed residual are not read)
+    // stw: the first workgroup of each image first applies the previous iteration's
+    // stop rule to it, as in the A u product of FP32 storage (the image's other
+    // workgroups may read the flag before or after; a stopped image's r and
+    // transformed residual are not read)
     if (stw && blockIdx.x == 0) {
-        if (threadIdx.x < 64 && stw->active) stop_rule(stw, parts, nparts, nullptr);
+        if (threadIdx.x < 64 && stw[b].active)
+            stop_rule(stw + b, parts + (size_t)b * nparts * 2, nparts, nullptr);
         __syncthreads();
     }
     if (st && !st[b].active) return;
@@ -263,8 +265,8 @@ void launch_dct_cols_fwd(int n, int B, float *T, const int *selT, const float *F
                          float *R, int ldr, bool adjoint, const float2 *tw, const float4 *tab,
                          const ImgState *st, hipStream_t s, ImgState *stw, const double *parts,
                          int nparts) {
-    if (stw && (B != 1 || st != stw || !parts || nparts < 1))
-        fail(TVCS_EINVAL, "dct_cols: the stop rule is folded in for one image only");
+    if (stw && (st != stw || !parts || nparts < 1))
+        fail(TVCS_EINVAL, "dct_cols: the folded stop rule needs the image states and partials");
     const int lines = dct_lines(n);
     const size_t lds = dct_lds_bytes(n, lines);
     const dim3 grid(n / lines, B);

@@ -42,7 +42,7 @@ struct DevBuf {
 
 constexpr int kGraphIters = 10;   // iterations per captured graph (even: q ping-pong)
 #ifndef TVCS_FOLD_STOP
-#define TVCS_FOLD_STOP 1          // one image (FP32 A, partial DCT): stop rule folded into the next A u pass
+#define TVCS_FOLD_STOP 1          // stop rule folded into the next A u pass (one image FP32; partial DCT)
 #endif
 constexpr int kPowerIters = 100;
 constexpr double kPowerRtol = 1e-10;
@@ -307,12 +307,12 @@ struct tvcs_ctx {
         return a;
     }
 
-    // One image with FP32 A or the partial DCT: the stop rule of an iteration is
-    // applied by the first workgroup of the next iteration's A u product (fold_prev),
-    // and only the last iteration of a captured graph ends with its own stop-rule
-    // pass (stop_here).
+    // One image with FP32 A, or any batch with the partial DCT: the stop rule of an
+    // iteration is applied by the first workgroup (of each image) of the next
+    // iteration's A u pass (fold_prev), and only the last iteration of a captured
+    // graph ends with its own stop-rule pass (stop_here).
     bool fold_stop(int B) const {
-        return TVCS_FOLD_STOP && !lowprec() && B == 1 && (dct() || pass_nv(padded(B)) == 1);
+        return TVCS_FOLD_STOP && !lowprec() && (dct() || (B == 1 && pass_nv(padded(B)) == 1));
     }
 
     void enqueue_iteration(int B, int parity, bool iadm, double beta, double c, double ctau,

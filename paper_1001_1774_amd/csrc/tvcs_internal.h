@@ -202,8 +202,8 @@ void launch_dct_forward(int n, int B, const float *U, float *T, const int *selT,
 // the row pass alone (T from U), and the column pass alone (continuing from T)
 void launch_dct_rows_fwd(int n, int B, const float *U, float *T, const float2 *tw,
                          const float4 *tab, const ImgState *st, hipStream_t s);
-// stw, parts, nparts (one image, stw == st): workgroup 0 first applies the previous
-// iteration's stop rule, as launch_gemv_rows does
+// stw, parts, nparts (stw == st): the first workgroup of each image first applies
+// the previous iteration's stop rule to it, as launch_gemv_rows does for one image
 void launch_dct_cols_fwd(int n, int B, float *T, const int *selT, const float *F, int ldf,
                          float *R, int ldr, bool adjoint, const float2 *tw, const float4 *tab,
                          const ImgState *st, hipStream_t s, ImgState *stw = nullptr,
