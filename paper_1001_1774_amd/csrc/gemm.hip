@@ -38,6 +38,7 @@
 // ordered so that each XCD works on one K slice and its Y slice stays in that
 // XCD's L2.  No order of summation depends on the batch, the image group or the
 // tile shape, so an image's products are the same bits in any batch.
+#include "device_stop.h"
 #include "tvcs_internal.h"
 
 #include <algorithm>
@@ -456,9 +457,16 @@ __global__ void k_frag(const float *__restrict__ A, int m, int N, int mp,
 // Block (image tile t, k tile u) of part p sits at (p ? lo : hi) + t * yimg + u * ytile;
 // lane l of a block holds image 16 t + l % 16, columns 32 u + 8 (l / 16) .. +7.
 // One thread per lane-chunk of 8 elements, blocks visited in storage order.
+// stw (the forward product's split of U): workgroup b also applies the previous
+// iteration's stop rule to images b, b + gridDim.x, ... < B first (the products
+// read the flags after this pass).
 __global__ void k_split_frag(const float *__restrict__ V, int kv, int K, int Bp,
                              const float *__restrict__ scale, u16 *__restrict__ hi,
-                             u16 *__restrict__ lo, long long yimg, long long ytile) {
+                             u16 *__restrict__ lo, long long yimg, long long ytile,
+                             ImgState *stw, const double *parts, int nparts, int B) {
+    if (stw && threadIdx.x < 64)
+        for (int b = blockIdx.x; b < B; b += gridDim.x)
+            if (stw[b].active) stop_rule(stw + b, parts + (size_t)b * nparts * 2, nparts, nullptr);
     const size_t chunks = (size_t)Bp * K / 8, ktiles = (size_t)K / 32, itiles = (size_t)Bp / 16;
     for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < chunks;
          c += (size_t)gridDim.x * blockDim.x) {
@@ -819,14 +827,18 @@ void lowp_autotune(const LowpA &L, LowpWork &W, int Bp, const float *U, float *R
 }
 
 void lowp_apply_A(const LowpA &L, LowpWork &W, int B, const float *U, const float *F, float *R,
-                  const ImgState *st, hipStream_t s) {
+                  const ImgState *st, hipStream_t s, ImgState *stw, const double *parts,
+                  int nparts) {
     const int mode = mode_of(L.storage);
     const int Bp = ((B + kBTile - 1) / kBTile) * kBTile;
     if (Bp > W.Bp) fail(TVCS_EINVAL, "MFMA workspace too small for the batch");
     long long yimg, ytile;
     y_strides(L.N, Bp, yimg, ytile);
+    if (stw && (st != stw || !parts || nparts < 1))
+        fail(TVCS_EINVAL, "MFMA product: the folded stop rule needs the image states and partials");
     hipLaunchKernelGGL(k_split_frag, dim3(grid1d((size_t)Bp * L.N / 8)), dim3(256), 0, s, U, L.N,
-                       L.N, Bp, nullptr, (u16 *)W.Ubf_hi, (u16 *)W.Ubf_lo, yimg, ytile);
+                       L.N, Bp, nullptr, (u16 *)W.Ubf_hi, (u16 *)W.Ubf_lo, yimg, ytile, stw, parts,
+                       nparts, B);
     int KS, kspan;
     fwd_split(L, KS, kspan);
     const long long split_stride = (long long)Bp * L.mp;
@@ -849,7 +861,8 @@ void lowp_apply_At(const LowpA &L, LowpWork &W, int B, const float *R, float *G,
     long long yimg, ytile;
     y_strides(L.mp, Bp, yimg, ytile);
     hipLaunchKernelGGL(k_split_frag, dim3(grid1d((size_t)Bp * L.mp / 8)), dim3(256), 0, s, R, L.m,
-                       L.mp, Bp, L.scale, (u16 *)W.Rbf_hi, (u16 *)W.Rbf_lo, yimg, ytile);
+                       L.mp, Bp, L.scale, (u16 *)W.Rbf_hi, (u16 *)W.Rbf_lo, yimg, ytile, nullptr,
+                       nullptr, 0, 0);
     int KS, kspan;
     adj_split(L, KS, kspan);
     const long long split_stride = (long long)Bp * L.N;

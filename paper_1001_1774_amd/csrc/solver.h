@@ -42,7 +42,7 @@ struct DevBuf {
 
 constexpr int kGraphIters = 10;   // iterations per captured graph (even: q ping-pong)
 #ifndef TVCS_FOLD_STOP
-#define TVCS_FOLD_STOP 1          // stop rule folded into the next A u pass (one image FP32; partial DCT)
+#define TVCS_FOLD_STOP 1          // stop rule folded into the next A u pass (one image FP32; DCT, MFMA)
 #endif
 constexpr int kPowerIters = 100;
 constexpr double kPowerRtol = 1e-10;
@@ -307,12 +307,13 @@ struct tvcs_ctx {
         return a;
     }
 
-    // One image with FP32 A, or any batch with the partial DCT: the stop rule of an
-    // iteration is applied by the first workgroup (of each image) of the next
-    // iteration's A u pass (fold_prev), and only the last iteration of a captured
-    // graph ends with its own stop-rule pass (stop_here).
+    // One image with FP32 A, or any batch with the partial DCT or MFMA storage: the
+    // stop rule of an iteration is applied by the next iteration's first pass (its
+    // first workgroup per image; for MFMA storage the split of U) (fold_prev), and
+    // only the last iteration of a captured graph ends with its own stop-rule pass
+    // (stop_here).
     bool fold_stop(int B) const {
-        return TVCS_FOLD_STOP && !lowprec() && (dct() || (B == 1 && pass_nv(padded(B)) == 1));
+        return TVCS_FOLD_STOP && (dct() || lowprec() || (B == 1 && pass_nv(padded(B)) == 1));
     }
 
     void enqueue_iteration(int B, int parity, bool iadm, double beta, double c, double ctau,
@@ -330,6 +331,10 @@ struct tvcs_ctx {
                                 fold_prev ? parts.as<double>() : nullptr,
                                 fold_prev ? stop_parts(n, B) : 0);
             // the inverse row transform (g = A^T r) is computed by the shrink pass
+        } else if (fold_prev && lowprec()) {
+            lowp_apply_A(lowp, lw, B, U.as<float>(), F.as<float>(), R.as<float>(), st, work, st,
+                         parts.as<double>(), stop_parts(n, B));
+            apply_At(Bp, B, R.as<float>(), st);
         } else if (fold_prev) {
             launch_gemv_rows(A32.as<float>(), m, N, U.as<float>(), N, F.as<float>(), m,
                              R.as<float>(), m, 1, st, 1, work, st, parts.as<double>(),

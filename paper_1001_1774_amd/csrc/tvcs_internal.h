@@ -170,8 +170,11 @@ struct LowpWork {
 };
 size_t lowp_work_bytes(const LowpA &L, int B);
 void lowp_work_bind(LowpWork &W, const LowpA &L, int B, void *base);
+// stw, parts, nparts (stw == st): the pass that splits U also applies the previous
+// iteration's stop rule to every image first, as launch_gemv_rows does for one image
 void lowp_apply_A(const LowpA &L, LowpWork &W, int B, const float *U, const float *F, float *R,
-                  const ImgState *st, hipStream_t s);
+                  const ImgState *st, hipStream_t s, ImgState *stw = nullptr,
+                  const double *parts = nullptr, int nparts = 0);
 // K slices of the adjoint product: G holds that many partial sums, [slice][Bp][N]
 int lowp_adj_splits(const LowpA &L);
 // G[(k*Bp + b)*N + j] = slice k of (A^T r_b)_j
