@@ -81,16 +81,28 @@ int solve_impl(tvcs_ctx *h, const float *Fin, int B, double mu, double beta, dou
 
     h->build_graph(B, flags & TVCS_IADM, beta, c, ctau);
     const int launches = (maxit + kGraphIters - 1) / kGraphIters;
-    for (int i = 0; i < launches; ++i) {
-        TVCS_HIP(hipGraphLaunch(h->exec, h->work));
-        if (tol > 0 && i + 1 < launches) {
-            TVCS_HIP(hipMemcpyAsync(h->host_state, st, sizeof(ImgState) * B,
-                                    hipMemcpyDeviceToHost, h->work));
-            TVCS_HIP(hipStreamSynchronize(h->work));
+    if (tol > 0) {
+        // The state after launch i is copied into one half of the pinned mirror and
+        // read while launch i + 1 runs, so the device never waits for the host; a
+        // launch queued after every image has stopped finds them all inactive and
+        // each of its kernels returns at once.
+        for (hipEvent_t &e : h->ev_poll)
+            if (!e) TVCS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        for (int i = 0; i < launches; ++i) {
+            TVCS_HIP(hipGraphLaunch(h->exec, h->work));
+            if (i + 1 == launches) break;
+            TVCS_HIP(hipMemcpyAsync(h->host_state + (size_t)(i & 1) * B, st,
+                                    sizeof(ImgState) * B, hipMemcpyDeviceToHost, h->work));
+            TVCS_HIP(hipEventRecord(h->ev_poll[i & 1], h->work));
+            if (i == 0) continue;
+            TVCS_HIP(hipEventSynchronize(h->ev_poll[(i - 1) & 1]));
+            const ImgState *prev = h->host_state + (size_t)((i - 1) & 1) * B;
             bool any = false;
-            for (int b = 0; b < B; ++b) any |= h->host_state[b].active != 0;
+            for (int b = 0; b < B; ++b) any |= prev[b].active != 0;
             if (!any) break;
         }
+    } else {
+        for (int i = 0; i < launches; ++i) TVCS_HIP(hipGraphLaunch(h->exec, h->work));
     }
 
     if (iadm && lam) {

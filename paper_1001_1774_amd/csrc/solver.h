@@ -73,8 +73,9 @@ struct tvcs_ctx {
     DevBuf U, F, R, P, RHS, Q0, Q1, S, parts, state, obj, lowp_work, lamb, counters;
     DevBuf DT;             // partial DCT: the half-transformed images between passes
     LowpWork lw{};
-    ImgState *host_state = nullptr;   // pinned mirror for polling
+    ImgState *host_state = nullptr;   // pinned mirror for polling: two halves of cap images
     int host_state_cap = 0;
+    hipEvent_t ev_poll[2] = {nullptr, nullptr};   // copies into the two halves
 
     // graph cache
     hipGraphExec_t exec = nullptr;
@@ -85,6 +86,8 @@ struct tvcs_ctx {
     ~tvcs_ctx() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (host_state) (void)hipHostFree(host_state);
+        for (hipEvent_t e : ev_poll)
+            if (e) (void)hipEventDestroy(e);
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (ev_t0) (void)hipEventDestroy(ev_t0);
         if (ev_t1) (void)hipEventDestroy(ev_t1);
@@ -138,7 +141,7 @@ struct tvcs_ctx {
         if (host_state_cap < B) {
             if (host_state) TVCS_HIP(hipHostFree(host_state));
             host_state = nullptr;
-            TVCS_HIP(hipHostMalloc((void **)&host_state, sizeof(ImgState) * B));
+            TVCS_HIP(hipHostMalloc((void **)&host_state, sizeof(ImgState) * 2 * B));
             host_state_cap = B;
         }
         cap = B;
