@@ -247,7 +247,13 @@ def _as_batch(f):
 
 
 def initial_u(A, f, n, u0):
-    """u^0: A^T f by default (Alg. 1 and 2 print "u^0 = f", which has the wrong length)."""
+    """u^0: A^T f by default (Alg. 1 and 2 print "u^0 = f", which has the wrong length),
+    else a copy of the given u0 broadcast over the batch.
+
+    Pinned by tests/test_oracle_start_storage.py: for A = I the default is the printed
+    start f itself, and it is minus the gradient of 1/2 ||A u - f||^2 at u = 0 taken by
+    finite differences of that objective.
+    """
     B = f.shape[0]
     if u0 is None:                                  # reading: u^0 = A^T f
         return apply_At(A, f).reshape(B, n, n)
@@ -426,6 +432,8 @@ def dequantized_A(A: np.ndarray, storage: str) -> np.ndarray:
     """The FP64 matrix that a storage format represents, after rounding A to FP32.
 
     storage: "fp32", "bf16", "bf16_split" (hi + lo) or "fp8_rowscale" (s_i * q_ij).
+    Pinned by tests/test_oracle_start_storage.py (bf16 against torch's cast, the
+    split's error bounds) and tests/test_oracle_ops.py (FP8 with row scales).
     """
     A32 = np.asarray(A, dtype=np.float32)
     if storage == "fp32":
