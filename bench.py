@@ -79,7 +79,24 @@ def main():
                     help="add the n = 512, m = 26214, B = 128 section (FP8 vs BF16 storage)")
     ap.add_argument("--large-iters", type=int, default=300)
     ap.add_argument("--no-dct", action="store_true", help="skip the partial-DCT section")
+    # profiler modes: run one piece of the path and print one JSON line (no benchmark)
+    ap.add_argument("--products", choices=sorted(PRODUCT_WORKLOADS), default=None,
+                    help="only launch the two products of this workload `--reps` times each "
+                         "(for rocprofv3), after a 256 MiB device copy that calibrates byte "
+                         "counters")
+    ap.add_argument("--storage", default="fp32",
+                    choices=["fp32", "bf16", "bf16_split", "fp8_rowscale"])
+    ap.add_argument("--batch", type=int, default=1)
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--form", choices=["fresh", "increment"], default="fresh",
+                    help="form of the low-precision products for --products")
+    ap.add_argument("--dct-solve", type=int, default=0, metavar="N",
+                    help="only solve a batch of `--batch` N x N partial-DCT problems for "
+                         "`--iters` iterations (for rocprofv3)")
     args = ap.parse_args()
+    if args.products or args.dct_solve:
+        profile_mode(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py measures one GPU: the method's images are "
                           "independent given A, so more GPUs only replicate A and split the "
@@ -206,6 +223,50 @@ def main():
     if not args.no_dct:
         out["partial_dct"] = bench_dct(args, np, torch, O, synth, tvcs)
     print(json.dumps(out), flush=True)
+
+
+PRODUCT_WORKLOADS = {"n128_m4096", "n256_m13107_b64", "n512_m26214_b128"}
+COPY_BYTES = 256 << 20     # the plain copy that calibrates FETCH_SIZE / WRITE_SIZE
+
+
+def profile_mode(args):
+    """Launch one piece of the path for a profiler and print what it timed.
+
+    --products W: the forward product (r = A u - f) and the adjoint product (A^T r)
+    of workload W's A in `--storage`, for a batch of `--batch`, `--reps` launches
+    each through tvcs_time_products (`--form increment`: the one-part increment form
+    of the low-precision products).  First copies a 256 MiB device buffer once: a
+    plain copy of known size (reads and writes 268435456 bytes) against which the
+    FETCH_SIZE / WRITE_SIZE counters are scaled.
+    --dct-solve N: a batch of seeded N x N partial-DCT problems (30 % of the
+    coefficients, IADM, mu = 500, beta = 2^6, tau = 1.9) solved for `--iters`
+    iterations, once to warm up and once timed."""
+    import torch
+
+    from paper_1001_1774_amd import synth, tvcs
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    if args.dct_solve:
+        q = synth.make_dct_problem(f"dct{args.dct_solve}", args.dct_solve, 0.3, batch=args.batch)
+        F = torch.from_numpy(q.f.astype(np.float32)).cuda()
+        with tvcs.Solver.partial_dct(q.rows, q.n) as s:
+            s.solve_batch(F, mu=q.mu, beta=q.beta, maxit=args.iters, iadm=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.solve_batch(F, mu=q.mu, beta=q.beta, maxit=args.iters, iadm=True)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        print(json.dumps({"dct": args.dct_solve, "m": q.m, "batch": args.batch,
+                          "iters": args.iters, "ms_per_iter": 1e3 * dt / args.iters}), flush=True)
+        return
+    p = synth.workload(args.products, batch=1, dtype=np.float32)
+    with tvcs.Solver(p.A, p.n, storage=args.storage) as s:
+        fwd, adj = s.time_products(args.batch, args.reps, increment=args.form == "increment")
+    print(json.dumps({"workload": args.products, "storage": args.storage, "batch": args.batch,
+                      "form": args.form, "reps": args.reps, "forward_ms": fwd,
+                      "adjoint_ms": adj, "copy_bytes": COPY_BYTES}), flush=True)
 
 
 MFMA_BF16_PEAK = 2.5e15   # MI355X dense bf16 MFMA, FLOP/s

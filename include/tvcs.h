@@ -62,7 +62,14 @@ extern "C" {
 /* ---- storage of A on the device ------------------------------------------ */
 /* A is first rounded to FP32 (nearest-even), then to the storage format.    */
 #define TVCS_A_FP32          0  /* FP32, 4 bytes/entry; FP32 GEMV kernels           */
-#define TVCS_A_BF16          1  /* bf16(A), 2 bytes/entry; MFMA with FP32 accumulate */
+#define TVCS_A_BF16          1  /* bf16(A), 2 bytes/entry; MFMA with FP32 accumulate.
+                                   For this and the next two formats an image's
+                                   products are computed afresh (batch operand v split
+                                   into bf16 hi + lo) while its relative change
+                                   exceeds 2^-8 and every 64th iteration, and
+                                   otherwise as increments: r += A bf16(u - u~) and
+                                   g += A^T bf16(v - v~) for v the residual, u~ and v~
+                                   being the vectors the current r and g belong to */
 #define TVCS_A_BF16_SPLIT    2  /* hi = bf16(A), lo = bf16(A - hi); hi*x_hi +
                                    hi*x_lo + lo*x_hi on MFMA, 4 bytes/entry          */
 #define TVCS_A_FP8_ROWSCALE  3  /* s_i = max_j |A_ij| / 448 (FP32), q_ij = OCP E4M3
@@ -82,6 +89,10 @@ typedef struct {
                            with the stored A (only with TVCS_OBJECTIVE, else 0)  */
     double tau;         /* step parameter tau used                               */
     float  ms;          /* device time of the whole solve call, milliseconds     */
+    int    fresh_iters; /* bf16, split bf16 and FP8 storage: iterations whose two
+                           products were computed afresh from a two-part batch
+                           operand; the others added the one-part increment form
+                           (see TVCS_A_BF16); 0 for FP32 and the partial DCT     */
 } tvcs_stats;
 
 /*
@@ -205,8 +216,14 @@ int tvcs_solve_continuation(tvcs_handle h, const float *F, int B, double mu,
  * launches of each timed with HIP events on the stream the solver launches them
  * on, with the launch configuration a solve of B images uses.  Inputs are the
  * handle's workspace contents (any values).  Either output may be NULL.
+ *   form  0: the fresh products every storage format computes (for bf16, split
+ *         bf16 and FP8 storage: from a two-part bf16 batch operand);
+ *         1: the increment form of those three formats' products (one-part batch
+ *         operand; the form most iterations take once the iterates change by
+ *         less than 2^-8 per iteration); the same as 0 for FP32 and the DCT.
  */
-int tvcs_time_products(tvcs_handle h, int B, int reps, float *ms_forward, float *ms_adjoint);
+int tvcs_time_products(tvcs_handle h, int B, int reps, int form, float *ms_forward,
+                       float *ms_adjoint);
 
 /*
  * tvcs_measure_peaks: measurement helper, independent of any handle.  Achievable

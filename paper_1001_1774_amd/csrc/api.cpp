@@ -142,6 +142,7 @@ int solve_impl(tvcs_ctx *h, const float *Fin, int B, double mu, double beta, dou
             stats[b].iters = s.iters;
             stats[b].status = s.status;
             stats[b].rel_change = s.rel;
+            stats[b].fresh_iters = h->lowprec() ? s.fresh : 0;
             stats[b].objective = objv[b];
             stats[b].tau = tau;
             stats[b].ms = ms;
@@ -372,26 +373,35 @@ int tvcs_solve_continuation(tvcs_handle h, const float *F, int B, double mu,
     });
 }
 
-int tvcs_time_products(tvcs_handle h, int B, int reps, float *ms_forward, float *ms_adjoint) {
+int tvcs_time_products(tvcs_handle h, int B, int reps, int form, float *ms_forward,
+                       float *ms_adjoint) {
     return guarded([&] {
         if (!h) fail(TVCS_EINVAL, "null handle");
         if (B < 1 || reps < 1) fail(TVCS_EINVAL, "B and reps must be >= 1");
+        if (form != 0 && form != 1) fail(TVCS_EINVAL, "form must be 0 (fresh) or 1 (increment)");
         h->begin_call();
         h->ensure_workspace(B);
         const int Bp = h->padded(B);
         float *U = h->U.as<float>(), *F = h->F.as<float>(), *R = h->R.as<float>();
+        ImgState *st = h->state.as<ImgState>();
+        // one fresh pair of products sets the vectors the increments are taken from,
+        // then every image takes the requested form (mode slot 0, parity 0)
+        launch_init_state(st, B, 0.0, 1, h->work, 1);
+        h->apply_A(Bp, B, U, F, R, st, 0);
+        h->apply_At(Bp, B, R, st, 0);
+        launch_init_state(st, B, 0.0, 1, h->work, form ? 0 : 1);
         // warm-up launch of each, then the timed runs
-        h->apply_A(Bp, B, U, F, R, nullptr);
-        h->apply_At(Bp, B, R, nullptr);
+        h->apply_A(Bp, B, U, F, R, st, 0);
+        h->apply_At(Bp, B, R, st, 0);
         TVCS_HIP(hipEventRecord(h->ev_t0, h->work));
-        for (int i = 0; i < reps; ++i) h->apply_A(Bp, B, U, F, R, nullptr);
+        for (int i = 0; i < reps; ++i) h->apply_A(Bp, B, U, F, R, st, 0);
         TVCS_HIP(hipEventRecord(h->ev_t1, h->work));
         TVCS_HIP(hipEventSynchronize(h->ev_t1));
         float ms = 0.f;
         TVCS_HIP(hipEventElapsedTime(&ms, h->ev_t0, h->ev_t1));
         if (ms_forward) *ms_forward = ms / reps;
         TVCS_HIP(hipEventRecord(h->ev_t0, h->work));
-        for (int i = 0; i < reps; ++i) h->apply_At(Bp, B, R, nullptr);
+        for (int i = 0; i < reps; ++i) h->apply_At(Bp, B, R, st, 0);
         TVCS_HIP(hipEventRecord(h->ev_t1, h->work));
         TVCS_HIP(hipEventSynchronize(h->ev_t1));
         TVCS_HIP(hipEventElapsedTime(&ms, h->ev_t0, h->ev_t1));

@@ -40,7 +40,10 @@ __device__ inline D2 q_of(D2 d, D2 o, double inv_beta) {
 
 // g_k at pixel p of image b: fixed-order sum of the A^T r partials, PL loads in
 // flight.  For nchunk <= PL every PL gives the same bits (the pairwise tree over
-// the first nchunk slots, the rest exact zeros).
+// the first nchunk slots, the rest exact zeros).  With a running g (MFMA storage,
+// a.Gacc): fresh iterations store the sum as the running g, increment iterations
+// add it to the running g (FP64 addition, FP32 store); the pass visits every pixel
+// once, so each thread updates its own pixel.
 template <int PL>
 __device__ inline double g_at(const ShrinkArgs &a, int b, int p) {
     const int N = a.n * a.n;
@@ -58,6 +61,11 @@ __device__ inline double g_at(const ShrinkArgs &a, int b, int p) {
     for (int w = PL / 2; w > 0; w >>= 1)
 #pragma unroll
         for (int j = 0; j < w; ++j) gs[j] += gs[j + w];
+    if (a.Gacc) {
+        float *acc = a.Gacc + (size_t)b * N + p;
+        if (!a.st[b].mode[a.parity]) gs[0] += (double)*acc;
+        *acc = (float)gs[0];
+    }
     return gs[0];
 }
 

@@ -12,7 +12,12 @@ namespace tvcs {
 // The stop rule of eq. (stop), ||u^{k+1} - u^k|| <= tol ||u^k|| (inclusive, FP64),
 // for one image from its row blocks' partial sums (added in block order by one
 // 64-lane wave, so the result does not depend on how the pass was launched).
-__device__ inline void stop_rule(ImgState *st, const double *parts, int nparts, int *counter) {
+// slot >= 0: also sets mode[slot] = 1 (fresh products two iterations later) when
+// the relative change exceeds kFreshTheta or that iteration is a multiple of
+// kFreshEvery.  Only the fields the rule changes are written: other passes of the
+// next iteration may read mode[] of this image while the rule runs.
+__device__ inline void stop_rule(ImgState *st, const double *parts, int nparts, int *counter,
+                                 int slot = -1) {
     const int lane = threadIdx.x & 63;
     double sd = 0.0, su = 0.0;
     for (int p = lane; p < nparts; p += 64) {
@@ -25,23 +30,32 @@ __device__ inline void stop_rule(ImgState *st, const double *parts, int nparts, 
         su += __shfl_xor(su, off, 64);
     }
     if (lane == 0) {
-        ImgState s = *st;
-        s.iters += 1;
-        s.du2 = sd;
-        s.u2 = su;
+        const int iters = st->iters + 1;
+        int status = st->status, active = st->active;
         const double du = sqrt(sd), nu = sqrt(su);
-        s.rel = nu > 0.0 ? du / nu : (du > 0.0 ? INFINITY : 0.0);
+        const double rel = nu > 0.0 ? du / nu : (du > 0.0 ? INFINITY : 0.0);
         if (!isfinite(sd) || !isfinite(su)) {
-            s.status = TVCS_ENONFINITE;
-            s.active = 0;
-        } else if (s.tol > 0.0 && du <= s.tol * nu) {
-            s.status = TVCS_OK;
-            s.active = 0;
-        } else if (s.iters >= s.maxit) {
-            s.status = s.tol > 0.0 ? TVCS_MAXIT : TVCS_OK;
-            s.active = 0;
+            status = TVCS_ENONFINITE;
+            active = 0;
+        } else if (st->tol > 0.0 && du <= st->tol * nu) {
+            status = TVCS_OK;
+            active = 0;
+        } else if (iters >= st->maxit) {
+            status = st->tol > 0.0 ? TVCS_MAXIT : TVCS_OK;
+            active = 0;
         }
-        *st = s;
+        st->iters = iters;
+        st->du2 = sd;
+        st->u2 = su;
+        st->rel = rel;
+        st->status = status;
+        st->active = active;
+        // iteration `iters - 1` just ended with the mode in mode[slot]; the slot now
+        // takes the mode of iteration iters + 1
+        if (slot >= 0) {
+            st->fresh += st->mode[slot];
+            st->mode[slot] = (rel > kFreshTheta || (iters + 1) % kFreshEvery == 0) ? 1 : 0;
+        }
         if (counter) *counter = 0;   // ready for the next pass
     }
 }

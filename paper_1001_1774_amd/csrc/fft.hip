@@ -330,7 +330,8 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
                                                        ImgState *__restrict__ st,
                                                        int *__restrict__ counters,
                                                        float *__restrict__ T,
-                                                       const float4 *__restrict__ dtab) {
+                                                       const float4 *__restrict__ dtab,
+                                                       int parity) {
     const int b = blockIdx.y;
     if (!st[b].active) return;
     extern __shared__ float2 lds[];
@@ -426,16 +427,17 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
     if (!s_last) return;
     // The last block of image b applies the stop rule
     __threadfence();
-    if (threadIdx.x < 64) stop_rule(st + b, myparts, gridDim.x, counters + b);
+    if (threadIdx.x < 64) stop_rule(st + b, myparts, gridDim.x, counters + b, parity);
 }
 
 // Stop rule after an inverse row pass, for images whose row passes ran without
 // the fused reduction (batches): one 64-lane block per image.
 __global__ __launch_bounds__(64) void k_stop_rule(ImgState *__restrict__ st,
-                                                  const double *__restrict__ parts, int nparts) {
+                                                  const double *__restrict__ parts, int nparts,
+                                                  int parity) {
     const int b = blockIdx.x;
     if (!st[b].active) return;
-    stop_rule(st + b, parts + (size_t)b * nparts * 2, nparts, nullptr);
+    stop_rule(st + b, parts + (size_t)b * nparts * 2, nparts, nullptr, parity);
 }
 
 // Rows (columns) per workgroup: enough workgroups for one image to spread over
@@ -504,13 +506,13 @@ int stop_parts(int n, int B) { return n / rows_per_block(n, B); }
 
 void launch_fft_rows_inv(int n, int B, const float2 *S, float *U, double *parts,
                          const float2 *tw, ImgState *st, int *counters, hipStream_t s, float *T,
-                         const float4 *dtab, bool stop_pass) {
+                         const float4 *dtab, bool stop_pass, int parity) {
     const int rpb = rows_per_block(n, B);
     const size_t lds = sizeof(float2) * (kMaxN + 2 * lp_size((rpb / 2) * n + rpb)) +
                        (T ? sizeof(float4) * n : 0);
 #define TVCS_ROWS_INV(FUSEDV, P2V)                                                            \
     hipLaunchKernelGGL((k_rows_inv<FUSEDV, P2V>), dim3(n / rpb, B), dim3(kThreads), lds, s, n, rpb, \
-                       S, U, parts, tw, st, counters, T, dtab)
+                       S, U, parts, tw, st, counters, T, dtab, parity)
     const bool p2 = is_pow2(n);
     if (TVCS_FUSED_STOP && B == 1 && stop_pass) {
         if (p2) TVCS_ROWS_INV(true, true);
@@ -518,7 +520,8 @@ void launch_fft_rows_inv(int n, int B, const float2 *S, float *U, double *parts,
     } else {
         if (p2) TVCS_ROWS_INV(false, true);
         else TVCS_ROWS_INV(false, false);
-        if (stop_pass) hipLaunchKernelGGL(k_stop_rule, dim3(B), dim3(64), 0, s, st, parts, n / rpb);
+        if (stop_pass)
+            hipLaunchKernelGGL(k_stop_rule, dim3(B), dim3(64), 0, s, st, parts, n / rpb, parity);
     }
 #undef TVCS_ROWS_INV
 }

@@ -16,12 +16,26 @@
 // streams each of its row tiles sequentially.
 //
 // GEMM: C[b][row] = sum_k X[row][k] Y[b][k] with X the streamed matrix (A or A^T)
-// and Y the small batch operand (U or R).  Y is always split, Y = Y_hi + Y_lo with
-// Y_hi = bf16(Y), Y_lo = bf16(Y - Y_hi): a bf16-only Y would add fresh relative
-// noise of ~2^-9 to every product in every iteration, which puts a floor under the
-// relative change of the iterates and keeps the stop rule (eq. (stop)) from ever
-// firing at tol = 1e-3.  With the split, the products carry only the fixed
-// rounding of A's storage format.  Y is written in the same fragment order as X
+// and Y the small batch operand.  A bf16-only copy of U (or R) would add fresh
+// relative noise of ~2^-9 to every product in every iteration, which puts a floor
+// under the relative change of the iterates and keeps the stop rule (eq. (stop))
+// from firing.  Each image's products therefore take one of two forms, chosen per
+// iteration by ImgState::mode:
+//   fresh      Y = Y_hi + Y_lo, Y_hi = bf16(v), Y_lo = bf16(v - Y_hi) of v = u (or
+//              s o r): r = A Y - f and g = A^T Y from scratch, carrying only the
+//              fixed rounding of A's storage plus at most 2^-16 of v;
+//   increment  Y = bf16(v - v~), one part, where v~ is the vector the current r (g)
+//              was computed from: r += A Y, v~ += Y (and g += A^T Y).  What the
+//              rounding drops stays in v - v~ and is applied by the next
+//              increment, so it does not accumulate; it is at most 2^-8 of the
+//              change since the last product, which vanishes as the iterates
+//              converge.
+// Fresh products run while an image's relative change exceeds 2^-8 and every 64th
+// iteration (FP32 sums of increments add rounding relative to the sizes of the
+// increments, which are large early on).  A group of images runs the Y_lo MFMAs
+// only if one of its active images is fresh; an image in increment mode then has
+// Y_lo = 0, whose MFMA adds exact zeros, so its bits do not depend on the group.
+// Y is written in the same fragment order as X
 // (16 images x 32 k per 1 KiB block).  A workgroup (4 waves) owns 4*RT*16
 // consecutive rows of X and all 16*NT images of its group; each wave streams its
 // RT 16-row tiles of X straight from HBM into registers (every X element is used
@@ -29,8 +43,8 @@
 // the Y blocks of each step in LDS (double-buffered, moved through registers).
 // The loop is software-pipelined: X of step t + 1 and Y of step t + 2 are in
 // flight while step t runs v_mfma_f32_16x16x32_bf16 with FP32 accumulation:
-// X Y_hi + X Y_lo, plus X_lo Y_hi for split storage (X_lo Y_lo, of relative size
-// 2^-18, is left out).  FP8 X is widened to bf16 in registers (exact); the row
+// X Y_hi, plus X_lo Y_hi for split storage (X_lo Y_lo, at most 2^-16 of the product,
+// is left out), plus X Y_lo for fresh products.  FP8 X is widened to bf16 in registers (exact); the row
 // scale folds into vectors: (A u)_i = s_i sum_j q_ij u_j and
 // (A^T r)_j = sum_i q_ij (s_i r_i).
 // The forward product splits its reduction (length N) into KS slices whose FP32
@@ -68,11 +82,23 @@
 #ifndef TVCS_X_GROUP
 #define TVCS_X_GROUP 16        // row tiles per group in the fragment order of A and A^T
 #endif
-#ifndef TVCS_GEMM_DEPTH
-#define TVCS_GEMM_DEPTH 1      // steps of X prefetched ahead (1 or 2)
+// X prefetch distance (steps in flight ahead of the one computed) of tiles with 2 row
+// tiles per wave and 1 k tile per step, per storage format (a step is 1 KiB of FP8
+// per wave, 4 VGPRs a register set; 2 KiB of bf16, 8 VGPRs; 4 KiB of split bf16).
+// Tiles with 4 row tiles per wave, or several k tiles per step, take distance 1:
+// their accumulators leave no room for more register sets at 2 waves per SIMD.
+#ifndef TVCS_GEMM_DEPTH_FP8
+#define TVCS_GEMM_DEPTH_FP8 3
 #endif
-#ifndef TVCS_GEMM_YPRELOAD
-#define TVCS_GEMM_YPRELOAD 0   // 1: read all Y fragments of a step from LDS before its MFMAs
+#ifndef TVCS_GEMM_DEPTH_BF16
+#define TVCS_GEMM_DEPTH_BF16 2
+#endif
+#ifndef TVCS_GEMM_DEPTH_SPLIT
+#define TVCS_GEMM_DEPTH_SPLIT 1
+#endif
+// ... and of FP8 tiles with 4 row tiles per wave (a register set is 8 VGPRs)
+#ifndef TVCS_GEMM_DEPTH_FP8_RT4
+#define TVCS_GEMM_DEPTH_FP8_RT4 3
 #endif
 #ifndef TVCS_GEMM_FORCE_RT
 #define TVCS_GEMM_FORCE_RT 0   // 2 or 4: skip the autotuner's choice of row tiles per wave
@@ -132,22 +158,29 @@ __device__ inline bool any_active(const ImgState *st, int nact) {
     return a != 0;
 }
 
-// 8 E4M3 codes -> 8 bf16 (every E4M3 value is exact in bf16)
+// the products of image b this iteration are fresh (parity < 0: outside the loop;
+// b >= B: padding images, whose operands are zero)
+__device__ inline bool fresh_of(const ImgState *st, int b, int B, int parity) {
+    return parity < 0 || st == nullptr || b >= B || st[b].mode[parity] != 0;
+}
+
+// some active image of the group takes fresh products (two-part batch operand)
+__device__ inline bool any_fresh(const ImgState *st, int nact, int parity) {
+    if (st == nullptr || parity < 0) return true;
+    int a = 0;
+    for (int i = 0; i < nact; ++i) a |= st[i].active & st[i].mode[parity];
+    return a != 0;
+}
+
+// 8 E4M3 codes -> 8 bf16 (every E4M3 value is exact in bf16): the packed conversion
+// with scale 1, two codes per instruction
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 __device__ inline bf16x8 fp8x8_to_bf16(u32x2 q) {
-    bf16x8 r;
-    const unsigned w[2] = {q.x, q.y};
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[h], false);   // bytes 0, 1
-        const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[h], true);    // bytes 2, 3
-        const float f[4] = {lo[0], lo[1], hi[0], hi[1]};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const u16 b = (u16)(__float_as_uint(f[j]) >> 16);   // exact: low 16 bits are 0
-            r[4 * h + j] = __builtin_bit_cast(__bf16, b);
-        }
-    }
-    return r;
+    const bf16x2 a = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8((int)q.x, 1.0f, false);
+    const bf16x2 b = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8((int)q.x, 1.0f, true);
+    const bf16x2 c = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8((int)q.y, 1.0f, false);
+    const bf16x2 d = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8((int)q.y, 1.0f, true);
+    return bf16x8{a[0], a[1], b[0], b[1], c[0], c[1], d[0], d[1]};
 }
 
 // X fragments of one reduction step held in registers (FP8 stays packed until use)
@@ -185,27 +218,19 @@ __device__ inline void load_x(XRegs<MODE, RT, KF> &x, const void *Xhi, const voi
 // Y (the batch operand) is stored in the same fragment order as X: image tile t
 // (16 images), k tile u (32) is the 512-element block (t * ktiles + u), so the Y
 // fragments of one step are whole 1 KiB blocks.  Per step the workgroup needs
-// 2 (hi, lo) x NT x KF blocks; wave w moves blocks w, w + 4, ... through registers
-// into LDS, where every fragment read is one contiguous 1 KiB (no bank conflicts).
-template <int MODE, int RT, int NT, int KF>
-__global__ __launch_bounds__(kThreads) void k_gemm(
-    const void *__restrict__ Xhi, const void *__restrict__ Xlo, long long xkt,
-    const u16 *__restrict__ Yhi, const u16 *__restrict__ Ylo, long long yimg, long long ytile,
-    int M, int kspan,
-    int RB, int KS, float *__restrict__ out, long long split_stride, long long ldo,
-    const ImgState *__restrict__ st, int nact) {
-    if (!any_active(st, nact)) return;
-    // XCD-aware order: consecutive tiles (same K slice, neighbouring rows) on one XCD
-    const int total = RB * KS;
-    const int nloc = (total + 7) / 8;
-    const int L = (blockIdx.x & 7) * nloc + (blockIdx.x >> 3);
-    if (L >= total) return;
-    const int ks = L / RB, rb = L % RB;
-
-    constexpr int NB = NT * KF;       // Y blocks per step and part
-    constexpr int YPW = 2 * NB / 4;   // Y blocks moved per wave and step
-    static_assert(2 * NB % 4 == 0, "the four waves share the Y blocks evenly");
-    __shared__ __attribute__((aligned(16))) u16 ys[2][2 * NB][512];
+// PARTS (hi, and lo for fresh products) x NT x KF blocks; wave w moves blocks w,
+// w + 4, ... through registers into LDS, where every fragment read is one
+// contiguous 1 KiB (no bank conflicts).
+template <int MODE, int RT, int NT, int KF, int PARTS>
+__device__ inline void gemm_body(const void *__restrict__ Xhi, const void *__restrict__ Xlo,
+                                 long long xkt, const u16 *__restrict__ Yhi,
+                                 const u16 *__restrict__ Ylo, long long yimg, long long ytile,
+                                 int M, int kspan, int ks, int rb, float *__restrict__ out,
+                                 long long split_stride, long long ldo,
+                                 u16 (*ys)[2 * NT * KF][512]) {
+    constexpr int NB = NT * KF;           // Y blocks per step and part
+    constexpr int YPW = PARTS * NB / 4;   // Y blocks moved per wave and step
+    static_assert(PARTS * NB % 4 == 0, "the four waves share the Y blocks evenly");
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int row_wave = rb * (4 * RT * 16) + wave * RT * 16;
@@ -235,29 +260,29 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
         ysrc[q] = (part ? Ylo : Yhi) + (long long)(r / KF) * yimg +
                   (long long)(kt_begin + r % KF) * ytile + lane * 8;
     }
-    u32x4 yr[YPW];
-    auto load_y = [&](int t) {
+    // two register sets for Y with one k tile per step: the set filled in stage t - 1
+    // is stored to LDS in stage t while stage t's own Y load is already in flight
+    // (steps of several k tiles, 256-image groups and split storage keep one set:
+    // the second would leave too few registers for two waves per SIMD)
+    constexpr int YS = (KF == 1 && NT <= 8 && MODE != M_SPLIT) ? 2 : 1;
+    u32x4 yr[YS][YPW];
+    auto load_y = [&](int set, int t) {
 #pragma unroll
         for (int q = 0; q < YPW; ++q)
-            yr[q] = *reinterpret_cast<const u32x4 *>(ysrc[q] + (long long)t * KF * ytile);
+            yr[set][q] = *reinterpret_cast<const u32x4 *>(ysrc[q] + (long long)t * KF * ytile);
     };
-    auto store_y = [&](int buf) {
+    auto store_y = [&](int set, int buf) {
 #pragma unroll
         for (int q = 0; q < YPW; ++q)
-            *reinterpret_cast<u32x4 *>(&ys[buf][wave + 4 * q][lane * 8]) = yr[q];
+            *reinterpret_cast<u32x4 *>(&ys[buf][wave + 4 * q][lane * 8]) = yr[set][q];
     };
+    // One step: per k tile, the Y fragments of YC image tiles at a time are read from
+    // LDS before their MFMAs (one LDS round trip waited for per chunk, not per image
+    // tile).  Every accumulator sees X Y_hi, then X_lo Y_hi (split storage), then
+    // X Y_lo (fresh products), in this order whatever the path.
+    constexpr int YC = MODE == M_SPLIT ? (NT < 4 ? NT : 4) : (NT < 8 ? NT : 8);
+    static_assert(NT % YC == 0, "whole chunks of image tiles");
     auto compute = [&](const XRegs<MODE, RT, KF> &x, int buf) {
-#if TVCS_GEMM_YPRELOAD
-        // all Y fragments of the step first, so LDS latency overlaps the MFMAs
-        bf16x8 yf[2][KF][NT];
-#pragma unroll
-        for (int s = 0; s < KF; ++s)
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                yf[0][s][nt] = *reinterpret_cast<const bf16x8 *>(&ys[buf][nt * KF + s][lane * 8]);
-                yf[1][s][nt] = *reinterpret_cast<const bf16x8 *>(&ys[buf][NB + nt * KF + s][lane * 8]);
-            }
-#endif
 #pragma unroll
         for (int s = 0; s < KF; ++s) {
             bf16x8 xc[RT];
@@ -268,104 +293,87 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
                 else
                     xc[rt] = x.h[rt][s];
             }
-            // the RT accumulators of an image tile are updated in turn, so RT - 1
-            // independent MFMAs separate two that share an accumulator
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-#if TVCS_GEMM_YPRELOAD
-                const bf16x8 yh = yf[0][s][nt], yl = yf[1][s][nt];
-#else
-                const bf16x8 yh = *reinterpret_cast<const bf16x8 *>(&ys[buf][nt * KF + s][lane * 8]);
-                const bf16x8 yl = *reinterpret_cast<const bf16x8 *>(&ys[buf][NB + nt * KF + s][lane * 8]);
-#endif
+            for (int p = 0; p < PARTS; ++p)
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt)
-                    acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[rt], yh, acc[rt][nt], 0, 0, 0);
+                for (int c0 = 0; c0 < NT; c0 += YC) {
+                    bf16x8 y[YC];
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt)
-                    acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[rt], yl, acc[rt][nt], 0, 0, 0);
-                if constexpr (MODE == M_SPLIT) {
+                    for (int c = 0; c < YC; ++c)
+                        y[c] = *reinterpret_cast<const bf16x8 *>(
+                            &ys[buf][p * NB + (c0 + c) * KF + s][lane * 8]);
+                    // the RT accumulators of an image tile are updated in turn, so RT - 1
+                    // independent MFMAs separate two that share an accumulator
 #pragma unroll
-                    for (int rt = 0; rt < RT; ++rt)
-                        acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x.l[rt][s], yh, acc[rt][nt], 0, 0, 0);
+                    for (int c = 0; c < YC; ++c)
+#pragma unroll
+                        for (int rt = 0; rt < RT; ++rt)
+                            acc[rt][c0 + c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                xc[rt], y[c], acc[rt][c0 + c], 0, 0, 0);
+                    if constexpr (MODE == M_SPLIT) {
+                        if (p == 0) {
+#pragma unroll
+                            for (int c = 0; c < YC; ++c)
+#pragma unroll
+                                for (int rt = 0; rt < RT; ++rt)
+                                    acc[rt][c0 + c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                        x.l[rt][s], y[c], acc[rt][c0 + c], 0, 0, 0);
+                        }
+                    }
                 }
-            }
         }
     };
 
-    // Software pipeline: the X fragments of step t + 1 and the Y blocks of step
-    // t + 2 are in flight while step t computes; Y is double-buffered in LDS.  The
-    // loop takes steps in pairs (X alternates between two register sets) and a
-    // last odd step follows it, so the accumulators never change registers.  Loads
-    // past the last step re-read the last step (in bounds, results unused), which
-    // keeps the body branch-free so that each wait covers only the data it needs;
-    // scheduling barriers keep the compiler from sinking the prefetches.
+    // Software pipeline: the X fragments of steps t + 1 .. t + D and the Y blocks of
+    // steps t + 1 and t + 2 are in flight while step t computes (Y is double-buffered
+    // in LDS: step t reads buffer t & 1).  Each stage issues its Y load before its X
+    // load: memory waits retire in issue order, so storing Y(t + 1), loaded a stage
+    // earlier, then waits for nothing issued after it, and the X loads keep their
+    // full distance.  X rotates through D + 1 register sets and Y through 2, and the
+    // loop is unrolled by D + 1 (even, or doubled) so that every set index is a
+    // constant (the accumulators never change registers).  Loads past the last step
+    // re-read the last step (in bounds, results unused), which keeps the body
+    // branch-free; scheduling barriers keep the compiler from reordering the loads.
+    constexpr int D = KF > 1 ? 1
+                    : RT > 2 ? (MODE == M_FP8 ? TVCS_GEMM_DEPTH_FP8_RT4 : 1)
+                    : MODE == M_FP8 ? TVCS_GEMM_DEPTH_FP8
+                    : MODE == M_SPLIT ? TVCS_GEMM_DEPTH_SPLIT : TVCS_GEMM_DEPTH_BF16;
+    static_assert(D >= 1 && D <= 4, "prefetch distance 1 .. 4");
+    constexpr int U = (D + 1) % 2 == 0 ? D + 1 : 2 * (D + 1);   // unroll: both rotations close
     const int last = steps - 1;
-    if constexpr (TVCS_GEMM_DEPTH == 1) {
-        XRegs<MODE, RT, KF> xa, xb;
-        load_y(0);
-        store_y(0);
-        load_x(xa, Xhi, Xlo, xoff, kt_begin);
-        load_y(min(1, last));
+    XRegs<MODE, RT, KF> x[D + 1];
+    // step t (= j mod the unroll) from X set j % (D + 1); step t + D is loaded into the
+    // set step t - 1 used; Y(t + 2) into Y set t & 1, whose Y(t) went to LDS in stage t - 1
+    auto stage = [&](int j, int t) {
+        if constexpr (YS == 2) {
+            load_y(j & 1, min(t + 2, last));
+            load_x(x[(j + D) % (D + 1)], Xhi, Xlo, xoff, kt_begin + min(t + D, last) * KF);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(x[j % (D + 1)], t & 1);
+            store_y((j + 1) & 1, (t + 1) & 1);   // Y(t + 1), loaded in stage t - 1
+        } else {
+            load_x(x[(j + D) % (D + 1)], Xhi, Xlo, xoff, kt_begin + min(t + D, last) * KF);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(x[j % (D + 1)], t & 1);
+            store_y(0, (t + 1) & 1);
+            load_y(0, min(t + 2, last));
+        }
         __syncthreads();
-        int t = 0;
-        for (; t + 1 < steps; t += 2) {
-            load_x(xb, Xhi, Xlo, xoff, kt_begin + (t + 1) * KF);
-            __builtin_amdgcn_sched_barrier(0);
-            compute(xa, 0);
-            store_y(1);
-            load_y(min(t + 2, last));
-            __syncthreads();
-            load_x(xa, Xhi, Xlo, xoff, kt_begin + min(t + 2, last) * KF);
-            __builtin_amdgcn_sched_barrier(0);
-            compute(xb, 1);
-            store_y(0);
-            load_y(min(t + 3, last));
-            __syncthreads();
-        }
-        if (t < steps) compute(xa, 0);
-    } else {
-        // prefetch distance 2: three X register sets, loop unrolled by three;
-        // invariant at the top of the loop: x0 = X(t), x1 = X(t + 1), LDS buffer
-        // t & 1 = Y(t), yr = Y(t + 1) (indices clamped to the last step)
-        XRegs<MODE, RT, KF> x0, x1, x2;
-        load_y(0);
-        store_y(0);
-        load_x(x0, Xhi, Xlo, xoff, kt_begin);
-        load_x(x1, Xhi, Xlo, xoff, kt_begin + min(1, last) * KF);
-        load_y(min(1, last));
-        __syncthreads();
-        int t = 0;
-        for (; t + 3 <= steps; t += 3) {
-            const int p = t & 1;
-            load_x(x2, Xhi, Xlo, xoff, kt_begin + min(t + 2, last) * KF);
-            __builtin_amdgcn_sched_barrier(0);
-            compute(x0, p);
-            store_y(p ^ 1);
-            load_y(min(t + 2, last));
-            __syncthreads();
-            load_x(x0, Xhi, Xlo, xoff, kt_begin + min(t + 3, last) * KF);
-            __builtin_amdgcn_sched_barrier(0);
-            compute(x1, p ^ 1);
-            store_y(p);
-            load_y(min(t + 3, last));
-            __syncthreads();
-            load_x(x1, Xhi, Xlo, xoff, kt_begin + min(t + 4, last) * KF);
-            __builtin_amdgcn_sched_barrier(0);
-            compute(x2, p);
-            store_y(p ^ 1);
-            load_y(min(t + 4, last));
-            __syncthreads();
-        }
-        if (t < steps) {   // one or two steps left
-            compute(x0, t & 1);
-            if (t + 1 < steps) {
-                store_y((t & 1) ^ 1);
-                __syncthreads();
-                compute(x1, (t & 1) ^ 1);
-            }
-        }
+    };
+    load_y(0, 0);
+    store_y(0, 0);
+    load_y(YS - 1, min(1, last));
+#pragma unroll
+    for (int j = 0; j < D; ++j) load_x(x[j], Xhi, Xlo, xoff, kt_begin + min(j, last) * KF);
+    __syncthreads();
+    int t = 0;
+    for (; t + U <= steps; t += U) {
+#pragma unroll
+        for (int j = 0; j < U; ++j) stage(j, t + j);
     }
+#pragma unroll
+    for (int j = 0; j < U - 1; ++j)
+        if (t + j < steps) stage(j, t + j);
     // lane holds rows 4*(lane/16) .. +3 of its 16-row tile, image lane % 16 of its tile
     float *o = out + ks * split_stride;
     const int lr = lane & 15;
@@ -379,6 +387,32 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
             *reinterpret_cast<f32x4 *>(o + img * ldo + row) = acc[rt][nt];
         }
     }
+}
+
+// One launch: the group's images are nact states at st (null: all active, fresh);
+// parity selects each image's mode (< 0: fresh).  The whole workgroup takes the
+// two-part path if any active image of the group is fresh.
+template <int MODE, int RT, int NT, int KF>
+__global__ __launch_bounds__(kThreads) void k_gemm(
+    const void *__restrict__ Xhi, const void *__restrict__ Xlo, long long xkt,
+    const u16 *__restrict__ Yhi, const u16 *__restrict__ Ylo, long long yimg, long long ytile,
+    int M, int kspan,
+    int RB, int KS, float *__restrict__ out, long long split_stride, long long ldo,
+    const ImgState *__restrict__ st, int nact, int parity) {
+    if (!any_active(st, nact)) return;
+    // XCD-aware order: consecutive tiles (same K slice, neighbouring rows) on one XCD
+    const int total = RB * KS;
+    const int nloc = (total + 7) / 8;
+    const int L = (blockIdx.x & 7) * nloc + (blockIdx.x >> 3);
+    if (L >= total) return;
+    const int ks = L / RB, rb = L % RB;
+    __shared__ __attribute__((aligned(16))) u16 ys[2][2 * NT * KF][512];
+    if (any_fresh(st, nact, parity))
+        gemm_body<MODE, RT, NT, KF, 2>(Xhi, Xlo, xkt, Yhi, Ylo, yimg, ytile, M, kspan, ks, rb,
+                                       out, split_stride, ldo, ys);
+    else
+        gemm_body<MODE, RT, NT, KF, 1>(Xhi, Xlo, xkt, Yhi, Ylo, yimg, ytile, M, kspan, ks, rb,
+                                       out, split_stride, ldo, ys);
 }
 
 // ---- conversions ---------------------------------------------------------------
@@ -451,74 +485,134 @@ __global__ void k_frag(const float *__restrict__ A, int m, int N, int mp,
     }
 }
 
-// Batch operand Y of a product, in fragment order: V (Bp rows of length kv, FP32)
-// -> bf16 hi and lo = bf16(v - hi) over K >= kv columns (columns >= kv are zero),
-// each column optionally multiplied by scale[k] first (FP64 product, FP32 result).
-// Block (image tile t, k tile u) of part p sits at (p ? lo : hi) + t * yimg + u * ytile;
-// lane l of a block holds image 16 t + l % 16, columns 32 u + 8 (l / 16) .. +7.
-// One thread per lane-chunk of 8 elements, blocks visited in storage order.
-// stw (the forward product's split of U): workgroup b also applies the previous
-// iteration's stop rule to images b, b + gridDim.x, ... < B first (the products
-// read the flags after this pass).
-__global__ void k_split_frag(const float *__restrict__ V, int kv, int K, int Bp,
-                             const float *__restrict__ scale, u16 *__restrict__ hi,
-                             u16 *__restrict__ lo, long long yimg, long long ytile,
-                             ImgState *stw, const double *parts, int nparts, int B) {
+// Batch operand Y of a product, in fragment order, from V (Bp rows of length kv,
+// FP32; columns kv .. K-1 are zero), each column optionally multiplied by scale[k]
+// first (FP64 product, FP32 result: v = s o r for the FP8 adjoint).  Per image b:
+//   fresh (fresh_of): hi = bf16(v), lo = bf16(v - hi); Vt = hi + lo (exact in FP32)
+//   increment:        hi = bf16(v - Vt), lo = 0;        Vt += hi
+// where Vt (Bp x kv, may be null outside the loop) is the vector the product
+// results belong to.  Block (image tile t, k tile u) of part p sits at
+// (p ? lo : hi) + t * yimg + u * ytile; lane l of a block holds image 16 t + l % 16,
+// columns 32 u + 8 (l / 16) .. +7.
+// A workgroup takes one image tile and 128 columns (4 k tiles): thread i handles
+// image 16 t + i / 16, columns 8 (i % 16) .. +7, so 16 threads read 512 contiguous
+// bytes of one image (16-byte loads when rows are 16-byte aligned), and each block
+// the workgroup writes is written whole by it.
+// stw (the forward product's split of U): the workgroups also apply the previous
+// iteration's stop rule to images < B first, one image per workgroup in turn (the
+// products read the flags after this pass; the rule writes mode[parity ^ 1], which
+// this iteration does not read).
+__global__ __launch_bounds__(256) void k_split_frag(
+    const float *__restrict__ V, int kv, int K, int Bp, const float *__restrict__ scale,
+    u16 *__restrict__ hi, u16 *__restrict__ lo, long long yimg, long long ytile, ImgState *stw,
+    const double *parts, int nparts, int B, float *__restrict__ Vt, const ImgState *mst,
+    int parity) {
+    const int bid = blockIdx.y * gridDim.x + blockIdx.x, nblk = gridDim.x * gridDim.y;
     if (stw && threadIdx.x < 64)
-        for (int b = blockIdx.x; b < B; b += gridDim.x)
-            if (stw[b].active) stop_rule(stw + b, parts + (size_t)b * nparts * 2, nparts, nullptr);
-    const size_t chunks = (size_t)Bp * K / 8, ktiles = (size_t)K / 32, itiles = (size_t)Bp / 16;
-    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < chunks;
-         c += (size_t)gridDim.x * blockDim.x) {
-        const size_t f = c >> 6;
-        const int l = (int)(c & 63);
-        const size_t it = kYKMajor ? f % itiles : f / ktiles, u = kYKMajor ? f / itiles : f % ktiles;
-        const size_t b = it * 16 + (l & 15);
-        const int k0 = (int)u * 32 + 8 * (l >> 4);
-        u16 h[8], w[8];
+        for (int b = bid; b < B; b += nblk)
+            if (stw[b].active)
+                stop_rule(stw + b, parts + (size_t)b * nparts * 2, nparts, nullptr,
+                          parity >= 0 ? parity ^ 1 : -1);
+    const int it = blockIdx.y, i = threadIdx.x;
+    const int b = it * 16 + (i >> 4);
+    const int k0 = blockIdx.x * 128 + 8 * (i & 15);
+    const bool fresh = fresh_of(mst, b, B, parity);
+    const size_t row = (size_t)b * kv;
+    float x[8], base[8];
+    if ((kv & 3) == 0 && k0 + 8 <= kv) {   // whole aligned chunk: 16-byte loads
+        const float4 a0 = *reinterpret_cast<const float4 *>(V + row + k0);
+        const float4 a1 = *reinterpret_cast<const float4 *>(V + row + k0 + 4);
+        x[0] = a0.x; x[1] = a0.y; x[2] = a0.z; x[3] = a0.w;
+        x[4] = a1.x; x[5] = a1.y; x[6] = a1.z; x[7] = a1.w;
+        if (scale) {
+            const float4 s0 = *reinterpret_cast<const float4 *>(scale + k0);
+            const float4 s1 = *reinterpret_cast<const float4 *>(scale + k0 + 4);
+            const float sc[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+#pragma unroll
+            for (int j = 0; j < 8; ++j) x[j] = (float)((double)x[j] * (double)sc[j]);
+        }
+        if (!fresh) {
+            const float4 t0 = *reinterpret_cast<const float4 *>(Vt + row + k0);
+            const float4 t1 = *reinterpret_cast<const float4 *>(Vt + row + k0 + 4);
+            base[0] = t0.x; base[1] = t0.y; base[2] = t0.z; base[3] = t0.w;
+            base[4] = t1.x; base[5] = t1.y; base[6] = t1.z; base[7] = t1.w;
+        }
+    } else {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int k = k0 + j;
-            float x = 0.f;
+            x[j] = 0.f;
+            base[j] = 0.f;
             if (k < kv) {
-                x = V[b * kv + k];
-                if (scale) x = (float)((double)x * (double)scale[k]);
+                x[j] = V[row + k];
+                if (scale) x[j] = (float)((double)x[j] * (double)scale[k]);
+                if (!fresh) base[j] = Vt[row + k];
             }
-            h[j] = bf16_rne(x);
-            w[j] = bf16_rne(x - bf16_f32(h[j]));   // exact in FP32
         }
-        const size_t o = it * yimg + u * ytile + l * 8;
-        *reinterpret_cast<uint4 *>(hi + o) = *reinterpret_cast<const uint4 *>(h);
-        *reinterpret_cast<uint4 *>(lo + o) = *reinterpret_cast<const uint4 *>(w);
     }
+    u16 h[8], w[8];
+    float nt[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        if (fresh) {
+            h[j] = bf16_rne(x[j]);
+            w[j] = bf16_rne(x[j] - bf16_f32(h[j]));          // exact in FP32
+            nt[j] = bf16_f32(h[j]) + bf16_f32(w[j]);         // exact
+        } else {
+            h[j] = bf16_rne(x[j] - base[j]);
+            w[j] = 0;
+            nt[j] = base[j] + bf16_f32(h[j]);
+        }
+    }
+    if (Vt) {
+        if ((kv & 3) == 0 && k0 + 8 <= kv) {
+            *reinterpret_cast<float4 *>(Vt + row + k0) = make_float4(nt[0], nt[1], nt[2], nt[3]);
+            *reinterpret_cast<float4 *>(Vt + row + k0 + 4) = make_float4(nt[4], nt[5], nt[6], nt[7]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (k0 + j < kv) Vt[row + k0 + j] = nt[j];
+        }
+    }
+    const int u = k0 >> 5, l = (i >> 4) + 16 * ((k0 >> 3) & 3);
+    const size_t o = (size_t)it * yimg + (size_t)u * ytile + (size_t)l * 8;
+    *reinterpret_cast<uint4 *>(hi + o) = *reinterpret_cast<const uint4 *>(h);
+    *reinterpret_cast<uint4 *>(lo + o) = *reinterpret_cast<const uint4 *>(w);
 }
 
-// R[b][i] = s_i * sum_ks P[ks][b][i] - F[b][i]  (FP64 sum, fixed order), i < m
+// R[b][i] = s_i * sum_ks P[ks][b][i] - F[b][i] for fresh products, or
+// R[b][i] + s_i * sum_ks P[ks][b][i] for increments (FP64 sum, fixed order), i < m
 __global__ void k_reduce_r(const float *__restrict__ P, int KS, long long split_stride, int mp,
                            const float *__restrict__ F, const float *__restrict__ scale, int m,
-                           float *__restrict__ R) {
+                           float *__restrict__ R, const ImgState *__restrict__ mst, int parity,
+                           int B) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
     if (i >= m) return;
     double acc = 0.0;
     for (int k = 0; k < KS; ++k) acc += (double)P[k * split_stride + (size_t)b * mp + i];
     if (scale) acc *= (double)scale[i];
-    if (F) acc -= (double)F[(size_t)b * m + i];
-    R[(size_t)b * m + i] = (float)acc;
+    float *r = R + (size_t)b * m + i;
+    if (fresh_of(mst, b, B, parity)) {
+        if (F) acc -= (double)F[(size_t)b * m + i];
+    } else {
+        acc += (double)*r;
+    }
+    *r = (float)acc;
 }
 
 template <int MODE, int RT>
 void gemm_dispatch(int NT, const void *Xhi, const void *Xlo, long long ldx, const u16 *Yhi,
                    const u16 *Ylo, long long yimg, long long ytile, int M, int kspan, int RB, int KS, float *out,
                    long long split_stride, long long ldo, const ImgState *st, int nact,
-                   hipStream_t s) {
+                   int parity, hipStream_t s) {
     const int total = RB * KS;
     const dim3 grid(((total + 7) / 8) * 8);
 #define TVCS_GEMM_CASE(NTV, KFV)                                                               \
     case NTV:                                                                                  \
         hipLaunchKernelGGL((k_gemm<MODE, RT, NTV, KFV>), grid, dim3(kThreads), 0, s, Xhi, Xlo,  \
                            ldx >> 5, Yhi, Ylo, yimg, ytile, M, kspan, RB, KS, out,            \
-                           split_stride, ldo, st, nact);                                       \
+                           split_stride, ldo, st, nact, parity);                               \
         break;
     switch (NT) {
         TVCS_GEMM_CASE(1, TVCS_GEMM_KF_NT1)
@@ -530,7 +624,7 @@ void gemm_dispatch(int NT, const void *Xhi, const void *Xlo, long long ldx, cons
             if constexpr (RT == 2) {
                 hipLaunchKernelGGL((k_gemm<MODE, 2, 16, TVCS_GEMM_KF_NT16>), grid, dim3(kThreads), 0,
                                    s, Xhi, Xlo, ldx >> 5, Yhi, Ylo, yimg, ytile, M, kspan, RB, KS,
-                                   out, split_stride, ldo, st, nact);
+                                   out, split_stride, ldo, st, nact, parity);
                 break;
             }
             fail(TVCS_EUNSUPPORTED, "MFMA product: 256-image groups take 2 row tiles per wave");
@@ -543,20 +637,20 @@ void gemm_dispatch(int NT, const void *Xhi, const void *Xlo, long long ldx, cons
 template <int RT>
 void gemm_mode(int mode, int NT, const void *Xhi, const void *Xlo, long long ldx, const u16 *Yhi,
                const u16 *Ylo, long long yimg, long long ytile, int M, int kspan, int RB, int KS, float *out,
-               long long split_stride, long long ldo, const ImgState *st, int nact,
+               long long split_stride, long long ldo, const ImgState *st, int nact, int parity,
                hipStream_t s) {
     switch (mode) {
         case M_BF16:
             gemm_dispatch<M_BF16, RT>(NT, Xhi, Xlo, ldx, Yhi, Ylo, yimg, ytile, M, kspan, RB, KS, out,
-                                      split_stride, ldo, st, nact, s);
+                                      split_stride, ldo, st, nact, parity, s);
             break;
         case M_SPLIT:
             gemm_dispatch<M_SPLIT, RT>(NT, Xhi, Xlo, ldx, Yhi, Ylo, yimg, ytile, M, kspan, RB, KS, out,
-                                       split_stride, ldo, st, nact, s);
+                                       split_stride, ldo, st, nact, parity, s);
             break;
         default:
             gemm_dispatch<M_FP8, RT>(NT, Xhi, Xlo, ldx, Yhi, Ylo, yimg, ytile, M, kspan, RB, KS, out,
-                                     split_stride, ldo, st, nact, s);
+                                     split_stride, ldo, st, nact, parity, s);
     }
 }
 
@@ -565,15 +659,15 @@ void gemm_any(int RT, int mode, int NT, const void *Xhi, const void *Xlo, long l
               const u16 *Yhi, const u16 *Ylo, long long yimg, long long ytile, int M, int kspan,
               int KS,
               float *out, long long split_stride, long long ldo, const ImgState *st, int nact,
-              hipStream_t s) {
+              int parity, hipStream_t s) {
     if (NT == 16) RT = 2;
     const int RB = (M + 4 * RT * 16 - 1) / (4 * RT * 16);
     if (RT == 4)
         gemm_mode<4>(mode, NT, Xhi, Xlo, ldx, Yhi, Ylo, yimg, ytile, M, kspan, RB, KS, out, split_stride,
-                     ldo, st, nact, s);
+                     ldo, st, nact, parity, s);
     else
         gemm_mode<2>(mode, NT, Xhi, Xlo, ldx, Yhi, Ylo, yimg, ytile, M, kspan, RB, KS, out, split_stride,
-                     ldo, st, nact, s);
+                     ldo, st, nact, parity, s);
 }
 
 size_t elem_bytes(int mode) { return mode == M_FP8 ? 1 : 2; }
@@ -758,7 +852,8 @@ void lowp_convert(LowpA &L, const float *A32, hipStream_t s) {
 
 size_t lowp_work_bytes(const LowpA &L, int Bp) {
     const size_t u = (size_t)Bp * L.N * sizeof(u16), r = (size_t)Bp * L.mp * sizeof(u16);
-    return 2 * u + 2 * r + (size_t)fwd_splits(L) * Bp * L.mp * sizeof(float) + 4 * 256;
+    return 2 * u + 2 * r + (size_t)fwd_splits(L) * Bp * L.mp * sizeof(float) +
+           (size_t)Bp * (L.N + L.m) * sizeof(float) + 6 * 256;
 }
 
 void lowp_work_bind(LowpWork &W, const LowpA &L, int Bp, void *base) {
@@ -781,6 +876,8 @@ void lowp_work_bind(LowpWork &W, const LowpA &L, int Bp, void *base) {
         W.Rbf_lo = take(r);
     }
     W.Rpart = static_cast<float *>(take((size_t)fwd_splits(L) * Bp * L.mp * sizeof(float)));
+    W.Ut = static_cast<float *>(take((size_t)Bp * L.N * sizeof(float)));
+    W.St = static_cast<float *>(take((size_t)Bp * L.m * sizeof(float)));
     W.Bp = Bp;
     W.fwd_rt = 4;
     W.adj_rt = 2;
@@ -828,7 +925,7 @@ void lowp_autotune(const LowpA &L, LowpWork &W, int Bp, const float *U, float *R
 
 void lowp_apply_A(const LowpA &L, LowpWork &W, int B, const float *U, const float *F, float *R,
                   const ImgState *st, hipStream_t s, ImgState *stw, const double *parts,
-                  int nparts) {
+                  int nparts, int parity) {
     const int mode = mode_of(L.storage);
     const int Bp = ((B + kBTile - 1) / kBTile) * kBTile;
     if (Bp > W.Bp) fail(TVCS_EINVAL, "MFMA workspace too small for the batch");
@@ -836,9 +933,12 @@ void lowp_apply_A(const LowpA &L, LowpWork &W, int B, const float *U, const floa
     y_strides(L.N, Bp, yimg, ytile);
     if (stw && (st != stw || !parts || nparts < 1))
         fail(TVCS_EINVAL, "MFMA product: the folded stop rule needs the image states and partials");
-    hipLaunchKernelGGL(k_split_frag, dim3(grid1d((size_t)Bp * L.N / 8)), dim3(256), 0, s, U, L.N,
-                       L.N, Bp, nullptr, (u16 *)W.Ubf_hi, (u16 *)W.Ubf_lo, yimg, ytile, stw, parts,
-                       nparts, B);
+    if (parity >= 0 && !st) fail(TVCS_EINVAL, "MFMA product: increments need the image states");
+    // outside the loop (parity < 0) every product is fresh and the tracked vectors
+    // of a running loop (the request loop's other slots) are left alone
+    hipLaunchKernelGGL(k_split_frag, dim3(L.N / 128, Bp / 16), dim3(256), 0, s, U, L.N, L.N, Bp,
+                       nullptr, (u16 *)W.Ubf_hi, (u16 *)W.Ubf_lo, yimg, ytile, stw, parts, nparts, B,
+                       parity >= 0 ? W.Ut : nullptr, st, parity);
     int KS, kspan;
     fwd_split(L, KS, kspan);
     const long long split_stride = (long long)Bp * L.mp;
@@ -847,22 +947,23 @@ void lowp_apply_A(const LowpA &L, LowpWork &W, int B, const float *U, const floa
                  (const u16 *)W.Ubf_hi + (img0 / 16) * yimg,
                  (const u16 *)W.Ubf_lo + (img0 / 16) * yimg, yimg, ytile, L.mp, kspan, KS,
                  W.Rpart + (size_t)img0 * L.mp, split_stride, L.mp, st ? st + img0 : nullptr,
-                 nact, s);
+                 nact, parity, s);
     });
     hipLaunchKernelGGL(k_reduce_r, dim3((L.m + 255) / 256, Bp), dim3(256), 0, s, W.Rpart, KS,
-                       split_stride, L.mp, F, L.scale, L.m, R);
+                       split_stride, L.mp, F, L.scale, L.m, R, st, parity, B);
 }
 
 void lowp_apply_At(const LowpA &L, LowpWork &W, int B, const float *R, float *G,
-                   const ImgState *st, hipStream_t s) {
+                   const ImgState *st, hipStream_t s, int parity) {
     const int mode = mode_of(L.storage);
     const int Bp = ((B + kBTile - 1) / kBTile) * kBTile;
     if (Bp > W.Bp) fail(TVCS_EINVAL, "MFMA workspace too small for the batch");
     long long yimg, ytile;
     y_strides(L.mp, Bp, yimg, ytile);
-    hipLaunchKernelGGL(k_split_frag, dim3(grid1d((size_t)Bp * L.mp / 8)), dim3(256), 0, s, R, L.m,
-                       L.mp, Bp, L.scale, (u16 *)W.Rbf_hi, (u16 *)W.Rbf_lo, yimg, ytile, nullptr,
-                       nullptr, 0, 0);
+    if (parity >= 0 && !st) fail(TVCS_EINVAL, "MFMA product: increments need the image states");
+    hipLaunchKernelGGL(k_split_frag, dim3(L.mp / 128, Bp / 16), dim3(256), 0, s, R, L.m, L.mp, Bp,
+                       L.scale, (u16 *)W.Rbf_hi, (u16 *)W.Rbf_lo, yimg, ytile, nullptr, nullptr, 0, B,
+                       parity >= 0 ? W.St : nullptr, st, parity);
     int KS, kspan;
     adj_split(L, KS, kspan);
     const long long split_stride = (long long)Bp * L.N;
@@ -870,7 +971,8 @@ void lowp_apply_At(const LowpA &L, LowpWork &W, int B, const float *R, float *G,
         gemm_any(W.adj_rt, mode, nt, L.XT_hi, L.XT_lo, L.mp,
                  (const u16 *)W.Rbf_hi + (img0 / 16) * yimg,
                  (const u16 *)W.Rbf_lo + (img0 / 16) * yimg, yimg, ytile, L.N, kspan, KS,
-                 G + (size_t)img0 * L.N, split_stride, L.N, st ? st + img0 : nullptr, nact, s);
+                 G + (size_t)img0 * L.N, split_stride, L.N, st ? st + img0 : nullptr, nact,
+                 parity, s);
     });
 }
 

@@ -92,7 +92,7 @@ struct tvcs_server {
         h->ensure_denominators(c);
         // every slot starts free and inactive
         for (int s = 0; s < slots; ++s) {
-            h->host_state[s] = ImgState{0, 0, TVCS_OK, 1, 0.0, 0.0, 0.0, 0.0};
+            h->host_state[s] = ImgState{0, 0, TVCS_OK, 1, 0.0, 0.0, 0.0, 0.0, {1, 1}, 0, 0};
         }
         TVCS_HIP(hipMemcpyAsync(h->state.p, h->host_state, sizeof(ImgState) * slots,
                                 hipMemcpyHostToDevice, h->work));
@@ -124,7 +124,7 @@ struct tvcs_server {
             SrvRequest &r = reqs[g.slot[s]];
             r.t_admit = t;
             h->load_measurements(r.f.data(), s, 1);
-            h->host_state[s] = ImgState{0, 1, TVCS_OK, r.maxit, 0.0, 0.0, 0.0, r.tol};
+            h->host_state[s] = ImgState{0, 1, TVCS_OK, r.maxit, 0.0, 0.0, 0.0, r.tol, {1, 1}, 0, 0};
             TVCS_HIP(hipMemcpyAsync(st + s, h->host_state + s, sizeof(ImgState),
                                     hipMemcpyHostToDevice, h->work));
         }
@@ -170,6 +170,7 @@ struct tvcs_server {
                 r.st.iters = is.iters;
                 r.st.status = is.status;
                 r.st.rel_change = is.rel;
+                r.st.fresh_iters = h->lowprec() ? is.fresh : 0;
                 r.st.objective = 0.0;
                 r.st.tau = h->tau();
                 r.st.ms = (float)(t - r.t_admit);

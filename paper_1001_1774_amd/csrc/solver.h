@@ -71,6 +71,7 @@ struct tvcs_ctx {
     int cap = 0, capP = 0;
     int gnv = 1;           // largest images-per-pass of the FP32 products
     DevBuf U, F, R, P, RHS, Q0, Q1, S, parts, state, obj, lowp_work, lamb, counters;
+    DevBuf Gacc;           // MFMA storage: the running g of the product increments (B x N)
     DevBuf DT;             // partial DCT: the half-transformed images between passes
     LowpWork lw{};
     ImgState *host_state = nullptr;   // pinned mirror for polling: two halves of cap images
@@ -116,6 +117,9 @@ struct tvcs_ctx {
             TVCS_HIP(hipGraphExecDestroy(exec));
             exec = nullptr;
         }
+        // until every buffer below is allocated the workspace counts as empty, so a
+        // grow that fails part-way (ENOMEM) makes the next call allocate again
+        cap = capP = 0;
         const int Bp = padded(B);
         const size_t Nn = (size_t)N, mm = (size_t)m, h = (size_t)(n / 2 + 1);
         gnv = (lowprec() || dct()) ? Bp : std::min(Bp, 8);
@@ -135,22 +139,24 @@ struct tvcs_ctx {
         if (dct()) DT.ensure(sizeof(float) * Bp * Nn);
         launch_fill(counters.as<float>(), (size_t)B, 0.f, work);   // all-zero bits
         if (lowprec()) {
+            Gacc.ensure(sizeof(float) * B * Nn);
             lowp_work.ensure(lowp_work_bytes(lowp, Bp));
             lowp_work_bind(lw, lowp, Bp, lowp_work.p);
         }
         if (host_state_cap < B) {
             if (host_state) TVCS_HIP(hipHostFree(host_state));
             host_state = nullptr;
+            host_state_cap = 0;
             TVCS_HIP(hipHostMalloc((void **)&host_state, sizeof(ImgState) * 2 * B));
             host_state_cap = B;
         }
-        cap = B;
-        capP = Bp;
         // padded images must hold zeros (their products are computed and ignored)
         launch_fill(U.as<float>(), (size_t)Bp * Nn, 0.f, work);
         launch_fill(F.as<float>(), (size_t)Bp * mm, 0.f, work);
         // the adjoint writes all its K slices: P is sized for them
         if (lowprec()) lowp_autotune(lowp, lw, Bp, U.as<float>(), R.as<float>(), P.as<float>(), work);
+        cap = B;
+        capP = Bp;
     }
 
     // vectors per pass and row chunks of the FP32 products for a padded batch Bp.
@@ -172,7 +178,7 @@ struct tvcs_ctx {
                    2 * sizeof(float2) * B * Nn + sizeof(float2) * B * h * n +
                    sizeof(double) * 2 * B * (size_t)n + sizeof(ImgState) * B + sizeof(double) * B +
                    sizeof(int) * B;
-        if (lowprec()) b += lowp_work_bytes(lowp, Bp);
+        if (lowprec()) b += lowp_work_bytes(lowp, Bp) + sizeof(float) * B * Nn;
         if (dct()) b += sizeof(float) * Bp * Nn;
         return b;
     }
@@ -201,7 +207,7 @@ struct tvcs_ctx {
             exec = nullptr;
         }
         for (DevBuf *b : {&U, &F, &R, &P, &RHS, &Q0, &Q1, &S, &parts, &state, &obj, &lowp_work, &lamb,
-                          &counters, &DT})
+                          &counters, &DT, &Gacc})
             b->release();
         cap = capP = 0;
     }
@@ -215,16 +221,17 @@ struct tvcs_ctx {
         }
     }
 
-    // R = A U - F for the first Bp images (F may be null)
+    // R = A U - F for the first Bp images (F may be null).  parity >= 0: inside the
+    // iteration loop (MFMA storage: per-image fresh or increment products)
     void apply_A(int Bp, int B, const float *Uin, const float *Fin, float *Rout,
-                 const ImgState *st) {
+                 const ImgState *st, int parity = -1) {
         if (dct()) {
             launch_dct_forward(n, B, Uin, DT.as<float>(), selT.as<int>(), Fin, m, Rout, m, false,
                                tw.as<float2>(), dtab.as<float4>(), st, work);
             return;
         }
         if (lowprec()) {
-            lowp_apply_A(lowp, lw, B, Uin, Fin, Rout, st, work);
+            lowp_apply_A(lowp, lw, B, Uin, Fin, Rout, st, work, nullptr, nullptr, 0, parity);
             return;
         }
         const int nv = pass_nv(Bp);
@@ -239,14 +246,14 @@ struct tvcs_ctx {
     }
 
     // partial sums of A^T Rin into P (layout described by shrink_args)
-    void apply_At(int Bp, int B, const float *Rin, const ImgState *st) {
+    void apply_At(int Bp, int B, const float *Rin, const ImgState *st, int parity = -1) {
         if (dct()) {
             launch_dct_adjoint(n, B, Rin, m, DT.as<float>(), selT.as<int>(), true, P.as<float>(), N,
                                tw.as<float2>(), dtab.as<float4>(), st, work);
             return;
         }
         if (lowprec()) {
-            lowp_apply_At(lowp, lw, B, Rin, P.as<float>(), st, work);
+            lowp_apply_At(lowp, lw, B, Rin, P.as<float>(), st, work, parity);
             return;
         }
         const int nv = pass_nv(Bp), nchunk = chunks(Bp);
@@ -307,6 +314,8 @@ struct tvcs_ctx {
             a.nchunk = nchunk;
         }
         a.st = state.as<ImgState>();
+        a.Gacc = lowprec() ? Gacc.as<float>() : nullptr;
+        a.parity = 0;
         return a;
     }
 
@@ -336,18 +345,19 @@ struct tvcs_ctx {
             // the inverse row transform (g = A^T r) is computed by the shrink pass
         } else if (fold_prev && lowprec()) {
             lowp_apply_A(lowp, lw, B, U.as<float>(), F.as<float>(), R.as<float>(), st, work, st,
-                         parts.as<double>(), stop_parts(n, B));
-            apply_At(Bp, B, R.as<float>(), st);
+                         parts.as<double>(), stop_parts(n, B), parity);
+            apply_At(Bp, B, R.as<float>(), st, parity);
         } else if (fold_prev) {
             launch_gemv_rows(A32.as<float>(), m, N, U.as<float>(), N, F.as<float>(), m,
                              R.as<float>(), m, 1, st, 1, work, st, parts.as<double>(),
                              stop_parts(n, B));
             apply_At(Bp, B, R.as<float>(), st);
         } else {
-            apply_A(Bp, B, U.as<float>(), F.as<float>(), R.as<float>(), st);
-            apply_At(Bp, B, R.as<float>(), st);
+            apply_A(Bp, B, U.as<float>(), F.as<float>(), R.as<float>(), st, parity);
+            apply_At(Bp, B, R.as<float>(), st, parity);
         }
         ShrinkArgs a = shrink_args(B, Bp);
+        a.parity = parity;
         if (dct()) {
             a.T = DT.as<float>();
             a.dtab = dtab.as<float4>();
@@ -363,7 +373,7 @@ struct tvcs_ctx {
         launch_fft_cols_solve(n, B, Sp, invd.as<double>(), twp, st, work);
         launch_fft_rows_inv(n, B, Sp, U.as<float>(), parts.as<double>(), twp, st,
                             counters.as<int>(), work, dct() ? DT.as<float>() : nullptr,
-                            dct() ? dtab.as<float4>() : nullptr, stop_here);
+                            dct() ? dtab.as<float4>() : nullptr, stop_here, parity);
     }
 
     void build_graph(int B, unsigned flags, double beta, double c, double ctau) {
@@ -437,7 +447,7 @@ struct tvcs_ctx {
         return A32.bytes + lowp_mem.bytes + selT.bytes + dperm.bytes + dtab.bytes + DT.bytes +
                tw.bytes + invd.bytes + U.bytes + F.bytes + R.bytes +
                P.bytes + RHS.bytes + Q0.bytes + Q1.bytes + S.bytes + parts.bytes + state.bytes +
-               obj.bytes + lowp_work.bytes + lamb.bytes + counters.bytes;
+               obj.bytes + lowp_work.bytes + lamb.bytes + counters.bytes + Gacc.bytes;
     }
 };
 

@@ -37,7 +37,23 @@ struct ImgState {
     double du2;     // last ||u^{k+1}-u^k||^2
     double u2;      // last ||u^k||^2
     double tol;     // stop tolerance of this image (0: run maxit iterations)
+    // Products of MFMA storage: mode[k & 1] != 0 makes iteration k compute A u and
+    // A^T r afresh from a two-part bf16 batch operand; 0 makes it add A d to the
+    // previous r (and A^T e to the previous g) with d the one-part bf16 difference
+    // between u and the point the previous r belongs to (see gemm.hip).  The stop
+    // rule of iteration j sets mode[j & 1], the mode of iteration j + 2.
+    int mode[2];
+    int fresh;      // iterations so far whose products were fresh (counted by the stop rule)
+    int pad_;
 };
+
+// Fresh (two-part) products while the relative change of the iterates exceeds this
+// (bf16 rounding errs by at most 2^-8 of a value: the one-part increment then drops
+// at most 2^-8 of a change of at most 2^-8 of u, the size of what the two-part split
+// itself drops), and every kFreshEvery-th iteration, which bounds how long FP32 sums
+// of increments run.
+constexpr double kFreshTheta = 0.00390625;   // 2^-8
+constexpr int kFreshEvery = 64;
 
 // Largest image side the FFT kernels handle (LDS twiddle table length).
 constexpr int kMaxN = 512;
@@ -74,7 +90,10 @@ void launch_gemv_cols(const float *A, int m, int N, const float *R, int ldr, flo
 void launch_sum_partials(const float *P, int nchunk, long long chunk_stride, int nv, int N,
                          float *out, int ldo, hipStream_t s);
 void launch_fill(float *x, size_t count, float value, hipStream_t s);
-void launch_init_state(ImgState *st, int B, double tol, int maxit, hipStream_t s);
+// fresh: the mode of the first two iterations (1: fresh products; 0 only for timing
+// the increment form of the products)
+void launch_init_state(ImgState *st, int B, double tol, int maxit, hipStream_t s,
+                       int fresh = 1);
 // Power-iteration step for lambda_max(A^T A): rq = v.w, v <- w/||w||; st->rel = rq,
 // st->iters counts steps, st->active cleared once |rq - rq_prev| <= rtol rq.
 void launch_power_normalize(float *v, const float *w, int N, ImgState *st, double rtol,
@@ -103,6 +122,10 @@ struct ShrinkArgs {
     float2 *Qnew;          // B x N pairs (IADM)
     double beta, c, ctau;  // c = mu/(beta tau), ctau = c*tau = mu/beta
     const ImgState *st;
+    // MFMA storage: the running g (B x N FP32).  Iterations in increment mode add
+    // the partials to it, fresh ones replace it; null: g is the partials' sum alone
+    float *Gacc;
+    int parity;            // iteration parity (selects ImgState::mode)
     // partial DCT: g is the inverse row DCT of T (the column pass's output,
     // column-major per image), computed in the pass; G is then unused
     const float *T;
@@ -134,11 +157,12 @@ void launch_fft_cols_solve(int n, int B, float2 *S, const double *inv_d, const f
 // T, dtab (partial DCT): also write the DCT-II of the new rows of u to T, as
 // launch_dct_rows_fwd does (null: not)
 // stop_pass = false: no k_stop_rule after the pass (the caller applies the rule
-// later, e.g. folded into the next A u product); stop_parts(n, B) partials per image
+// later, e.g. folded into the next A u product); stop_parts(n, B) partials per image.
+// parity: the iteration's parity (the stop rule sets ImgState::mode[parity]; < 0: not)
 void launch_fft_rows_inv(int n, int B, const float2 *S, float *U, double *parts,
                          const float2 *tw, ImgState *st, int *counters, hipStream_t s,
                          float *T = nullptr, const float4 *dtab = nullptr,
-                         bool stop_pass = true);
+                         bool stop_pass = true, int parity = -1);
 int stop_parts(int n, int B);
 // shrinkage + right-hand side fused with the forward row FFT
 void launch_shrink_rows(const ShrinkArgs &a, bool iadm, float2 *S, const float2 *tw,
@@ -165,21 +189,28 @@ struct LowpWork {
     void *Ubf_hi, *Ubf_lo;       // Bp x N   bf16 copies of U
     void *Rbf_hi, *Rbf_lo;       // Bp x m_p bf16 copies of (scaled) R
     float *Rpart;                // ksplit x Bp x m_p
+    float *Ut;                   // Bp x N: the point the current R belongs to
+    float *St;                   // Bp x m: the vector the current g belongs to (s o r)
     int Bp;
     int fwd_rt, adj_rt;          // 16-row tiles per wave of the two products (autotuned)
 };
 size_t lowp_work_bytes(const LowpA &L, int B);
 void lowp_work_bind(LowpWork &W, const LowpA &L, int B, void *base);
 // stw, parts, nparts (stw == st): the pass that splits U also applies the previous
-// iteration's stop rule to every image first, as launch_gemv_rows does for one image
+// iteration's stop rule to every image first, as launch_gemv_rows does for one image.
+// parity >= 0 (inside the iteration loop): image b's products follow
+// st[b].mode[parity] (fresh, or the increment form that updates R in place);
+// parity < 0: fresh products for every image.
 void lowp_apply_A(const LowpA &L, LowpWork &W, int B, const float *U, const float *F, float *R,
                   const ImgState *st, hipStream_t s, ImgState *stw = nullptr,
-                  const double *parts = nullptr, int nparts = 0);
+                  const double *parts = nullptr, int nparts = 0, int parity = -1);
 // K slices of the adjoint product: G holds that many partial sums, [slice][Bp][N]
 int lowp_adj_splits(const LowpA &L);
 // G[(k*Bp + b)*N + j] = slice k of (A^T r_b)_j
+// (parity as for lowp_apply_A; in increment mode G receives the partials of the
+// increment of g, which the shrink pass adds to the running g)
 void lowp_apply_At(const LowpA &L, LowpWork &W, int B, const float *R, float *G,
-                   const ImgState *st, hipStream_t s);
+                   const ImgState *st, hipStream_t s, int parity = -1);
 // pick the tile shape of each product by timing the candidates on this batch
 void lowp_autotune(const LowpA &L, LowpWork &W, int Bp, const float *U, float *R, float *G,
                    hipStream_t s);

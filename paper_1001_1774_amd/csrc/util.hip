@@ -24,7 +24,7 @@ __global__ void k_fill(float *x, size_t count, float value) {
         x[i] = value;
 }
 
-__global__ void k_init_state(ImgState *st, int B, double tol, int maxit) {
+__global__ void k_init_state(ImgState *st, int B, double tol, int maxit, int fresh) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
     ImgState s;
@@ -36,6 +36,9 @@ __global__ void k_init_state(ImgState *st, int B, double tol, int maxit) {
     s.du2 = 0.0;
     s.u2 = 0.0;
     s.tol = tol;
+    s.mode[0] = s.mode[1] = fresh;
+    s.fresh = 0;
+    s.pad_ = 0;
     st[b] = s;
 }
 
@@ -113,8 +116,9 @@ void launch_fill(float *x, size_t count, float value, hipStream_t s) {
     hipLaunchKernelGGL(k_fill, dim3(grid), dim3(256), 0, s, x, count, value);
 }
 
-void launch_init_state(ImgState *st, int B, double tol, int maxit, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_state, dim3((B + 63) / 64), dim3(64), 0, s, st, B, tol, maxit);
+void launch_init_state(ImgState *st, int B, double tol, int maxit, hipStream_t s, int fresh) {
+    hipLaunchKernelGGL(k_init_state, dim3((B + 63) / 64), dim3(64), 0, s, st, B, tol, maxit,
+                       fresh);
 }
 
 void launch_power_normalize(float *v, const float *w, int N, ImgState *st, double rtol,

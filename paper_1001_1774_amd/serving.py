@@ -53,7 +53,8 @@ class Server:
         if rc == 0:
             return None
         return u.reshape(n, n), dict(iters=st.iters, status=st.status,
-                                     rel_change=st.rel_change, ms=st.ms)
+                                     rel_change=st.rel_change, ms=st.ms,
+                                     fresh_iters=st.fresh_iters)
 
     @property
     def device_bytes(self):

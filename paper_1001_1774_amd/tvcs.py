@@ -47,7 +47,8 @@ STORAGE = {"fp32": TVCS_A_FP32, "bf16": TVCS_A_BF16, "bf16_split": TVCS_A_BF16_S
 class tvcs_stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int),
                 ("rel_change", ctypes.c_double), ("objective", ctypes.c_double),
-                ("tau", ctypes.c_double), ("ms", ctypes.c_float)]
+                ("tau", ctypes.c_double), ("ms", ctypes.c_float),
+                ("fresh_iters", ctypes.c_int)]
 
 
 class TvcsError(RuntimeError):
@@ -84,7 +85,7 @@ _SIGS = {
     "tvcs_measure_peaks": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p,
                                           ctypes.c_void_p]),
     "tvcs_time_products": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
-                                          ctypes.c_void_p, ctypes.c_void_p]),
+                                          ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "tvcs_destroy": (None, [ctypes.c_void_p]),
     "tvcs_server_create": (ctypes.c_void_p, [ctypes.c_size_t, ctypes.c_int, ctypes.c_double,
                                              ctypes.c_double, ctypes.c_uint]),
@@ -206,9 +207,10 @@ def tvcs_solve_continuation(h, F, B, mu, betas, nbeta, tol, maxit, flags, U, st=
                                          _ptr(U, torch.float32), st if st is not None else None)
 
 
-def tvcs_time_products(h, B, reps, ms_forward=None, ms_adjoint=None):
-    """ms_forward / ms_adjoint: ctypes.c_float objects (or None)."""
-    return lib().tvcs_time_products(h, B, reps,
+def tvcs_time_products(h, B, reps, form=0, ms_forward=None, ms_adjoint=None):
+    """form 0: fresh products, 1: their increment form (MFMA storage);
+    ms_forward / ms_adjoint: ctypes.c_float objects (or None)."""
+    return lib().tvcs_time_products(h, B, reps, form,
                                     ctypes.byref(ms_forward) if ms_forward is not None else None,
                                     ctypes.byref(ms_adjoint) if ms_adjoint is not None else None)
 
@@ -368,7 +370,8 @@ class Solver:
         if rc < 0:
             raise TvcsError(rc, tvcs_last_error())
         stats = [dict(iters=s.iters, status=s.status, rel_change=s.rel_change,
-                      objective=s.objective, tau=s.tau, ms=s.ms) for s in st]
+                      objective=s.objective, tau=s.tau, ms=s.ms,
+                      fresh_iters=s.fresh_iters) for s in st]
         out = dict(u=U.reshape(B, self.n, self.n), stats=stats, rc=rc)
         if lam is not None:
             out["lam"] = lam.reshape(B, 2, self.n, self.n)
@@ -393,13 +396,15 @@ class Solver:
         if rc < 0:
             raise TvcsError(rc, tvcs_last_error())
         stats = [dict(iters=s.iters, status=s.status, rel_change=s.rel_change,
-                      objective=s.objective, tau=s.tau, ms=s.ms) for s in st]
+                      objective=s.objective, tau=s.tau, ms=s.ms,
+                      fresh_iters=s.fresh_iters) for s in st]
         return dict(u=U.reshape(B, self.n, self.n), stats=stats, rc=rc)
 
-    def time_products(self, B=1, reps=20):
-        """Average ms per launch of the forward and adjoint products (HIP events)."""
+    def time_products(self, B=1, reps=20, increment=False):
+        """Average ms per launch of the forward and adjoint products (HIP events);
+        increment=True times the one-part increment form of the MFMA products."""
         a, b = ctypes.c_float(), ctypes.c_float()
-        rc = tvcs_time_products(self.h, B, reps, a, b)
+        rc = tvcs_time_products(self.h, B, reps, 1 if increment else 0, a, b)
         if rc < 0:
             raise TvcsError(rc, tvcs_last_error())
         return a.value, b.value
