@@ -9,11 +9,11 @@ import pytest
 
 import oracle as O
 from paper_1001_1774_amd import synth
+from tests._parity import TOL_FP32, check, rel
 
 pytestmark = pytest.mark.gpu
 
 BETAS = [2.0 ** 4, 2.0 ** 5, 2.0 ** 6, 2.0 ** 7]
-EPS32 = 2.0 ** -24
 
 
 def say(*a):
@@ -36,32 +36,20 @@ def prob():
     return p, O.default_tau(p.A)
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
 
 
 def test_continuation_fixed_iterations_parity(T, prob):
     p, tau = prob
     K = 60
-    path = np.zeros(p.B)
-    prev = [O.initial_u(p.A, p.f, p.n, None).copy()]
-
-    def rec(s, k, u):
-        path[:] += np.sqrt(np.sum((u - prev[0]) ** 2, axis=(1, 2)))
-        prev[0] = u.copy()
-    ref = O.ftvcs_continuation(p.A, p.f, p.n, p.mu, BETAS, tau, tol=0, maxit=K, record=rec)
+    ref = O.ftvcs_continuation(p.A, p.f, p.n, p.mu, BETAS, tau, tol=0, maxit=K)
     with T.Solver(p.A, p.n) as s:
         s.tau = tau
         out = s.solve_continuation(p.f.astype(np.float32), mu=p.mu, betas=BETAS, tol=0,
                                    maxit=K)
     U = out["u"].cpu().numpy()
     for b in range(p.B):
-        S = path[b] / np.linalg.norm(ref.u[b])
-        bound = max(1e-5, EPS32 * np.log2(p.n) * S)     # the FP32 bound of the plain path
-        e = rel(U[b], ref.u[b])
-        say(f"  image {b}: rel err {e:.3e} (bound {bound:.2e})")
         assert out["stats"][b]["iters"] == len(BETAS) * K
-        assert e <= bound
+        check(U[b], ref.u[b], TOL_FP32, f"image {b}", say)
 
 
 def test_continuation_stop_rule(T, prob):

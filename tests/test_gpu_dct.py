@@ -15,6 +15,7 @@ import pytest
 
 import oracle as O
 from paper_1001_1774_amd import synth
+from tests._parity import rel, rel_norm
 
 pytestmark = pytest.mark.gpu
 
@@ -35,8 +36,6 @@ def T():
     return tvcs
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
 
 
 def op(p):
@@ -110,7 +109,7 @@ def test_table1_setting_stop_rule(T):
         out = s.solve(f32[0], mu=p.mu, beta=p.beta, tol=5e-5, maxit=6000, iadm=True)
     it, it_ref = out["stats"]["iters"], int(ref.iters[0])
     e = rel(out["u"].cpu().numpy(), ref.u[0])
-    err_truth = rel(out["u"].cpu().numpy(), p.ubar[0])
+    err_truth = rel_norm(out["u"].cpu().numpy(), p.ubar[0])
     say(f"  iterations {it} (oracle {it_ref}), rel err vs oracle {e:.3e}, vs truth {err_truth:.3e}")
     assert out["stats"]["status"] == T.TVCS_OK
     assert abs(it - it_ref) <= max(2, it_ref // 100)

@@ -18,6 +18,7 @@ import pytest
 
 import oracle as O
 from paper_1001_1774_amd import synth
+from tests._parity import rel
 
 pytestmark = pytest.mark.gpu
 
@@ -36,8 +37,6 @@ def T():
     return tvcs
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
 
 
 def test_n256_m13107_b64_split_sampled_images(T):

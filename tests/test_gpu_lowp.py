@@ -15,6 +15,7 @@ import pytest
 
 import oracle as O
 from paper_1001_1774_amd import synth
+from tests._parity import rel
 
 pytestmark = pytest.mark.gpu
 
@@ -31,11 +32,6 @@ def T():
     from paper_1001_1774_amd import tvcs
     tvcs.lib()
     return tvcs
-
-
-def rel(a, b):
-    a = np.asarray(a, np.float64)
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def tau_for(A):

@@ -12,6 +12,7 @@ import pytest
 
 import oracle as O
 from paper_1001_1774_amd import synth
+from tests._parity import rel
 
 pytestmark = pytest.mark.gpu
 
@@ -30,8 +31,6 @@ def T():
     return tvcs
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
 
 
 def tau_for(A):

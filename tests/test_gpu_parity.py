@@ -1,9 +1,11 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle.
 
 Bar (single image, FP32 storage): relative iterate error ||u_gpu - u_oracle|| /
-||u_oracle|| <= 1e-5 after a fixed number of iterations (tol = 0), with the same
-tau on both sides.  Inputs are the seeded synthetic workloads; the oracle runs
-on the FP64 A that the FP32 copy was rounded from.
+||u_oracle|| <= 1e-5 and per-pixel max |u_gpu - u_oracle| / max |u_oracle| <= 1e-5
+after a fixed number of iterations (tol = 0), with the same tau on both sides
+(tests/_parity.py; the strongly undersampled n = 256, m = 1500 case has a fixed
+bound of its own there).  Inputs are the seeded synthetic workloads; the oracle
+runs on the FP64 A that the FP32 copy was rounded from.
 """
 import sys
 
@@ -12,35 +14,11 @@ import pytest
 
 import oracle as O
 from paper_1001_1774_amd import synth
+from tests._parity import TOL_FP32, bar_for, check, rel
 
 pytestmark = pytest.mark.gpu
 
-TOL_U = 1e-5
-EPS32 = 2.0 ** -24
-
-
-def fp32_bound(n, S):
-    """Relative error bound of the FP32 path after K iterations.
-
-    Each FP32 FFT solve of the increment u^{k+1} - u^k errs by about
-    log2(n) eps32 ||u^{k+1} - u^k||; summed over the run and divided by ||u^K|| this
-    is eps32 log2(n) S with S = sum_k ||u^{k+1} - u^k|| / ||u^K|| taken from the
-    oracle's trajectory.  At the paper-like workloads this is below 1e-5, and the
-    1e-5 bar applies; it only matters for deliberately undersampled cases whose
-    early steps are much larger than the final iterate.
-    """
-    return max(TOL_U, EPS32 * np.log2(n) * S)
-
-
-def run_oracle(alg, p, mu, beta, tau, K):
-    prev = [O.initial_u(p.A, np.atleast_2d(p.f), p.n, None).copy()]
-    path = [0.0]
-
-    def rec(k, u):
-        path[0] += np.linalg.norm(u - prev[0])
-        prev[0] = u.copy()
-    r = alg(p.A, p.f, p.n, mu, beta, tau, tol=0, maxit=K, record=rec)
-    return r, path[0] / np.linalg.norm(r.u)
+TOL_U = TOL_FP32
 
 
 def say(*a):
@@ -57,8 +35,6 @@ def T():
     return tvcs
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
 
 
 def gpu_solver(T, p, tau, storage="fp32"):
@@ -72,7 +48,8 @@ CASES = [  # (n, m, iterations, mu)
     (16, 77, 150, 300.0),
     (32, 307, 200, 1e3),      # n = 32, m = 307 workload, 200 iterations
     (64, 1229, 100, 1e3),
-    (256, 1500, 20, 1e3),
+    (256, 6554, 20, 1e3),     # 10 %, the lowest sampling ratio of the workloads
+    (256, 1500, 20, 1e3),     # 2.3 %: a fixed bound of its own (tests/_parity.py)
     (512, 500, 10, 1e3),
 ]
 
@@ -92,16 +69,13 @@ def test_parity_fixed_iterations(T, n, m, K, mu, iadm):
                            sigma=1e-3)
     tau = tau_for(p.A)
     alg = O.iadm if iadm else O.ftvcs
-    ref, S = run_oracle(alg, p, mu, 10.0, tau, K)
+    ref = alg(p.A, p.f, p.n, mu, 10.0, tau, tol=0, maxit=K)
     with gpu_solver(T, p, tau) as s:
         out = s.solve(p.f[0].astype(np.float32), mu=mu, beta=10.0, tol=0.0, maxit=K, iadm=iadm,
                       want_lambda=True)
     u = out["u"].cpu().numpy()
     assert out["stats"]["iters"] == K
-    e = rel(u, ref.u[0])
-    bound = fp32_bound(n, S)
-    say(f"  rel err u = {e:.3e}  (bound {bound:.2e}, path factor S = {S:.1f})")
-    assert e <= bound
+    check(u, ref.u[0], bar_for(n, m), "u", say)
     if iadm:
         lam = out["lam"].cpu().numpy()
         el = rel(lam, ref.lam[0])
@@ -121,14 +95,12 @@ def test_parity_n128_m4096_500_iterations(T, n128, iadm):
     say(f"case n128_m4096 K=500 iadm={iadm}")
     tau = O.default_tau(p.A)
     alg = O.iadm if iadm else O.ftvcs
-    ref, S = run_oracle(alg, p, p.mu, p.beta, tau, 500)
-    assert fp32_bound(p.n, S) == TOL_U        # the 1e-5 bar applies at this workload
+    ref = alg(p.A, p.f, p.n, p.mu, p.beta, tau, tol=0, maxit=500)
     with gpu_solver(T, p, tau) as s:
         out = s.solve(p.f[0].astype(np.float32), mu=p.mu, beta=p.beta, tol=0.0, maxit=500,
                       iadm=iadm)
-    e = rel(out["u"].cpu().numpy(), ref.u[0])
-    say(f"  rel err u = {e:.3e}  ms = {out['stats']['ms']:.2f}")
-    assert e <= TOL_U
+    say(f"  ms = {out['stats']['ms']:.2f}")
+    check(out["u"].cpu().numpy(), ref.u[0], TOL_U, "u", say)
 
 
 def test_one_step_from_warm_start_n128(T, n128):
@@ -142,9 +114,7 @@ def test_one_step_from_warm_start_n128(T, n128):
             ref = O.ftvcs(p.A, p.f, p.n, p.mu, p.beta, tau, tol=0, maxit=1,
                           u0=u0.astype(np.float64))
             out = s.solve(p.f[0].astype(np.float32), mu=p.mu, beta=p.beta, maxit=1, u0=u0)
-            e = rel(out["u"].cpu().numpy(), ref.u[0])
-            say(f"  trial {trial}: one-step rel err {e:.3e}")
-            assert e <= 2e-6
+            check(out["u"].cpu().numpy(), ref.u[0], 2e-6, f"trial {trial}: one step", say)
 
 
 def test_stop_rule_iteration_count(T):
@@ -179,7 +149,7 @@ def test_batch_equals_single(T):
                                                  maxit=300)
             for b in range(5):
                 assert rb["stats"][b]["iters"] == ref.iters[b]
-                assert rel(rb["u"][b].cpu().numpy(), ref.u[b]) <= TOL_U
+                check(rb["u"][b].cpu().numpy(), ref.u[b], TOL_U, f"image {b}", say)
 
 
 def test_lambda_max_and_objective(T):
