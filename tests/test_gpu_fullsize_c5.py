@@ -100,8 +100,12 @@ def test_n512_m26214_b128_iadm(T, c5, storage):
     Aq = dequantized(p.A, storage)
     say(f"  de-quantised A in {time.time() - t0:.1f}s")
     t0 = time.time()
+
+    def progress(k, u):
+        if (k + 1) % 10 == 0:
+            say(f"  oracle iteration {k + 1} ({time.time() - t0:.0f}s)")
     ref = O.iadm(Aq, p.f[SAMPLE].astype(np.float32).astype(np.float64), p.n, p.mu, p.beta,
-                 tau, tol=0, maxit=K)
+                 tau, tol=0, maxit=K, record=progress)
     say(f"  oracle {time.time() - t0:.1f}s")
     del Aq
     for j, b in enumerate(SAMPLE):
