@@ -245,10 +245,13 @@ typedef struct tvcs_server *tvcs_server_handle;
  * reconstruction requests).  Each matrix gets `slots` image slots (1..1024): its
  * batch.  A matrix's slots are allocated when its first request is admitted, and
  * only if the device bytes of all registered matrices and allocated slot groups
- * stay within hbm_budget (0: no limit); a group with no request in flight or queued
- * gives its slots back when another matrix's requests wait for room.  mu, beta and
- * flags (0 or TVCS_IADM) apply to every request; each request has its own tol and
- * maxit.  Returns NULL on error (see tvcs_last_error).
+ * stay within hbm_budget (0: no limit); a group with no request in flight gives its
+ * slots back when another matrix's requests wait for room.  A matrix that has
+ * waited for room for a few rounds makes the other groups stop admitting, finish
+ * the requests they hold and give their slots back, so no matrix waits longer
+ * than about one request's iteration cap.  mu, beta and flags (0 or TVCS_IADM)
+ * apply to every request; each request has its own tol and maxit.  Returns NULL on
+ * error (see tvcs_last_error).
  */
 tvcs_server_handle tvcs_server_create(size_t hbm_budget, int slots, double mu, double beta,
                                       unsigned flags);
@@ -266,14 +269,17 @@ long long tvcs_server_submit(tvcs_server_handle s, int matrix, const float *f, d
                              int maxit);
 
 /*
- * tvcs_server_step: one scheduling round.  Admits queued requests into free slots
- * (u^0 = A^T f for the new slots), advances every matrix that holds requests by one
- * replay of its captured iteration graph (10 iterations; each matrix on its own
- * stream, so their work overlaps on the device), and retires the requests that met
- * their stop rule or cap mid-replay.  Requests submitted between rounds join the
- * running batches at the next round.  A request's iterates do not depend on its
- * slot, on the other requests or on when it was admitted.  Returns the number of
- * requests queued or in flight after the round, or a negative error code.
+ * tvcs_server_step: one scheduling round.  Every matrix whose previous replay has
+ * ended retires the requests that met their stop rule or cap, admits queued
+ * requests into its free slots (u^0 = A^T f computed for the new slots only) and,
+ * if it holds requests, starts the next replay of its captured iteration graph (10
+ * iterations) on its own stream.  Matrices do not wait for each other: the call
+ * returns as soon as one running replay has ended.  Requests submitted between
+ * rounds join the running batches at their matrix's next replay.  A request's
+ * iterates do not depend on its slot, on the other requests or on when it was
+ * admitted.  Returns the number of requests queued or in flight after the round,
+ * or a negative error code (TVCS_ENOMEM if queued requests can never fit the
+ * budget).
  */
 int tvcs_server_step(tvcs_server_handle s);
 

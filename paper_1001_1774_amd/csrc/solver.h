@@ -72,6 +72,7 @@ struct tvcs_ctx {
     int gnv = 1;           // largest images-per-pass of the FP32 products
     DevBuf U, F, R, P, RHS, Q0, Q1, S, parts, state, obj, lowp_work, lamb, counters;
     DevBuf Gacc;           // MFMA storage: the running g of the product increments (B x N)
+    DevBuf adm_F, adm_U;   // request loop: f and A^T f of newly admitted slots (capP rows)
     DevBuf DT;             // partial DCT: the half-transformed images between passes
     LowpWork lw{};
     ImgState *host_state = nullptr;   // pinned mirror for polling: two halves of cap images
@@ -183,6 +184,11 @@ struct tvcs_ctx {
         return b;
     }
 
+    // device bytes of the request loop's admission buffers for B slots
+    size_t admission_bytes(int B) const {
+        return sizeof(float) * (size_t)padded(B) * ((size_t)m + (size_t)N);
+    }
+
     // device bytes of A's storage and the FFT tables
     size_t storage_bytes() const {
         return A32.bytes + lowp_mem.bytes + selT.bytes + dperm.bytes + dtab.bytes + tw.bytes +
@@ -207,7 +213,7 @@ struct tvcs_ctx {
             exec = nullptr;
         }
         for (DevBuf *b : {&U, &F, &R, &P, &RHS, &Q0, &Q1, &S, &parts, &state, &obj, &lowp_work, &lamb,
-                          &counters, &DT, &Gacc})
+                          &counters, &DT, &Gacc, &adm_F, &adm_U})
             b->release();
         cap = capP = 0;
     }
@@ -447,7 +453,8 @@ struct tvcs_ctx {
         return A32.bytes + lowp_mem.bytes + selT.bytes + dperm.bytes + dtab.bytes + DT.bytes +
                tw.bytes + invd.bytes + U.bytes + F.bytes + R.bytes +
                P.bytes + RHS.bytes + Q0.bytes + Q1.bytes + S.bytes + parts.bytes + state.bytes +
-               obj.bytes + lowp_work.bytes + lamb.bytes + counters.bytes + Gacc.bytes;
+               obj.bytes + lowp_work.bytes + lamb.bytes + counters.bytes + Gacc.bytes + adm_F.bytes +
+               adm_U.bytes;
     }
 };
 

@@ -74,6 +74,41 @@ def test_alone_equals_in_the_mix(T, problems, iadm):
         s.close()
 
 
+def test_alone_equals_in_the_mix_at_request_sizes(T):
+    """The serving mix's image sides: bf16 groups at n = 64 (30 %), 128 (20 %) and 256
+    (10 %) running side by side; every request equals its solve alone (bitwise, same
+    iteration count), with products in both forms (fresh and increment)."""
+    from paper_1001_1774_amd import serving as S
+    problems = [synth.make_problem("c64", n=64, ratio=0.3, batch=4, seed_A=61, dtype=np.float32),
+                synth.make_problem("c128", n=128, ratio=0.2, batch=4, seed_A=62, dtype=np.float32),
+                synth.make_problem("c256", n=256, ratio=0.1, batch=4, seed_A=63, dtype=np.float32)]
+    solvers = [T.Solver(p.A, p.n, storage="bf16") for p in problems]
+    reqs = make_mix(30, 17, problems, maxit=200)
+    arr = S.poisson_arrivals(len(reqs), rate=300.0, seed=5)
+    for r, a in zip(reqs, arr):
+        r.arrival = float(a)
+    with S.Server(slots=16, mu=1e3, beta=10.0, iadm=True) as srv:
+        for s in solvers:
+            srv.add_matrix(s)
+        out = S.run_arrivals(srv, reqs, keep_results=True)
+    say(f"  mix: {out['count']} requests, {out['rec_per_s']:.1f} rec/s, p50 {out['p50_ms']:.1f} ms,"
+        f" p99 {out['p99_ms']:.1f} ms, mean iters {out['mean_iters']:.0f}")
+    mism, incr = 0, 0
+    for i, r in enumerate(reqs):
+        u_mix, st_mix = out["results"][i]
+        u_alone, st_alone = S.solve_alone(solvers[r.matrix], r, 1e3, 10.0, True)
+        assert st_mix["iters"] == st_alone["iters"], (i, st_mix, st_alone)
+        assert st_mix["fresh_iters"] == st_alone["fresh_iters"], (i, st_mix, st_alone)
+        incr += st_mix["iters"] - st_mix["fresh_iters"]
+        if not np.array_equal(u_mix.ravel(), u_alone.ravel()):
+            mism += 1
+    say(f"  bitwise mismatches: {mism} of {len(reqs)}; increment-form iterations {incr}")
+    assert mism == 0
+    assert incr > 0
+    for s in solvers:
+        s.close()
+
+
 def test_mix_matches_oracle(T, problems):
     """FP32 requests served in the mix agree with the FP64 oracle (same tau)."""
     from paper_1001_1774_amd import serving as S
@@ -137,6 +172,48 @@ def test_budget_admission(T, problems):
         with pytest.raises(T.TvcsError) as ei:
             srv.step()
         assert ei.value.code == T.TVCS_ENOMEM
+    for s in sols:
+        s.close()
+
+
+def test_budget_wait_is_bounded(T, problems):
+    """With room for one group, a matrix whose requests keep arriving does not hold
+    the memory forever: a request for the other matrix is served within a bounded
+    number of rounds (the resident group stops admitting after a few rounds of
+    waiting, finishes what it holds and gives its slots back)."""
+    from paper_1001_1774_amd import serving as S
+    sols = [T.Solver(problems[i].A, problems[i].n, storage="bf16") for i in (1, 2)]
+    with S.Server(slots=8, mu=1e3, beta=10.0, iadm=True) as probe:
+        for s in sols:
+            probe.add_matrix(s)
+        base = probe.device_bytes
+        rid = probe.submit(0, problems[1].f[0], 1e-3, 20)
+        probe.step()
+        group = probe.device_bytes - base
+        while probe.step():
+            pass
+        assert probe.result(rid, 64) is not None
+    budget = base + group + group // 2      # room for one group of slots, not two
+    f0, f1 = problems[1].f.astype(np.float32), problems[2].f.astype(np.float32)
+    with S.Server(slots=8, mu=1e3, beta=10.0, iadm=True, hbm_budget=budget) as srv:
+        for s in sols:
+            srv.add_matrix(s)
+        ids0 = [srv.submit(0, f0[k % len(f0)], 0.0, 40) for k in range(8)]
+        srv.step()                          # matrix 0 resident and running
+        rid1 = srv.submit(1, f1[0], 0.0, 30)
+        rounds = 0
+        while srv.result(rid1, 64) is None:
+            ids0.append(srv.submit(0, f0[rounds % len(f0)], 0.0, 40))   # never idle
+            srv.step()
+            rounds += 1
+            # 4 rounds of waiting + 4 replays to finish matrix 0's slots + 3 replays
+            # for the 30 iterations of the request, with room for early returns
+            assert rounds <= 60, "request for matrix 1 still waiting"
+        say(f"  matrix 1 served after {rounds} rounds while matrix 0 kept receiving requests")
+        while srv.step():
+            pass
+        for rid in ids0:
+            assert srv.result(rid, 64) is not None
     for s in sols:
         s.close()
 
