@@ -73,10 +73,11 @@ def main():
                     help="skip the n = 256 batched-vs-plain section")
     ap.add_argument("--batched-iters", type=int, default=300)
     ap.add_argument("--no-serving", action="store_true", help="skip the request-loop section")
-    ap.add_argument("--serving-full", action="store_true",
-                    help="4 matrices per (n, ratio) instead of 1 in the request-loop section")
-    ap.add_argument("--large", action="store_true",
-                    help="add the n = 512, m = 26214, B = 128 section (FP8 vs BF16 storage)")
+    ap.add_argument("--serving-per", type=int, default=4,
+                    help="matrices per (n, ratio) in the request-loop section (4: 36 matrices)")
+    ap.add_argument("--serving-requests", type=int, default=1000)
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the n = 512, m = 26214, B = 128 section (FP8 vs BF16 storage)")
     ap.add_argument("--large-iters", type=int, default=300)
     ap.add_argument("--no-dct", action="store_true", help="skip the partial-DCT section")
     # profiler modes: run one piece of the path and print one JSON line (no benchmark)
@@ -216,12 +217,30 @@ def main():
     del solver
     if not args.no_batched:
         out["batched_n256"] = bench_batched(args, np, torch, O, synth, tvcs)
+        # the FP32 products where A (3.4 GB) is far larger than the 256 MB Infinity
+        # Cache: an HBM rate, not a cache rate
+        pf = out["batched_n256"]["plain_fp32"]
+        out["gemv_hbm_n256"] = {
+            "forward_gbs": pf["gemv_gbs_forward"], "adjoint_gbs": pf["gemv_gbs_adjoint"],
+            "forward_frac": pf["gemv_gbs_forward"] / HBM_PEAK_GBS,
+            "adjoint_frac": pf["gemv_gbs_adjoint"] / HBM_PEAK_GBS,
+            "a_bytes": 4 * 13107 * 65536}
     if not args.no_serving:
         out["serving"] = bench_serving(args, np, synth, tvcs)
-    if args.large:
-        out["large_n512"] = bench_large(args, np, torch, synth, tvcs)
+    if not args.no_large:
+        out["large_n512"] = bench_large(args, np, torch, O, synth, tvcs)
     if not args.no_dct:
         out["partial_dct"] = bench_dct(args, np, torch, O, synth, tvcs)
+    if "batched_n256" in out:
+        # the metric's comparison: batched low-precision against the plain FP32 path at
+        # n = 256, with the error against the FP64 oracle at the timed iteration count
+        bn = out["batched_n256"]
+        out["batched_vs_plain_n256"] = {
+            k: {"rec_per_s": bn[k]["rec_per_s"], "speedup": bn[k]["speedup_vs_plain_fp32"],
+                "max_rel_err_vs_fp64": max(e["rel_err"] for e in
+                                           bn[k]["error_vs_fp64_oracle_fp64_A"].values()),
+                "meets_1e-4": bn[k]["meets_1e-4"]} for k in ("bf16_split", "bf16")}
+        out["batched_vs_plain_n256"]["plain_fp32_rec_per_s"] = bn["plain_fp32"]["rec_per_s"]
     print(json.dumps(out), flush=True)
 
 
@@ -273,12 +292,14 @@ MFMA_BF16_PEAK = 2.5e15   # MI355X dense bf16 MFMA, FLOP/s
 ACHIEVABLE = {}           # peaks measured on the device (filled in main)
 
 
-def product_rates(storage, m, N, B, ms_f, ms_a):
+def product_rates(storage, m, N, B, ms_f, ms_a, increment=False):
     """HBM and MFMA rates of the two batched products (HIP-event times per launch).
-    Useful flops are 2 m N B per product; the MFMA path executes 2 bf16 products
-    per useful one (batch operand split hi + lo), 3 with split storage of A."""
+    Useful flops are 2 m N B per product; fresh products execute 2 bf16 MFMA
+    products per useful one (batch operand split hi + lo), 3 with split storage of
+    A; the increment form executes 1 (2 with split storage)."""
     elem = {"bf16": 2, "bf16_split": 4, "fp8_rowscale": 1}[storage]
-    execd = 3 if storage == "bf16_split" else 2
+    execd = (2 if storage == "bf16_split" else 1) if increment else \
+        (3 if storage == "bf16_split" else 2)
     a_bytes = elem * m * N
     useful = 2.0 * m * N * B
     out = {"gemm_forward_ms": ms_f, "gemm_adjoint_ms": ms_a}
@@ -295,14 +316,23 @@ def product_rates(storage, m, N, B, ms_f, ms_a):
     return out
 
 
+def fresh_fraction(stats):
+    """Share of the iterations whose products were fresh (the rest were increments)."""
+    it = sum(st["iters"] for st in stats)
+    return sum(st["fresh_iters"] for st in stats) / it if it else None
+
+
 def bench_batched(args, np, torch, O, synth, tvcs):
     """n = 256, m = 13107 (20 %), 64 images sharing A: plain FP32 (one image per
-    solve) against the batched MFMA path in split and plain BF16 storage, at a fixed
-    number of IADM iterations.  Error against the FP64 oracle is checked on image 0
-    after a bounded number of iterations (the FP64 A is 6.9 GB)."""
+    solve) against the batched MFMA path in split and plain BF16 storage, at the same
+    number of IADM iterations.  Images 0 (noise 1e-3) and 45 (noise 1e-2) are checked
+    against the FP64 oracle on the FP64 A at that iteration count.  The CPU baseline
+    is the FP64 oracle on the whole batch (products as A @ U over the 64 images) for
+    a bounded number of iterations, scaled to the timed count."""
     K = args.batched_iters
     t0 = time.time()
-    p = synth.workload("n256_m13107_b64", sigma=[1e-3 if i % 2 == 0 else 1e-2 for i in range(64)])
+    sig = [1e-3 if i % 2 == 0 else 1e-2 for i in range(64)]
+    p = synth.workload("n256_m13107_b64", sigma=sig)
     log(f"workload n256_m13107_b64 generated in {time.time() - t0:.1f}s")
     A32 = p.A.astype(np.float32)
     F = torch.from_numpy(p.f.astype(np.float32)).cuda()
@@ -324,64 +354,80 @@ def bench_batched(args, np, torch, O, synth, tvcs):
                          "gemv_gbs_forward": gbs / (ms_f * 1e-3),
                          "gemv_gbs_adjoint": gbs / (ms_a * 1e-3)}
     log(f"plain fp32 n=256: {1e3 * dt / K:.3f} ms/iter")
-    # FP64 oracle on image 0, bounded: KC iterations
-    KC = 20
-    ref = O.iadm(p.A, p.f[:1], p.n, p.mu, p.beta, tau, tol=0, maxit=KC)
+    # FP64 oracle on images 0 and 45 at the timed iteration count
+    sample = [0, 45]
+    t0 = time.perf_counter()
+    ref = O.iadm(p.A, p.f[sample], p.n, p.mu, p.beta, tau, tol=0, maxit=K)
+    log(f"oracle check ({len(sample)} images, {K} iterations): {time.perf_counter() - t0:.1f}s")
     for storage in ("bf16_split", "bf16"):
         with tvcs.Solver(A32, p.n, storage=storage) as s:
             s.tau = tau
-            chk = s.solve_batch(F, mu=p.mu, beta=p.beta, maxit=KC, iadm=True)
-            u0 = chk["u"][0].cpu().numpy().astype(np.float64)
-            err = float(np.linalg.norm(u0 - ref.u[0]) / np.linalg.norm(ref.u[0]))
+            s.solve_batch(F, mu=p.mu, beta=p.beta, maxit=10, iadm=True)    # warm-up
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            s.solve_batch(F, mu=p.mu, beta=p.beta, maxit=K, iadm=True)
+            out = s.solve_batch(F, mu=p.mu, beta=p.beta, maxit=K, iadm=True)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             ms_f, ms_a = s.time_products(B=p.B, reps=10)
+            mi_f, mi_a = s.time_products(B=p.B, reps=10, increment=True)
+        U = out["u"].cpu().numpy().astype(np.float64)
+        errs = {}
+        for j, b in enumerate(sample):
+            d = U[b] - ref.u[j]
+            errs[f"image{b}_sigma{sig[b]:g}"] = {
+                "rel_err": float(np.linalg.norm(d) / np.linalg.norm(ref.u[j])),
+                "max_rel_err": float(np.abs(d).max() / np.abs(ref.u[j]).max()),
+                "psnr_db": psnr_db(U[b], ref.u[j])}
         res[storage] = {
             "rec_per_s": p.B / dt, "ms_per_iter": 1e3 * dt / K,
             "speedup_vs_plain_fp32": (p.B / dt) / res["plain_fp32"]["rec_per_s"],
-            "rel_err_vs_fp64_oracle_image0": err,
-            "psnr_db_vs_fp64_oracle_image0": psnr_db(u0, ref.u[0]), "oracle_check_iterations": KC,
-            **product_rates(storage, p.m, p.N, p.B, ms_f, ms_a),
+            "error_vs_fp64_oracle_fp64_A": errs, "oracle_check_iterations": K,
+            "meets_1e-4": all(e["rel_err"] <= 1e-4 for e in errs.values()),
+            "fresh_iteration_fraction": fresh_fraction(out["stats"]),
+            "fresh": product_rates(storage, p.m, p.N, p.B, ms_f, ms_a),
+            "increment": product_rates(storage, p.m, p.N, p.B, mi_f, mi_a, increment=True),
         }
-        log(f"{storage} B=64: {1e3 * dt / K:.3f} ms/iter, err {err:.2e}")
-    # the products' rates as the batch grows (bf16 storage): the arithmetic intensity
-    # 2B / s_A moves the products from the HBM roofline towards the MFMA one
+        log(f"{storage} B=64: {1e3 * dt / K:.3f} ms/iter, errors {[round(e['rel_err'], 8) for e in errs.values()]}")
+    # FP64 oracle on the whole batch (the host's batched baseline), bounded iterations
+    KC = 10
+    t0 = time.perf_counter()
+    O.iadm(p.A, p.f, p.n, p.mu, p.beta, tau, tol=0, maxit=KC)
+    tc = time.perf_counter() - t0
+    res["cpu_baseline"] = {
+        "value": p.B / (tc * K / KC), "unit": "reconstructions/s", "cores": cpu_threads(),
+        "kind": "oracle",
+        "sample": f"FP64 oracle on all {p.B} images at once (A @ U products) for {KC} "
+                  f"iterations ({tc:.1f} s), scaled to {K} iterations"}
+    log(f"cpu oracle batched: {tc:.1f}s for {KC} iterations of {p.B} images")
+    # the products' rates as the batch grows (bf16 storage, increment form): the
+    # arithmetic intensity 2B / s_A moves the products from the HBM roofline towards
+    # the MFMA one
     sweep = {}
     with tvcs.Solver(A32, p.n, storage="bf16") as s:
         for Bs in (64, 128, 256):
-            ms_f, ms_a = s.time_products(B=Bs, reps=5)
-            r = product_rates("bf16", p.m, p.N, Bs, ms_f, ms_a)
+            ms_f, ms_a = s.time_products(B=Bs, reps=5, increment=True)
+            r = product_rates("bf16", p.m, p.N, Bs, ms_f, ms_a, increment=True)
             ai = 2.0 * Bs / 2.0                           # useful flops per A byte
-            # useful-flop bound: HBM x intensity, or the MFMA peak divided by the 2
-            # bf16 products executed per useful one (batch operand hi + lo)
-            bound = min(MFMA_BF16_PEAK / 2.0, ai * HBM_PEAK_GBS * 1e9)
+            bound = min(MFMA_BF16_PEAK, ai * HBM_PEAK_GBS * 1e9)
             r["roofline_bound_tflops"] = bound / 1e12
-            r["roofline_bound"] = "mfma" if MFMA_BF16_PEAK / 2.0 < ai * HBM_PEAK_GBS * 1e9 else "hbm"
+            r["roofline_bound"] = "mfma" if MFMA_BF16_PEAK < ai * HBM_PEAK_GBS * 1e9 else "hbm"
             r["frac_of_roofline_forward"] = 2.0 * p.m * p.N * Bs / (ms_f * 1e-3) / bound
             r["frac_of_roofline_adjoint"] = 2.0 * p.m * p.N * Bs / (ms_a * 1e-3) / bound
             sweep[f"B{Bs}"] = r
-            log(f"bf16 products B={Bs}: {ms_f:.3f} / {ms_a:.3f} ms")
-    res["bf16_batch_sweep"] = sweep
-    # split storage at 256 images (one 256-image group per workgroup): the MFMA
-    # pipes execute 3 bf16 products per useful one
-    with tvcs.Solver(A32, p.n, storage="bf16_split") as s:
-        ms_f, ms_a = s.time_products(B=256, reps=5)
-        res["bf16_split_products_B256"] = product_rates("bf16_split", p.m, p.N, 256, ms_f, ms_a)
-        log(f"split products B=256: {ms_f:.3f} / {ms_a:.3f} ms")
+            log(f"bf16 increment products B={Bs}: {ms_f:.3f} / {ms_a:.3f} ms")
+    res["bf16_increment_batch_sweep"] = sweep
     return res
-
 
 
 def bench_serving(args, np, synth, tvcs):
     """Request loop: Poisson arrivals over resident BF16 matrices for n in {64, 128,
-    256} and sampling ratios {0.1, 0.2, 0.3} (1 or 4 matrices per pair), per-request
-    tol in {1e-3, 1e-4}, IADM, mu = 1e3, beta = 10.  First the saturated throughput
-    (all requests at t = 0), then arrival rates of 0.5, 0.8 and 0.95 of it."""
+    256} and sampling ratios {0.1, 0.2, 0.3} (`--serving-per` matrices per pair),
+    per-request tol in {1e-3, 1e-4} (cap 3000 iterations), IADM, mu = 1e3, beta = 10.
+    First the saturated throughput (all requests at t = 0), then arrival rates of 0.5,
+    0.8 and 0.95 of it.  The A-stream rate is the bytes of A the replays streamed
+    over the wall time, against the HBM roofline."""
     from paper_1001_1774_amd import serving as S
-    per = 4 if args.serving_full else 1
+    per = args.serving_per
     t0 = time.time()
     pools, solvers = [], []
     seed = 2001
@@ -395,7 +441,7 @@ def bench_serving(args, np, synth, tvcs):
                 seed += 1
     log(f"serving: {len(solvers)} matrices ready in {time.time() - t0:.1f}s")
     rng = np.random.default_rng(7)
-    count = 300
+    count = args.serving_requests
 
     def requests(rate):
         reqs = []
@@ -408,18 +454,19 @@ def bench_serving(args, np, synth, tvcs):
             r_.arrival = float(a)
         return reqs
 
+    keys = ("rec_per_s", "p50_ms", "p99_ms", "mean_iters", "a_stream_gbs", "wall_s")
     res = {"matrices": len(solvers), "storage": "bf16", "slots_per_matrix": 32,
            "requests_per_run": count, "algorithm": "IADM"}
     with S.Server(slots=32, mu=1e3, beta=10.0, iadm=True) as srv:
         for s_ in solvers:
             srv.add_matrix(s_)
         sat = S.run_arrivals(srv, requests(None))
-        res["saturated"] = {k: sat[k] for k in ("rec_per_s", "p50_ms", "p99_ms", "mean_iters")}
-        log(f"serving saturated: {sat['rec_per_s']:.1f} rec/s")
+        res["saturated"] = {k: sat[k] for k in keys}
+        res["saturated"]["a_stream_frac_of_hbm"] = sat["a_stream_gbs"] / HBM_PEAK_GBS
+        log(f"serving saturated: {sat['rec_per_s']:.1f} rec/s, A stream {sat['a_stream_gbs']:.0f} GB/s")
         for frac in (0.5, 0.8, 0.95):
             o = S.run_arrivals(srv, requests(frac * sat["rec_per_s"]))
-            res[f"poisson_{frac}"] = {k: o[k] for k in ("rec_per_s", "p50_ms", "p99_ms",
-                                                          "mean_iters")}
+            res[f"poisson_{frac}"] = {k: o[k] for k in keys}
             log(f"serving at {frac} of saturation: p50 {o['p50_ms']:.1f} ms, "
                 f"p99 {o['p99_ms']:.1f} ms")
         res["device_bytes"] = srv.device_bytes
@@ -428,30 +475,94 @@ def bench_serving(args, np, synth, tvcs):
     return res
 
 
-def bench_large(args, np, torch, synth, tvcs):
+def bench_large(args, np, torch, O, synth, tvcs):
     """n = 512, m = 26214 (10 %), 128 images sharing A, IADM, 300 iterations:
-    FP8-E4M3 with row scales against BF16 storage."""
+    FP8-E4M3 with row scales against BF16 storage.  Images 5 and 100 are checked after
+    KC iterations against the FP64 oracle on the matrix each format represents (the
+    de-quantised A: the arithmetic's error) and on the FP64 A (the storage format's
+    effect), as relative error and PSNR; the oracle run on the de-quantised A, held in
+    host memory, is the CPU baseline, scaled to the timed count."""
+    import threading
     t0 = time.time()
     p = synth.workload("n512_m26214_b128", dtype=np.float32)
     log(f"workload n512_m26214_b128 generated in {time.time() - t0:.1f}s")
     F = torch.from_numpy(p.f.astype(np.float32)).cuda()
-    K = args.large_iters
+    K, KC, sample = args.large_iters, 30, [5, 100]
     res = {"workload": "n512_m26214_b128", "n": p.n, "m": p.m, "batch": p.B, "iterations": K,
-           "algorithm": "IADM"}
+           "algorithm": "IADM", "oracle_check_iterations": KC, "oracle_check_images": sample}
     A = p.A
     p.A = None
+    fs = p.f[sample].astype(np.float32).astype(np.float64)
+
+    def dequantized(storage):
+        out = np.empty(A.shape, np.float64)
+        nxt, lock = [0], threading.Lock()
+
+        def work():
+            while True:
+                with lock:
+                    i = nxt[0]
+                    nxt[0] += 256
+                if i >= A.shape[0]:
+                    return
+                out[i:i + 256] = O.dequantized_A(A[i:i + 256], storage) if storage else A[i:i + 256]
+        ths = [threading.Thread(target=work) for _ in range(min(16, len(os.sched_getaffinity(0))))]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        return out
+
+    tau = {}
     for storage in ("fp8_rowscale", "bf16"):
         with tvcs.Solver(A, p.n, storage=storage) as s:
+            tau[storage] = s.tau
             s.solve_batch(F, mu=p.mu, beta=p.beta, maxit=10, iadm=True)     # warm-up
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            s.solve_batch(F, mu=p.mu, beta=p.beta, maxit=K, iadm=True)
+            out = s.solve_batch(F, mu=p.mu, beta=p.beta, maxit=K, iadm=True)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t1
+            chk = s.solve_batch(F, mu=p.mu, beta=p.beta, maxit=KC, iadm=True)["u"]
+            Uc = chk.cpu().numpy()[sample].astype(np.float64)
             ms_f, ms_a = s.time_products(B=p.B, reps=5)
+            mi_f, mi_a = s.time_products(B=p.B, reps=5, increment=True)
         res[storage] = {"rec_per_s": p.B / dt, "ms_per_iter": 1e3 * dt / K,
-                        **product_rates(storage, p.m, p.N, p.B, ms_f, ms_a)}
+                        "fresh_iteration_fraction": fresh_fraction(out["stats"]),
+                        "fresh": product_rates(storage, p.m, p.N, p.B, ms_f, ms_a),
+                        "increment": product_rates(storage, p.m, p.N, p.B, mi_f, mi_a,
+                                                   increment=True)}
         log(f"{storage} n=512 B=128: {1e3 * dt / K:.3f} ms/iter")
+        t1 = time.perf_counter()
+        Aq = dequantized(storage)
+        td = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        ref = O.iadm(Aq, fs, p.n, p.mu, p.beta, tau[storage], tol=0, maxit=KC)
+        tc = time.perf_counter() - t1
+        del Aq
+        res[storage]["error_vs_fp64_oracle_dequantized_A"] = [
+            {"image": b, "rel_err": float(np.linalg.norm(Uc[j] - ref.u[j]) / np.linalg.norm(ref.u[j])),
+             "max_rel_err": float(np.abs(Uc[j] - ref.u[j]).max() / np.abs(ref.u[j]).max()),
+             "psnr_db": psnr_db(Uc[j], ref.u[j])} for j, b in enumerate(sample)]
+        res[storage]["cpu_baseline"] = {
+            "value": len(sample) / (tc * K / KC), "unit": "reconstructions/s",
+            "cores": cpu_threads(), "kind": "oracle",
+            "sample": f"FP64 oracle on the de-quantised A (55 GB, in host memory, built in "
+                      f"{td:.0f} s) for {len(sample)} images x {KC} iterations ({tc:.1f} s), "
+                      f"scaled to {K} iterations"}
+        res[storage]["_u_check"] = Uc
+        log(f"{storage} oracle check: {tc:.1f}s")
+    # the storage formats' effect: the oracle on the FP64 A (the FP32 copy, whose
+    # rounding is 2^-24 relative) with the same tau per format
+    A64 = dequantized(None)
+    for storage in ("fp8_rowscale", "bf16"):
+        ref = O.iadm(A64, fs, p.n, p.mu, p.beta, tau[storage], tol=0, maxit=KC)
+        Uc = res[storage].pop("_u_check")
+        res[storage]["error_vs_fp64_oracle_fp64_A"] = [
+            {"image": b, "rel_err": float(np.linalg.norm(Uc[j] - ref.u[j]) / np.linalg.norm(ref.u[j])),
+             "psnr_db": psnr_db(Uc[j], ref.u[j])} for j, b in enumerate(sample)]
+    del A64
+    res["fp8_vs_bf16_speedup"] = res["fp8_rowscale"]["rec_per_s"] / res["bf16"]["rec_per_s"]
     return res
 
 

@@ -295,6 +295,12 @@ int tvcs_server_pending(tvcs_server_handle s);
 /* Device bytes counted against the budget (registered matrices and slot groups). */
 size_t tvcs_server_device_bytes(tvcs_server_handle s);
 
+/* Bytes of A the replays launched so far stream: 10 iterations x 2 products x one
+ * copy of the stored matrix per replay (the A^T copy of the MFMA formats has the
+ * same size).  Divided by wall time, the request loop's A-stream rate, to be set
+ * against the HBM roofline.  Returns a negative value for a NULL server. */
+double tvcs_server_a_bytes(tvcs_server_handle s);
+
 /* Release the server (not the registered handles).  NULL is ignored. */
 void tvcs_server_destroy(tvcs_server_handle s);
 

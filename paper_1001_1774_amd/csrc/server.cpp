@@ -75,6 +75,7 @@ struct tvcs_server {
     long long next_id = 0;
     int starving = -1;       // group waiting for memory (first in line), or -1
     int starve_rounds = 0;
+    double a_bytes = 0.0;    // bytes of A the launched replays stream (two products per iteration)
 
     ~tvcs_server() {
         for (SrvGroup &g : groups) {
@@ -211,6 +212,7 @@ struct tvcs_server {
     void launch(int gi) {
         SrvGroup &g = groups[gi];
         TVCS_HIP(hipGraphLaunch(g.h->exec, g.h->work));
+        a_bytes += 2.0 * kGraphIters * (double)g.h->a_copy_bytes();
         TVCS_HIP(hipMemcpyAsync(g.h->host_state, g.h->state.p, sizeof(ImgState) * slots,
                                 hipMemcpyDeviceToHost, g.h->work));
         TVCS_HIP(hipEventRecord(g.done, g.h->work));
@@ -377,6 +379,8 @@ int tvcs_server_result(tvcs_server *s, long long request, float *u, tvcs_stats *
 int tvcs_server_pending(tvcs_server *s) { return s ? s->pending() : TVCS_EINVAL; }
 
 size_t tvcs_server_device_bytes(tvcs_server *s) { return s ? s->counted_bytes() : 0; }
+
+double tvcs_server_a_bytes(tvcs_server *s) { return s ? s->a_bytes : -1.0; }
 
 void tvcs_server_destroy(tvcs_server *s) {
     if (!s) return;

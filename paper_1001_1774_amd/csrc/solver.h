@@ -189,6 +189,15 @@ struct tvcs_ctx {
         return sizeof(float) * (size_t)padded(B) * ((size_t)m + (size_t)N);
     }
 
+    // bytes of A one product streams: one copy of the stored matrix (MFMA storage
+    // keeps A and A^T; a product reads one of them)
+    size_t a_copy_bytes() const {
+        if (dct()) return 0;
+        if (!lowprec()) return A32.bytes;
+        const size_t el = storage == TVCS_A_FP8_ROWSCALE ? 1 : storage == TVCS_A_BF16_SPLIT ? 4 : 2;
+        return el * (size_t)lowp.mp * (size_t)N;
+    }
+
     // device bytes of A's storage and the FFT tables
     size_t storage_bytes() const {
         return A32.bytes + lowp_mem.bytes + selT.bytes + dperm.bytes + dtab.bytes + tw.bytes +

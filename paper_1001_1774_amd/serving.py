@@ -60,6 +60,11 @@ class Server:
     def device_bytes(self):
         return T.tvcs_server_device_bytes(self.s)
 
+    @property
+    def a_bytes(self):
+        """Bytes of A the replays launched so far stream (tvcs_server_a_bytes)."""
+        return T.tvcs_server_a_bytes(self.s)
+
     def close(self):
         if getattr(self, "s", None):
             T.tvcs_server_destroy(self.s)
@@ -96,6 +101,7 @@ def run_arrivals(server: Server, requests, keep_results=False):
     lat = np.zeros(len(requests))
     iters = np.zeros(len(requests), dtype=np.int64)
     results = {} if keep_results else None
+    a0 = server.a_bytes
     t0 = time.perf_counter()
     nxt = 0
     done = 0
@@ -124,7 +130,9 @@ def run_arrivals(server: Server, requests, keep_results=False):
                 results[i] = out
             done += 1
     wall = time.perf_counter() - t0
+    a_gbs = (server.a_bytes - a0) / wall / 1e9
     return dict(count=len(requests), wall_s=wall, rec_per_s=len(requests) / wall,
+                a_stream_gbs=a_gbs,
                 p50_ms=1e3 * float(np.percentile(lat, 50)),
                 p99_ms=1e3 * float(np.percentile(lat, 99)),
                 mean_iters=float(iters.mean()), latencies=lat, results=results)

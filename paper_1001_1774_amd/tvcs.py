@@ -97,6 +97,7 @@ _SIGS = {
                                           ctypes.c_void_p]),
     "tvcs_server_pending": (ctypes.c_int, [ctypes.c_void_p]),
     "tvcs_server_device_bytes": (ctypes.c_size_t, [ctypes.c_void_p]),
+    "tvcs_server_a_bytes": (ctypes.c_double, [ctypes.c_void_p]),
     "tvcs_server_destroy": (None, [ctypes.c_void_p]),
     "tvcs_last_error": (ctypes.c_char_p, []),
 }
@@ -268,6 +269,10 @@ def tvcs_server_pending(s):
 
 def tvcs_server_device_bytes(s):
     return lib().tvcs_server_device_bytes(s)
+
+
+def tvcs_server_a_bytes(s):
+    return lib().tvcs_server_a_bytes(s)
 
 
 def tvcs_server_destroy(s):
