@@ -189,6 +189,26 @@ int tvcs_solve_batch(tvcs_handle h, const float *F, int B, double mu, double bet
                      int maxit, unsigned flags, float *U, double *lambda, tvcs_stats *st);
 
 /*
+ * tvcs_solve_noalloc: tvcs_solve for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  It allocates nothing: no device or pinned memory and no graph.
+ * Its buffers come from one static device array of 16 MiB per GPU, which holds
+ * u, f, r, the A^T r partial sums, the IADM fields, the FFT spectrum and
+ * denominators and the loop state of one image, and it launches the iteration's
+ * kernels one by one.
+ *   Arguments as for tvcs_solve, without lambda; st->fresh_iters is 0.
+ *   Handles: FP32 storage only (TVCS_EUNSUPPORTED otherwise), used on the device
+ *   that was current when the handle was created (TVCS_EINVAL otherwise).
+ *   Sizes: TVCS_EINVAL when the workspace exceeds the 16 MiB array (e.g. n = 128,
+ *   m = 4096 needs 4.6 MB; n = 512 does not fit).
+ * Results are those of tvcs_solve: the same kernels in the same order.  Every call
+ * on one GPU shares that GPU's array: calls that overlap on one GPU (from several
+ * threads or handles) race and must be serialised by the caller.
+ */
+int tvcs_solve_noalloc(tvcs_handle h, const float *f, double mu, double beta, double tol,
+                       int maxit, unsigned flags, float *u, tvcs_stats *st);
+
+/*
  * tvcs_solve_continuation: Algorithm 1 (FTVCS) with continuation in beta, as the
  * paper runs it (Sec. 3.1): one FTVCS run per value of betas[0..nbeta-1] (an
  * increasing sequence, e.g. 2^4, 2^5, 2^6, 2^7), each stage warm-started from the

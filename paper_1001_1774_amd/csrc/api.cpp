@@ -169,6 +169,7 @@ tvcs_ctx *create_impl(const void *A, int a_is_fp64, int m, int n, int storage, v
     h->n = n;
     h->N = n * n;
     h->storage = storage;
+    TVCS_HIP(hipGetDevice(&h->device));
     h->user = static_cast<hipStream_t>(stream);
     TVCS_HIP(hipStreamCreateWithFlags(&h->work, hipStreamNonBlocking));
     TVCS_HIP(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
@@ -240,6 +241,7 @@ tvcs_ctx *create_dct_impl(const int *rows, int m, int n, void *stream) {
     h->n = n;
     h->N = N;
     h->storage = TVCS_A_PARTIAL_DCT;
+    TVCS_HIP(hipGetDevice(&h->device));
     h->user = static_cast<hipStream_t>(stream);
     TVCS_HIP(hipStreamCreateWithFlags(&h->work, hipStreamNonBlocking));
     TVCS_HIP(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));

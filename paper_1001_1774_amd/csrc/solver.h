@@ -53,6 +53,7 @@ using namespace tvcs;
 
 struct tvcs_ctx {
     int m = 0, n = 0, N = 0, storage = TVCS_A_FP32;
+    int device = -1;              // the device current when the handle was created
     hipStream_t user = nullptr;   // caller's stream (may be null)
     hipStream_t work = nullptr;   // internal stream all work and captures run on
     hipEvent_t ev_in = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;

@@ -78,6 +78,9 @@ _SIGS = {
                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_int, ctypes.c_uint, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p]),
+    "tvcs_solve_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                          ctypes.c_uint, ctypes.c_void_p, ctypes.c_void_p]),
     "tvcs_solve_continuation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                                ctypes.c_double, ctypes.c_void_p, ctypes.c_int,
                                                ctypes.c_double, ctypes.c_int, ctypes.c_uint,
@@ -193,6 +196,12 @@ def tvcs_solve(h, f, mu, beta, tol, maxit, flags, u, lam=None, st=None):
     return lib().tvcs_solve(h, _ptr(f, torch.float32), mu, beta, tol, maxit, flags,
                             _ptr(u, torch.float32), _ptr(lam, torch.float64),
                             ctypes.byref(st) if st is not None else None)
+
+
+def tvcs_solve_noalloc(h, f, mu, beta, tol, maxit, flags, u, st=None):
+    return lib().tvcs_solve_noalloc(h, _ptr(f, torch.float32), mu, beta, tol, maxit, flags,
+                                    _ptr(u, torch.float32),
+                                    ctypes.byref(st) if st is not None else None)
 
 
 def tvcs_solve_batch(h, F, B, mu, beta, tol, maxit, flags, U, lam=None, st=None):
