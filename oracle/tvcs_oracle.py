@@ -36,7 +36,7 @@ import numpy as np
 __all__ = [
     "D", "Dt", "project_disc", "shrink", "dtd_eigenvalues", "solve_u", "gradient",
     "lambda_max", "default_tau", "tv", "objective_tv", "huber_objective",
-    "OracleResult", "initial_u", "ftvcs", "ftvcs_continuation", "iadm", "bf16_rne",
+    "OracleResult", "initial_u", "ftvcs", "ftvcs_continuation", "iadm", "iadm_bb", "bf16_rne",
     "PartialDCT", "apply_A", "apply_At", "split_bf16", "fp8_e4m3_values",
     "fp8_e4m3_rne", "fp8_rowscale_quantize", "dequantized_A",
 ]
@@ -360,6 +360,95 @@ def iadm(A, f, n, mu, beta, tau, tol=0.0, maxit=200, u0=None, lam0=None, sign=+1
         if record is not None:
             record(k, u)
     return OracleResult(u=u, iters=iters, rel_change=rel, w=w, lam=lam)
+
+
+def iadm_bb(A, f, n, mu, beta, tau, tol=0.0, maxit=200, inner=4, memory=5, sigma=1e-4,
+            u0=None, record=None) -> OracleResult:
+    """Algorithm 2 with its u-step replaced by `inner` steps of a gradient method with
+    BB step lengths and a non-monotone line search on the u-subproblem of (ALP), the
+    acceleration the concluding remarks (Sec. 4) suggest.
+
+    For fixed w^{k+1} and lambda^k, with q = w^{k+1} - lambda^k / beta, (ALP) in u is
+    Phi(v) = beta/2 ||q - D v||^2 + mu/2 ||A v - f||^2 up to a constant, a convex
+    quadratic with gradient beta D^T (D v - q) + mu A^T (A v - f) and Hessian
+    H = beta D^T D + mu A^T A.  The steps are preconditioned by
+    M = beta D^T D + (mu / tau) I, the matrix of the u-step (eqnorm11) times beta, so
+    the direction p = -M^{-1} grad Phi costs one FFT solve, and the first step with
+    length 1 is exactly the IADM u-step (inner = 1 gives Algorithm 2).  Later
+    lengths are BB step lengths in the M metric: for the previous step
+    s = a p_prev, y = H s (Phi is quadratic), so s^T M s / s^T y =
+    (p_prev^T M p_prev) / (p_prev^T H p_prev).  A length a is accepted when
+    Phi(v + a p) <= max of the last `memory` accepted values + sigma a grad^T p
+    (non-monotone Armijo test of Grippo, Lampariello and Lucidi, SIAM J. Numer.
+    Anal. 23 (1986)), else halved; along the line Phi is the exact quadratic
+    Phi(v) + a grad^T p + a^2/2 p^T H p, with grad^T p = -p^T M p.  The residual is
+    carried as r <- r + a A p, so each inner step costs two products with A (A^T r
+    and A p), as one IADM iteration does.  lambda is then updated by (udlamb) and
+    the stop rule (eq. (stop)) compares consecutive outer iterates.
+    Readings: w-step with the "+" centre as in `iadm`; tau as in `iadm`.
+    Pinned by tests/test_oracle_bb.py: inner = 1 reproduces `iadm`; many inner steps
+    solve the u-subproblem to the dense direct solution; every accepted step meets
+    the non-monotone test; the limit satisfies the dual certificate of (tv).
+    `record(k, u)` is called after every outer iteration; the result's `history`
+    holds, per outer iteration, (A-products, [Phi(v_J) - Phi(v_0) per image], [step
+    lengths of the last image's inner steps]).
+    """
+    A = _as_A(A)
+    f = _as_batch(f)
+    u = initial_u(A, f, n, u0)
+    B = u.shape[0]
+    lam = np.zeros((B, 2, n, n))
+    c = mu / (beta * tau)
+    iters = np.zeros(B, dtype=np.int64)
+    rel = np.full(B, np.inf)
+    active = np.ones(B, dtype=bool)
+    w = np.zeros((B, 2, n, n))
+    hist = []
+    for k in range(maxit):
+        if not active.any():
+            break
+        idx = np.nonzero(active)[0]
+        drops, lengths = [], []
+        for b in idx:
+            ub, lb = u[b], lam[b]
+            wb = shrink(D(ub) + lb / beta, beta)                     # eq. (iadmw)
+            q = wb - lb / beta
+            v = ub.copy()
+            r = apply_A(A, v.reshape(1, -1))[0] - f[b]
+            phis = [0.0]                                             # Phi(v_j) - Phi(v_0)
+            prev = None                                              # (p^T M p, p^T H p)
+            for j in range(inner):
+                grad = beta * Dt(D(v) - q) + mu * apply_At(A, r[None])[0].reshape(n, n)
+                p = solve_u(-grad / beta, c)                         # -M^{-1} grad
+                Dp = D(p)
+                Ap = apply_A(A, p.reshape(1, -1))[0]
+                pMp = beta * np.sum(Dp * Dp) + (mu / tau) * np.sum(p * p)
+                pHp = beta * np.sum(Dp * Dp) + mu * np.sum(Ap * Ap)
+                gp = -pMp
+                a = 1.0 if prev is None else prev[0] / prev[1]
+                ref = max(phis[-memory:])
+                while phis[-1] + a * gp + 0.5 * a * a * pHp > ref + sigma * a * gp:
+                    a *= 0.5
+                v = v + a * p
+                r = r + a * Ap
+                phis.append(phis[-1] + a * gp + 0.5 * a * a * pHp)
+                prev = (pMp, pHp)
+                if b == idx[-1]:
+                    lengths.append(a)
+            drops.append(phis[-1])
+            lam[b] = lb - beta * (wb - D(v))                         # eq. (udlamb)
+            du = np.sqrt(np.sum((v - ub) ** 2))
+            nu = np.sqrt(np.sum(ub ** 2))
+            u[b] = v
+            w[b] = wb
+            iters[b] += 1
+            rel[b] = du / (nu if nu > 0 else 1.0)
+            if tol > 0 and du <= tol * nu:                          # eq. (stop)
+                active[b] = False
+        hist.append((2 * inner * len(idx), drops, lengths))
+        if record is not None:
+            record(k, u)
+    return OracleResult(u=u, iters=iters, rel_change=rel, w=w, lam=lam, history=hist)
 
 
 # ---------------------------------------------------------------------------
