@@ -58,6 +58,20 @@ extern "C" {
  * lambda holds lambda^0 (otherwise lambda^0 = 0).  Used to continue a run, e.g.
  * across the stages of a continuation in beta (Sec. 3.1). */
 #define TVCS_WARM_START 0x8u
+/* IADM (with TVCS_IADM) whose u-step is J inner steps (2 <= J <= 15) on the
+ * u-subproblem of (ALP) instead of one: the acceleration the concluding remarks
+ * (Sec. 4) suggest, a gradient method with Barzilai-Borwein step lengths and a
+ * non-monotone line search.  With q = w^{k+1} - lambda^k / beta fixed, the
+ * subproblem is Phi(v) = beta/2 ||q - D v||^2 + mu/2 ||A v - f||^2; each step goes
+ * along p = -M^{-1} grad Phi (M = beta D^T D + (mu / tau) I, one FFT solve), the
+ * first with length 1 (the IADM step), later ones with the BB length
+ * p'M p / p'H p of the previous direction (H = beta D^T D + mu A^T A), halved until
+ * Phi(v + a p) <= max of the last 5 accepted values + 1e-4 a grad'p (Phi along the
+ * line is an exact quadratic).  Each inner step costs two products with A (A^T r
+ * and A p; r is carried).  The stop rule compares outer iterates; stats.iters
+ * counts outer iterations.  FP32 storage of A only (TVCS_EUNSUPPORTED otherwise). */
+#define TVCS_BB_SHIFT 8
+#define TVCS_BB_STEPS(J) (((unsigned)(J) & 0xFu) << TVCS_BB_SHIFT)
 
 /* ---- storage of A on the device ------------------------------------------ */
 /* A is first rounded to FP32 (nearest-even), then to the storage format.    */

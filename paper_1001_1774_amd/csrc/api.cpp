@@ -42,11 +42,16 @@ int solve_impl(tvcs_ctx *h, const float *Fin, int B, double mu, double beta, dou
         fail(TVCS_EINVAL, "mu and beta must be positive and finite");
     if (!(tol >= 0) || !std::isfinite(tol)) fail(TVCS_EINVAL, "tol must be >= 0");
     if (maxit < 1) fail(TVCS_EINVAL, "maxit must be >= 1");
-    if (flags & ~(TVCS_IADM | TVCS_U0_ZERO | TVCS_OBJECTIVE | TVCS_WARM_START))
+    if (flags & ~(TVCS_IADM | TVCS_U0_ZERO | TVCS_OBJECTIVE | TVCS_WARM_START | TVCS_BB_STEPS(15)))
         fail(TVCS_EINVAL, "unknown flag bits");
     if ((flags & TVCS_U0_ZERO) && (flags & TVCS_WARM_START))
         fail(TVCS_EINVAL, "TVCS_U0_ZERO and TVCS_WARM_START exclude each other");
     const bool iadm = (flags & TVCS_IADM) != 0;
+    if (bb_inner(flags) > 1) {
+        if (!iadm) fail(TVCS_EINVAL, "inner steps on the u-subproblem need TVCS_IADM");
+        if (h->storage != TVCS_A_FP32)
+            fail(TVCS_EUNSUPPORTED, "inner steps on the u-subproblem take FP32 storage of A");
+    }
 
     h->begin_call();
     h->ensure_workspace(B);
@@ -79,7 +84,7 @@ int solve_impl(tvcs_ctx *h, const float *Fin, int B, double mu, double beta, dou
     if (iadm) launch_init_q(h->n, B, U, lam0, beta, h->Q0.as<float2>(), h->work);
     h->seed_dct_rows(B);
 
-    h->build_graph(B, flags & TVCS_IADM, beta, c, ctau);
+    h->build_graph(B, flags & (TVCS_IADM | TVCS_BB_STEPS(15)), beta, c, ctau);
     const int launches = (maxit + kGraphIters - 1) / kGraphIters;
     if (tol > 0) {
         // The state after launch i is copied into one half of the pinned mirror and

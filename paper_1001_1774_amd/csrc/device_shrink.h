@@ -115,9 +115,10 @@ __device__ inline double finish_pix(const ShrinkArgs &a, int b, int p, const Pix
     const D2 dW = {u0 - in.uW, (double)in.uSW - in.uW};                  // D u at (r, c-1)
     const D2 dN = {(double)in.uNE - in.uN, u0 - in.uN};                  // D u at (r-1, c)
     const double ib = 1.0 / a.beta;
-    const D2 q0 = q_of<IADM>(d0, in.o0, ib), qW = q_of<IADM>(dW, in.oW, ib),
-             qN = q_of<IADM>(dN, in.oN, ib);
-    if (IADM) {
+    const bool fz = IADM && a.frozen;   // q held fixed: the given field itself
+    const D2 q0 = fz ? in.o0 : q_of<IADM>(d0, in.o0, ib), qW = fz ? in.oW : q_of<IADM>(dW, in.oW, ib),
+             qN = fz ? in.oN : q_of<IADM>(dN, in.oN, ib);
+    if (IADM && !fz) {
         const int N = a.n * a.n;
         a.Qnew[(size_t)b * N + p] = make_float2((float)q0.x, (float)q0.y);
     }

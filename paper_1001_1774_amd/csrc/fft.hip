@@ -255,8 +255,8 @@ __global__ __launch_bounds__(kThreads) void k_shrink_walk(ShrinkArgs a, int rpb,
             const int p = ring.mul(r) + c[j];
             const shrinkdev::D2 d = {(double)uE[j] - ucur[j], (double)uS[j] - ucur[j]};
             const shrinkdev::D2 o = {(double)qo[j].x, (double)qo[j].y};
-            const shrinkdev::D2 q = shrinkdev::q_of<IADM>(d, o, ib);
-            if (IADM && s > 0) qnew[p] = make_float2((float)q.x, (float)q.y);
+            const shrinkdev::D2 q = (IADM && a.frozen) ? o : shrinkdev::q_of<IADM>(d, o, ib);
+            if (IADM && s > 0 && !a.frozen) qnew[p] = make_float2((float)q.x, (float)q.y);
             zxv[j] = q.x - d.x;
             zyv[j] = q.y - d.y;
             ucur[j] = uS[j];
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
                                                        int *__restrict__ counters,
                                                        float *__restrict__ T,
                                                        const float4 *__restrict__ dtab,
-                                                       int parity) {
+                                                       int parity, float *__restrict__ dir) {
     const int b = blockIdx.y;
     if (!st[b].active) return;
     extern __shared__ float2 lds[];
@@ -366,7 +366,17 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
     float *Wf = reinterpret_cast<float *>(W);
     float *dstU = U + (size_t)b * n * n + (size_t)row0 * n;
     double du2 = 0.0, u2 = 0.0;
-    for (int e = threadIdx.x; e < npair * n; e += kThreads) {
+    if (dir) {   // the increment is a search direction: stored apart, with its squared norm
+        float *dstD = dir + (size_t)b * n * n + (size_t)row0 * n;
+        for (int e = threadIdx.x; e < npair * n; e += kThreads) {
+            const int pr = ring.div(e), j = e - ring.mul(pr);
+            const float2 v = z[lp(e)];
+            dstD[(2 * pr) * n + j] = v.x;
+            dstD[(2 * pr + 1) * n + j] = v.y;
+            du2 += (double)v.x * v.x + (double)v.y * v.y;
+        }
+    }
+    for (int e = threadIdx.x; !dir && e < npair * n; e += kThreads) {
         const int pr = ring.div(e), j = e - ring.mul(pr);
         const float2 v = z[lp(e)];
         float *p0 = dstU + (2 * pr) * n + j, *p1 = p0 + n;
@@ -506,13 +516,13 @@ int stop_parts(int n, int B) { return n / rows_per_block(n, B); }
 
 void launch_fft_rows_inv(int n, int B, const float2 *S, float *U, double *parts,
                          const float2 *tw, ImgState *st, int *counters, hipStream_t s, float *T,
-                         const float4 *dtab, bool stop_pass, int parity) {
+                         const float4 *dtab, bool stop_pass, int parity, float *dir) {
     const int rpb = rows_per_block(n, B);
     const size_t lds = sizeof(float2) * (kMaxN + 2 * lp_size((rpb / 2) * n + rpb)) +
                        (T ? sizeof(float4) * n : 0);
 #define TVCS_ROWS_INV(FUSEDV, P2V)                                                            \
     hipLaunchKernelGGL((k_rows_inv<FUSEDV, P2V>), dim3(n / rpb, B), dim3(kThreads), lds, s, n, rpb, \
-                       S, U, parts, tw, st, counters, T, dtab, parity)
+                       S, U, parts, tw, st, counters, T, dtab, parity, dir)
     const bool p2 = is_pow2(n);
     if (TVCS_FUSED_STOP && B == 1 && stop_pass) {
         if (p2) TVCS_ROWS_INV(true, true);

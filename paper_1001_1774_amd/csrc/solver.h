@@ -45,6 +45,11 @@ constexpr int kGraphIters = 10;   // iterations per captured graph (even: q ping
 #define TVCS_FOLD_STOP 1          // stop rule folded into the next A u pass (one image FP32; DCT, MFMA)
 #endif
 constexpr int kPowerIters = 100;
+// inner steps on the u-subproblem requested by the solve flags (1: the IADM u-step)
+inline int bb_inner(unsigned flags) {
+    const int j = (int)((flags >> TVCS_BB_SHIFT) & 0xFu);
+    return j > 1 ? j : 1;
+}
 constexpr double kPowerRtol = 1e-10;
 
 }  // namespace tvcs
@@ -74,6 +79,7 @@ struct tvcs_ctx {
     DevBuf U, F, R, P, RHS, Q0, Q1, S, parts, state, obj, lowp_work, lamb, counters;
     DevBuf Gacc;           // MFMA storage: the running g of the product increments (B x N)
     DevBuf adm_F, adm_U;   // request loop: f and A^T f of newly admitted slots (capP rows)
+    DevBuf bb_Uk, bb_P, bb_AP, bb_parts, bb_state;   // IADM with inner BB steps
     DevBuf DT;             // partial DCT: the half-transformed images between passes
     LowpWork lw{};
     ImgState *host_state = nullptr;   // pinned mirror for polling: two halves of cap images
@@ -223,7 +229,8 @@ struct tvcs_ctx {
             exec = nullptr;
         }
         for (DevBuf *b : {&U, &F, &R, &P, &RHS, &Q0, &Q1, &S, &parts, &state, &obj, &lowp_work, &lamb,
-                          &counters, &DT, &Gacc, &adm_F, &adm_U})
+                          &counters, &DT, &Gacc, &adm_F, &adm_U, &bb_Uk, &bb_P, &bb_AP, &bb_parts,
+                          &bb_state})
             b->release();
         cap = capP = 0;
     }
@@ -392,6 +399,56 @@ struct tvcs_ctx {
                             dct() ? dtab.as<float4>() : nullptr, stop_here, parity);
     }
 
+    // buffers of IADM with inner steps for a batch of B (FP32 storage)
+    void ensure_bb(int B) {
+        const int Bp = padded(B);
+        const size_t Nn = (size_t)N;
+        bb_Uk.ensure(sizeof(float) * B * Nn);
+        if (bb_P.bytes < sizeof(float) * Bp * Nn) {
+            bb_P.ensure(sizeof(float) * Bp * Nn);
+            launch_fill(bb_P.as<float>(), (size_t)Bp * Nn, 0.f, work);   // padded rows stay 0
+        }
+        bb_AP.ensure(sizeof(float) * Bp * (size_t)m);
+        bb_parts.ensure(sizeof(double) * 3 * B * (size_t)bb_blocks(n));
+        bb_state.ensure(sizeof(BBState) * B);
+    }
+
+    // One outer iteration of IADM whose u-step is `inner` steps on the u-subproblem
+    // of (ALP) (bb.hip): r = A u - f, then per inner step A^T r, the direction p (shrink
+    // pass with q held fixed after the first step, FFT solve into bb_P), A p, the step
+    // length and v += a p, r += a A p; the stop rule compares u with the u saved first.
+    void enqueue_iteration_bb(int B, int parity, int inner, double mu, double beta, double c,
+                              double ctau, double tau) {
+        const int Bp = padded(B);
+        ImgState *st = state.as<ImgState>();
+        float *Up = U.as<float>(), *Pd = bb_P.as<float>(), *AP = bb_AP.as<float>();
+        launch_copy(Up, bb_Uk.as<float>(), (size_t)B * N, work);
+        apply_A(Bp, B, Up, F.as<float>(), R.as<float>(), st);
+        const float2 *twp = tw.as<float2>();
+        float2 *Sp = S.as<float2>();
+        for (int j = 0; j < inner; ++j) {
+            apply_At(Bp, B, R.as<float>(), st);
+            ShrinkArgs a = shrink_args(B, Bp);
+            a.beta = beta;
+            a.c = c;
+            a.ctau = ctau;
+            a.parity = parity;
+            // the first step computes q^k from q^{k-1} into Qnew; later ones read it
+            a.Qnew = parity ? Q0.as<float2>() : Q1.as<float2>();
+            a.Qold = j == 0 ? (parity ? Q1.as<float2>() : Q0.as<float2>()) : a.Qnew;
+            a.frozen = j > 0;
+            launch_shrink_rows(a, true, Sp, twp, work);
+            launch_fft_cols_solve(n, B, Sp, invd.as<double>(), twp, st, work);
+            launch_fft_rows_inv(n, B, Sp, Up, parts.as<double>(), twp, st, counters.as<int>(), work,
+                                nullptr, nullptr, false, parity, Pd);
+            apply_A(Bp, B, Pd, nullptr, AP, st);
+            launch_bb_step(n, m, B, Pd, AP, m, bb_parts.as<double>(), bb_state.as<BBState>(), st, j,
+                           beta, mu, tau, kBBSigma, work);
+            launch_bb_update(B, N, m, Up, Pd, R.as<float>(), AP, m, bb_state.as<BBState>(), st, work);
+        }
+        launch_bb_stop(n, B, Up, bb_Uk.as<float>(), bb_parts.as<double>(), st, parity, work);
+    }
+
     void build_graph(int B, unsigned flags, double beta, double c, double ctau) {
         if (exec && g_B == B && g_flags == flags && g_beta == beta && g_c == c && g_ctau == ctau)
             return;
@@ -400,12 +457,19 @@ struct tvcs_ctx {
             exec = nullptr;
         }
         hipGraph_t graph = nullptr;
+        const int inner = bb_inner(flags);
+        if (inner > 1) ensure_bb(B);
         TVCS_HIP(hipStreamBeginCapture(work, hipStreamCaptureModeRelaxed));
         try {
             const bool fold = fold_stop(B);
-            for (int i = 0; i < kGraphIters; ++i)
-                enqueue_iteration(B, i & 1, (flags & TVCS_IADM) != 0, beta, c, ctau,
-                                  fold && i > 0, !fold || i == kGraphIters - 1);
+            for (int i = 0; i < kGraphIters; ++i) {
+                if (inner > 1)
+                    enqueue_iteration_bb(B, i & 1, inner, ctau * beta, beta, c, ctau,
+                                         ctau * beta / (beta * c));
+                else
+                    enqueue_iteration(B, i & 1, (flags & TVCS_IADM) != 0, beta, c, ctau,
+                                      fold && i > 0, !fold || i == kGraphIters - 1);
+            }
         } catch (...) {
             (void)hipStreamEndCapture(work, &graph);
             if (graph) (void)hipGraphDestroy(graph);
@@ -464,7 +528,8 @@ struct tvcs_ctx {
                tw.bytes + invd.bytes + U.bytes + F.bytes + R.bytes +
                P.bytes + RHS.bytes + Q0.bytes + Q1.bytes + S.bytes + parts.bytes + state.bytes +
                obj.bytes + lowp_work.bytes + lamb.bytes + counters.bytes + Gacc.bytes + adm_F.bytes +
-               adm_U.bytes;
+               adm_U.bytes + bb_Uk.bytes + bb_P.bytes + bb_AP.bytes + bb_parts.bytes +
+               bb_state.bytes;
     }
 };
 

@@ -126,6 +126,9 @@ struct ShrinkArgs {
     // the partials to it, fresh ones replace it; null: g is the partials' sum alone
     float *Gacc;
     int parity;            // iteration parity (selects ImgState::mode)
+    // IADM with inner steps on the u-subproblem: q = w^{k+1} - lambda^k / beta is
+    // held fixed (read from Qold, nothing written) after the first inner step
+    int frozen;
     // partial DCT: g is the inverse row DCT of T (the column pass's output,
     // column-major per image), computed in the pass; G is then unused
     const float *T;
@@ -159,14 +162,43 @@ void launch_fft_cols_solve(int n, int B, float2 *S, const double *inv_d, const f
 // stop_pass = false: no k_stop_rule after the pass (the caller applies the rule
 // later, e.g. folded into the next A u product); stop_parts(n, B) partials per image.
 // parity: the iteration's parity (the stop rule sets ImgState::mode[parity]; < 0: not)
+// dir: the increment is a search direction (IADM with inner steps): written to dir
+// (B x N) instead of added to U, parts receive (sum of its squares, 0) per block; use
+// with stop_pass = false and T null
 void launch_fft_rows_inv(int n, int B, const float2 *S, float *U, double *parts,
                          const float2 *tw, ImgState *st, int *counters, hipStream_t s,
                          float *T = nullptr, const float4 *dtab = nullptr,
-                         bool stop_pass = true, int parity = -1);
+                         bool stop_pass = true, int parity = -1, float *dir = nullptr);
 int stop_parts(int n, int B);
 // shrinkage + right-hand side fused with the forward row FFT
 void launch_shrink_rows(const ShrinkArgs &a, bool iadm, float2 *S, const float2 *tw,
                         hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// IADM with inner BB / non-monotone line-search steps on its u-subproblem (bb.hip)
+// ---------------------------------------------------------------------------
+constexpr int kBBMemory = 5;          // accepted values the non-monotone test looks back over
+constexpr double kBBSigma = 1e-4;     // sufficient-decrease constant of that test
+struct BBState {                      // per image, rewritten at the first inner step
+    double phis[kBBMemory];           // the last accepted Phi(v) - Phi(v_0), circular
+    double phi;                       // Phi(v) - Phi(v_0) at the current inner iterate
+    double prev_pMp, prev_pHp;        // p'M p and p'H p of the previous direction
+    double alpha;                     // the step length of the current inner step
+    int nphi, pad_;
+};
+int bb_blocks(int n);                 // partial sums per image of the BB reductions
+// k_bb_partials + k_bb_step: squared norms of p, D p, A p; the step length of inner
+// step j into bs (parts: B x bb_blocks(n) x 3 doubles)
+void launch_bb_step(int n, int m, int B, const float *P, const float *AP, int ldap, double *parts,
+                    BBState *bs, const ImgState *st, int j, double beta, double mu, double tau,
+                    double sigma, hipStream_t s);
+// U += a P (B x N) and R += a AP (B x m, row stride ldr), a per image from bs
+void launch_bb_update(int B, int N, int m, float *U, const float *P, float *R, const float *AP,
+                      int ldr, const BBState *bs, const ImgState *st, hipStream_t s);
+// the stop rule for the outer step from Uk to U (parts: B x bb_blocks(n) x 2 doubles)
+void launch_bb_stop(int n, int B, const float *U, const float *Uk, double *parts, ImgState *st,
+                    int parity, hipStream_t s);
+void launch_copy(const float *src, float *dst, size_t count, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // MFMA products for bf16 / split-bf16 / fp8 storage (gemm.hip)

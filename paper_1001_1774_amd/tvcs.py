@@ -33,6 +33,12 @@ TVCS_IADM = 0x1
 TVCS_U0_ZERO = 0x2
 TVCS_OBJECTIVE = 0x4
 TVCS_WARM_START = 0x8
+TVCS_BB_SHIFT = 8
+
+
+def TVCS_BB_STEPS(j):
+    """Solve flag: IADM with j inner BB / line-search steps on its u-subproblem."""
+    return (int(j) & 0xF) << TVCS_BB_SHIFT
 
 TVCS_A_FP32 = 0
 TVCS_A_BF16 = 1
@@ -362,13 +368,13 @@ class Solver:
         return t.contiguous()
 
     def solve_batch(self, F, mu=1e3, beta=10.0, tol=0.0, maxit=500, iadm=False, objective=False,
-                    u0=None, lam0=None, want_lambda=False, u0_zero=False):
+                    u0=None, lam0=None, want_lambda=False, u0_zero=False, bb_steps=1):
         F = self._as_dev(F, torch.float32)
         if F.dim() == 1:
             F = F[None]
         B = F.shape[0]
         flags = (TVCS_IADM if iadm else 0) | (TVCS_OBJECTIVE if objective else 0) | \
-            (TVCS_U0_ZERO if u0_zero else 0)
+            (TVCS_U0_ZERO if u0_zero else 0) | (TVCS_BB_STEPS(bb_steps) if bb_steps > 1 else 0)
         if u0 is not None:
             U = self._as_dev(u0, torch.float32).reshape(B, self.N).clone()
             flags |= TVCS_WARM_START

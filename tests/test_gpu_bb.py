@@ -1,0 +1,121 @@
+"""GPU parity of IADM with inner BB / non-monotone line-search steps on its
+u-subproblem (TVCS_BB_STEPS, the acceleration of the concluding remarks, Sec. 4)
+against the oracle's iadm_bb (FP32 storage); batch invariance; the flag's limits.
+
+BB iterations amplify rounding: in the FP64 oracle itself a relative perturbation
+of 1e-7 in f grows to about 1e-2 in u after 30 to 60 outer iterations (n = 32,
+J = 3: 1e-7 up to 20 iterations, 3e-4 at 22, 2e-2 at 30; C2: 2e-6 at 18, 1e-2 at
+33), because long BB lengths (up to a few hundred) multiply the error of the
+direction and the halvings of the line search switch on small differences.  The
+bars below come from a rounding model of the FP32 path: the oracle's iteration
+with every product, FFT solve and stored vector given a relative error of 1e-7
+(FP32 storage and sums), four seeds; the bar is about three times the largest
+model error, and 1e-5 (the FP32 bar of the plain iterations) where that is
+smaller.  The counts include steps with halvings (n = 32, J = 8: outer iterations
+4 and 5).  Longer runs are compared where the method goes: to the same fixed
+point, at a rate like the oracle's."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1001_1774_amd import synth
+from tests._parity import check
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    from paper_1001_1774_amd import tvcs
+    tvcs.lib()
+    return tvcs
+
+
+# (workload, inner steps J, outer iterations K, bar): model error max over 4 seeds
+# 5.7e-7 (J = 8, K = 3), 7.8e-7 (C2, K = 4), 1.2e-5 (J = 8, K = 5), 2.6e-5 (J = 3,
+# K = 15)
+CASES = [("n32_m307", 8, 3, 1e-5), ("n128_m4096", 3, 4, 1e-5), ("n32_m307", 8, 5, 5e-5),
+         ("n32_m307", 3, 15, 1e-4)]
+
+
+@pytest.mark.parametrize("name,J,K,bar", CASES)
+def test_bb_parity(T, name, J, K, bar):
+    p = synth.workload(name)
+    tau = O.default_tau(p.A)
+    say(f"case {name} J={J} K={K}")
+    ref = O.iadm_bb(p.A, p.f[:1], p.n, p.mu, p.beta, tau, tol=0, maxit=K, inner=J)
+    with T.Solver(p.A.astype(np.float32), p.n) as s:
+        s.tau = tau
+        out = s.solve(p.f[0].astype(np.float32), mu=p.mu, beta=p.beta, maxit=K, iadm=True,
+                      bb_steps=J, want_lambda=True)
+    assert out["stats"]["iters"] == K
+    check(out["u"].cpu().numpy(), ref.u[0], bar, "u", say)
+    lam = out["lam"].cpu().numpy()
+    el = float(np.linalg.norm(lam - ref.lam[0]) / np.linalg.norm(ref.lam[0]))
+    say(f"  lambda rel err {el:.3e}")
+    assert el <= 10 * bar   # beta (D u - q): a difference of close fields
+
+
+def test_bb_batch_equals_single_and_stop_rule(T):
+    p = synth.make_problem("bbb", n=32, m=307, batch=3, seed_A=31, sigma=[1e-3, 1e-2, 1e-3])
+    tau = O.default_tau(p.A)
+    F = p.f.astype(np.float32)
+    with T.Solver(p.A.astype(np.float32), p.n) as s:
+        s.tau = tau
+        rb = s.solve_batch(F, mu=p.mu, beta=p.beta, tol=1e-3, maxit=300, iadm=True, bb_steps=3)
+        for b in range(3):
+            r1 = s.solve(F[b], mu=p.mu, beta=p.beta, tol=1e-3, maxit=300, iadm=True, bb_steps=3)
+            assert r1["stats"]["iters"] == rb["stats"][b]["iters"]
+            assert np.array_equal(r1["u"].cpu().numpy(), rb["u"][b].cpu().numpy())
+    ref = O.iadm_bb(p.A, p.f, p.n, p.mu, p.beta, tau, tol=1e-3, maxit=300, inner=3)
+    it = np.array([st["iters"] for st in rb["stats"]])
+    say(f"  outer iterations gpu {it.tolist()} oracle {ref.iters.tolist()}")
+    assert np.all(np.abs(it - ref.iters) <= np.maximum(2, 0.25 * ref.iters))
+
+
+def test_bb_reaches_the_oracle_fixed_point(T):
+    """n = 32, J = 3, stop at a relative change of 1e-6: the oracle stops after about
+    550 outer iterations at 2.7e-4 from its own limit (6000 iterations, change
+    1.6e-9); the GPU run stops at a similar count, as close to that limit."""
+    p = synth.workload("n32_m307")
+    tau = O.default_tau(p.A)
+    star = O.iadm_bb(p.A, p.f[:1], p.n, p.mu, p.beta, tau, tol=1e-9, maxit=6000, inner=3)
+    ref = O.iadm_bb(p.A, p.f[:1], p.n, p.mu, p.beta, tau, tol=1e-6, maxit=3000, inner=3)
+    with T.Solver(p.A.astype(np.float32), p.n) as s:
+        s.tau = tau
+        out = s.solve(p.f[0].astype(np.float32), mu=p.mu, beta=p.beta, tol=1e-6, maxit=3000,
+                      iadm=True, bb_steps=3)
+    u = out["u"].cpu().numpy().astype(np.float64)
+    dg = float(np.linalg.norm(u - star.u[0]) / np.linalg.norm(star.u[0]))
+    do = float(np.linalg.norm(ref.u[0] - star.u[0]) / np.linalg.norm(star.u[0]))
+    it = out["stats"]["iters"]
+    say(f"  distance to the limit: gpu {dg:.2e} after {it}, oracle {do:.2e} after {ref.iters[0]}")
+    assert it < 3000
+    assert 0.6 * ref.iters[0] <= it <= 1.6 * ref.iters[0]
+    assert dg <= max(3 * do, 1e-5)
+
+
+def test_bb_flag_limits(T):
+    import torch
+    p = synth.workload("n32_m307")
+    f = torch.from_numpy(p.f[0].astype(np.float32)).cuda()
+    with T.Solver(p.A.astype(np.float32), p.n) as s:
+        with pytest.raises(T.TvcsError) as ei:
+            s.solve(f, mu=p.mu, beta=p.beta, maxit=5, iadm=False, bb_steps=3)
+        assert ei.value.code == T.TVCS_EINVAL
+        one = s.solve(f, mu=p.mu, beta=p.beta, maxit=20, iadm=True, bb_steps=1)["u"]
+        plain = s.solve(f, mu=p.mu, beta=p.beta, maxit=20, iadm=True)["u"]
+        assert np.array_equal(one.cpu().numpy(), plain.cpu().numpy())
+    with T.Solver(p.A.astype(np.float32), p.n, storage="bf16") as s:
+        with pytest.raises(T.TvcsError) as ei:
+            s.solve(f, mu=p.mu, beta=p.beta, maxit=5, iadm=True, bb_steps=3)
+        assert ei.value.code == T.TVCS_EUNSUPPORTED
