@@ -80,6 +80,8 @@ def main():
                     help="skip the n = 512, m = 26214, B = 128 section (FP8 vs BF16 storage)")
     ap.add_argument("--large-iters", type=int, default=300)
     ap.add_argument("--no-dct", action="store_true", help="skip the partial-DCT section")
+    ap.add_argument("--no-bb", action="store_true",
+                    help="skip the n = 128 section of IADM with inner BB steps")
     # profiler modes: run one piece of the path and print one JSON line (no benchmark)
     ap.add_argument("--products", choices=sorted(PRODUCT_WORKLOADS), default=None,
                     help="only launch the two products of this workload `--reps` times each "
@@ -213,6 +215,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if not args.no_bb:
+        out["bb_n128"] = bench_bb(np, torch, p, tau, solver)
     solver.close()
     del solver
     if not args.no_batched:
@@ -283,7 +287,9 @@ def profile_mode(args):
     p = synth.workload(args.products, batch=1, dtype=np.float32)
     with tvcs.Solver(p.A, p.n, storage=args.storage) as s:
         fwd, adj = s.time_products(args.batch, args.reps, increment=args.form == "increment")
+        tiles = s.tiles
     print(json.dumps({"workload": args.products, "storage": args.storage, "batch": args.batch,
+                      "tiles": tiles,
                       "form": args.form, "reps": args.reps, "forward_ms": fwd,
                       "adjoint_ms": adj, "copy_bytes": COPY_BYTES}), flush=True)
 
@@ -370,6 +376,7 @@ def bench_batched(args, np, torch, O, synth, tvcs):
             dt = time.perf_counter() - t0
             ms_f, ms_a = s.time_products(B=p.B, reps=10)
             mi_f, mi_a = s.time_products(B=p.B, reps=10, increment=True)
+            tiles = s.tiles
         U = out["u"].cpu().numpy().astype(np.float64)
         errs = {}
         for j, b in enumerate(sample):
@@ -386,6 +393,7 @@ def bench_batched(args, np, torch, O, synth, tvcs):
             "fresh_iteration_fraction": fresh_fraction(out["stats"]),
             "fresh": product_rates(storage, p.m, p.N, p.B, ms_f, ms_a),
             "increment": product_rates(storage, p.m, p.N, p.B, mi_f, mi_a, increment=True),
+            "tiles_autotuned": tiles,
         }
         log(f"{storage} B=64: {1e3 * dt / K:.3f} ms/iter, errors {[round(e['rel_err'], 8) for e in errs.values()]}")
     # FP64 oracle on the whole batch (the host's batched baseline), bounded iterations
@@ -407,6 +415,7 @@ def bench_batched(args, np, torch, O, synth, tvcs):
         for Bs in (64, 128, 256):
             ms_f, ms_a = s.time_products(B=Bs, reps=5, increment=True)
             r = product_rates("bf16", p.m, p.N, Bs, ms_f, ms_a, increment=True)
+            r["tiles_autotuned"] = s.tiles
             ai = 2.0 * Bs / 2.0                           # useful flops per A byte
             bound = min(MFMA_BF16_PEAK, ai * HBM_PEAK_GBS * 1e9)
             r["roofline_bound_tflops"] = bound / 1e12
@@ -527,7 +536,9 @@ def bench_large(args, np, torch, O, synth, tvcs):
             Uc = chk.cpu().numpy()[sample].astype(np.float64)
             ms_f, ms_a = s.time_products(B=p.B, reps=5)
             mi_f, mi_a = s.time_products(B=p.B, reps=5, increment=True)
+            tiles = s.tiles
         res[storage] = {"rec_per_s": p.B / dt, "ms_per_iter": 1e3 * dt / K,
+                        "tiles_autotuned": tiles,
                         "fresh_iteration_fraction": fresh_fraction(out["stats"]),
                         "fresh": product_rates(storage, p.m, p.N, p.B, ms_f, ms_a),
                         "increment": product_rates(storage, p.m, p.N, p.B, mi_f, mi_a,
@@ -564,6 +575,41 @@ def bench_large(args, np, torch, O, synth, tvcs):
     del A64
     res["fp8_vs_bf16_speedup"] = res["fp8_rowscale"]["rec_per_s"] / res["bf16"]["rec_per_s"]
     return res
+
+
+def bench_bb(np, torch, p, tau, solver, J=3):
+    """IADM against IADM with J inner BB / line-search steps on the u-subproblem, on
+    the n = 128, m = 4096 FP32 problem: the distance to the limit of the iteration
+    (BB for 4000 outer iterations, 24000 products) after a given number of products
+    with A, and the time to get there."""
+    f = p.f[0].astype(np.float32)
+
+    def run(maxit, bb):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = solver.solve(f, mu=p.mu, beta=p.beta, maxit=maxit, iadm=True, bb_steps=bb)
+        torch.cuda.synchronize()
+        return r["u"].cpu().numpy().astype(np.float64), 1e3 * (time.perf_counter() - t0)
+
+    run(10, J)
+    ref, ms_ref = run(4000, J)
+    nr = np.linalg.norm(ref)
+    rows = []
+    for bb, ks in ((1, (500, 1500, 3000)), (J, (100, 200, 300, 400, 530, 700, 1000))):
+        for k in ks:
+            u, ms = run(k, bb)
+            rows.append({"method": "iadm" if bb == 1 else f"iadm_bb{J}", "outer_iters": k,
+                         "a_products": 2 * k * bb, "ms": ms,
+                         "rel_err_vs_limit": float(np.linalg.norm(u - ref) / nr)})
+            log(f"bb section: {rows[-1]}")
+    out = {"limit": f"IADM with {J} BB steps, 4000 outer iterations ({ms_ref:.0f} ms)",
+           "runs": rows}
+    for thr in (1e-2, 1e-3, 1e-4):
+        for meth in ("iadm", f"iadm_bb{J}"):
+            hit = [r for r in rows if r["method"] == meth and r["rel_err_vs_limit"] <= thr]
+            out[f"{meth}_to_{thr:g}"] = ({"a_products": hit[0]["a_products"], "ms": hit[0]["ms"]}
+                                        if hit else None)
+    return out
 
 
 def dct_product_bytes(n, m, B):

@@ -107,6 +107,11 @@ typedef struct {
                            products were computed afresh from a two-part batch
                            operand; the others added the one-part increment form
                            (see TVCS_A_BF16); 0 for FP32 and the partial DCT     */
+    int    tiles[6];    /* bf16, split bf16 and FP8 storage: the tile shapes of the
+                           two MFMA products, {rows of A per wave / 16, images per
+                           group, 32-wide k tiles per pipeline step} of the forward
+                           product (A u), then of the adjoint (A^T r); zeros
+                           otherwise (see tvcs_set_tiles)                        */
 } tvcs_stats;
 
 /*
@@ -242,6 +247,31 @@ int tvcs_solve_noalloc(tvcs_handle h, const float *f, double mu, double beta, do
 int tvcs_solve_continuation(tvcs_handle h, const float *F, int B, double mu,
                             const double *betas, int nbeta, double tol, int maxit,
                             unsigned flags, float *U, tvcs_stats *st);
+
+/*
+ * tvcs_set_tiles / tvcs_get_tiles: tile shapes of the MFMA products (bf16, split
+ * bf16 and FP8 storage).  By default an autotuner picks each product's shape when a
+ * workspace is set up for a batch (the first solve of a larger batch, a request
+ * loop's slots): it times every candidate on the handle's matrix and padded batch
+ * and keeps the fastest.  Candidates: 2 or 4 sixteen-row tiles of A per wave;
+ * groups of the whole padded batch (at most 256 images, A streamed once per group),
+ * half or a quarter of it; and two tables of k tiles per pipeline step.  No shape
+ * changes the order of any sum, so every shape gives the same bits; a forced shape
+ * changes only the speed.  The shapes apply to solves, the request loop and
+ * tvcs_time_products.
+ *   tiles   six ints as in tvcs_stats.tiles: {rt, images, kf} of the forward product,
+ *           then of the adjoint, used from the next call on; NULL: autotune again
+ *           (now if a workspace exists, else at its set-up).  rt is 2 or 4 (2 with
+ *           256 images); images 16, 32, 64, 128 or 256 (batches that are not a
+ *           multiple end with smaller groups); kf is that group size's entry in one
+ *           of the two tables ({4, 4, 4, 1, 1} and {4, 2, 1, 2, 1} for 16 .. 256
+ *           images).
+ * Returns TVCS_OK, TVCS_EINVAL for a shape that does not exist, TVCS_EUNSUPPORTED
+ * for FP32 storage and the partial DCT.  tvcs_get_tiles writes the shapes in use
+ * (zeros for those formats, and before the first workspace the defaults).
+ */
+int tvcs_set_tiles(tvcs_handle h, const int *tiles);
+int tvcs_get_tiles(tvcs_handle h, int *tiles);
 
 /*
  * tvcs_time_products: measurement helper.  Average device time in milliseconds

@@ -148,6 +148,7 @@ int solve_impl(tvcs_ctx *h, const float *Fin, int B, double mu, double beta, dou
             stats[b].status = s.status;
             stats[b].rel_change = s.rel;
             stats[b].fresh_iters = h->lowprec() ? s.fresh : 0;
+            h->tiles_out(stats[b].tiles);
             stats[b].objective = objv[b];
             stats[b].tau = tau;
             stats[b].ms = ms;
@@ -414,6 +415,54 @@ int tvcs_time_products(tvcs_handle h, int B, int reps, int form, float *ms_forwa
         TVCS_HIP(hipEventElapsedTime(&ms, h->ev_t0, h->ev_t1));
         if (ms_adjoint) *ms_adjoint = ms / reps;
         TVCS_HIP(hipGetLastError());
+        return TVCS_OK;
+    });
+}
+
+int tvcs_set_tiles(tvcs_handle h, const int *tiles) {
+    return guarded([&] {
+        if (!h) fail(TVCS_EINVAL, "null handle");
+        if (!h->lowprec()) fail(TVCS_EUNSUPPORTED, "tile shapes exist for MFMA storage only");
+        TileCfg c[2];
+        if (tiles) {
+            for (int k = 0; k < 2; ++k) {
+                const int rt = tiles[3 * k], img = tiles[3 * k + 1], kf = tiles[3 * k + 2];
+                c[k] = TileCfg{rt, img / 16, -1};
+                if (img % 16 != 0) fail(TVCS_EINVAL, "images per group: 16, 32, 64, 128 or 256");
+                if (img >= 16 && img <= 256)
+                    for (int v = 1; v >= 0; --v)
+                        if (tile_kf(c[k].nt, v) == kf) c[k].kfv = v;
+                if (c[k].kfv < 0 || !tile_valid(c[k]))
+                    fail(TVCS_EINVAL, "no such tile shape (rt 2 or 4, 4 not with 256 images; "
+                                      "k tiles per step from the shape's two tables)");
+            }
+        }
+        h->begin_call();
+        if (h->exec) {   // the captured iterations hold the old shapes
+            TVCS_HIP(hipGraphExecDestroy(h->exec));
+            h->exec = nullptr;
+        }
+        h->tiles_forced = tiles != nullptr;
+        if (tiles) {
+            h->forced_fwd = c[0];
+            h->forced_adj = c[1];
+            if (h->capP) {
+                h->lw.fwd = c[0];
+                h->lw.adj = c[1];
+            }
+        } else if (h->capP) {
+            lowp_autotune(h->lowp, h->lw, h->capP, h->U.as<float>(), h->R.as<float>(),
+                          h->P.as<float>(), h->state.as<ImgState>(), h->work);
+        }
+        TVCS_HIP(hipStreamSynchronize(h->work));
+        return TVCS_OK;
+    });
+}
+
+int tvcs_get_tiles(tvcs_handle h, int *tiles) {
+    return guarded([&] {
+        if (!h || !tiles) fail(TVCS_EINVAL, "null argument");
+        h->tiles_out(tiles);
         return TVCS_OK;
     });
 }

@@ -57,25 +57,10 @@
 
 #include <algorithm>
 
-// Tile parameters (compile-time; the defaults are the measured best on MI355X)
-#ifndef TVCS_GEMM_NT_MAX
-#define TVCS_GEMM_NT_MAX 16    // image tiles per workgroup of split storage at most (16: 256 images)
-#endif
-#ifndef TVCS_GEMM_KF_NT16
-#define TVCS_GEMM_KF_NT16 1    // 32-wide k tiles per pipeline step for 256-image groups
-#endif
-#ifndef TVCS_GEMM_KF_NT8
-#define TVCS_GEMM_KF_NT8 1     // ... 128-image groups
-#endif
-#ifndef TVCS_GEMM_KF_NT4
-#define TVCS_GEMM_KF_NT4 4     // ... 64-image groups
-#endif
-#ifndef TVCS_GEMM_KF_NT2
-#define TVCS_GEMM_KF_NT2 4     // ... 32-image groups
-#endif
-#ifndef TVCS_GEMM_KF_NT1
-#define TVCS_GEMM_KF_NT1 4     // ... 16-image groups (at least 2)
-#endif
+// Tile shapes are chosen at run time per product and batch (lowp_autotune) among
+// rt in {2, 4} row tiles per wave, image groups of 16 nt images (nt <= 16; 256-image
+// groups with 2 row tiles per wave only) and two tables of k tiles per pipeline step
+// (kKF below).
 #ifndef TVCS_Y_KMAJOR
 #define TVCS_Y_KMAJOR 1        // batch operand blocks k-tile major, hi/lo interleaved
 #endif
@@ -99,9 +84,6 @@
 // ... and of FP8 tiles with 4 row tiles per wave (a register set is 8 VGPRs)
 #ifndef TVCS_GEMM_DEPTH_FP8_RT4
 #define TVCS_GEMM_DEPTH_FP8_RT4 3
-#endif
-#ifndef TVCS_GEMM_FORCE_RT
-#define TVCS_GEMM_FORCE_RT 0   // 2 or 4: skip the autotuner's choice of row tiles per wave
 #endif
 #ifndef TVCS_FWD_TARGET_WG
 #define TVCS_FWD_TARGET_WG 256 // K slices of the forward product grow until this many tiles
@@ -131,6 +113,13 @@ constexpr bool kYKMajor = TVCS_Y_KMAJOR != 0;
 static_assert(kMPad % (16 * kXGroup) == 0 && 16 * kXGroup <= 256,
               "row counts (m_p, and n * n for n >= 16) must be whole groups");
 constexpr int KMAX = 128;        // longest reduction step; every K slice is a multiple of it
+// 32-wide k tiles per pipeline step by image tiles per group (1, 2, 4, 8, 16), two
+// tables.  With one part of the batch operand a step moves NT * KF Y blocks over the
+// four waves, so NT * KF is a multiple of 4.  Table 0 holds the measured defaults
+// (longer steps for small groups, whose X stream dominates; one k tile for large
+// groups, whose accumulators fill the registers), table 1 the neighbours.
+constexpr int kKF[2][5] = {{4, 4, 4, 1, 1}, {4, 2, 1, 2, 1}};
+constexpr int log2_nt(int nt) { return nt == 1 ? 0 : nt == 2 ? 1 : nt == 4 ? 2 : nt == 8 ? 3 : 4; }
 constexpr int kRowsRT4 = 4 * 4 * 16;   // rows per workgroup with 4 row tiles per wave
 
 enum { M_BF16 = 0, M_SPLIT = 1, M_FP8 = 2 };
@@ -601,73 +590,65 @@ __global__ void k_reduce_r(const float *__restrict__ P, int KS, long long split_
     *r = (float)acc;
 }
 
+// Arguments of one product launch (k_gemm's parameters)
+struct GemmArgs {
+    const void *Xhi, *Xlo;
+    long long ldx;
+    const u16 *Yhi, *Ylo;
+    long long yimg, ytile;
+    int M, kspan, RB, KS;
+    float *out;
+    long long split_stride, ldo;
+    const ImgState *st;
+    int nact, parity;
+};
+
+template <int MODE, int RT, int NT, int KF>
+void launch_gemm(const GemmArgs &a, hipStream_t s) {
+    const int total = a.RB * a.KS;
+    hipLaunchKernelGGL((k_gemm<MODE, RT, NT, KF>), dim3(((total + 7) / 8) * 8), dim3(kThreads), 0, s,
+                       a.Xhi, a.Xlo, a.ldx >> 5, a.Yhi, a.Ylo, a.yimg, a.ytile, a.M, a.kspan, a.RB,
+                       a.KS, a.out, a.split_stride, a.ldo, a.st, a.nact, a.parity);
+}
+
+template <int MODE, int RT, int NT>
+void launch_nt(int kfv, const GemmArgs &a, hipStream_t s) {
+    constexpr int K0 = kKF[0][log2_nt(NT)], K1 = kKF[1][log2_nt(NT)];
+    if (kfv == 0 || K0 == K1)
+        launch_gemm<MODE, RT, NT, K0>(a, s);
+    else
+        launch_gemm<MODE, RT, NT, K1>(a, s);
+}
+
 template <int MODE, int RT>
-void gemm_dispatch(int NT, const void *Xhi, const void *Xlo, long long ldx, const u16 *Yhi,
-                   const u16 *Ylo, long long yimg, long long ytile, int M, int kspan, int RB, int KS, float *out,
-                   long long split_stride, long long ldo, const ImgState *st, int nact,
-                   int parity, hipStream_t s) {
-    const int total = RB * KS;
-    const dim3 grid(((total + 7) / 8) * 8);
-#define TVCS_GEMM_CASE(NTV, KFV)                                                               \
-    case NTV:                                                                                  \
-        hipLaunchKernelGGL((k_gemm<MODE, RT, NTV, KFV>), grid, dim3(kThreads), 0, s, Xhi, Xlo,  \
-                           ldx >> 5, Yhi, Ylo, yimg, ytile, M, kspan, RB, KS, out,            \
-                           split_stride, ldo, st, nact, parity);                               \
-        break;
+void gemm_dispatch(int NT, int kfv, const GemmArgs &a, hipStream_t s) {
     switch (NT) {
-        TVCS_GEMM_CASE(1, TVCS_GEMM_KF_NT1)
-        TVCS_GEMM_CASE(2, TVCS_GEMM_KF_NT2)
-        TVCS_GEMM_CASE(4, TVCS_GEMM_KF_NT4)
-        TVCS_GEMM_CASE(8, TVCS_GEMM_KF_NT8)
-#if TVCS_GEMM_NT_MAX >= 16
+        case 1: launch_nt<MODE, RT, 1>(kfv, a, s); break;
+        case 2: launch_nt<MODE, RT, 2>(kfv, a, s); break;
+        case 4: launch_nt<MODE, RT, 4>(kfv, a, s); break;
+        case 8: launch_nt<MODE, RT, 8>(kfv, a, s); break;
         case 16:   // 2 row tiles per wave only (the accumulators of 4 do not fit)
             if constexpr (RT == 2) {
-                hipLaunchKernelGGL((k_gemm<MODE, 2, 16, TVCS_GEMM_KF_NT16>), grid, dim3(kThreads), 0,
-                                   s, Xhi, Xlo, ldx >> 5, Yhi, Ylo, yimg, ytile, M, kspan, RB, KS,
-                                   out, split_stride, ldo, st, nact, parity);
+                launch_nt<MODE, 2, 16>(kfv, a, s);
                 break;
             }
             fail(TVCS_EUNSUPPORTED, "MFMA product: 256-image groups take 2 row tiles per wave");
-#endif
         default: fail(TVCS_EUNSUPPORTED, "MFMA product: image groups of 16, 32, 64, 128 or 256");
     }
-#undef TVCS_GEMM_CASE
 }
 
-template <int RT>
-void gemm_mode(int mode, int NT, const void *Xhi, const void *Xlo, long long ldx, const u16 *Yhi,
-               const u16 *Ylo, long long yimg, long long ytile, int M, int kspan, int RB, int KS, float *out,
-               long long split_stride, long long ldo, const ImgState *st, int nact, int parity,
-               hipStream_t s) {
-    switch (mode) {
-        case M_BF16:
-            gemm_dispatch<M_BF16, RT>(NT, Xhi, Xlo, ldx, Yhi, Ylo, yimg, ytile, M, kspan, RB, KS, out,
-                                      split_stride, ldo, st, nact, parity, s);
-            break;
-        case M_SPLIT:
-            gemm_dispatch<M_SPLIT, RT>(NT, Xhi, Xlo, ldx, Yhi, Ylo, yimg, ytile, M, kspan, RB, KS, out,
-                                       split_stride, ldo, st, nact, parity, s);
-            break;
-        default:
-            gemm_dispatch<M_FP8, RT>(NT, Xhi, Xlo, ldx, Yhi, Ylo, yimg, ytile, M, kspan, RB, KS, out,
-                                     split_stride, ldo, st, nact, parity, s);
+// one image group of nt tiles with the tile shape c (c.nt is the largest group size)
+void gemm_any(const TileCfg &c, int mode, int NT, GemmArgs a, hipStream_t s) {
+    const int RT = NT == 16 ? 2 : c.rt;
+    a.RB = (a.M + 4 * RT * 16 - 1) / (4 * RT * 16);
+    switch (mode * 2 + (RT == 4)) {
+        case M_BF16 * 2: gemm_dispatch<M_BF16, 2>(NT, c.kfv, a, s); break;
+        case M_BF16 * 2 + 1: gemm_dispatch<M_BF16, 4>(NT, c.kfv, a, s); break;
+        case M_SPLIT * 2: gemm_dispatch<M_SPLIT, 2>(NT, c.kfv, a, s); break;
+        case M_SPLIT * 2 + 1: gemm_dispatch<M_SPLIT, 4>(NT, c.kfv, a, s); break;
+        case M_FP8 * 2: gemm_dispatch<M_FP8, 2>(NT, c.kfv, a, s); break;
+        default: gemm_dispatch<M_FP8, 4>(NT, c.kfv, a, s);
     }
-}
-
-// RT (16-row tiles per wave) is chosen at run time by the autotuner
-void gemm_any(int RT, int mode, int NT, const void *Xhi, const void *Xlo, long long ldx,
-              const u16 *Yhi, const u16 *Ylo, long long yimg, long long ytile, int M, int kspan,
-              int KS,
-              float *out, long long split_stride, long long ldo, const ImgState *st, int nact,
-              int parity, hipStream_t s) {
-    if (NT == 16) RT = 2;
-    const int RB = (M + 4 * RT * 16 - 1) / (4 * RT * 16);
-    if (RT == 4)
-        gemm_mode<4>(mode, NT, Xhi, Xlo, ldx, Yhi, Ylo, yimg, ytile, M, kspan, RB, KS, out, split_stride,
-                     ldo, st, nact, parity, s);
-    else
-        gemm_mode<2>(mode, NT, Xhi, Xlo, ldx, Yhi, Ylo, yimg, ytile, M, kspan, RB, KS, out, split_stride,
-                     ldo, st, nact, parity, s);
 }
 
 size_t elem_bytes(int mode) { return mode == M_FP8 ? 1 : 2; }
@@ -747,10 +728,9 @@ void y_strides(long long K, int Bp, long long &yimg, long long &ytile) {
     }
 }
 
-// Image tiles per group: up to 16 (256 images, A streamed once for them) for split
-// storage, whose products then run 10-15 % faster at 256 images; 8 for BF16 and
-// FP8, which run as fast (BF16) or 17 % slower (FP8) with 16.
-int nt_max(int mode) { return mode == M_SPLIT ? TVCS_GEMM_NT_MAX : std::min(8, TVCS_GEMM_NT_MAX); }
+// Default image tiles per group before the autotuner has run: 16 (256 images, A
+// streamed once for them) for split storage, 8 for BF16 and FP8.
+int nt_default(int mode) { return mode == M_SPLIT ? 16 : 8; }
 
 // Cover the padded batch with image groups of 16 * nt, nt in {ntmax, ..., 2, 1};
 // groups holding only padding images are skipped.  fn(first image, nt, real images).
@@ -879,46 +859,73 @@ void lowp_work_bind(LowpWork &W, const LowpA &L, int Bp, void *base) {
     W.Ut = static_cast<float *>(take((size_t)Bp * L.N * sizeof(float)));
     W.St = static_cast<float *>(take((size_t)Bp * L.m * sizeof(float)));
     W.Bp = Bp;
-    W.fwd_rt = 4;
-    W.adj_rt = 2;
+    W.fwd = TileCfg{4, nt_default(mode_of(L.storage)), 0};
+    W.adj = TileCfg{2, nt_default(mode_of(L.storage)), 0};
 }
 
-// Autotuner: time each product with 2 and 4 row tiles per wave on this shape and
-// batch (one warm-up and three timed launches each, HIP events) and keep the
-// faster.  G is scratch for the adjoint output (lowp_adj_splits(L) x Bp x N floats).
+int tile_kf(int nt, int kfv) { return kKF[kfv ? 1 : 0][log2_nt(nt)]; }
+
+bool tile_valid(const TileCfg &c) {
+    const bool nt_ok = c.nt == 1 || c.nt == 2 || c.nt == 4 || c.nt == 8 || c.nt == 16;
+    return nt_ok && (c.rt == 2 || (c.rt == 4 && c.nt < 16)) && (c.kfv == 0 || c.kfv == 1);
+}
+
+// Autotuner: for each product, time every candidate tile shape on this matrix and
+// padded batch (HIP events; one warm-up launch, then three of each form) and keep the
+// fastest.  Candidates: 2 or 4 row tiles per wave, both k-tile tables, and image
+// groups of the whole padded batch (up to 256) or of a half or a quarter of it.  The
+// time of a candidate is three increment-form launches plus one fresh launch (about
+// a fifth of the iterations are fresh).  st (Bp states) is overwritten; U, R and G
+// are scratch of the workspace's sizes.
 void lowp_autotune(const LowpA &L, LowpWork &W, int Bp, const float *U, float *R, float *G,
-                   hipStream_t s) {
+                   ImgState *st, hipStream_t s) {
     hipEvent_t e0, e1;
     TVCS_HIP(hipEventCreate(&e0));
     TVCS_HIP(hipEventCreate(&e1));
-    auto time_it = [&](auto &&launch) {
-        launch();
+    launch_init_state(st, Bp, 0.0, 1 << 30, s, 0);   // active, increment form
+    auto elapsed = [&](auto &&launch, int reps) {
         TVCS_HIP(hipEventRecord(e0, s));
-        for (int i = 0; i < 3; ++i) launch();
+        for (int i = 0; i < reps; ++i) launch();
         TVCS_HIP(hipEventRecord(e1, s));
         TVCS_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
         TVCS_HIP(hipEventElapsedTime(&ms, e0, e1));
         return ms;
     };
+    auto cost = [&](auto &&product) {   // product(parity): 0 increment, -1 fresh
+        product(0);
+        return elapsed([&] { product(0); }, 3) + elapsed([&] { product(-1); }, 1);
+    };
+    int ntop = 1;
+    while (2 * ntop <= std::min(Bp / 16, 16)) ntop *= 2;
     float best_f = 1e30f, best_a = 1e30f;
-    int fr = 4, ar = 2;
-    for (int rt : {2, 4}) {
-        W.fwd_rt = rt;
-        W.adj_rt = rt;
-        const float tf = time_it([&] { lowp_apply_A(L, W, Bp, U, nullptr, R, nullptr, s); });
-        const float ta = time_it([&] { lowp_apply_At(L, W, Bp, R, G, nullptr, s); });
-        if (tf < best_f) {
-            best_f = tf;
-            fr = rt;
-        }
-        if (ta < best_a) {
-            best_a = ta;
-            ar = rt;
-        }
-    }
-    W.fwd_rt = TVCS_GEMM_FORCE_RT ? TVCS_GEMM_FORCE_RT : fr;
-    W.adj_rt = TVCS_GEMM_FORCE_RT ? TVCS_GEMM_FORCE_RT : ar;
+    TileCfg bf = W.fwd, ba = W.adj;
+    for (int nt = ntop; nt >= std::max(1, ntop / 4); nt /= 2)
+        for (int rt : {2, 4})
+            for (int kfv : {0, 1}) {
+                const TileCfg c{rt, nt, kfv};
+                if (!tile_valid(c)) continue;
+                // skip a table that gives this group size (and the smaller groups a
+                // batch may end with) the same steps as table 0
+                bool same = kfv == 1;
+                for (int t = nt; t >= 1 && same; t /= 2) same = tile_kf(t, 0) == tile_kf(t, 1);
+                if (same) continue;
+                W.fwd = W.adj = c;
+                const float tf = cost([&](int par) {
+                    lowp_apply_A(L, W, Bp, U, nullptr, R, st, s, nullptr, nullptr, 0, par);
+                });
+                const float ta = cost([&](int par) { lowp_apply_At(L, W, Bp, R, G, st, s, par); });
+                if (tf < best_f) {
+                    best_f = tf;
+                    bf = c;
+                }
+                if (ta < best_a) {
+                    best_a = ta;
+                    ba = c;
+                }
+            }
+    W.fwd = bf;
+    W.adj = ba;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
 }
@@ -942,12 +949,12 @@ void lowp_apply_A(const LowpA &L, LowpWork &W, int B, const float *U, const floa
     int KS, kspan;
     fwd_split(L, KS, kspan);
     const long long split_stride = (long long)Bp * L.mp;
-    for_each_group(Bp, B, nt_max(mode), [&](int img0, int nt, int nact) {
-        gemm_any(W.fwd_rt, mode, nt, L.X_hi, L.X_lo, L.N,
-                 (const u16 *)W.Ubf_hi + (img0 / 16) * yimg,
-                 (const u16 *)W.Ubf_lo + (img0 / 16) * yimg, yimg, ytile, L.mp, kspan, KS,
-                 W.Rpart + (size_t)img0 * L.mp, split_stride, L.mp, st ? st + img0 : nullptr,
-                 nact, parity, s);
+    for_each_group(Bp, B, W.fwd.nt, [&](int img0, int nt, int nact) {
+        const GemmArgs a{L.X_hi, L.X_lo, L.N, (const u16 *)W.Ubf_hi + (img0 / 16) * yimg,
+                         (const u16 *)W.Ubf_lo + (img0 / 16) * yimg, yimg, ytile, L.mp, kspan,
+                         0, KS, W.Rpart + (size_t)img0 * L.mp, split_stride, L.mp,
+                         st ? st + img0 : nullptr, nact, parity};
+        gemm_any(W.fwd, mode, nt, a, s);
     });
     hipLaunchKernelGGL(k_reduce_r, dim3((L.m + 255) / 256, Bp), dim3(256), 0, s, W.Rpart, KS,
                        split_stride, L.mp, F, L.scale, L.m, R, st, parity, B);
@@ -967,12 +974,12 @@ void lowp_apply_At(const LowpA &L, LowpWork &W, int B, const float *R, float *G,
     int KS, kspan;
     adj_split(L, KS, kspan);
     const long long split_stride = (long long)Bp * L.N;
-    for_each_group(Bp, B, nt_max(mode), [&](int img0, int nt, int nact) {
-        gemm_any(W.adj_rt, mode, nt, L.XT_hi, L.XT_lo, L.mp,
-                 (const u16 *)W.Rbf_hi + (img0 / 16) * yimg,
-                 (const u16 *)W.Rbf_lo + (img0 / 16) * yimg, yimg, ytile, L.N, kspan, KS,
-                 G + (size_t)img0 * L.N, split_stride, L.N, st ? st + img0 : nullptr, nact,
-                 parity, s);
+    for_each_group(Bp, B, W.adj.nt, [&](int img0, int nt, int nact) {
+        const GemmArgs a{L.XT_hi, L.XT_lo, L.mp, (const u16 *)W.Rbf_hi + (img0 / 16) * yimg,
+                         (const u16 *)W.Rbf_lo + (img0 / 16) * yimg, yimg, ytile, L.N, kspan, 0,
+                         KS, G + (size_t)img0 * L.N, split_stride, L.N,
+                         st ? st + img0 : nullptr, nact, parity};
+        gemm_any(W.adj, mode, nt, a, s);
     });
 }
 

@@ -185,6 +185,7 @@ int solve_noalloc_impl(tvcs_ctx *h, const float *f, double mu, double beta, doub
         stats->tau = tau;
         stats->ms = ms;
         stats->fresh_iters = 0;
+        for (int i = 0; i < 6; ++i) stats->tiles[i] = 0;
     }
     if (rc == TVCS_ENONFINITE) g_last_error = "an iterate became NaN or Inf";
     return rc;

@@ -147,6 +147,7 @@ struct tvcs_server {
             r.st.status = is.status;
             r.st.rel_change = is.rel;
             r.st.fresh_iters = h->lowprec() ? is.fresh : 0;
+            h->tiles_out(r.st.tiles);
             r.st.objective = 0.0;
             r.st.tau = h->tau();
             r.st.ms = (float)(t - r.t_admit);

@@ -82,6 +82,8 @@ struct tvcs_ctx {
     DevBuf bb_Uk, bb_P, bb_AP, bb_parts, bb_state;   // IADM with inner BB steps
     DevBuf DT;             // partial DCT: the half-transformed images between passes
     LowpWork lw{};
+    bool tiles_forced = false;   // tile shapes set by tvcs_set_tiles instead of the autotuner
+    TileCfg forced_fwd{}, forced_adj{};
     ImgState *host_state = nullptr;   // pinned mirror for polling: two halves of cap images
     int host_state_cap = 0;
     hipEvent_t ev_poll[2] = {nullptr, nullptr};   // copies into the two halves
@@ -141,7 +143,7 @@ struct tvcs_ctx {
         Q1.ensure(sizeof(float2) * B * Nn);
         S.ensure(sizeof(float2) * B * h * n);
         parts.ensure(sizeof(double) * 2 * B * (size_t)n);   // >= n / rows-per-block
-        state.ensure(sizeof(ImgState) * B);
+        state.ensure(sizeof(ImgState) * Bp);   // Bp: the autotuner times whole groups
         obj.ensure(sizeof(double) * B);
         counters.ensure(sizeof(int) * B);
         if (dct()) DT.ensure(sizeof(float) * Bp * Nn);
@@ -162,9 +164,30 @@ struct tvcs_ctx {
         launch_fill(U.as<float>(), (size_t)Bp * Nn, 0.f, work);
         launch_fill(F.as<float>(), (size_t)Bp * mm, 0.f, work);
         // the adjoint writes all its K slices: P is sized for them
-        if (lowprec()) lowp_autotune(lowp, lw, Bp, U.as<float>(), R.as<float>(), P.as<float>(), work);
+        if (lowprec()) {
+            if (tiles_forced) {
+                lw.fwd = forced_fwd;
+                lw.adj = forced_adj;
+            } else {
+                lowp_autotune(lowp, lw, Bp, U.as<float>(), R.as<float>(), P.as<float>(),
+                              state.as<ImgState>(), work);
+            }
+        }
         cap = B;
         capP = Bp;
+    }
+
+    // tile shapes of the two MFMA products as {rt, images per group, k tiles per step}
+    // of each (zeros for other storage)
+    void tiles_out(int *t) const {
+        for (int i = 0; i < 6; ++i) t[i] = 0;
+        if (!lowprec()) return;
+        const TileCfg c[2] = {lw.fwd, lw.adj};
+        for (int k = 0; k < 2; ++k) {
+            t[3 * k] = c[k].nt == 16 ? 2 : c[k].rt;
+            t[3 * k + 1] = 16 * c[k].nt;
+            t[3 * k + 2] = tile_kf(c[k].nt, c[k].kfv);
+        }
     }
 
     // vectors per pass and row chunks of the FP32 products for a padded batch Bp.
@@ -184,7 +207,7 @@ struct tvcs_ctx {
         const int nchunk = partial_count(Bp);
         size_t b = sizeof(float) * Bp * (2 * Nn + 2 * mm) + sizeof(float) * (size_t)nchunk * Bp * Nn +
                    2 * sizeof(float2) * B * Nn + sizeof(float2) * B * h * n +
-                   sizeof(double) * 2 * B * (size_t)n + sizeof(ImgState) * B + sizeof(double) * B +
+                   sizeof(double) * 2 * B * (size_t)n + sizeof(ImgState) * Bp + sizeof(double) * B +
                    sizeof(int) * B;
         if (lowprec()) b += lowp_work_bytes(lowp, Bp) + sizeof(float) * B * Nn;
         if (dct()) b += sizeof(float) * Bp * Nn;

@@ -216,6 +216,15 @@ constexpr int kBTile = 16;       // batch granularity of the MFMA products
 size_t lowp_storage_bytes(const LowpA &L);          // bytes for the formats of L.storage
 void lowp_bind_storage(LowpA &L, void *base);        // fills mp, Np and the pointers
 void lowp_convert(LowpA &L, const float *A32, hipStream_t s);
+// Tile shape of one MFMA product: rt 16-row tiles of the streamed matrix per wave;
+// image groups of up to 16 * nt images (nt in 1, 2, 4, 8, 16; A is streamed once per
+// group); kfv picks the table of 32-wide k tiles per pipeline step (tile_kf).  No
+// choice changes the order of any sum, so results are the same bits for all.
+struct TileCfg {
+    int rt, nt, kfv;
+};
+int tile_kf(int nt, int kfv);                        // k tiles per step of an nt group
+bool tile_valid(const TileCfg &c);
 // R[b*ldr + i] = (A u_b)_i - F[b*ldf + i] for b < B (B padded to kBTile in workspace)
 struct LowpWork {
     void *Ubf_hi, *Ubf_lo;       // Bp x N   bf16 copies of U
@@ -224,7 +233,7 @@ struct LowpWork {
     float *Ut;                   // Bp x N: the point the current R belongs to
     float *St;                   // Bp x m: the vector the current g belongs to (s o r)
     int Bp;
-    int fwd_rt, adj_rt;          // 16-row tiles per wave of the two products (autotuned)
+    TileCfg fwd, adj;            // tile shapes of the two products (autotuned)
 };
 size_t lowp_work_bytes(const LowpA &L, int B);
 void lowp_work_bind(LowpWork &W, const LowpA &L, int B, void *base);
@@ -243,9 +252,10 @@ int lowp_adj_splits(const LowpA &L);
 // increment of g, which the shrink pass adds to the running g)
 void lowp_apply_At(const LowpA &L, LowpWork &W, int B, const float *R, float *G,
                    const ImgState *st, hipStream_t s, int parity = -1);
-// pick the tile shape of each product by timing the candidates on this batch
+// pick the tile shape of each product by timing the candidates on this batch; st
+// holds Bp image states (overwritten: the search times both product forms)
 void lowp_autotune(const LowpA &L, LowpWork &W, int Bp, const float *U, float *R, float *G,
-                   hipStream_t s);
+                   ImgState *st, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Partial-DCT operator (dct.hip): A = rows of the orthonormal 2-D DCT-II.

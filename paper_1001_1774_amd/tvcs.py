@@ -54,7 +54,7 @@ class tvcs_stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int),
                 ("rel_change", ctypes.c_double), ("objective", ctypes.c_double),
                 ("tau", ctypes.c_double), ("ms", ctypes.c_float),
-                ("fresh_iters", ctypes.c_int)]
+                ("fresh_iters", ctypes.c_int), ("tiles", ctypes.c_int * 6)]
 
 
 class TvcsError(RuntimeError):
@@ -95,6 +95,8 @@ _SIGS = {
                                           ctypes.c_void_p]),
     "tvcs_time_products": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "tvcs_set_tiles": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "tvcs_get_tiles": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "tvcs_destroy": (None, [ctypes.c_void_p]),
     "tvcs_server_create": (ctypes.c_void_p, [ctypes.c_size_t, ctypes.c_int, ctypes.c_double,
                                              ctypes.c_double, ctypes.c_uint]),
@@ -229,6 +231,18 @@ def tvcs_time_products(h, B, reps, form=0, ms_forward=None, ms_adjoint=None):
     return lib().tvcs_time_products(h, B, reps, form,
                                     ctypes.byref(ms_forward) if ms_forward is not None else None,
                                     ctypes.byref(ms_adjoint) if ms_adjoint is not None else None)
+
+
+def tvcs_set_tiles(h, tiles=None):
+    """tiles: six ints {rt, images, kf} of the forward then the adjoint product, or
+    None (autotune)."""
+    arr = (ctypes.c_int * 6)(*tiles) if tiles is not None else None
+    return lib().tvcs_set_tiles(h, arr)
+
+
+def tvcs_get_tiles(h, tiles):
+    """tiles: a (ctypes.c_int * 6) array filled with the shapes in use."""
+    return lib().tvcs_get_tiles(h, tiles)
 
 
 def tvcs_measure_peaks(nbytes, reps, read_gbs=None, mfma_tflops=None):
@@ -391,7 +405,7 @@ class Solver:
             raise TvcsError(rc, tvcs_last_error())
         stats = [dict(iters=s.iters, status=s.status, rel_change=s.rel_change,
                       objective=s.objective, tau=s.tau, ms=s.ms,
-                      fresh_iters=s.fresh_iters) for s in st]
+                      fresh_iters=s.fresh_iters, tiles=tuple(s.tiles)) for s in st]
         out = dict(u=U.reshape(B, self.n, self.n), stats=stats, rc=rc)
         if lam is not None:
             out["lam"] = lam.reshape(B, 2, self.n, self.n)
@@ -417,8 +431,24 @@ class Solver:
             raise TvcsError(rc, tvcs_last_error())
         stats = [dict(iters=s.iters, status=s.status, rel_change=s.rel_change,
                       objective=s.objective, tau=s.tau, ms=s.ms,
-                      fresh_iters=s.fresh_iters) for s in st]
+                      fresh_iters=s.fresh_iters, tiles=tuple(s.tiles)) for s in st]
         return dict(u=U.reshape(B, self.n, self.n), stats=stats, rc=rc)
+
+    @property
+    def tiles(self):
+        """The MFMA products' tile shapes: (rt, images, kf) of the forward product, then
+        of the adjoint (zeros for FP32 storage and the partial DCT)."""
+        t = (ctypes.c_int * 6)()
+        rc = tvcs_get_tiles(self.h, t)
+        if rc < 0:
+            raise TvcsError(rc, tvcs_last_error())
+        return tuple(t)
+
+    @tiles.setter
+    def tiles(self, value):
+        rc = tvcs_set_tiles(self.h, None if value is None else [int(x) for x in value])
+        if rc < 0:
+            raise TvcsError(rc, tvcs_last_error())
 
     def time_products(self, B=1, reps=20, increment=False):
         """Average ms per launch of the forward and adjoint products (HIP events);

@@ -110,7 +110,19 @@ def test_argument_errors_without_device(clib):
     T.tvcs_destroy(None)
 
 
-def test_stats_struct_layout():
+def test_stats_struct_layout(tmp_path):
+    """The binding's tvcs_stats has the C struct's size and field offsets."""
     from paper_1001_1774_amd import tvcs as T
-    # int, int, double, double, double, float (+ tail padding) = 40 bytes on x86-64
-    assert ctypes.sizeof(T.tvcs_stats) == 40
+    fields = [f[0] for f in T.tvcs_stats._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "tvcs.h"\n'
+                   'int main(void){ printf("%zu", sizeof(tvcs_stats));'
+                   + "".join(f' printf(" %zu", offsetof(tvcs_stats, {f}));' for f in fields)
+                   + " return 0; }\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", f"-I{os.path.dirname(HEADER)}", str(src), "-o", str(exe)],
+                   check=True)
+    c = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                         text=True).stdout.split()]
+    py = [ctypes.sizeof(T.tvcs_stats)] + [getattr(T.tvcs_stats, f).offset for f in fields]
+    assert py == c
