@@ -93,11 +93,17 @@ def main():
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--form", choices=["fresh", "increment"], default="fresh",
                     help="form of the low-precision products for --products")
+    ap.add_argument("--solve", choices=sorted(PRODUCT_WORKLOADS), default=None,
+                    help="only solve `--batch` images of this workload with A in `--storage` "
+                         "for `--iters` IADM iterations, once to warm up and once timed (for "
+                         "rocprofv3), after the calibrating copy")
+    ap.add_argument("--bb", type=int, default=1, metavar="J",
+                    help="with --solve: J inner BB steps per IADM iteration (FP32 storage)")
     ap.add_argument("--dct-solve", type=int, default=0, metavar="N",
                     help="only solve a batch of `--batch` N x N partial-DCT problems for "
                          "`--iters` iterations (for rocprofv3)")
     args = ap.parse_args()
-    if args.products or args.dct_solve:
+    if args.products or args.dct_solve or args.solve:
         profile_mode(args)
         return
     if args.gpus != 1:
@@ -261,6 +267,9 @@ def profile_mode(args):
     of the low-precision products).  First copies a 256 MiB device buffer once: a
     plain copy of known size (reads and writes 268435456 bytes) against which the
     FETCH_SIZE / WRITE_SIZE counters are scaled.
+    --solve W: `--batch` images of workload W (its seeded images, repeated when the
+    batch is larger) with A in `--storage`, IADM for `--iters` iterations, once to warm
+    up and once timed (`--bb J`: with J inner BB steps per iteration).
     --dct-solve N: a batch of seeded N x N partial-DCT problems (30 % of the
     coefficients, IADM, mu = 500, beta = 2^6, tau = 1.9) solved for `--iters`
     iterations, once to warm up and once timed."""
@@ -283,6 +292,23 @@ def profile_mode(args):
             dt = time.perf_counter() - t0
         print(json.dumps({"dct": args.dct_solve, "m": q.m, "batch": args.batch,
                           "iters": args.iters, "ms_per_iter": 1e3 * dt / args.iters}), flush=True)
+        return
+    if args.solve:
+        p = synth.workload(args.solve, dtype=np.float32)
+        F = torch.from_numpy(p.f[np.arange(args.batch) % p.B].astype(np.float32)).cuda()
+        with tvcs.Solver(p.A, p.n, storage=args.storage) as s:
+            s.solve_batch(F, mu=p.mu, beta=p.beta, maxit=args.iters, iadm=True, bb_steps=args.bb)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = s.solve_batch(F, mu=p.mu, beta=p.beta, maxit=args.iters, iadm=True,
+                                bb_steps=args.bb)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            tiles = s.tiles
+        print(json.dumps({"workload": args.solve, "storage": args.storage, "batch": args.batch,
+                          "iters": args.iters, "bb_steps": args.bb, "ms_per_iter": 1e3 * dt / args.iters,
+                          "tiles": tiles, "fresh_iteration_fraction": fresh_fraction(out["stats"]),
+                          "copy_bytes": COPY_BYTES}), flush=True)
         return
     p = synth.workload(args.products, batch=1, dtype=np.float32)
     with tvcs.Solver(p.A, p.n, storage=args.storage) as s:

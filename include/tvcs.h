@@ -278,13 +278,17 @@ int tvcs_get_tiles(tvcs_handle h, int *tiles);
  * of one forward product (r = A u - f, all images of a batch of B) and of one
  * adjoint product (A^T r, including its partial-sum reduction), over `reps`
  * launches of each timed with HIP events on the stream the solver launches them
- * on, with the launch configuration a solve of B images uses.  Inputs are the
- * handle's workspace contents (any values).  Either output may be NULL.
+ * on, with the launch configuration a solve of B images uses.  The inputs are
+ * deterministic hashed values of unit size, not zeros (MFMA clocks depend on the
+ * operands' bits); the workspace contents are overwritten.  Either output may
+ * be NULL.
  *   form  0: the fresh products every storage format computes (for bf16, split
  *         bf16 and FP8 storage: from a two-part bf16 batch operand);
  *         1: the increment form of those three formats' products (one-part batch
  *         operand; the form most iterations take once the iterates change by
- *         less than 2^-8 per iteration); the same as 0 for FP32 and the DCT.
+ *         less than 2^-8 per iteration); each timed launch follows a move of its
+ *         input by 2^-10 of its size, outside the timed span, as between two
+ *         iterations.  The same as 0 for FP32 and the DCT.
  */
 int tvcs_time_products(tvcs_handle h, int B, int reps, int form, float *ms_forward,
                        float *ms_adjoint);

@@ -392,28 +392,51 @@ int tvcs_time_products(tvcs_handle h, int B, int reps, int form, float *ms_forwa
         const int Bp = h->padded(B);
         float *U = h->U.as<float>(), *F = h->F.as<float>(), *R = h->R.as<float>();
         ImgState *st = h->state.as<ImgState>();
-        // one fresh pair of products sets the vectors the increments are taken from,
-        // then every image takes the requested form (mode slot 0, parity 0)
+        // inputs like a solve's: u and f of unit size with hashed (nonzero, unstructured)
+        // entries, since MFMA clocks depend on the operands' bits.  One fresh pair of
+        // products sets the vectors the increments are taken from; u then moves by
+        // 2^-10 of its size, so the increment operands are nonzero (after the warm-up
+        // launch, the rounding residuals of that move), and every image takes the
+        // requested form (mode slot 0, parity 0)
+        launch_fill_hash(U, (size_t)B * h->N, 1u, 1.0f, false, h->work);
+        launch_fill_hash(F, (size_t)B * h->m, 2u, 1.0f, false, h->work);
         launch_init_state(st, B, 0.0, 1, h->work, 1);
         h->apply_A(Bp, B, U, F, R, st, 0);
         h->apply_At(Bp, B, R, st, 0);
+        launch_fill_hash(U, (size_t)B * h->N, 3u, 1.0f / 1024.0f, true, h->work);
         launch_init_state(st, B, 0.0, 1, h->work, form ? 0 : 1);
-        // warm-up launch of each, then the timed runs
+        // warm-up launch of each, then the timed runs.  In the increment form each
+        // timed launch follows (outside its timed span) a move of its input by 2^-10
+        // of its size, as between two iterations: otherwise the increments of
+        // repeated launches on one input round to zero after a few launches.
+        const bool incr = form == 1 && h->lowprec();
         h->apply_A(Bp, B, U, F, R, st, 0);
         h->apply_At(Bp, B, R, st, 0);
-        TVCS_HIP(hipEventRecord(h->ev_t0, h->work));
-        for (int i = 0; i < reps; ++i) h->apply_A(Bp, B, U, F, R, st, 0);
-        TVCS_HIP(hipEventRecord(h->ev_t1, h->work));
-        TVCS_HIP(hipEventSynchronize(h->ev_t1));
-        float ms = 0.f;
-        TVCS_HIP(hipEventElapsedTime(&ms, h->ev_t0, h->ev_t1));
-        if (ms_forward) *ms_forward = ms / reps;
-        TVCS_HIP(hipEventRecord(h->ev_t0, h->work));
-        for (int i = 0; i < reps; ++i) h->apply_At(Bp, B, R, st, 0);
-        TVCS_HIP(hipEventRecord(h->ev_t1, h->work));
-        TVCS_HIP(hipEventSynchronize(h->ev_t1));
-        TVCS_HIP(hipEventElapsedTime(&ms, h->ev_t0, h->ev_t1));
-        if (ms_adjoint) *ms_adjoint = ms / reps;
+        auto timed = [&](auto &&op, float *moved, size_t count) {
+            float total = 0.f, ms = 0.f;
+            if (!incr) {
+                TVCS_HIP(hipEventRecord(h->ev_t0, h->work));
+                for (int i = 0; i < reps; ++i) op();
+                TVCS_HIP(hipEventRecord(h->ev_t1, h->work));
+                TVCS_HIP(hipEventSynchronize(h->ev_t1));
+                TVCS_HIP(hipEventElapsedTime(&total, h->ev_t0, h->ev_t1));
+                return total / reps;
+            }
+            for (int i = 0; i < reps; ++i) {
+                launch_fill_hash(moved, count, 16u + (unsigned)i, 1.0f / 1024.0f, true, h->work);
+                TVCS_HIP(hipEventRecord(h->ev_t0, h->work));
+                op();
+                TVCS_HIP(hipEventRecord(h->ev_t1, h->work));
+                TVCS_HIP(hipEventSynchronize(h->ev_t1));
+                TVCS_HIP(hipEventElapsedTime(&ms, h->ev_t0, h->ev_t1));
+                total += ms;
+            }
+            return total / reps;
+        };
+        const float msf = timed([&] { h->apply_A(Bp, B, U, F, R, st, 0); }, U, (size_t)B * h->N);
+        if (ms_forward) *ms_forward = msf;
+        const float msa = timed([&] { h->apply_At(Bp, B, R, st, 0); }, R, (size_t)B * h->m);
+        if (ms_adjoint) *ms_adjoint = msa;
         TVCS_HIP(hipGetLastError());
         return TVCS_OK;
     });
@@ -453,6 +476,7 @@ int tvcs_set_tiles(tvcs_handle h, const int *tiles) {
         } else if (h->capP) {
             lowp_autotune(h->lowp, h->lw, h->capP, h->U.as<float>(), h->R.as<float>(),
                           h->P.as<float>(), h->state.as<ImgState>(), h->work);
+            launch_fill(h->U.as<float>(), (size_t)h->capP * h->N, 0.f, h->work);
         }
         TVCS_HIP(hipStreamSynchronize(h->work));
         return TVCS_OK;

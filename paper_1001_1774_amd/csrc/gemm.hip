@@ -327,7 +327,7 @@ __device__ inline void gemm_body(const void *__restrict__ Xhi, const void *__res
                     : RT > 2 ? (MODE == M_FP8 ? TVCS_GEMM_DEPTH_FP8_RT4 : 1)
                     : MODE == M_FP8 ? TVCS_GEMM_DEPTH_FP8
                     : MODE == M_SPLIT ? TVCS_GEMM_DEPTH_SPLIT : TVCS_GEMM_DEPTH_BF16;
-    static_assert(D >= 1 && D <= 4, "prefetch distance 1 .. 4");
+    static_assert(D >= 1 && D <= 8, "prefetch distance 1 .. 8");
     constexpr int U = (D + 1) % 2 == 0 ? D + 1 : 2 * (D + 1);   // unroll: both rotations close
     const int last = steps - 1;
     XRegs<MODE, RT, KF> x[D + 1];
@@ -871,30 +871,37 @@ bool tile_valid(const TileCfg &c) {
 }
 
 // Autotuner: for each product, time every candidate tile shape on this matrix and
-// padded batch (HIP events; one warm-up launch, then three of each form) and keep the
-// fastest.  Candidates: 2 or 4 row tiles per wave, both k-tile tables, and image
-// groups of the whole padded batch (up to 256) or of a half or a quarter of it.  The
-// time of a candidate is three increment-form launches plus one fresh launch (about
-// a fifth of the iterations are fresh).  st (Bp states) is overwritten; U, R and G
-// are scratch of the workspace's sizes.
-void lowp_autotune(const LowpA &L, LowpWork &W, int Bp, const float *U, float *R, float *G,
+// padded batch (HIP events) and keep the fastest.  Candidates: 2 or 4 row tiles per
+// wave, both k-tile tables, and image groups of the whole padded batch (up to 256)
+// or of a half or a quarter of it.  The cost of a candidate is three increment-form
+// launches plus one fresh launch (about a fifth of the iterations are fresh), after
+// one warm-up launch.  The inputs are hashed values of unit size (MFMA clocks depend
+// on the operands' bits), and each increment launch follows a move of its input by
+// 2^-10 of its size, as between two iterations, so its operand is never zero.  st (Bp
+// states) is overwritten, and so are U, R and G (scratch of the workspace's sizes).
+void lowp_autotune(const LowpA &L, LowpWork &W, int Bp, float *U, float *R, float *G,
                    ImgState *st, hipStream_t s) {
     hipEvent_t e0, e1;
     TVCS_HIP(hipEventCreate(&e0));
     TVCS_HIP(hipEventCreate(&e1));
     launch_init_state(st, Bp, 0.0, 1 << 30, s, 0);   // active, increment form
-    auto elapsed = [&](auto &&launch, int reps) {
-        TVCS_HIP(hipEventRecord(e0, s));
-        for (int i = 0; i < reps; ++i) launch();
-        TVCS_HIP(hipEventRecord(e1, s));
-        TVCS_HIP(hipEventSynchronize(e1));
-        float ms = 0.f;
-        TVCS_HIP(hipEventElapsedTime(&ms, e0, e1));
-        return ms;
-    };
-    auto cost = [&](auto &&product) {   // product(parity): 0 increment, -1 fresh
+    launch_fill_hash(U, (size_t)Bp * L.N, 1u, 1.0f, false, s);
+    launch_fill_hash(R, (size_t)Bp * L.m, 2u, 1.0f, false, s);
+    unsigned seed = 16;
+    // product(parity): 0 increment, -1 fresh; moved / count: its input
+    auto cost = [&](auto &&product, float *moved, size_t count) {
         product(0);
-        return elapsed([&] { product(0); }, 3) + elapsed([&] { product(-1); }, 1);
+        float total = 0.f, ms = 0.f;
+        for (int i = 0; i < 4; ++i) {
+            if (i < 3) launch_fill_hash(moved, count, seed++, 1.0f / 1024.0f, true, s);
+            TVCS_HIP(hipEventRecord(e0, s));
+            product(i < 3 ? 0 : -1);
+            TVCS_HIP(hipEventRecord(e1, s));
+            TVCS_HIP(hipEventSynchronize(e1));
+            TVCS_HIP(hipEventElapsedTime(&ms, e0, e1));
+            total += ms;
+        }
+        return total;
     };
     int ntop = 1;
     while (2 * ntop <= std::min(Bp / 16, 16)) ntop *= 2;
@@ -911,10 +918,13 @@ void lowp_autotune(const LowpA &L, LowpWork &W, int Bp, const float *U, float *R
                 for (int t = nt; t >= 1 && same; t /= 2) same = tile_kf(t, 0) == tile_kf(t, 1);
                 if (same) continue;
                 W.fwd = W.adj = c;
-                const float tf = cost([&](int par) {
-                    lowp_apply_A(L, W, Bp, U, nullptr, R, st, s, nullptr, nullptr, 0, par);
-                });
-                const float ta = cost([&](int par) { lowp_apply_At(L, W, Bp, R, G, st, s, par); });
+                const float tf = cost(
+                    [&](int par) {
+                        lowp_apply_A(L, W, Bp, U, nullptr, R, st, s, nullptr, nullptr, 0, par);
+                    },
+                    U, (size_t)Bp * L.N);
+                const float ta = cost([&](int par) { lowp_apply_At(L, W, Bp, R, G, st, s, par); },
+                                      R, (size_t)Bp * L.m);
                 if (tf < best_f) {
                     best_f = tf;
                     bf = c;

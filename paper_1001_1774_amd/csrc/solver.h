@@ -171,6 +171,7 @@ struct tvcs_ctx {
             } else {
                 lowp_autotune(lowp, lw, Bp, U.as<float>(), R.as<float>(), P.as<float>(),
                               state.as<ImgState>(), work);
+                launch_fill(U.as<float>(), (size_t)Bp * Nn, 0.f, work);   // padding: zeros
             }
         }
         cap = B;

@@ -90,6 +90,8 @@ void launch_gemv_cols(const float *A, int m, int N, const float *R, int ldr, flo
 void launch_sum_partials(const float *P, int nchunk, long long chunk_stride, int nv, int N,
                          float *out, int ldo, hipStream_t s);
 void launch_fill(float *x, size_t count, float value, hipStream_t s);
+// x = scale * (hashed index in [-1, 1)), or x += that with add (measurement inputs)
+void launch_fill_hash(float *x, size_t count, unsigned seed, float scale, bool add, hipStream_t s);
 // fresh: the mode of the first two iterations (1: fresh products; 0 only for timing
 // the increment form of the products)
 void launch_init_state(ImgState *st, int B, double tol, int maxit, hipStream_t s,
@@ -253,8 +255,8 @@ int lowp_adj_splits(const LowpA &L);
 void lowp_apply_At(const LowpA &L, LowpWork &W, int B, const float *R, float *G,
                    const ImgState *st, hipStream_t s, int parity = -1);
 // pick the tile shape of each product by timing the candidates on this batch; st
-// holds Bp image states (overwritten: the search times both product forms)
-void lowp_autotune(const LowpA &L, LowpWork &W, int Bp, const float *U, float *R, float *G,
+// holds Bp image states, U, R and G are workspace arrays (all overwritten)
+void lowp_autotune(const LowpA &L, LowpWork &W, int Bp, float *U, float *R, float *G,
                    ImgState *st, hipStream_t s);
 
 // ---------------------------------------------------------------------------

@@ -24,6 +24,22 @@ __global__ void k_fill(float *x, size_t count, float value) {
         x[i] = value;
 }
 
+// x[i] = scale * h(i, seed) with h a hash of the index uniform in [-1, 1) (2^-23 steps)
+// (+= with add): deterministic data that is neither zero nor structured
+__global__ void k_fill_hash(float *x, size_t count, unsigned seed, float scale, int add) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
+         i += (size_t)gridDim.x * blockDim.x) {
+        unsigned h = (unsigned)i * 0x9E3779B1u ^ (unsigned)(i >> 32) ^ seed;
+        h ^= h >> 16;
+        h *= 0x85EBCA6Bu;
+        h ^= h >> 13;
+        h *= 0xC2B2AE35u;
+        h ^= h >> 16;
+        const float v = scale * ((float)(h >> 8) * (1.0f / 8388608.0f) - 1.0f);
+        x[i] = add ? x[i] + v : v;
+    }
+}
+
 __global__ void k_init_state(ImgState *st, int B, double tol, int maxit, int fresh) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
@@ -114,6 +130,12 @@ void launch_fill(float *x, size_t count, float value, hipStream_t s) {
     if (count == 0) return;
     const int grid = (int)std::min<size_t>((count + 255) / 256, 4096);
     hipLaunchKernelGGL(k_fill, dim3(grid), dim3(256), 0, s, x, count, value);
+}
+
+void launch_fill_hash(float *x, size_t count, unsigned seed, float scale, bool add, hipStream_t s) {
+    if (count == 0) return;
+    const int grid = (int)std::min<size_t>((count + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_fill_hash, dim3(grid), dim3(256), 0, s, x, count, seed, scale, add ? 1 : 0);
 }
 
 void launch_init_state(ImgState *st, int B, double tol, int maxit, hipStream_t s, int fresh) {
