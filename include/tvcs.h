@@ -135,9 +135,9 @@ tvcs_handle tvcs_create(const float *A, int m, int n);
  *              work of this handle is ordered.
  * Storage formats other than FP32 also keep a transposed copy of A so that
  * both products read their reduction dimension contiguously (2x the bytes of
- * the format; the HBM traffic per product is unchanged), and need n a power of
- * two >= 16 (their MFMA tiles take 32-wide slices of n*n; TVCS_EUNSUPPORTED
- * otherwise).
+ * the format; the HBM traffic per product is unchanged), and need n >= 16
+ * (TVCS_EUNSUPPORTED otherwise); m and n*n are padded with zero rows and
+ * columns to multiples of 256 in the stored copies.
  */
 tvcs_handle tvcs_create_ex(const void *A, int a_is_fp64, int m, int n, int storage,
                            void *stream);

@@ -168,8 +168,8 @@ tvcs_ctx *create_impl(const void *A, int a_is_fp64, int m, int n, int storage, v
         fail(TVCS_EINVAL, "the partial-DCT operator is created with tvcs_create_dct");
     if (storage < TVCS_A_FP32 || storage > TVCS_A_FP8_ROWSCALE)
         fail(TVCS_EINVAL, "unknown storage format");
-    if (storage != TVCS_A_FP32 && (n < 16 || !is_pow2(n)))
-        fail(TVCS_EUNSUPPORTED, "low-precision storage needs n a power of two >= 16");
+    if (storage != TVCS_A_FP32 && n < 16)
+        fail(TVCS_EUNSUPPORTED, "low-precision storage needs n >= 16");
     std::unique_ptr<tvcs_ctx> h(new tvcs_ctx());
     h->m = m;
     h->n = n;

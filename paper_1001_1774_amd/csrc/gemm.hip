@@ -7,8 +7,10 @@
 //   FP8         Q = E4M3(A_ij / s_i), s_i = max_j |A_ij| / 448 (FP32), and Q^T
 // Both orientations are stored so that each product is a GEMM whose operands are
 // contiguous along the reduction dimension; the HBM bytes per product are the same
-// as for one copy (each product streams one copy once).  m_p = m rounded up to
-// 256 with zero rows.  Both copies are stored in MFMA fragment order: the 16 x 32
+// as for one copy (each product streams one copy once).  m_p = m and N_p = n^2
+// rounded up to 256 (zero rows of A, and zero columns for sides whose n^2 is not a
+// multiple of 256, e.g. 450; the forward product's batch operand is zero there and
+// the adjoint does not store those rows).  Both copies are stored in MFMA fragment order: the 16 x 32
 // block (rows 16 t .. +15, k 32 u .. +31) is 512 contiguous elements laid out as
 // the A operand of v_mfma_f32_16x16x32_bf16 expects them (lane l holds row l % 16,
 // k 8 (l / 16) .. +7), blocks ordered row-tile major.  A wave's operand load is then
@@ -111,7 +113,7 @@ constexpr int kXGroup = TVCS_X_GROUP;
 // Y blocks of a workgroup are then adjacent), or image-tile major in two arrays.
 constexpr bool kYKMajor = TVCS_Y_KMAJOR != 0;
 static_assert(kMPad % (16 * kXGroup) == 0 && 16 * kXGroup <= 256,
-              "row counts (m_p, and n * n for n >= 16) must be whole groups");
+              "row counts (m_p, and N_p) must be whole groups");
 constexpr int KMAX = 128;        // longest reduction step; every K slice is a multiple of it
 // 32-wide k tiles per pipeline step by image tiles per group (1, 2, 4, 8, 16), two
 // tables.  With one part of the batch operand a step moves NT * KF Y blocks over the
@@ -214,8 +216,8 @@ template <int MODE, int RT, int NT, int KF, int PARTS>
 __device__ inline void gemm_body(const void *__restrict__ Xhi, const void *__restrict__ Xlo,
                                  long long xkt, const u16 *__restrict__ Yhi,
                                  const u16 *__restrict__ Ylo, long long yimg, long long ytile,
-                                 int M, int kspan, int ks, int rb, float *__restrict__ out,
-                                 long long split_stride, long long ldo,
+                                 int M, int mstore, int kspan, int ks, int rb,
+                                 float *__restrict__ out, long long split_stride, long long ldo,
                                  u16 (*ys)[2 * NT * KF][512]) {
     constexpr int NB = NT * KF;           // Y blocks per step and part
     constexpr int YPW = PARTS * NB / 4;   // Y blocks moved per wave and step
@@ -369,7 +371,7 @@ __device__ inline void gemm_body(const void *__restrict__ Xhi, const void *__res
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
         const int row = row_wave + rt * 16 + 4 * (lane >> 4);
-        if (row >= M) continue;
+        if (row >= mstore) continue;
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             const int img = nt * 16 + lr;
@@ -385,7 +387,7 @@ template <int MODE, int RT, int NT, int KF>
 __global__ __launch_bounds__(kThreads) void k_gemm(
     const void *__restrict__ Xhi, const void *__restrict__ Xlo, long long xkt,
     const u16 *__restrict__ Yhi, const u16 *__restrict__ Ylo, long long yimg, long long ytile,
-    int M, int kspan,
+    int M, int mstore, int kspan,
     int RB, int KS, float *__restrict__ out, long long split_stride, long long ldo,
     const ImgState *__restrict__ st, int nact, int parity) {
     if (!any_active(st, nact)) return;
@@ -397,11 +399,11 @@ __global__ __launch_bounds__(kThreads) void k_gemm(
     const int ks = L / RB, rb = L % RB;
     __shared__ __attribute__((aligned(16))) u16 ys[2][2 * NT * KF][512];
     if (any_fresh(st, nact, parity))
-        gemm_body<MODE, RT, NT, KF, 2>(Xhi, Xlo, xkt, Yhi, Ylo, yimg, ytile, M, kspan, ks, rb,
-                                       out, split_stride, ldo, ys);
+        gemm_body<MODE, RT, NT, KF, 2>(Xhi, Xlo, xkt, Yhi, Ylo, yimg, ytile, M, mstore, kspan, ks,
+                                       rb, out, split_stride, ldo, ys);
     else
-        gemm_body<MODE, RT, NT, KF, 1>(Xhi, Xlo, xkt, Yhi, Ylo, yimg, ytile, M, kspan, ks, rb,
-                                       out, split_stride, ldo, ys);
+        gemm_body<MODE, RT, NT, KF, 1>(Xhi, Xlo, xkt, Yhi, Ylo, yimg, ytile, M, mstore, kspan, ks,
+                                       rb, out, split_stride, ldo, ys);
 }
 
 // ---- conversions ---------------------------------------------------------------
@@ -438,10 +440,10 @@ __device__ inline unsigned fp8_pack4(float a, float b, float c, float d) {
 // TRANS = true: rows j < N of A^T, reduction over i < m_p).  Each thread writes one
 // lane's 8 consecutive elements of a block; rows i >= m are zero.
 template <int MODE, bool TRANS>
-__global__ void k_frag(const float *__restrict__ A, int m, int N, int mp,
+__global__ void k_frag(const float *__restrict__ A, int m, int N, int Np, int mp,
                        const float *__restrict__ scale, void *__restrict__ hi,
                        void *__restrict__ lo) {
-    const size_t R = TRANS ? (size_t)N : (size_t)mp, K = TRANS ? (size_t)mp : (size_t)N;
+    const size_t R = TRANS ? (size_t)Np : (size_t)mp, K = TRANS ? (size_t)mp : (size_t)Np;
     const size_t chunks = R * K / 8, ktiles = K / 32;
     for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < chunks;
          c += (size_t)gridDim.x * blockDim.x) {
@@ -455,7 +457,7 @@ __global__ void k_frag(const float *__restrict__ A, int m, int N, int mp,
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const size_t i = TRANS ? k0 + j : r, col = TRANS ? r : k0 + j;   // A[i][col]
-            v[j] = i < (size_t)m ? A[i * N + col] : 0.f;
+            v[j] = (i < (size_t)m && col < (size_t)N) ? A[i * N + col] : 0.f;
             if (MODE == M_FP8) v[j] = fminf(fmaxf(v[j] / scale[i], -448.f), 448.f);
         }
         if (MODE == M_FP8) {
@@ -596,7 +598,7 @@ struct GemmArgs {
     long long ldx;
     const u16 *Yhi, *Ylo;
     long long yimg, ytile;
-    int M, kspan, RB, KS;
+    int M, mstore, kspan, RB, KS;   // rows of X (whole groups), rows written, ...
     float *out;
     long long split_stride, ldo;
     const ImgState *st;
@@ -607,8 +609,8 @@ template <int MODE, int RT, int NT, int KF>
 void launch_gemm(const GemmArgs &a, hipStream_t s) {
     const int total = a.RB * a.KS;
     hipLaunchKernelGGL((k_gemm<MODE, RT, NT, KF>), dim3(((total + 7) / 8) * 8), dim3(kThreads), 0, s,
-                       a.Xhi, a.Xlo, a.ldx >> 5, a.Yhi, a.Ylo, a.yimg, a.ytile, a.M, a.kspan, a.RB,
-                       a.KS, a.out, a.split_stride, a.ldo, a.st, a.nact, a.parity);
+                       a.Xhi, a.Xlo, a.ldx >> 5, a.Yhi, a.Ylo, a.yimg, a.ytile, a.M, a.mstore,
+                       a.kspan, a.RB, a.KS, a.out, a.split_stride, a.ldo, a.st, a.nact, a.parity);
 }
 
 template <int MODE, int RT, int NT>
@@ -701,13 +703,13 @@ void fwd_split(const LowpA &L, int &KS, int &kspan) {
     const int RB = L.mp / kRowsRT4;
     if (!TVCS_FWD_BALANCE) {
         KS = 1;
-        while (RB * KS < TVCS_FWD_TARGET_WG && (L.N / (KS * 2)) % KMAX == 0 &&
-               L.N / (KS * 2) >= 4 * KMAX)
+        while (RB * KS < TVCS_FWD_TARGET_WG && (L.Np / (KS * 2)) % KMAX == 0 &&
+               L.Np / (KS * 2) >= 4 * KMAX)
             KS *= 2;
-        kspan = L.N / KS;
+        kspan = L.Np / KS;
         return;
     }
-    balanced_split(RB, L.N, 64, KS, kspan);
+    balanced_split(RB, L.Np, 64, KS, kspan);
 }
 
 int fwd_splits(const LowpA &L) {
@@ -770,7 +772,7 @@ void adj_split(const LowpA &L, int &KS, int &kspan) {
         kspan = L.mp / KS;
         return;
     }
-    balanced_split(L.N / kRowsRT4, L.mp, TVCS_ADJ_SPLIT_MAX, KS, kspan);
+    balanced_split(L.Np / kRowsRT4, L.mp, TVCS_ADJ_SPLIT_MAX, KS, kspan);
 }
 
 int lowp_adj_splits(const LowpA &L) {
@@ -782,17 +784,18 @@ int lowp_adj_splits(const LowpA &L) {
 size_t lowp_storage_bytes(const LowpA &L0) {
     LowpA L = L0;
     L.mp = ((L.m + kMPad - 1) / kMPad) * kMPad;
+    L.Np = ((L.N + kMPad - 1) / kMPad) * kMPad;
     const int mode = mode_of(L.storage);
-    const size_t one = (size_t)L.mp * L.N * elem_bytes(mode);
+    const size_t one = (size_t)L.mp * L.Np * elem_bytes(mode);
     const size_t copies = mode == M_SPLIT ? 4 : 2;
     return copies * one + (mode == M_FP8 ? sizeof(float) * L.mp : 0) + 256 * 8;
 }
 
 void lowp_bind_storage(LowpA &L, void *base) {
     L.mp = ((L.m + kMPad - 1) / kMPad) * kMPad;
-    L.Np = L.N;
+    L.Np = ((L.N + kMPad - 1) / kMPad) * kMPad;
     const int mode = mode_of(L.storage);
-    const size_t one = (size_t)L.mp * L.N * elem_bytes(mode);
+    const size_t one = (size_t)L.mp * L.Np * elem_bytes(mode);
     char *p = static_cast<char *>(base);
     auto take = [&](size_t b) {
         void *r = p;
@@ -812,14 +815,14 @@ void lowp_bind_storage(LowpA &L, void *base) {
 
 void lowp_convert(LowpA &L, const float *A32, hipStream_t s) {
     const int mode = mode_of(L.storage);
-    const int grid = grid1d((size_t)L.mp * L.N / 8);
+    const int grid = grid1d((size_t)L.mp * L.Np / 8);
     if (mode == M_FP8)
         hipLaunchKernelGGL(k_fp8_scale, dim3(L.mp), dim3(256), 0, s, A32, L.m, L.N, L.scale);
 #define TVCS_FRAG(MODEV)                                                                     \
     hipLaunchKernelGGL((k_frag<MODEV, false>), dim3(grid), dim3(256), 0, s, A32, L.m, L.N,    \
-                       L.mp, L.scale, L.X_hi, L.X_lo);                                        \
-    hipLaunchKernelGGL((k_frag<MODEV, true>), dim3(grid), dim3(256), 0, s, A32, L.m, L.N, L.mp, \
-                       L.scale, L.XT_hi, L.XT_lo);
+                       L.Np, L.mp, L.scale, L.X_hi, L.X_lo);                                  \
+    hipLaunchKernelGGL((k_frag<MODEV, true>), dim3(grid), dim3(256), 0, s, A32, L.m, L.N, L.Np, \
+                       L.mp, L.scale, L.XT_hi, L.XT_lo);
     if (mode == M_FP8) {
         TVCS_FRAG(M_FP8)
     } else if (mode == M_SPLIT) {
@@ -831,7 +834,7 @@ void lowp_convert(LowpA &L, const float *A32, hipStream_t s) {
 }
 
 size_t lowp_work_bytes(const LowpA &L, int Bp) {
-    const size_t u = (size_t)Bp * L.N * sizeof(u16), r = (size_t)Bp * L.mp * sizeof(u16);
+    const size_t u = (size_t)Bp * L.Np * sizeof(u16), r = (size_t)Bp * L.mp * sizeof(u16);
     return 2 * u + 2 * r + (size_t)fwd_splits(L) * Bp * L.mp * sizeof(float) +
            (size_t)Bp * (L.N + L.m) * sizeof(float) + 6 * 256;
 }
@@ -843,7 +846,7 @@ void lowp_work_bind(LowpWork &W, const LowpA &L, int Bp, void *base) {
         p += (b + 255) / 256 * 256;
         return r;
     };
-    const size_t u = (size_t)Bp * L.N * sizeof(u16), r = (size_t)Bp * L.mp * sizeof(u16);
+    const size_t u = (size_t)Bp * L.Np * sizeof(u16), r = (size_t)Bp * L.mp * sizeof(u16);
     if (kYKMajor) {   // one array per operand, hi and lo blocks interleaved
         W.Ubf_hi = take(2 * u);
         W.Ubf_lo = (u16 *)W.Ubf_hi + 512;
@@ -947,22 +950,22 @@ void lowp_apply_A(const LowpA &L, LowpWork &W, int B, const float *U, const floa
     const int Bp = ((B + kBTile - 1) / kBTile) * kBTile;
     if (Bp > W.Bp) fail(TVCS_EINVAL, "MFMA workspace too small for the batch");
     long long yimg, ytile;
-    y_strides(L.N, Bp, yimg, ytile);
+    y_strides(L.Np, Bp, yimg, ytile);
     if (stw && (st != stw || !parts || nparts < 1))
         fail(TVCS_EINVAL, "MFMA product: the folded stop rule needs the image states and partials");
     if (parity >= 0 && !st) fail(TVCS_EINVAL, "MFMA product: increments need the image states");
     // outside the loop (parity < 0) every product is fresh and the tracked vectors
     // of a running loop (the request loop's other slots) are left alone
-    hipLaunchKernelGGL(k_split_frag, dim3(L.N / 128, Bp / 16), dim3(256), 0, s, U, L.N, L.N, Bp,
+    hipLaunchKernelGGL(k_split_frag, dim3(L.Np / 128, Bp / 16), dim3(256), 0, s, U, L.N, L.Np, Bp,
                        nullptr, (u16 *)W.Ubf_hi, (u16 *)W.Ubf_lo, yimg, ytile, stw, parts, nparts, B,
                        parity >= 0 ? W.Ut : nullptr, st, parity);
     int KS, kspan;
     fwd_split(L, KS, kspan);
     const long long split_stride = (long long)Bp * L.mp;
     for_each_group(Bp, B, W.fwd.nt, [&](int img0, int nt, int nact) {
-        const GemmArgs a{L.X_hi, L.X_lo, L.N, (const u16 *)W.Ubf_hi + (img0 / 16) * yimg,
-                         (const u16 *)W.Ubf_lo + (img0 / 16) * yimg, yimg, ytile, L.mp, kspan,
-                         0, KS, W.Rpart + (size_t)img0 * L.mp, split_stride, L.mp,
+        const GemmArgs a{L.X_hi, L.X_lo, L.Np, (const u16 *)W.Ubf_hi + (img0 / 16) * yimg,
+                         (const u16 *)W.Ubf_lo + (img0 / 16) * yimg, yimg, ytile, L.mp, L.mp,
+                         kspan, 0, KS, W.Rpart + (size_t)img0 * L.mp, split_stride, L.mp,
                          st ? st + img0 : nullptr, nact, parity};
         gemm_any(W.fwd, mode, nt, a, s);
     });
@@ -986,8 +989,8 @@ void lowp_apply_At(const LowpA &L, LowpWork &W, int B, const float *R, float *G,
     const long long split_stride = (long long)Bp * L.N;
     for_each_group(Bp, B, W.adj.nt, [&](int img0, int nt, int nact) {
         const GemmArgs a{L.XT_hi, L.XT_lo, L.mp, (const u16 *)W.Rbf_hi + (img0 / 16) * yimg,
-                         (const u16 *)W.Rbf_lo + (img0 / 16) * yimg, yimg, ytile, L.N, kspan, 0,
-                         KS, G + (size_t)img0 * L.N, split_stride, L.N,
+                         (const u16 *)W.Rbf_lo + (img0 / 16) * yimg, yimg, ytile, L.Np, L.N,
+                         kspan, 0, KS, G + (size_t)img0 * L.N, split_stride, L.N,
                          st ? st + img0 : nullptr, nact, parity};
         gemm_any(W.adj, mode, nt, a, s);
     });

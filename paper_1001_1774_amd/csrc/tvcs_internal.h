@@ -207,9 +207,9 @@ void launch_copy(const float *src, float *dst, size_t count, hipStream_t s);
 // ---------------------------------------------------------------------------
 struct LowpA {
     int storage;                 // TVCS_A_BF16 / _BF16_SPLIT / _FP8_ROWSCALE
-    int m, N, mp, Np;            // logical and padded sizes (mp multiple of kMPad)
-    void *X_hi, *X_lo;           // m_p x N   (row products, K = N contiguous)
-    void *XT_hi, *XT_lo;         // N   x m_p (column products, K = m contiguous)
+    int m, N, mp, Np;            // logical and padded sizes (mp, Np multiples of kMPad)
+    void *X_hi, *X_lo;           // m_p x N_p (row products, K = N_p contiguous)
+    void *XT_hi, *XT_lo;         // N_p x m_p (column products, K = m_p contiguous)
     float *scale;                // m_p row scales (fp8)
 };
 constexpr int kMPad = 256;       // row padding of A (and K padding of A^T)

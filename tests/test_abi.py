@@ -61,10 +61,7 @@ def test_argument_errors_without_device(clib):
     assert not T.tvcs_create_ex(A, 0, 4, 8, 9, None)
     assert "storage" in T.tvcs_last_error()
     assert not T.tvcs_create_ex(A, 0, 4, 8, T.TVCS_A_BF16, None)
-    assert "n a power of two >= 16" in T.tvcs_last_error()
-    assert not T.tvcs_create_ex(np.zeros((4, 24 * 24), np.float32), 0, 4, 24, T.TVCS_A_BF16,
-                                None)
-    assert "n a power of two >= 16" in T.tvcs_last_error()
+    assert "n >= 16" in T.tvcs_last_error()
     # NULL handle
     u = np.zeros(64, np.float32)
     f = np.zeros(4, np.float32)

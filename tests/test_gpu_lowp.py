@@ -3,10 +3,11 @@
 Bars: split storage must stay within 1e-4 relative iterate error of the FP64
 oracle on the FP64 A after a fixed number of iterations.  Plain BF16 and FP8
 storage must stay within 1e-4 of the oracle run on the de-quantised A they
-represent (FP64 arithmetic): the batch operand is split hi + lo in every mode, so
-what remains is the products' FP32 accumulation and the 2^-18 cross term.  Their
-error against the FP64-A oracle is set by the storage format itself; it is
-reported (relative error and PSNR), not bounded tightly.
+represent (FP64 arithmetic): what remains is the rounding of the batch operand
+(two bf16 parts in fresh products, the one-part increment otherwise, whose rounding
+is carried to the next increment) and the products' FP32 accumulation.  Their error
+against the FP64-A oracle is set by the storage format itself; it is reported
+(relative error and PSNR), not bounded tightly.
 """
 import sys
 
