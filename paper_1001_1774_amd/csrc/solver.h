@@ -123,6 +123,14 @@ struct tvcs_ctx {
 
     void ensure_workspace(int B) {
         if (B <= cap) return;
+        // a batch whose workspace cannot fit the device is refused before anything
+        // is freed, so the current workspace stays usable
+        size_t free_b = 0, total_b = 0;
+        TVCS_HIP(hipMemGetInfo(&free_b, &total_b));
+        if (workspace_bytes(B) > total_b)
+            fail(TVCS_ENOMEM, "the workspace of " + std::to_string(B) + " images (" +
+                                  std::to_string(workspace_bytes(B)) +
+                                  " bytes) exceeds the device memory");
         if (exec) {
             TVCS_HIP(hipGraphExecDestroy(exec));
             exec = nullptr;

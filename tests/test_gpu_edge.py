@@ -96,3 +96,22 @@ def test_ragged_rows_in_padded_storage(T, m):
     U = out["u"].cpu().numpy()
     for b in range(p.B):
         check(U[b], ref.u[b], bar_for(p.n, m, "bf16_split"), f"m={m} image {b}", say)
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+def test_batch_beyond_device_memory_is_refused(T, storage):
+    """A batch whose workspace exceeds the device (2^27 images of 32 x 32: half a TB of
+    iterates alone) is refused with TVCS_ENOMEM before any buffer is touched, and the
+    handle keeps working: the next solve gives the same bits as before."""
+    import torch
+    p = synth.make_problem("big", n=32, m=307, batch=1, seed_A=81)
+    with T.Solver(p.A.astype(np.float32), p.n, storage=storage) as s:
+        f = p.f[0].astype(np.float32)
+        u1 = s.solve(f, mu=p.mu, beta=p.beta, maxit=30, iadm=True)["u"].cpu().numpy()
+        F = torch.from_numpy(f[None]).cuda()
+        U = torch.empty(1, p.N, dtype=torch.float32, device="cuda")
+        rc = T.tvcs_solve_batch(s.h, F, 1 << 27, p.mu, p.beta, 0.0, 30, T.TVCS_IADM, U)
+        say(f"  {storage}: rc {rc}: {T.tvcs_last_error()}")
+        assert rc == T.TVCS_ENOMEM
+        u2 = s.solve(f, mu=p.mu, beta=p.beta, maxit=30, iadm=True)["u"].cpu().numpy()
+        assert np.array_equal(u1, u2)
