@@ -451,7 +451,40 @@ def bench_batched(args, np, torch, O, synth, tvcs):
             sweep[f"B{Bs}"] = r
             log(f"bf16 increment products B={Bs}: {ms_f:.3f} / {ms_a:.3f} ms")
     res["bf16_increment_batch_sweep"] = sweep
+    res["bb_split"] = bench_bb_batched(np, torch, tvcs, p, A32, F, tau)
     return res
+
+
+def bench_bb_batched(np, torch, tvcs, p, A32, F, tau, J=3):
+    """Split storage, all 64 images: IADM against IADM with J inner BB steps, as the
+    distance of each image to the limit of the iteration (IADM + J BB steps after 1500
+    outer iterations, 9000 products) after a given number of products with A, and the
+    time to get there (median and largest distance over the images)."""
+    with tvcs.Solver(A32, p.n, storage="bf16_split") as s:
+        s.tau = tau
+
+        def run(maxit, bb):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = s.solve_batch(F, mu=p.mu, beta=p.beta, maxit=maxit, iadm=True, bb_steps=bb)
+            torch.cuda.synchronize()
+            return r["u"].cpu().numpy().astype(np.float64), 1e3 * (time.perf_counter() - t0)
+
+        run(5, J)
+        ref, ms_ref = run(1500, J)
+        nr = np.linalg.norm(ref.reshape(p.B, -1), axis=1)
+        rows = []
+        for bb, ks in ((1, (300, 900)), (J, (100, 150, 200, 300))):
+            for k in ks:
+                u, ms = run(k, bb)
+                d = np.linalg.norm((u - ref).reshape(p.B, -1), axis=1) / nr
+                rows.append({"method": "iadm" if bb == 1 else f"iadm_bb{J}", "outer_iters": k,
+                             "a_products": 2 * k * bb, "ms": ms, "rec_per_s": p.B / (ms * 1e-3),
+                             "median_dist_to_limit": float(np.median(d)),
+                             "max_dist_to_limit": float(d.max())})
+                log(f"bb split section: {rows[-1]}")
+    return {"limit": f"IADM with {J} BB steps, 1500 outer iterations ({ms_ref:.0f} ms for "
+                     f"{p.B} images)", "runs": rows}
 
 
 def bench_serving(args, np, synth, tvcs):

@@ -69,7 +69,9 @@ extern "C" {
  * Phi(v + a p) <= max of the last 5 accepted values + 1e-4 a grad'p (Phi along the
  * line is an exact quadratic).  Each inner step costs two products with A (A^T r
  * and A p; r is carried).  The stop rule compares outer iterates; stats.iters
- * counts outer iterations.  FP32 storage of A only (TVCS_EUNSUPPORTED otherwise). */
+ * counts outer iterations.  Any stored A (with bf16, split bf16 or FP8 storage
+ * every product is computed afresh from a two-part batch operand, and
+ * stats.fresh_iters equals stats.iters); TVCS_EUNSUPPORTED for the partial DCT. */
 #define TVCS_BB_SHIFT 8
 #define TVCS_BB_STEPS(J) (((unsigned)(J) & 0xFu) << TVCS_BB_SHIFT)
 

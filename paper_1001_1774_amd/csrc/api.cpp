@@ -49,8 +49,8 @@ int solve_impl(tvcs_ctx *h, const float *Fin, int B, double mu, double beta, dou
     const bool iadm = (flags & TVCS_IADM) != 0;
     if (bb_inner(flags) > 1) {
         if (!iadm) fail(TVCS_EINVAL, "inner steps on the u-subproblem need TVCS_IADM");
-        if (h->storage != TVCS_A_FP32)
-            fail(TVCS_EUNSUPPORTED, "inner steps on the u-subproblem take FP32 storage of A");
+        if (h->dct())
+            fail(TVCS_EUNSUPPORTED, "inner steps on the u-subproblem take a stored matrix A");
     }
 
     h->begin_call();
@@ -147,7 +147,8 @@ int solve_impl(tvcs_ctx *h, const float *Fin, int B, double mu, double beta, dou
             stats[b].iters = s.iters;
             stats[b].status = s.status;
             stats[b].rel_change = s.rel;
-            stats[b].fresh_iters = h->lowprec() ? s.fresh : 0;
+            // with inner steps every product is fresh (two-part batch operand)
+            stats[b].fresh_iters = !h->lowprec() ? 0 : bb_inner(flags) > 1 ? s.iters : s.fresh;
             h->tiles_out(stats[b].tiles);
             stats[b].objective = objv[b];
             stats[b].tau = tau;

@@ -449,6 +449,8 @@ struct tvcs_ctx {
     // of (ALP) (bb.hip): r = A u - f, then per inner step A^T r, the direction p (shrink
     // pass with q held fixed after the first step, FFT solve into bb_P), A p, the step
     // length and v += a p, r += a A p; the stop rule compares u with the u saved first.
+    // With MFMA storage every product is fresh (two-part batch operand, no running g):
+    // directions do not shrink the way the increments of the plain iteration do.
     void enqueue_iteration_bb(int B, int parity, int inner, double mu, double beta, double c,
                               double ctau, double tau) {
         const int Bp = padded(B);
@@ -465,6 +467,7 @@ struct tvcs_ctx {
             a.c = c;
             a.ctau = ctau;
             a.parity = parity;
+            a.Gacc = nullptr;   // g is the sum of this step's (fresh) partials
             // the first step computes q^k from q^{k-1} into Qnew; later ones read it
             a.Qnew = parity ? Q0.as<float2>() : Q1.as<float2>();
             a.Qold = j == 0 ? (parity ? Q1.as<float2>() : Q0.as<float2>()) : a.Qnew;
@@ -478,7 +481,8 @@ struct tvcs_ctx {
                            beta, mu, tau, kBBSigma, work);
             launch_bb_update(B, N, m, Up, Pd, R.as<float>(), AP, m, bb_state.as<BBState>(), st, work);
         }
-        launch_bb_stop(n, B, Up, bb_Uk.as<float>(), bb_parts.as<double>(), st, parity, work);
+        // no product-form bookkeeping: every product of this path is fresh
+        launch_bb_stop(n, B, Up, bb_Uk.as<float>(), bb_parts.as<double>(), st, -1, work);
     }
 
     void build_graph(int B, unsigned flags, double beta, double c, double ctau) {

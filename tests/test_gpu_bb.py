@@ -104,6 +104,57 @@ def test_bb_reaches_the_oracle_fixed_point(T):
     assert dg <= max(3 * do, 1e-5)
 
 
+# MFMA storage: every product is fresh, its batch operand split into two bf16 parts
+# (2^-17 of v left, about 7.6e-6 per product against ~1e-7 in FP32).  The same
+# rounding model with that product error gives (max over 4 seeds): n = 32, J = 8,
+# K = 3: 3.1e-5; n = 128, J = 3, K = 4: 4.7e-5 (bf16; split adds A's own 2^-16).
+# Bars: about three times those; bf16 and FP8 against the oracle on the de-quantised A,
+# split against the FP64 A.
+LOWP_CASES = [("n32_m307", 8, 3, "bf16", 1e-4), ("n32_m307", 8, 3, "fp8_rowscale", 1e-4),
+              ("n128_m4096", 3, 4, "bf16", 1.5e-4), ("n128_m4096", 3, 4, "bf16_split", 3e-4)]
+
+
+@pytest.mark.parametrize("name,J,K,storage,bar", LOWP_CASES)
+def test_bb_parity_mfma_storage(T, name, J, K, storage, bar):
+    p = synth.workload(name)
+    A_or = p.A if storage == "bf16_split" else O.dequantized_A(p.A, storage)
+    tau = O.default_tau(A_or)
+    say(f"case {name} J={J} K={K} {storage}")
+    ref = O.iadm_bb(A_or, p.f[:1], p.n, p.mu, p.beta, tau, tol=0, maxit=K, inner=J)
+    with T.Solver(p.A.astype(np.float32), p.n, storage=storage) as s:
+        s.tau = tau
+        out = s.solve(p.f[0].astype(np.float32), mu=p.mu, beta=p.beta, maxit=K, iadm=True,
+                      bb_steps=J)
+    assert out["stats"]["iters"] == K and out["stats"]["fresh_iters"] == K
+    check(out["u"].cpu().numpy(), ref.u[0], bar, "u", say)
+
+
+def test_bb_mfma_storage_batch_invariance_and_limit(T):
+    """bf16 storage, n = 32, J = 3: three images solved together equal each solved
+    alone (bitwise, same outer counts); at tol 1e-5 the first image stops near the
+    oracle's limit on the de-quantised A, as the oracle itself does."""
+    p = synth.make_problem("bbm", n=32, m=307, batch=3, seed_A=33, sigma=[1e-3, 1e-2, 1e-3])
+    A_or = O.dequantized_A(p.A, "bf16")
+    tau = O.default_tau(A_or)
+    F = p.f.astype(np.float32)
+    with T.Solver(p.A.astype(np.float32), p.n, storage="bf16") as s:
+        s.tau = tau
+        rb = s.solve_batch(F, mu=p.mu, beta=p.beta, tol=1e-5, maxit=3000, iadm=True, bb_steps=3)
+        for b in range(3):
+            r1 = s.solve(F[b], mu=p.mu, beta=p.beta, tol=1e-5, maxit=3000, iadm=True, bb_steps=3)
+            assert r1["stats"]["iters"] == rb["stats"][b]["iters"]
+            assert np.array_equal(r1["u"].cpu().numpy(), rb["u"][b].cpu().numpy())
+    star = O.iadm_bb(A_or, p.f[:1], p.n, p.mu, p.beta, tau, tol=1e-9, maxit=6000, inner=3)
+    ref = O.iadm_bb(A_or, p.f[:1], p.n, p.mu, p.beta, tau, tol=1e-5, maxit=3000, inner=3)
+    u = rb["u"][0].cpu().numpy().astype(np.float64)
+    dg = float(np.linalg.norm(u - star.u[0]) / np.linalg.norm(star.u[0]))
+    do = float(np.linalg.norm(ref.u[0] - star.u[0]) / np.linalg.norm(star.u[0]))
+    it = rb["stats"][0]["iters"]
+    say(f"  distance to the limit: gpu {dg:.2e} after {it}, oracle {do:.2e} after {ref.iters[0]}")
+    assert it < 3000
+    assert dg <= max(3 * do, 1e-4)
+
+
 def test_bb_flag_limits(T):
     import torch
     p = synth.workload("n32_m307")
@@ -115,7 +166,9 @@ def test_bb_flag_limits(T):
         one = s.solve(f, mu=p.mu, beta=p.beta, maxit=20, iadm=True, bb_steps=1)["u"]
         plain = s.solve(f, mu=p.mu, beta=p.beta, maxit=20, iadm=True)["u"]
         assert np.array_equal(one.cpu().numpy(), plain.cpu().numpy())
-    with T.Solver(p.A.astype(np.float32), p.n, storage="bf16") as s:
+    q = synth.make_dct_problem("bbdct", 16, 0.3)
+    with T.Solver.partial_dct(q.rows, q.n) as s:
         with pytest.raises(T.TvcsError) as ei:
-            s.solve(f, mu=p.mu, beta=p.beta, maxit=5, iadm=True, bb_steps=3)
+            s.solve(q.f[0].astype(np.float32), mu=q.mu, beta=q.beta, maxit=5, iadm=True,
+                    bb_steps=3)
         assert ei.value.code == T.TVCS_EUNSUPPORTED
