@@ -279,9 +279,8 @@ int tvcs_get_tiles(tvcs_handle h, int *tiles);
  * tvcs_time_products: measurement helper.  Average device time in milliseconds
  * of one forward product (r = A u - f, all images of a batch of B) and of one
  * adjoint product (A^T r, including its partial-sum reduction), over `reps`
- * launches of each in the order an iteration runs them (forward, then adjoint),
- * queued back to back with HIP events around each launch on the stream the solver
- * launches them on, with the launch configuration a solve of B images uses.  The inputs are
+ * launches of each timed with HIP events on the stream the solver launches them
+ * on, with the launch configuration a solve of B images uses.  The inputs are
  * deterministic hashed values of unit size, not zeros (MFMA clocks depend on the
  * operands' bits); the workspace contents are overwritten.  Either output may
  * be NULL.

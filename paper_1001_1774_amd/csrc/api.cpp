@@ -406,49 +406,38 @@ int tvcs_time_products(tvcs_handle h, int B, int reps, int form, float *ms_forwa
         h->apply_At(Bp, B, R, st, 0);
         launch_fill_hash(U, (size_t)B * h->N, 3u, 1.0f / 1024.0f, true, h->work);
         launch_init_state(st, B, 0.0, 1, h->work, form ? 0 : 1);
-        // a warm-up pair, then `reps` pairs in the order an iteration runs them (the
-        // forward product, then the adjoint), queued back to back with a pair of HIP
-        // events around each launch, so that each product finds A in the caches as it
-        // does in a solve and no launch waits for the host.  In the increment form each
+        // warm-up launch of each, then the timed runs.  In the increment form each
         // timed launch follows (outside its timed span) a move of its input by 2^-10
         // of its size, as between two iterations: otherwise the increments of
-        // repeated launches on one input round to zero.
+        // repeated launches on one input round to zero after a few launches.
         const bool incr = form == 1 && h->lowprec();
         h->apply_A(Bp, B, U, F, R, st, 0);
         h->apply_At(Bp, B, R, st, 0);
-        std::vector<hipEvent_t> ev((size_t)4 * reps, nullptr);
-        struct Events {   // destroyed on every exit path
-            std::vector<hipEvent_t> &v;
-            ~Events() {
-                for (hipEvent_t e : v)
-                    if (e) (void)hipEventDestroy(e);
+        auto timed = [&](auto &&op, float *moved, size_t count) {
+            float total = 0.f, ms = 0.f;
+            if (!incr) {
+                TVCS_HIP(hipEventRecord(h->ev_t0, h->work));
+                for (int i = 0; i < reps; ++i) op();
+                TVCS_HIP(hipEventRecord(h->ev_t1, h->work));
+                TVCS_HIP(hipEventSynchronize(h->ev_t1));
+                TVCS_HIP(hipEventElapsedTime(&total, h->ev_t0, h->ev_t1));
+                return total / reps;
             }
-        } guard{ev};
-        for (hipEvent_t &e : ev) TVCS_HIP(hipEventCreate(&e));
-        for (int i = 0; i < reps; ++i) {
-            if (incr)
-                launch_fill_hash(U, (size_t)B * h->N, 16u + 2u * (unsigned)i, 1.0f / 1024.0f, true,
-                                 h->work);
-            TVCS_HIP(hipEventRecord(ev[4 * i], h->work));
-            h->apply_A(Bp, B, U, F, R, st, 0);
-            TVCS_HIP(hipEventRecord(ev[4 * i + 1], h->work));
-            if (incr)
-                launch_fill_hash(R, (size_t)B * h->m, 17u + 2u * (unsigned)i, 1.0f / 1024.0f, true,
-                                 h->work);
-            TVCS_HIP(hipEventRecord(ev[4 * i + 2], h->work));
-            h->apply_At(Bp, B, R, st, 0);
-            TVCS_HIP(hipEventRecord(ev[4 * i + 3], h->work));
-        }
-        TVCS_HIP(hipEventSynchronize(ev.back()));
-        float tf = 0.f, ta = 0.f, ms = 0.f;
-        for (int i = 0; i < reps; ++i) {
-            TVCS_HIP(hipEventElapsedTime(&ms, ev[4 * i], ev[4 * i + 1]));
-            tf += ms;
-            TVCS_HIP(hipEventElapsedTime(&ms, ev[4 * i + 2], ev[4 * i + 3]));
-            ta += ms;
-        }
-        if (ms_forward) *ms_forward = tf / reps;
-        if (ms_adjoint) *ms_adjoint = ta / reps;
+            for (int i = 0; i < reps; ++i) {
+                launch_fill_hash(moved, count, 16u + (unsigned)i, 1.0f / 1024.0f, true, h->work);
+                TVCS_HIP(hipEventRecord(h->ev_t0, h->work));
+                op();
+                TVCS_HIP(hipEventRecord(h->ev_t1, h->work));
+                TVCS_HIP(hipEventSynchronize(h->ev_t1));
+                TVCS_HIP(hipEventElapsedTime(&ms, h->ev_t0, h->ev_t1));
+                total += ms;
+            }
+            return total / reps;
+        };
+        const float msf = timed([&] { h->apply_A(Bp, B, U, F, R, st, 0); }, U, (size_t)B * h->N);
+        if (ms_forward) *ms_forward = msf;
+        const float msa = timed([&] { h->apply_At(Bp, B, R, st, 0); }, R, (size_t)B * h->m);
+        if (ms_adjoint) *ms_adjoint = msa;
         TVCS_HIP(hipGetLastError());
         return TVCS_OK;
     });
