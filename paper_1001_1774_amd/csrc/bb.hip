@@ -9,15 +9,17 @@
 // kernels compute (shrink pass with q held fixed after the first step, FFT solve,
 // the increment written to a separate array), then
 //   * the squared norms of p, D p and A p (k_bb_partials, fixed-order sums),
-//   * the step length a (k_bb_step, one lane per image): 1 for the first step (the
-//     IADM u-step), else the BB length (p'M p / p'H p of the previous direction),
-//     halved until Phi(v + a p) <= max of the last kBBMemory values + sigma a g'p
-//     (non-monotone Armijo test), Phi along the line being the exact quadratic
-//     Phi(v) + a g'p + a^2/2 p'H p with g'p = -p'M p,
-//   * v += a p and r += a A p (k_bb_update; r = A v - f is carried, so an inner step
-//     costs the products A^T r and A p).
-// After the inner steps, k_bb_norms and k_bb_stop apply the stop rule (eq. (stop))
-// to the outer iterates u^{k+1} = v and u^k.
+//   * the step length a: 1 for the first step (the IADM u-step), else the BB length
+//     (p'M p / p'H p of the previous direction), halved until Phi(v + a p) <= max of
+//     the last kBBMemory values + sigma a g'p (non-monotone Armijo test), Phi along
+//     the line being the exact quadratic Phi(v) + a g'p + a^2/2 p'H p, g'p = -p'M p,
+//   * v += a p and r += a A p (r = A v - f is carried, so an inner step costs the
+//     products A^T r and A p).
+// One pass (k_bb_apply) does the last two: every workgroup of an image computes the
+// step length from the partials itself (the same fixed-order sums, so the same a),
+// then updates its share of v and r.  The first inner step also saves u^k, and the
+// last one adds the stop-rule partials ||u^{k+1} - u^k||^2 and ||u^k||^2 of its
+// pixels; k_bb_stop then applies the stop rule (eq. (stop)).
 #include "device_stop.h"
 #include "tvcs_internal.h"
 
@@ -79,15 +81,11 @@ __global__ __launch_bounds__(kThreads) void k_bb_partials(int n, int m, const fl
     }
 }
 
-// one 64-lane block per image: the step length of inner step j
-__global__ __launch_bounds__(64) void k_bb_step(const double *__restrict__ parts, int nb,
-                                                BBState *__restrict__ bs,
-                                                const ImgState *__restrict__ st, int j,
-                                                double beta, double mu, double mu_tau,
-                                                double sigma) {
-    const int b = blockIdx.x;
-    if (!st[b].active) return;
-    const int lane = threadIdx.x;
+// The step length of inner step j for image b from the k_bb_partials sums (wave 0;
+// lane 0 returns it, with the new state in s).
+__device__ inline double bb_length(const double *__restrict__ parts, int nb, BBState &s, int b,
+                                   int j, double beta, double mu, double mu_tau, double sigma) {
+    const int lane = threadIdx.x & 63;
     double pp = 0.0, dd = 0.0, aa = 0.0;
     for (int x = lane; x < nb; x += 64) {
         const double *o = parts + ((size_t)b * nb + x) * 3;
@@ -101,8 +99,6 @@ __global__ __launch_bounds__(64) void k_bb_step(const double *__restrict__ parts
         dd += __shfl_xor(dd, off, 64);
         aa += __shfl_xor(aa, off, 64);
     }
-    if (lane != 0) return;
-    BBState s = bs[b];
     if (j == 0) {   // a new u-subproblem: its history starts at Phi(v_0) = 0
         s.nphi = 1;
         s.phis[0] = 0.0;
@@ -111,63 +107,83 @@ __global__ __launch_bounds__(64) void k_bb_step(const double *__restrict__ parts
     }
     const double pMp = beta * dd + mu_tau * pp, pHp = beta * dd + mu * aa, gp = -pMp;
     double a = (j == 0 || !(s.prev_pHp > 0.0) || !(s.prev_pMp > 0.0)) ? 1.0 : s.prev_pMp / s.prev_pHp;
-    double ref = -INFINITY;   // the largest of the last kBBMemory accepted values
+    // the largest of the last kBBMemory accepted values: the circular buffer holds
+    // them in slots 0 .. min(nphi, kBBMemory) - 1 (constant indices keep s in registers)
+    double ref = -INFINITY;
     const int cnt = min(s.nphi, kBBMemory);
-    for (int i = 1; i <= cnt; ++i) ref = fmax(ref, s.phis[(s.nphi - i) % kBBMemory]);
+#pragma unroll
+    for (int k = 0; k < kBBMemory; ++k)
+        if (k < cnt) ref = fmax(ref, s.phis[k]);
     for (int it = 0; it < 64 && s.phi + a * gp + 0.5 * a * a * pHp > ref + sigma * a * gp; ++it)
         a *= 0.5;
     s.phi += a * gp + 0.5 * a * a * pHp;
-    s.phis[s.nphi % kBBMemory] = s.phi;
+    const int slot = s.nphi % kBBMemory;
+#pragma unroll
+    for (int k = 0; k < kBBMemory; ++k)
+        if (k == slot) s.phis[k] = s.phi;
     s.nphi += 1;
     s.prev_pMp = pMp;
     s.prev_pHp = pHp;
     s.alpha = a;
-    bs[b] = s;
+    return a;
 }
 
-// v += a p over B x N and r += a A p over B x m (FP64 arithmetic, FP32 stores)
-__global__ void k_bb_update(int B, int N, int m, float *__restrict__ U, const float *__restrict__ P,
-                            float *__restrict__ R, const float *__restrict__ AP, int ldr,
-                            const BBState *__restrict__ bs, const ImgState *__restrict__ st) {
-    const size_t per = (size_t)N + m, total = (size_t)B * per;
-    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
-         e += (size_t)gridDim.x * blockDim.x) {
-        const int b = (int)(e / per);
-        if (!st[b].active) continue;
-        const size_t i = e - (size_t)b * per;
-        const double a = bs[b].alpha;
-        if (i < (size_t)N) {
-            float *u = U + (size_t)b * N + i;
-            *u = (float)((double)*u + a * (double)P[(size_t)b * N + i]);
-        } else {
-            const size_t k = i - N;
-            float *r = R + (size_t)b * ldr + k;
-            *r = (float)((double)*r + a * (double)AP[(size_t)b * ldr + k]);
-        }
-    }
-}
-
-// stop-rule partials of the outer step: ||u - u_k||^2 and ||u_k||^2 per block
-__global__ __launch_bounds__(kThreads) void k_bb_norms(int N, const float *__restrict__ U,
-                                                       const float *__restrict__ Uk,
-                                                       double *__restrict__ parts,
-                                                       const ImgState *__restrict__ st) {
+// Inner step j of image b (blockIdx.y), workgroup x of nb: the step length (read
+// from bs_in, the new state written by workgroup 0 to bs_out: the workgroups of the
+// image all read the old state), then v += a p over pixels [x pc, (x + 1) pc) and
+// r += a A p over rows [x rc, (x + 1) rc), FP64 arithmetic, FP32 stores.  j == 0 first
+// copies v to Uk (u^k); the last step (last) writes the block's ||v - u^k||^2 and
+// ||u^k||^2 to nparts (2 doubles per block, fixed-order sums) for the stop rule.
+__global__ __launch_bounds__(kThreads) void k_bb_apply(
+    int N, int m, float *__restrict__ U, const float *__restrict__ P, float *__restrict__ R,
+    const float *__restrict__ AP, int ldr, float *__restrict__ Uk, const double *__restrict__ parts,
+    const BBState *__restrict__ bs_in, BBState *__restrict__ bs_out,
+    const ImgState *__restrict__ st, int j, int last, double beta, double mu, double mu_tau,
+    double sigma, double *__restrict__ nparts) {
     const int b = blockIdx.y;
     if (!st[b].active) return;
     __shared__ double red[kThreads / 64];
-    const int nb = gridDim.x, pc = (N + nb - 1) / nb;
+    __shared__ double s_a;
+    const int nb = gridDim.x;
+    if (threadIdx.x < 64) {
+        BBState s = bs_in[b];
+        const double a = bb_length(parts, nb, s, b, j, beta, mu, mu_tau, sigma);
+        if (threadIdx.x == 0) {
+            s_a = a;
+            if (blockIdx.x == 0) bs_out[b] = s;
+        }
+    }
+    __syncthreads();
+    const double a = s_a;
+    const int pc = (N + nb - 1) / nb, rc = (m + nb - 1) / nb;
     const int p0 = blockIdx.x * pc, p1 = min(N, p0 + pc);
+    float *u = U + (size_t)b * N;
+    const float *p = P + (size_t)b * N;
+    float *uk = Uk + (size_t)b * N;
     double du = 0.0, uu = 0.0;
     for (int e = p0 + threadIdx.x; e < p1; e += kThreads) {
-        const double o = Uk[(size_t)b * N + e], d = (double)U[(size_t)b * N + e] - o;
-        du += d * d;
-        uu += o * o;
+        const float old = u[e];
+        if (j == 0) uk[e] = old;
+        const float nv = (float)((double)old + a * (double)p[e]);
+        u[e] = nv;
+        if (last) {
+            const double o = j == 0 ? (double)old : (double)uk[e], d = (double)nv - o;
+            du += d * d;
+            uu += o * o;
+        }
     }
-    du = block_sum(du, red);
-    uu = block_sum(uu, red);
-    if (threadIdx.x == 0) {
-        parts[((size_t)b * nb + blockIdx.x) * 2] = du;
-        parts[((size_t)b * nb + blockIdx.x) * 2 + 1] = uu;
+    float *r = R + (size_t)b * ldr;
+    const float *ap = AP + (size_t)b * ldr;
+    const int r0 = blockIdx.x * rc, r1 = min(m, r0 + rc);
+    for (int i = r0 + threadIdx.x; i < r1; i += kThreads)
+        r[i] = (float)((double)r[i] + a * (double)ap[i]);
+    if (last) {
+        du = block_sum(du, red);
+        uu = block_sum(uu, red);
+        if (threadIdx.x == 0) {
+            nparts[((size_t)b * nb + blockIdx.x) * 2] = du;
+            nparts[((size_t)b * nb + blockIdx.x) * 2 + 1] = uu;
+        }
     }
 }
 
@@ -179,44 +195,29 @@ __global__ __launch_bounds__(64) void k_bb_stop(ImgState *__restrict__ st,
     stop_rule(st + b, parts + (size_t)b * nb * 2, nb, nullptr, parity);
 }
 
-__global__ void k_copy(const float *__restrict__ src, float *__restrict__ dst, size_t count) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
-         i += (size_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
-}
-
-int grid_of(size_t count) { return (int)std::min<size_t>((count + 255) / 256, 8192); }
-
 }  // namespace
 
 int bb_blocks(int n) { return std::max(1, std::min(64, n * n / 1024)); }
 
-void launch_bb_step(int n, int m, int B, const float *P, const float *AP, int ldap, double *parts,
-                    BBState *bs, const ImgState *st, int j, double beta, double mu, double tau,
-                    double sigma, hipStream_t s) {
+void launch_bb_step(int n, int m, int B, float *U, const float *P, float *R, const float *AP,
+                    int ldr, float *Uk, double *parts, BBState *bs, const ImgState *st, int j,
+                    bool last, double beta, double mu, double tau, double sigma, hipStream_t s) {
     const int nb = bb_blocks(n);
-    hipLaunchKernelGGL(k_bb_partials, dim3(nb, B), dim3(kThreads), 0, s, n, m, P, AP, ldap, parts,
+    hipLaunchKernelGGL(k_bb_partials, dim3(nb, B), dim3(kThreads), 0, s, n, m, P, AP, ldr, parts,
                        st);
-    hipLaunchKernelGGL(k_bb_step, dim3(B), dim3(64), 0, s, parts, nb, bs, st, j, beta, mu,
-                       mu / tau, sigma);
+    // the state ping-pongs between bs[0 .. B) and bs[B .. 2B) by the parity of j
+    const BBState *bs_in = bs + (size_t)(j & 1) * B;
+    BBState *bs_out = bs + (size_t)((j + 1) & 1) * B;
+    hipLaunchKernelGGL(k_bb_apply, dim3(nb, B), dim3(kThreads), 0, s, n * n, m, U, P, R, AP, ldr,
+                       Uk, parts, bs_in, bs_out, st, j, last ? 1 : 0, beta, mu, mu / tau, sigma,
+                       parts + (size_t)3 * B * nb);
 }
 
-void launch_bb_update(int B, int N, int m, float *U, const float *P, float *R, const float *AP,
-                      int ldr, const BBState *bs, const ImgState *st, hipStream_t s) {
-    hipLaunchKernelGGL(k_bb_update, dim3(grid_of((size_t)B * ((size_t)N + m))), dim3(256), 0, s, B,
-                       N, m, U, P, R, AP, ldr, bs, st);
-}
-
-void launch_bb_stop(int n, int B, const float *U, const float *Uk, double *parts, ImgState *st,
-                    int parity, hipStream_t s) {
+void launch_bb_stop(int n, int B, double *parts, ImgState *st, int parity, hipStream_t s) {
     const int nb = bb_blocks(n);
-    hipLaunchKernelGGL(k_bb_norms, dim3(nb, B), dim3(kThreads), 0, s, n * n, U, Uk, parts, st);
-    hipLaunchKernelGGL(k_bb_stop, dim3(B), dim3(64), 0, s, st, parts, nb, parity);
+    hipLaunchKernelGGL(k_bb_stop, dim3(B), dim3(64), 0, s, st, parts + (size_t)3 * B * nb, nb,
+                       parity);
 }
 
-void launch_copy(const float *src, float *dst, size_t count, hipStream_t s) {
-    if (count == 0) return;
-    hipLaunchKernelGGL(k_copy, dim3(grid_of(count)), dim3(256), 0, s, src, dst, count);
-}
 
 }  // namespace tvcs

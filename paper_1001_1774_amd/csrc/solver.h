@@ -441,14 +441,16 @@ struct tvcs_ctx {
             launch_fill(bb_P.as<float>(), (size_t)Bp * Nn, 0.f, work);   // padded rows stay 0
         }
         bb_AP.ensure(sizeof(float) * Bp * (size_t)m);
-        bb_parts.ensure(sizeof(double) * 3 * B * (size_t)bb_blocks(n));
-        bb_state.ensure(sizeof(BBState) * B);
+        bb_parts.ensure(sizeof(double) * 5 * B * (size_t)bb_blocks(n));
+        bb_state.ensure(sizeof(BBState) * 2 * B);
     }
 
     // One outer iteration of IADM whose u-step is `inner` steps on the u-subproblem
     // of (ALP) (bb.hip): r = A u - f, then per inner step A^T r, the direction p (shrink
     // pass with q held fixed after the first step, FFT solve into bb_P), A p, the step
-    // length and v += a p, r += a A p; the stop rule compares u with the u saved first.
+    // length and v += a p, r += a A p (one pass, which at the first step also saves u
+    // and at the last adds up the stop-rule norms); the stop rule compares u with the
+    // u saved first.
     // With MFMA storage every product is fresh (two-part batch operand, no running g):
     // directions do not shrink the way the increments of the plain iteration do.
     void enqueue_iteration_bb(int B, int parity, int inner, double mu, double beta, double c,
@@ -456,7 +458,6 @@ struct tvcs_ctx {
         const int Bp = padded(B);
         ImgState *st = state.as<ImgState>();
         float *Up = U.as<float>(), *Pd = bb_P.as<float>(), *AP = bb_AP.as<float>();
-        launch_copy(Up, bb_Uk.as<float>(), (size_t)B * N, work);
         apply_A(Bp, B, Up, F.as<float>(), R.as<float>(), st);
         const float2 *twp = tw.as<float2>();
         float2 *Sp = S.as<float2>();
@@ -477,12 +478,12 @@ struct tvcs_ctx {
             launch_fft_rows_inv(n, B, Sp, Up, parts.as<double>(), twp, st, counters.as<int>(), work,
                                 nullptr, nullptr, false, parity, Pd);
             apply_A(Bp, B, Pd, nullptr, AP, st);
-            launch_bb_step(n, m, B, Pd, AP, m, bb_parts.as<double>(), bb_state.as<BBState>(), st, j,
+            launch_bb_step(n, m, B, Up, Pd, R.as<float>(), AP, m, bb_Uk.as<float>(),
+                           bb_parts.as<double>(), bb_state.as<BBState>(), st, j, j == inner - 1,
                            beta, mu, tau, kBBSigma, work);
-            launch_bb_update(B, N, m, Up, Pd, R.as<float>(), AP, m, bb_state.as<BBState>(), st, work);
         }
         // no product-form bookkeeping: every product of this path is fresh
-        launch_bb_stop(n, B, Up, bb_Uk.as<float>(), bb_parts.as<double>(), st, -1, work);
+        launch_bb_stop(n, B, bb_parts.as<double>(), st, -1, work);
     }
 
     void build_graph(int B, unsigned flags, double beta, double c, double ctau) {

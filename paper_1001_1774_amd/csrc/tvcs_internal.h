@@ -189,18 +189,17 @@ struct BBState {                      // per image, rewritten at the first inner
     int nphi, pad_;
 };
 int bb_blocks(int n);                 // partial sums per image of the BB reductions
-// k_bb_partials + k_bb_step: squared norms of p, D p, A p; the step length of inner
-// step j into bs (parts: B x bb_blocks(n) x 3 doubles)
-void launch_bb_step(int n, int m, int B, const float *P, const float *AP, int ldap, double *parts,
-                    BBState *bs, const ImgState *st, int j, double beta, double mu, double tau,
-                    double sigma, hipStream_t s);
-// U += a P (B x N) and R += a AP (B x m, row stride ldr), a per image from bs
-void launch_bb_update(int B, int N, int m, float *U, const float *P, float *R, const float *AP,
-                      int ldr, const BBState *bs, const ImgState *st, hipStream_t s);
-// the stop rule for the outer step from Uk to U (parts: B x bb_blocks(n) x 2 doubles)
-void launch_bb_stop(int n, int B, const float *U, const float *Uk, double *parts, ImgState *st,
-                    int parity, hipStream_t s);
-void launch_copy(const float *src, float *dst, size_t count, hipStream_t s);
+// Inner step j of the B images (k_bb_partials, k_bb_apply): squared norms of p, D p
+// and A p, the step length, U += a P (B x N) and R += a AP (B x m, row stride ldr);
+// j == 0 first saves U into Uk, and the last step (last) leaves the stop-rule partials
+// of U against Uk.  parts: B x bb_blocks(n) x 5 doubles; bs: 2 B states (the state
+// alternates between the halves with the parity of j).
+void launch_bb_step(int n, int m, int B, float *U, const float *P, float *R, const float *AP,
+                    int ldr, float *Uk, double *parts, BBState *bs, const ImgState *st, int j,
+                    bool last, double beta, double mu, double tau, double sigma, hipStream_t s);
+// the stop rule for the outer step from Uk to U, from the partials the last inner
+// step left in parts
+void launch_bb_stop(int n, int B, double *parts, ImgState *st, int parity, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // MFMA products for bf16 / split-bf16 / fp8 storage (gemm.hip)
