@@ -8,7 +8,8 @@ rectangles/disks plus a linear ramp, noise sigma = 1e-3, mu = 1e3, beta = 10,
 one full reconstruction; inputs are resident in HBM before the timed region.
 
 Prints one JSON line with the throughput, the roofline of the dominant kernel
-(the A u product, timed with HIP events on the stream it runs on), the FP64
+(the one-pass product g = A^T (A u - f), timed with HIP events on the stream it
+runs on), the FP64
 oracle timed on the host cores, and the relative error of the GPU result
 against that oracle run (same tau on both sides).
 """
@@ -187,15 +188,18 @@ def main():
     log(f"measured peaks: HBM read {peak_read:.0f} GB/s, bf16 MFMA {peak_mfma:.0f} TFLOP/s")
     ACHIEVABLE.update(hbm_read_gbs=peak_read, mfma_bf16_tflops=peak_mfma)
 
-    # the dominant kernel is the slower of the two products (per launch)
-    if ms_adj >= ms_fwd:
-        dom = ("k_gemv_cols", "k_gemv_cols<1> (g = A^T r)", adj_gbs, adj_bytes)
-    else:
-        dom = ("k_gemv_rows", "k_gemv_rows<1,2> (r = A u - f)", fwd_gbs, fwd_bytes)
-    roofline = {"bound": "hbm", "achieved": dom[2], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": dom[2] / HBM_PEAK_GBS, "traffic": measured_traffic(dom[0]),
-                "algorithmic_bytes": dom[3], "kernel": dom[1],
-                "achievable_peak": peak_read, "frac_of_achievable": dom[2] / peak_read}
+    # The solve's dominant kernel: one image at n = 128 takes both products in one
+    # pass over A (k_gemv_fused; its band partials are then added by k_sum_bands);
+    # the two separate products above are what a batch of images uses.
+    ms_pass, ms_sum = solver.time_fused(reps=20)
+    pass_bytes = a_bytes + 4.0 * (2 * p.N + p.m)        # A, u, f, g
+    pass_gbs = pass_bytes / (ms_pass * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": pass_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": pass_gbs / HBM_PEAK_GBS, "traffic": measured_traffic("k_gemv_fused"),
+                "algorithmic_bytes": pass_bytes,
+                "kernel": "k_gemv_fused (g = A^T (A u - f), A read once)",
+                "launch_ms": ms_pass, "band_sum_ms": ms_sum,
+                "achievable_peak": peak_read, "frac_of_achievable": pass_gbs / peak_read}
 
     out = {
         "metric": "reconstructions/sec at <=1e-4 rel err vs FP64 (batched vs plain); GEMV GB/s",
@@ -216,6 +220,7 @@ def main():
         "rel_err_vs_fp64_oracle": rel_err,
         "psnr_db_vs_fp64_oracle": psnr,
         "measured_peaks": dict(ACHIEVABLE),
+        # the two products as separate passes (the path of batches of images)
         "gemv_gbs": {"forward": fwd_gbs, "adjoint": adj_gbs,
                      "forward_ms": ms_fwd, "adjoint_ms": ms_adj},
         "roofline": roofline,
@@ -264,7 +269,8 @@ def profile_mode(args):
     --products W: the forward product (r = A u - f) and the adjoint product (A^T r)
     of workload W's A in `--storage`, for a batch of `--batch`, `--reps` launches
     each through tvcs_time_products (`--form increment`: the one-part increment form
-    of the low-precision products).  First copies a 256 MiB device buffer once: a
+    of the low-precision products); for one image with FP32 A at n*n <= 16384 also
+    the one-pass product and its band sum (tvcs_time_fused).  First copies a 256 MiB device buffer once: a
     plain copy of known size (reads and writes 268435456 bytes) against which the
     FETCH_SIZE / WRITE_SIZE counters are scaled.
     --solve W: `--batch` images of workload W (its seeded images, repeated when the
@@ -314,10 +320,16 @@ def profile_mode(args):
     with tvcs.Solver(p.A, p.n, storage=args.storage) as s:
         fwd, adj = s.time_products(args.batch, args.reps, increment=args.form == "increment")
         tiles = s.tiles
+        # one image with FP32 A at n*n <= 16384: also the one-pass product and its
+        # band sum (the kernels a single-image solve runs)
+        fused = (s.time_fused(args.reps) if args.storage == "fp32" and args.batch == 1
+                 and p.N <= 16384 else None)
     print(json.dumps({"workload": args.products, "storage": args.storage, "batch": args.batch,
                       "tiles": tiles,
                       "form": args.form, "reps": args.reps, "forward_ms": fwd,
-                      "adjoint_ms": adj, "copy_bytes": COPY_BYTES}), flush=True)
+                      "adjoint_ms": adj, "fused_pass_ms": fused[0] if fused else None,
+                      "band_sum_ms": fused[1] if fused else None,
+                      "copy_bytes": COPY_BYTES}), flush=True)
 
 
 MFMA_BF16_PEAK = 2.5e15   # MI355X dense bf16 MFMA, FLOP/s

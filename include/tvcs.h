@@ -202,7 +202,11 @@ int tvcs_solve(tvcs_handle h, const float *f, double mu, double beta, double tol
  * updated any more, so its result and iteration count equal those of a solve
  * of that image alone (up to the products' rounding, which does not depend on
  * the image's slot).  FP32 storage applies A to up to 8 images per pass of A;
- * the other storage formats use MFMA GEMMs over the whole batch.
+ * the other storage formats use MFMA GEMMs over the whole batch.  With FP32
+ * storage and n*n <= 16384 a single image (B = 1, and tvcs_solve) takes both
+ * products in one pass over A, g = sum_i a_i (a_i . u - f_i) (see
+ * tvcs_time_fused): the same sums in another order, so its result agrees with the
+ * same image's in a batch to rounding, not bit for bit.
  * Returns TVCS_OK if every image met tol (or tol = 0), else TVCS_MAXIT, or an
  * error code (TVCS_ENONFINITE if any image became non-finite).
  */
@@ -213,15 +217,15 @@ int tvcs_solve_batch(tvcs_handle h, const float *F, int B, double mu, double bet
  * tvcs_solve_noalloc: tvcs_solve for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  It allocates nothing: no device or pinned memory and no graph.
- * Its buffers come from one static device array of 16 MiB per GPU, which holds
- * u, f, r, the A^T r partial sums, the IADM fields, the FFT spectrum and
- * denominators and the loop state of one image, and it launches the iteration's
- * kernels one by one.
+ * Its buffers come from one static device array of 32 MiB per GPU, which holds
+ * u, f, r, the A^T r partial sums (the band partials of the one-pass product for
+ * n*n <= 16384), the IADM fields, the FFT spectrum and denominators and the loop
+ * state of one image, and it launches the iteration's kernels one by one.
  *   Arguments as for tvcs_solve, without lambda; st->fresh_iters is 0.
  *   Handles: FP32 storage only (TVCS_EUNSUPPORTED otherwise), used on the device
  *   that was current when the handle was created (TVCS_EINVAL otherwise).
- *   Sizes: TVCS_EINVAL when the workspace exceeds the 16 MiB array (e.g. n = 128,
- *   m = 4096 needs 4.6 MB; n = 512 does not fit).
+ *   Sizes: TVCS_EINVAL when the workspace exceeds the 32 MiB array (e.g. n = 128,
+ *   m = 4096 needs 17.3 MB; n = 512 does not fit).
  * Results are those of tvcs_solve: the same kernels in the same order.  Every call
  * on one GPU shares that GPU's array: calls that overlap on one GPU (from several
  * threads or handles) race and must be serialised by the caller.
@@ -294,6 +298,21 @@ int tvcs_get_tiles(tvcs_handle h, int *tiles);
  */
 int tvcs_time_products(tvcs_handle h, int B, int reps, int form, float *ms_forward,
                        float *ms_adjoint);
+
+/*
+ * tvcs_time_fused: measurement helper for the one-pass product a single image
+ * takes with FP32 storage and n*n <= 16384: g = A^T (A u - f) as the sum over the
+ * rows of A of a_i (a_i . u - f_i) (eq. (line)), each row read once.  The pass
+ * (k_gemv_fused) gives each of up to 256 workgroups a band of consecutive rows;
+ * the workgroup keeps whole rows in registers, reduces a_i . u across its
+ * threads, and adds r_i a_i to its FP64 share of g, then writes the band's partial
+ * g; a second kernel (k_sum_bands) adds the partials in a fixed order.  Average
+ * device milliseconds of each kernel over `reps` launches back to back, timed with
+ * HIP events on the solver's stream, on hashed inputs of unit size; the workspace
+ * contents are overwritten.  Either output may be NULL.  Returns TVCS_EUNSUPPORTED
+ * for handles that do not take the pass (other storage, n*n > 16384).
+ */
+int tvcs_time_fused(tvcs_handle h, int reps, float *ms_pass, float *ms_sum);
 
 /*
  * tvcs_measure_peaks: measurement helper, independent of any handle.  Achievable

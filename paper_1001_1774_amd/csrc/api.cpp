@@ -443,6 +443,42 @@ int tvcs_time_products(tvcs_handle h, int B, int reps, int form, float *ms_forwa
     });
 }
 
+int tvcs_time_fused(tvcs_handle h, int reps, float *ms_pass, float *ms_sum) {
+    return guarded([&] {
+        if (!h) fail(TVCS_EINVAL, "null handle");
+        if (reps < 1) fail(TVCS_EINVAL, "reps must be >= 1");
+        if (!h->fused())
+            fail(TVCS_EUNSUPPORTED, "the one-pass product takes FP32 storage with n*n <= 16384");
+        h->begin_call();
+        h->ensure_workspace(1);
+        float *U = h->U.as<float>(), *F = h->F.as<float>(), *PF = h->PF.as<float>();
+        ImgState *st = h->state.as<ImgState>();
+        const int nb = fused_bands(h->m, h->N);
+        float *G = PF + (size_t)nb * h->N;
+        launch_fill_hash(U, (size_t)h->N, 1u, 1.0f, false, h->work);
+        launch_fill_hash(F, (size_t)h->m, 2u, 1.0f, false, h->work);
+        launch_init_state(st, 1, 0.0, 1, h->work, 1);
+        auto timed = [&](auto &&op) {
+            op();   // warm-up
+            float total = 0.f;
+            TVCS_HIP(hipEventRecord(h->ev_t0, h->work));
+            for (int i = 0; i < reps; ++i) op();
+            TVCS_HIP(hipEventRecord(h->ev_t1, h->work));
+            TVCS_HIP(hipEventSynchronize(h->ev_t1));
+            TVCS_HIP(hipEventElapsedTime(&total, h->ev_t0, h->ev_t1));
+            return total / reps;
+        };
+        const float mp = timed([&] {
+            launch_gemv_fused(h->A32.as<float>(), h->m, h->N, U, F, PF, nullptr, st, h->work);
+        });
+        const float msum = timed([&] { launch_sum_bands(PF, nb, h->N, G, st, h->work); });
+        if (ms_pass) *ms_pass = mp;
+        if (ms_sum) *ms_sum = msum;
+        TVCS_HIP(hipGetLastError());
+        return TVCS_OK;
+    });
+}
+
 int tvcs_set_tiles(tvcs_handle h, const int *tiles) {
     return guarded([&] {
         if (!h) fail(TVCS_EINVAL, "null handle");

@@ -12,6 +12,14 @@
 //     (no atomics), so results are bit-reproducible run to run.
 // Up to NV right-hand sides share one pass over A (batched solves).
 //
+// One image with n^2 <= 16384 takes both products in one pass (k_gemv_fused):
+// g = A^T (A u - f) = sum_i a_i (a_i . u - f_i) needs only row i of A for row i's
+// term, so a workgroup that holds a whole row in registers reduces a_i . u across
+// its threads, forms r_i, and adds r_i a_i to its share of g before the row leaves
+// the registers: A is read once per iteration instead of twice.  Each workgroup
+// owns a contiguous band of rows and writes one partial g; k_sum_bands adds the
+// bands' partials in a fixed order.
+//
 // Products and sums are formed in FP64 from the FP32 operands (each product is
 // exact).  r = A u - f is a small residual of O(1) terms, so FP32 accumulation
 // would put an error of ~sqrt(N) eps |A||u| into it; the FP64 units have an
@@ -259,6 +267,144 @@ void rows_dispatch(const float *A, int m, int N, const float *U, int ldu, const 
                            N, U, ldu, F, ldf, R, ldr, st, nact, stw, parts, nparts);
 }
 
+// ---- one image, both products in one pass over A --------------------------------
+constexpr int kFusedThreadsMax = 1024;   // up to 16 waves: four per SIMD
+
+// Rows [band * rpb, min(m, (band + 1) * rpb)) of A, band = blockIdx.x.  Thread t of
+// T = blockDim.x owns the float4 column groups t, t + T, ..., t + (G - 1) T (only
+// the last may fall past the row: it then reads a valid group and contributes
+// zero); u sits in LDS, rows are loaded two rows ahead, a_i . u is reduced
+// over the workgroup (wave shuffles, then the waves' sums in a fixed order through
+// LDS, one barrier per row; the LDS slot alternates with the row so no second
+// barrier is needed), r_i = a_i . u - f_i is rounded to FP32 (as the two-pass path
+// stores it), and r_i a_i is added to the thread's FP64 share of g.  The band's
+// partial g (FP32) goes to P[band * N ..].  stw: workgroup 0 first applies the
+// previous iteration's stop rule, as in k_gemv_rows.
+template <int G, bool NT>
+__global__ __launch_bounds__(kFusedThreadsMax) void k_gemv_fused(
+    const float *__restrict__ A, int m, int N, int rpb, const float *__restrict__ U,
+    const float *__restrict__ F, float *__restrict__ P, const ImgState *st, ImgState *stw,
+    const double *parts, int nparts) {
+    if (stw && blockIdx.x == 0) {
+        if (threadIdx.x < 64 && stw->active) stop_rule(stw, parts, nparts, nullptr);
+        __syncthreads();
+    }
+    if (!any_active(st, 1)) return;
+    const int T = blockDim.x, t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = T >> 6;
+    const int N4 = N >> 2;
+    const int jl = t + (G - 1) * T;            // the last group
+    const bool last_ok = jl < N4;
+    const int jlc = last_ok ? jl : N4 - 1;     // a valid group to read instead
+    auto col = [&](int k) { return k == G - 1 ? jlc : t + k * T; };
+    // u in LDS (the registers go to a third row in flight); a thread reads only its
+    // own groups, so the one barrier of the first row orders these stores
+    __shared__ f4 us[kFusedN / 4];
+    __shared__ double red[2][kFusedThreadsMax / 64];
+    double gs[G][4];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        const f4 x = reinterpret_cast<const f4 *>(U)[col(k)];
+        us[t + k * T] = (k < G - 1 || last_ok) ? x : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) gs[k][c] = 0.0;
+    }
+    const int r0 = blockIdx.x * rpb, r1 = min(m, r0 + rpb);
+    auto load = [&](f4 (&a)[G], int row) {
+        const f4 *rp = reinterpret_cast<const f4 *>(A + (size_t)row * N);
+#pragma unroll
+        for (int k = 0; k < G; ++k) a[k] = load_a<NT>(rp + col(k));
+    };
+    auto row_term = [&](f4 (&a)[G], int row) {
+        double d = 0.0;
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const f4 x = us[t + k * T];
+            const double xd[4] = {x.x, x.y, x.z, x.w};
+            d = dot4(a[k], xd, d);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
+        const int slot = row & 1;
+        if (lane == 0) red[slot][wave] = d;
+        __syncthreads();
+        double tot = red[slot][0];
+        for (int w = 1; w < nw; ++w) tot += red[slot][w];   // fixed order
+        const double r = (double)(float)(tot - (double)F[row]);
+        // keep the FP64 copies of the row from living across the barrier (they are
+        // cheaper to convert again than the registers they would hold)
+#pragma unroll
+        for (int k = 0; k < G; ++k) asm volatile("" : "+v"(a[k]));
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            gs[k][0] = fma((double)a[k].x, r, gs[k][0]);
+            gs[k][1] = fma((double)a[k].y, r, gs[k][1]);
+            gs[k][2] = fma((double)a[k].z, r, gs[k][2]);
+            gs[k][3] = fma((double)a[k].w, r, gs[k][3]);
+        }
+    };
+    // three rows in registers: rows i + 1 and i + 2 are in flight while row i is used
+    f4 a0[G], a1[G], a2[G];
+    if (r0 < r1) load(a0, r0);
+    if (r0 + 1 < r1) load(a1, r0 + 1);
+    for (int row = r0; row < r1; row += 3) {
+        if (row + 2 < r1) load(a2, row + 2);
+        row_term(a0, row);
+        if (row + 3 < r1) load(a0, row + 3);
+        if (row + 1 < r1) row_term(a1, row + 1);
+        if (row + 4 < r1) load(a1, row + 4);
+        if (row + 2 < r1) row_term(a2, row + 2);
+    }
+    float *out = P + (size_t)blockIdx.x * N;
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+        if (k < G - 1 || last_ok)
+            reinterpret_cast<f4 *>(out)[t + k * T] =
+                f4{(float)gs[k][0], (float)gs[k][1], (float)gs[k][2], (float)gs[k][3]};
+}
+
+// g = the sum of the nb band partials P[b * N ..] in a fixed order: a workgroup
+// takes 16 columns (4 float4 groups); thread t adds bands q, q + 64, ... (q = t / 4)
+// of group t % 4 in FP64, then the 64 subtotals are added pairwise through LDS.
+__global__ __launch_bounds__(256) void k_sum_bands(const float *__restrict__ P, int nb, int N,
+                                                   float *__restrict__ out,
+                                                   const ImgState *st) {
+    if (!any_active(st, 1)) return;
+    const int t = threadIdx.x, c4 = t & 3, q = t >> 2;
+    const int j = blockIdx.x * 4 + c4;   // float4 group
+    const int N4 = N >> 2;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (j < N4) {
+        constexpr int kMaxPer = kFusedMaxBands / 64;
+        f4 v[kMaxPer];
+#pragma unroll
+        for (int i = 0; i < kMaxPer; ++i) {
+            const int b = q + 64 * i;
+            v[i] = b < nb ? reinterpret_cast<const f4 *>(P + (size_t)b * N)[j]
+                          : f4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int i = 0; i < kMaxPer; ++i) {
+            acc[0] += (double)v[i].x;
+            acc[1] += (double)v[i].y;
+            acc[2] += (double)v[i].z;
+            acc[3] += (double)v[i].w;
+        }
+    }
+    __shared__ double red[64][4][4];   // [subtotal q][group c4][component]
+#pragma unroll
+    for (int c = 0; c < 4; ++c) red[q][c4][c] = acc[c];
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+        if (q < w)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) red[q][c4][c] += red[q + w][c4][c];
+        __syncthreads();
+    }
+    if (q == 0 && j < N4)
+        reinterpret_cast<f4 *>(out)[j] = f4{(float)red[0][c4][0], (float)red[0][c4][1],
+                                            (float)red[0][c4][2], (float)red[0][c4][3]};
+}
+
 // Row chunks of the A^T r product: aim for ~TVCS_COLS_TARGET_WG chunk x column
 // block pairs; keep chunks >= 16 rows so partial-sum traffic stays a few percent
 // of the A stream, and a chunk's coefficients (rows x nv doubles, nv <= 8) within
@@ -326,6 +472,51 @@ void launch_gemv_cols(const float *A, int m, int N, const float *R, int ldr, flo
         case 8: cols_dispatch<8>(A, m, N, R, ldr, P, chunk_stride, st, nact, s); break;
         default: fail(TVCS_EINVAL, "gemv_cols: nv must be 1, 2, 4 or 8");
     }
+}
+
+int fused_bands(int m, int N) {
+    if (N > kFusedN || (N & 3)) return 0;
+    const int rpb = (m + kFusedMaxBands - 1) / kFusedMaxBands;
+    return (m + rpb - 1) / rpb;
+}
+
+template <int G>
+void fused_dispatch(const float *A, int m, int N, int rpb, int nb, int T, const float *U,
+                    const float *F, float *P, const ImgState *st, ImgState *stw,
+                    const double *parts, int nparts, hipStream_t s) {
+    if ((size_t)m * N * sizeof(float) > TVCS_GEMV_NT_BYTES)
+        hipLaunchKernelGGL((k_gemv_fused<G, true>), dim3(nb), dim3(T), 0, s, A, m, N, rpb, U, F,
+                           P, st, stw, parts, nparts);
+    else
+        hipLaunchKernelGGL((k_gemv_fused<G, false>), dim3(nb), dim3(T), 0, s, A, m, N, rpb, U, F,
+                           P, st, stw, parts, nparts);
+}
+
+void launch_gemv_fused(const float *A, int m, int N, const float *U, const float *F, float *P,
+                       float *g_out, const ImgState *st, hipStream_t s, ImgState *stw,
+                       const double *parts, int nparts) {
+    const int nb = fused_bands(m, N);
+    if (nb < 1) fail(TVCS_EINVAL, "gemv_fused: n^2 must be a multiple of 4 and at most 16384");
+    if (stw && (st != stw || !parts || nparts < 1))
+        fail(TVCS_EINVAL, "gemv_fused: the folded stop rule needs the image state and partials");
+    const int rpb = (m + nb - 1) / nb;
+    // G float4 groups per thread, T threads (a multiple of 64, at most 1024)
+    const int N4 = N / 4;
+    const int G = (N4 + kFusedThreadsMax - 1) / kFusedThreadsMax;
+    const int T = ((N4 + G - 1) / G + 63) / 64 * 64;
+    switch (G) {
+        case 1: fused_dispatch<1>(A, m, N, rpb, nb, T, U, F, P, st, stw, parts, nparts, s); break;
+        case 2: fused_dispatch<2>(A, m, N, rpb, nb, T, U, F, P, st, stw, parts, nparts, s); break;
+        case 3: fused_dispatch<3>(A, m, N, rpb, nb, T, U, F, P, st, stw, parts, nparts, s); break;
+        default: fused_dispatch<4>(A, m, N, rpb, nb, T, U, F, P, st, stw, parts, nparts, s);
+    }
+    if (g_out) launch_sum_bands(P, nb, N, g_out, st, s);
+}
+
+void launch_sum_bands(const float *P, int nb, int N, float *g_out, const ImgState *st,
+                      hipStream_t s) {
+    if (nb < 1 || nb > kFusedMaxBands) fail(TVCS_EINVAL, "sum_bands: 1 to 256 band partials");
+    hipLaunchKernelGGL(k_sum_bands, dim3((N / 4 + 3) / 4), dim3(256), 0, s, P, nb, N, g_out, st);
 }
 
 }  // namespace tvcs

@@ -1,6 +1,7 @@
 // tvcs_solve_noalloc: the single-image solve of tvcs_solve (FP32 storage of A)
 // for callers that cannot allocate device memory.  Every per-solve buffer (u, f,
-// r, the A^T r partial sums, the two q fields, the half spectrum, the stop-rule
+// r, the A^T r partial sums (or, for n^2 <= 16384, the band partials of the
+// one-pass product and g), the two q fields, the half spectrum, the stop-rule
 // partials, the FFT denominators, the image state) lives in one file-scope device
 // array of kScratchBytes; the iteration's kernels are launched directly (no
 // captured graph, no pinned host memory).  The array's device address is taken
@@ -9,6 +10,7 @@
 // array it reads before reading it.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <mutex>
 
@@ -16,7 +18,7 @@
 
 namespace {
 
-constexpr size_t kScratchBytes = 16u << 20;   // 16 MiB per GPU
+constexpr size_t kScratchBytes = 32u << 20;   // 32 MiB per GPU
 constexpr int kMaxDevices = 64;
 
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
@@ -98,14 +100,18 @@ int solve_noalloc_impl(tvcs_ctx *h, const float *f, double mu, double beta, doub
         fail(TVCS_EINVAL, "the current device is not the one the handle was created on");
     const int n = h->n, m = h->m, N = h->N;
     const int nchunk = gemv_cols_chunks(m, N);
+    // the one-pass product (as tvcs_solve takes it for one image): nb band partials
+    // of g, then g, in the partial-sum buffer
+    const int nb = TVCS_FUSED_PASS ? fused_bands(m, N) : 0;
+    const int pslots = std::max(nchunk, nb > 0 ? nb + 1 : 0);
     size_t need = 0;
-    (void)carve(nullptr, n, m, nchunk, need);
+    (void)carve(nullptr, n, m, pslots, need);
     if (need > kScratchBytes)
         fail(TVCS_EINVAL, "tvcs_solve_noalloc: this problem's workspace is " +
                               std::to_string(need) + " bytes, beyond the " +
                               std::to_string(kScratchBytes) + "-byte scratch array");
     size_t used = 0;
-    const Work w = carve(scratch_on(dev), n, m, nchunk, used);
+    const Work w = carve(scratch_on(dev), n, m, pslots, used);
     const bool iadm = (flags & TVCS_IADM) != 0;
     const double tau = h->tau();
     const double c = mu / (beta * tau), ctau = mu / beta;
@@ -131,11 +137,11 @@ int solve_noalloc_impl(tvcs_ctx *h, const float *f, double mu, double beta, doub
     a.n = n;
     a.B = 1;
     a.U = w.U;
-    a.G = w.P;
+    a.G = nb > 0 ? w.P + (size_t)nb * N : w.P;
     a.gnv = 1;
     a.g_chunk_stride = N;
-    a.g_group_stride = (long long)nchunk * N;
-    a.nchunk = nchunk;
+    a.g_group_stride = nb > 0 ? (long long)N : (long long)nchunk * N;
+    a.nchunk = nb > 0 ? 1 : nchunk;
     a.beta = beta;
     a.c = c;
     a.ctau = ctau;
@@ -145,8 +151,13 @@ int solve_noalloc_impl(tvcs_ctx *h, const float *f, double mu, double beta, doub
     ImgState hs{};
     for (int k = 0; k < maxit; ++k) {
         const int parity = k & 1;
-        launch_gemv_rows(h->A32.as<float>(), m, N, w.U, N, w.F, m, w.R, m, 1, w.st, 1, s);
-        launch_gemv_cols(h->A32.as<float>(), m, N, w.R, m, w.P, N, 1, w.st, 1, s);
+        if (nb > 0) {
+            launch_gemv_fused(h->A32.as<float>(), m, N, w.U, w.F, w.P, w.P + (size_t)nb * N, w.st,
+                              s);
+        } else {
+            launch_gemv_rows(h->A32.as<float>(), m, N, w.U, N, w.F, m, w.R, m, 1, w.st, 1, s);
+            launch_gemv_cols(h->A32.as<float>(), m, N, w.R, m, w.P, N, 1, w.st, 1, s);
+        }
         a.Qold = parity ? w.Q1 : w.Q0;
         a.Qnew = parity ? w.Q0 : w.Q1;
         a.parity = parity;

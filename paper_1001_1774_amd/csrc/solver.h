@@ -41,6 +41,9 @@ struct DevBuf {
 };
 
 constexpr int kGraphIters = 10;   // iterations per captured graph (even: q ping-pong)
+#ifndef TVCS_FUSED_PASS
+#define TVCS_FUSED_PASS 1         // one image, FP32 A, n^2 <= 16384: A u and A^T r in one pass
+#endif
 #ifndef TVCS_FOLD_STOP
 #define TVCS_FOLD_STOP 1          // stop rule folded into the next A u pass (one image FP32; DCT, MFMA)
 #endif
@@ -81,6 +84,7 @@ struct tvcs_ctx {
     DevBuf adm_F, adm_U;   // request loop: f and A^T f of newly admitted slots (capP rows)
     DevBuf bb_Uk, bb_P, bb_AP, bb_parts, bb_state;   // IADM with inner BB steps
     DevBuf DT;             // partial DCT: the half-transformed images between passes
+    DevBuf PF;             // one image, FP32 A, n^2 <= kFusedN: band partials of g, then g
     LowpWork lw{};
     bool tiles_forced = false;   // tile shapes set by tvcs_set_tiles instead of the autotuner
     TileCfg forced_fwd{}, forced_adj{};
@@ -110,6 +114,8 @@ struct tvcs_ctx {
                storage == TVCS_A_FP8_ROWSCALE;
     }
     bool dct() const { return storage == TVCS_A_PARTIAL_DCT; }
+    // FP32 A with n^2 <= kFusedN: a single image takes both products in one pass over A
+    bool fused() const { return TVCS_FUSED_PASS && storage == TVCS_A_FP32 && fused_bands(m, N) > 0; }
     double tau() const { return tau_user > 0 ? tau_user : 1.9 / lmax; }
 
     // padded batch: FP32 products take 1, 2, 4 or 8 vectors per pass of A
@@ -155,6 +161,7 @@ struct tvcs_ctx {
         obj.ensure(sizeof(double) * B);
         counters.ensure(sizeof(int) * B);
         if (dct()) DT.ensure(sizeof(float) * Bp * Nn);
+        if (fused()) PF.ensure(sizeof(float) * (size_t)(fused_bands(m, N) + 1) * Nn);
         launch_fill(counters.as<float>(), (size_t)B, 0.f, work);   // all-zero bits
         if (lowprec()) {
             Gacc.ensure(sizeof(float) * B * Nn);
@@ -220,6 +227,7 @@ struct tvcs_ctx {
                    sizeof(int) * B;
         if (lowprec()) b += lowp_work_bytes(lowp, Bp) + sizeof(float) * B * Nn;
         if (dct()) b += sizeof(float) * Bp * Nn;
+        if (fused()) b += sizeof(float) * (size_t)(fused_bands(m, N) + 1) * Nn;
         return b;
     }
 
@@ -262,7 +270,7 @@ struct tvcs_ctx {
         }
         for (DevBuf *b : {&U, &F, &R, &P, &RHS, &Q0, &Q1, &S, &parts, &state, &obj, &lowp_work, &lamb,
                           &counters, &DT, &Gacc, &adm_F, &adm_U, &bb_Uk, &bb_P, &bb_AP, &bb_parts,
-                          &bb_state})
+                          &bb_state, &PF})
             b->release();
         cap = capP = 0;
     }
@@ -402,6 +410,12 @@ struct tvcs_ctx {
             lowp_apply_A(lowp, lw, B, U.as<float>(), F.as<float>(), R.as<float>(), st, work, st,
                          parts.as<double>(), stop_parts(n, B), parity);
             apply_At(Bp, B, R.as<float>(), st, parity);
+        } else if (fused() && B == 1) {
+            const int nb = fused_bands(m, N);
+            launch_gemv_fused(A32.as<float>(), m, N, U.as<float>(), F.as<float>(), PF.as<float>(),
+                              PF.as<float>() + (size_t)nb * N, st, work, fold_prev ? st : nullptr,
+                              fold_prev ? parts.as<double>() : nullptr,
+                              fold_prev ? stop_parts(n, B) : 0);
         } else if (fold_prev) {
             launch_gemv_rows(A32.as<float>(), m, N, U.as<float>(), N, F.as<float>(), m,
                              R.as<float>(), m, 1, st, 1, work, st, parts.as<double>(),
@@ -413,6 +427,13 @@ struct tvcs_ctx {
         }
         ShrinkArgs a = shrink_args(B, Bp);
         a.parity = parity;
+        if (fused() && B == 1) {   // g whole, after the band partials
+            a.G = PF.as<float>() + (size_t)fused_bands(m, N) * N;
+            a.gnv = 1;
+            a.nchunk = 1;
+            a.g_chunk_stride = N;
+            a.g_group_stride = N;
+        }
         if (dct()) {
             a.T = DT.as<float>();
             a.dtab = dtab.as<float4>();
@@ -566,7 +587,7 @@ struct tvcs_ctx {
                P.bytes + RHS.bytes + Q0.bytes + Q1.bytes + S.bytes + parts.bytes + state.bytes +
                obj.bytes + lowp_work.bytes + lamb.bytes + counters.bytes + Gacc.bytes + adm_F.bytes +
                adm_U.bytes + bb_Uk.bytes + bb_P.bytes + bb_AP.bytes + bb_parts.bytes +
-               bb_state.bytes;
+               bb_state.bytes + PF.bytes;
     }
 };
 

@@ -95,6 +95,8 @@ _SIGS = {
                                           ctypes.c_void_p]),
     "tvcs_time_products": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "tvcs_time_fused": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
     "tvcs_set_tiles": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "tvcs_get_tiles": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "tvcs_destroy": (None, [ctypes.c_void_p]),
@@ -231,6 +233,13 @@ def tvcs_time_products(h, B, reps, form=0, ms_forward=None, ms_adjoint=None):
     return lib().tvcs_time_products(h, B, reps, form,
                                     ctypes.byref(ms_forward) if ms_forward is not None else None,
                                     ctypes.byref(ms_adjoint) if ms_adjoint is not None else None)
+
+
+def tvcs_time_fused(h, reps, ms_pass=None, ms_sum=None):
+    """ms_pass / ms_sum: ctypes.c_float objects (or None)."""
+    return lib().tvcs_time_fused(h, reps,
+                                 ctypes.byref(ms_pass) if ms_pass is not None else None,
+                                 ctypes.byref(ms_sum) if ms_sum is not None else None)
 
 
 def tvcs_set_tiles(h, tiles=None):
@@ -455,6 +464,15 @@ class Solver:
         increment=True times the one-part increment form of the MFMA products."""
         a, b = ctypes.c_float(), ctypes.c_float()
         rc = tvcs_time_products(self.h, B, reps, 1 if increment else 0, a, b)
+        if rc < 0:
+            raise TvcsError(rc, tvcs_last_error())
+        return a.value, b.value
+
+    def time_fused(self, reps=20):
+        """Average ms per launch of the one-pass product of one image and of its
+        band-partial sum (FP32 storage, n*n <= 16384; TvcsError otherwise)."""
+        a, b = ctypes.c_float(), ctypes.c_float()
+        rc = tvcs_time_fused(self.h, reps, a, b)
         if rc < 0:
             raise TvcsError(rc, tvcs_last_error())
         return a.value, b.value

@@ -89,8 +89,10 @@ def test_dense_batch_equals_single(T):
         out = s.solve_batch(f32, mu=p.mu, beta=p.beta, tol=1e-4, maxit=600, iadm=True)
         U = out["u"].cpu().numpy()
         for b in (1, 4):
+            # alone, the image takes the one-pass product (n*n <= 16384): the same
+            # sums in another order, so the values agree to rounding
             alone = s.solve(f32[b], mu=p.mu, beta=p.beta, tol=1e-4, maxit=600, iadm=True)
-            assert np.array_equal(alone["u"].cpu().numpy(), U[b])
+            assert rel(alone["u"].cpu().numpy(), U[b].astype(np.float64)) <= 1e-5
             assert alone["stats"]["iters"] == out["stats"][b]["iters"]
 
 

@@ -133,8 +133,17 @@ def test_stop_rule_iteration_count(T):
             assert out["rc"] == (T.TVCS_OK if ref.iters[0] < 400 else T.TVCS_MAXIT)
 
 
+# A single image with FP32 storage and n*n <= 16384 takes both products in one pass
+# over A (the same sums as the batched passes in another order): alone and in a
+# batch it then agrees to rounding, within the FP32 bar each path meets against the
+# oracle (measured 6e-7 - 1e-6); elsewhere bit for bit.
+SINGLE_VS_BATCH = TOL_FP32
+
+
 def test_batch_equals_single(T):
-    """Images solved in one batch give the same bits and iteration counts as alone."""
+    """Images solved in one batch give the iteration counts of a solve alone, and the
+    same values: to rounding at n = 32 (one-pass product alone), bit for bit at
+    n = 144 (two passes either way)."""
     p = synth.make_problem("b", n=32, m=307, batch=5, seed_A=21, sigma=[1e-3, 1e-2, 1e-3, 0, 1e-3])
     tau = O.default_tau(p.A)
     F = p.f.astype(np.float32)
@@ -144,12 +153,23 @@ def test_batch_equals_single(T):
             for b in range(5):
                 r1 = s.solve(F[b], mu=p.mu, beta=p.beta, tol=1e-3, maxit=300, iadm=iadm)
                 assert r1["stats"]["iters"] == rb["stats"][b]["iters"]
-                assert np.array_equal(r1["u"].cpu().numpy(), rb["u"][b].cpu().numpy())
+                u1, ub = r1["u"].cpu().numpy(), rb["u"][b].cpu().numpy()
+                e = rel(u1, ub.astype(np.float64))
+                say(f"  n=32 iadm={iadm} image {b}: alone vs batch {e:.2e}")
+                assert e <= SINGLE_VS_BATCH
             ref = (O.iadm if iadm else O.ftvcs)(p.A, p.f, p.n, p.mu, p.beta, tau, tol=1e-3,
                                                  maxit=300)
             for b in range(5):
                 assert rb["stats"][b]["iters"] == ref.iters[b]
                 check(rb["u"][b].cpu().numpy(), ref.u[b], TOL_U, f"image {b}", say)
+    q = synth.make_problem("b144", n=144, m=2074, batch=3, seed_A=23, sigma=[1e-3, 1e-2, 0])
+    Fq = q.f.astype(np.float32)
+    with T.Solver(q.A, q.n) as s:
+        rb = s.solve_batch(Fq, mu=q.mu, beta=q.beta, tol=1e-3, maxit=200, iadm=True)
+        for b in range(3):
+            r1 = s.solve(Fq[b], mu=q.mu, beta=q.beta, tol=1e-3, maxit=200, iadm=True)
+            assert r1["stats"]["iters"] == rb["stats"][b]["iters"]
+            assert np.array_equal(r1["u"].cpu().numpy(), rb["u"][b].cpu().numpy())
 
 
 def test_lambda_max_and_objective(T):

@@ -47,7 +47,10 @@ def problems():
 
 @pytest.mark.parametrize("iadm", [True, False], ids=["iadm", "ftvcs"])
 def test_alone_equals_in_the_mix(T, problems, iadm):
-    """Each request's result and iteration count are the same in the mix as alone."""
+    """Each request's result and iteration count are the same in the mix as alone: bit
+    for bit for the MFMA-stored matrices; for the FP32 one (n = 32) a solve alone
+    takes the one-pass product, whose sums run in another order, so there the
+    results agree to rounding (within the FP32 bar of 1e-5)."""
     from paper_1001_1774_amd import serving as S
     storages = ["fp32", "bf16", "bf16_split"]
     solvers = [T.Solver(p.A, p.n, storage=st) for p, st in zip(problems, storages)]
@@ -66,9 +69,12 @@ def test_alone_equals_in_the_mix(T, problems, iadm):
         u_mix, st_mix = out["results"][i]
         u_alone, st_alone = S.solve_alone(solvers[r.matrix], r, 1e3, 10.0, iadm)
         assert st_mix["iters"] == st_alone["iters"], (i, st_mix, st_alone)
-        if not np.array_equal(u_mix.ravel(), u_alone.ravel()):
+        if storages[r.matrix] == "fp32":
+            e = rel(u_mix.ravel(), u_alone.ravel().astype(np.float64))
+            assert e <= 1e-5, (i, e)
+        elif not np.array_equal(u_mix.ravel(), u_alone.ravel()):
             mism += 1
-    say(f"  bitwise mismatches: {mism} of {len(reqs)}")
+    say(f"  bitwise mismatches (MFMA storage): {mism} of {len(reqs)}")
     assert mism == 0
     for s in solvers:
         s.close()

@@ -62,12 +62,14 @@ def test_noalloc_equals_solve_two_calls(T):
 
 def test_noalloc_rejects_what_it_cannot_hold(T):
     import torch
-    # n = 512, m = 12000: 12 row chunks of A^T r partial sums, a 19.1 MiB workspace
-    # (any values of A do: the call is refused before it computes anything)
-    n, m = 512, 12000
-    A = np.full((m, n * n), 1e-3, np.float32)
+    # n = 512, m = 26214: 26 row chunks of A^T r partial sums, a 33.1 MiB workspace
+    # beyond the 32 MiB array (any values of A do: the call is refused before it
+    # computes anything); A (27.5 GB) is made on the device
+    n, m = 512, 26214
+    A = torch.full((m, n * n), 1e-3, dtype=torch.float32, device="cuda")
     h = T.tvcs_create(A, m, n)
     del A
+    torch.cuda.empty_cache()
     assert h
     try:
         f = torch.ones(m, dtype=torch.float32, device="cuda")
