@@ -307,10 +307,13 @@ int tvcs_time_products(tvcs_handle h, int B, int reps, int form, float *ms_forwa
  * the workgroup keeps whole rows in registers, reduces a_i . u across its
  * threads, and adds r_i a_i to its FP64 share of g, then writes the band's partial
  * g; a second kernel (k_sum_bands) adds the partials in a fixed order.  Average
- * device milliseconds of each kernel over `reps` launches back to back, timed with
- * HIP events on the solver's stream, on hashed inputs of unit size; the workspace
- * contents are overwritten.  Either output may be NULL.  Returns TVCS_EUNSUPPORTED
- * for handles that do not take the pass (other storage, n*n > 16384).
+ * device milliseconds per launch of the pass (`reps` launches back to back, the
+ * row order alternating as in a solve) and of the sum (the time of `reps` pass +
+ * sum pairs less that of the passes alone, so the sum reads freshly written
+ * partials), timed with HIP events on the solver's stream, on hashed inputs of
+ * unit size; the workspace contents are overwritten.  Either output may be NULL.
+ * Returns TVCS_EUNSUPPORTED for handles that do not take the pass (other storage,
+ * n*n > 16384).
  */
 int tvcs_time_fused(tvcs_handle h, int reps, float *ms_pass, float *ms_sum);
 

@@ -270,6 +270,33 @@ void rows_dispatch(const float *A, int m, int N, const float *U, int ldu, const 
 // ---- one image, both products in one pass over A --------------------------------
 constexpr int kFusedThreadsMax = 1024;   // up to 16 waves: four per SIMD
 
+#ifndef TVCS_FUSED_DPP
+#define TVCS_FUSED_DPP 1   // the per-row wave sums through DPP moves (0: shuffles)
+#endif
+// One 32-bit half of a double through a DPP move (disabled rows give 0)
+template <int CTRL, int ROWS>
+__device__ inline double dpp_f64(double x) {
+    const unsigned long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWS, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+// The sum of x over a 64-lane wave (every lane gets it): pairs and quads by quad
+// permutes, 8 and 16 lanes by the half-row and row mirrors, then rows 0 + 1 and
+// 2 + 3 by the row-15 broadcast and all four by the row-31 broadcast into lane 63.
+__device__ inline double wave_sum_dpp(double x) {
+    x += dpp_f64<0xB1, 0xF>(x);    // quad_perm [1, 0, 3, 2]
+    x += dpp_f64<0x4E, 0xF>(x);    // quad_perm [2, 3, 0, 1]
+    x += dpp_f64<0x141, 0xF>(x);   // row_half_mirror
+    x += dpp_f64<0x140, 0xF>(x);   // row_mirror
+    x += dpp_f64<0x142, 0xA>(x);   // row_bcast:15 into rows 1 and 3
+    x += dpp_f64<0x143, 0xC>(x);   // row_bcast:31 into rows 2 and 3
+    const unsigned long long b = __double_as_longlong(x);
+    const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)b, 63);
+    const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Rows [band * rpb, min(m, (band + 1) * rpb)) of A, band = blockIdx.x.  Thread t of
 // T = blockDim.x owns the float4 column groups t, t + T, ..., t + (G - 1) T (only
 // the last may fall past the row: it then reads a valid group and contributes
@@ -278,17 +305,13 @@ constexpr int kFusedThreadsMax = 1024;   // up to 16 waves: four per SIMD
 // LDS, one barrier per row; the LDS slot alternates with the row so no second
 // barrier is needed), r_i = a_i . u - f_i is rounded to FP32 (as the two-pass path
 // stores it), and r_i a_i is added to the thread's FP64 share of g.  The band's
-// partial g (FP32) goes to P[band * N ..].  stw: workgroup 0 first applies the
-// previous iteration's stop rule, as in k_gemv_rows.
+// partial g (FP32) goes to P[band * N ..].  (The previous iteration's stop rule,
+// which k_gemv_rows applies in its workgroup 0, is applied by k_sum_bands here:
+// with one workgroup per CU, a late workgroup 0 would hold up the whole pass.)
 template <int G, bool NT>
 __global__ __launch_bounds__(kFusedThreadsMax) void k_gemv_fused(
     const float *__restrict__ A, int m, int N, int rpb, const float *__restrict__ U,
-    const float *__restrict__ F, float *__restrict__ P, const ImgState *st, ImgState *stw,
-    const double *parts, int nparts) {
-    if (stw && blockIdx.x == 0) {
-        if (threadIdx.x < 64 && stw->active) stop_rule(stw, parts, nparts, nullptr);
-        __syncthreads();
-    }
+    const float *__restrict__ F, float *__restrict__ P, const ImgState *st, int rev) {
     if (!any_active(st, 1)) return;
     const int T = blockDim.x, t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = T >> 6;
     const int N4 = N >> 2;
@@ -300,21 +323,14 @@ __global__ __launch_bounds__(kFusedThreadsMax) void k_gemv_fused(
     // own groups, so the one barrier of the first row orders these stores
     __shared__ f4 us[kFusedN / 4];
     __shared__ double red[2][kFusedThreadsMax / 64];
-    double gs[G][4];
-#pragma unroll
-    for (int k = 0; k < G; ++k) {
-        const f4 x = reinterpret_cast<const f4 *>(U)[col(k)];
-        us[t + k * T] = (k < G - 1 || last_ok) ? x : f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int c = 0; c < 4; ++c) gs[k][c] = 0.0;
-    }
     const int r0 = blockIdx.x * rpb, r1 = min(m, r0 + rpb);
+    double gs[G][4];
     auto load = [&](f4 (&a)[G], int row) {
         const f4 *rp = reinterpret_cast<const f4 *>(A + (size_t)row * N);
 #pragma unroll
         for (int k = 0; k < G; ++k) a[k] = load_a<NT>(rp + col(k));
     };
-    auto row_term = [&](f4 (&a)[G], int row) {
+    auto row_term = [&](f4 (&a)[G], int row, int idx) {
         double d = 0.0;
 #pragma unroll
         for (int k = 0; k < G; ++k) {
@@ -322,9 +338,13 @@ __global__ __launch_bounds__(kFusedThreadsMax) void k_gemv_fused(
             const double xd[4] = {x.x, x.y, x.z, x.w};
             d = dot4(a[k], xd, d);
         }
+        if (TVCS_FUSED_DPP) {
+            d = wave_sum_dpp(d);
+        } else {
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
-        const int slot = row & 1;
+            for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
+        }
+        const int slot = idx & 1;
         if (lane == 0) red[slot][wave] = d;
         __syncthreads();
         double tot = red[slot][0];
@@ -342,17 +362,30 @@ __global__ __launch_bounds__(kFusedThreadsMax) void k_gemv_fused(
             gs[k][3] = fma((double)a[k].w, r, gs[k][3]);
         }
     };
-    // three rows in registers: rows i + 1 and i + 2 are in flight while row i is used
+    // three rows in registers: rows i + 1 and i + 2 are in flight while row i is
+    // used.  rev: the band's rows last to first (the solve alternates the direction
+    // from one iteration to the next, so that each pass starts on the rows the
+    // previous one read last, which the Infinity Cache may still hold)
+    const int cnt = r1 - r0;
+    auto row_of = [&](int i) { return rev ? r1 - 1 - i : r0 + i; };
     f4 a0[G], a1[G], a2[G];
-    if (r0 < r1) load(a0, r0);
-    if (r0 + 1 < r1) load(a1, r0 + 1);
-    for (int row = r0; row < r1; row += 3) {
-        if (row + 2 < r1) load(a2, row + 2);
-        row_term(a0, row);
-        if (row + 3 < r1) load(a0, row + 3);
-        if (row + 1 < r1) row_term(a1, row + 1);
-        if (row + 4 < r1) load(a1, row + 4);
-        if (row + 2 < r1) row_term(a2, row + 2);
+    if (0 < cnt) load(a0, row_of(0));
+    if (1 < cnt) load(a1, row_of(1));
+    // u after the first rows' loads, so that those are in flight meanwhile
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        const f4 x = reinterpret_cast<const f4 *>(U)[col(k)];
+        us[t + k * T] = (k < G - 1 || last_ok) ? x : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) gs[k][c] = 0.0;
+    }
+    for (int i = 0; i < cnt; i += 3) {
+        if (i + 2 < cnt) load(a2, row_of(i + 2));
+        row_term(a0, row_of(i), i);
+        if (i + 3 < cnt) load(a0, row_of(i + 3));
+        if (i + 1 < cnt) row_term(a1, row_of(i + 1), i + 1);
+        if (i + 4 < cnt) load(a1, row_of(i + 4));
+        if (i + 2 < cnt) row_term(a2, row_of(i + 2), i + 2);
     }
     float *out = P + (size_t)blockIdx.x * N;
 #pragma unroll
@@ -363,46 +396,60 @@ __global__ __launch_bounds__(kFusedThreadsMax) void k_gemv_fused(
 }
 
 // g = the sum of the nb band partials P[b * N ..] in a fixed order: a workgroup
-// takes 16 columns (4 float4 groups); thread t adds bands q, q + 64, ... (q = t / 4)
-// of group t % 4 in FP64, then the 64 subtotals are added pairwise through LDS.
+// takes 16 float4 columns; thread t (column group t % 16, subset q = t / 16) adds
+// bands q, q + 16, ... in FP64, all its loads in flight at once (each load of a
+// wave reads 256 contiguous bytes of 4 band rows); then the 16 subtotals are added
+// pairwise through LDS.
+// stw (one image, non-null): an extra last workgroup applies the previous
+// iteration's stop rule from its nparts norm partials (alone, so that its latency
+// overlaps the sums instead of adding to one workgroup's); the other workgroups
+// may read the flag before or after, and when the rule stops the image some of
+// them still write g, which no later pass of a stopped image reads.
+constexpr int kSumCols4 = 16;   // float4 columns per workgroup
 __global__ __launch_bounds__(256) void k_sum_bands(const float *__restrict__ P, int nb, int N,
                                                    float *__restrict__ out,
-                                                   const ImgState *st) {
-    if (!any_active(st, 1)) return;
-    const int t = threadIdx.x, c4 = t & 3, q = t >> 2;
-    const int j = blockIdx.x * 4 + c4;   // float4 group
+                                                   const ImgState *st, ImgState *stw,
+                                                   const double *parts, int nparts) {
     const int N4 = N >> 2;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (j < N4) {
-        constexpr int kMaxPer = kFusedMaxBands / 64;
-        f4 v[kMaxPer];
-#pragma unroll
-        for (int i = 0; i < kMaxPer; ++i) {
-            const int b = q + 64 * i;
-            v[i] = b < nb ? reinterpret_cast<const f4 *>(P + (size_t)b * N)[j]
-                          : f4{0.f, 0.f, 0.f, 0.f};
-        }
-#pragma unroll
-        for (int i = 0; i < kMaxPer; ++i) {
-            acc[0] += (double)v[i].x;
-            acc[1] += (double)v[i].y;
-            acc[2] += (double)v[i].z;
-            acc[3] += (double)v[i].w;
-        }
+    const int nsum = (N4 + kSumCols4 - 1) / kSumCols4;   // workgroups of sums
+    if ((int)blockIdx.x >= nsum) {   // the stop-rule workgroup
+        if (stw && threadIdx.x < 64 && stw->active) stop_rule(stw, parts, nparts, nullptr);
+        return;
     }
-    __shared__ double red[64][4][4];   // [subtotal q][group c4][component]
+    if (!any_active(st, 1)) return;
+    constexpr int kSub = 256 / kSumCols4;                 // 16 subsets of bands
+    constexpr int kPer = kFusedMaxBands / kSub;           // bands per subset
+    const int t = threadIdx.x, c = t % kSumCols4, q = t / kSumCols4;
+    const int j = blockIdx.x * kSumCols4 + c;   // float4 group
+    const int jc = j < N4 ? j : N4 - 1;
+    f4 v[kPer];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) red[q][c4][c] = acc[c];
+    for (int i = 0; i < kPer; ++i) {
+        const int b = q + kSub * i;
+        v[i] = b < nb ? reinterpret_cast<const f4 *>(P + (size_t)b * N)[jc]
+                      : f4{0.f, 0.f, 0.f, 0.f};
+    }
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        acc[0] += (double)v[i].x;
+        acc[1] += (double)v[i].y;
+        acc[2] += (double)v[i].z;
+        acc[3] += (double)v[i].w;
+    }
+    __shared__ double red[kSub][kSumCols4][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[q][c][k] = acc[k];
     __syncthreads();
-    for (int w = 32; w > 0; w >>= 1) {
+    for (int w = kSub / 2; w > 0; w >>= 1) {
         if (q < w)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) red[q][c4][c] += red[q + w][c4][c];
+            for (int k = 0; k < 4; ++k) red[q][c][k] += red[q + w][c][k];
         __syncthreads();
     }
     if (q == 0 && j < N4)
-        reinterpret_cast<f4 *>(out)[j] = f4{(float)red[0][c4][0], (float)red[0][c4][1],
-                                            (float)red[0][c4][2], (float)red[0][c4][3]};
+        reinterpret_cast<f4 *>(out)[j] = f4{(float)red[0][c][0], (float)red[0][c][1],
+                                            (float)red[0][c][2], (float)red[0][c][3]};
 }
 
 // Row chunks of the A^T r product: aim for ~TVCS_COLS_TARGET_WG chunk x column
@@ -482,41 +529,43 @@ int fused_bands(int m, int N) {
 
 template <int G>
 void fused_dispatch(const float *A, int m, int N, int rpb, int nb, int T, const float *U,
-                    const float *F, float *P, const ImgState *st, ImgState *stw,
-                    const double *parts, int nparts, hipStream_t s) {
+                    const float *F, float *P, const ImgState *st, int rev, hipStream_t s) {
     if ((size_t)m * N * sizeof(float) > TVCS_GEMV_NT_BYTES)
         hipLaunchKernelGGL((k_gemv_fused<G, true>), dim3(nb), dim3(T), 0, s, A, m, N, rpb, U, F,
-                           P, st, stw, parts, nparts);
+                           P, st, rev);
     else
         hipLaunchKernelGGL((k_gemv_fused<G, false>), dim3(nb), dim3(T), 0, s, A, m, N, rpb, U, F,
-                           P, st, stw, parts, nparts);
+                           P, st, rev);
 }
 
 void launch_gemv_fused(const float *A, int m, int N, const float *U, const float *F, float *P,
-                       float *g_out, const ImgState *st, hipStream_t s, ImgState *stw,
+                       float *g_out, const ImgState *st, int rev, hipStream_t s, ImgState *stw,
                        const double *parts, int nparts) {
     const int nb = fused_bands(m, N);
     if (nb < 1) fail(TVCS_EINVAL, "gemv_fused: n^2 must be a multiple of 4 and at most 16384");
-    if (stw && (st != stw || !parts || nparts < 1))
-        fail(TVCS_EINVAL, "gemv_fused: the folded stop rule needs the image state and partials");
+    if (stw && (st != stw || !parts || nparts < 1 || !g_out))
+        fail(TVCS_EINVAL, "gemv_fused: the folded stop rule needs the image state, its partials "
+                          "and the partial-sum pass");
     const int rpb = (m + nb - 1) / nb;
     // G float4 groups per thread, T threads (a multiple of 64, at most 1024)
     const int N4 = N / 4;
     const int G = (N4 + kFusedThreadsMax - 1) / kFusedThreadsMax;
     const int T = ((N4 + G - 1) / G + 63) / 64 * 64;
     switch (G) {
-        case 1: fused_dispatch<1>(A, m, N, rpb, nb, T, U, F, P, st, stw, parts, nparts, s); break;
-        case 2: fused_dispatch<2>(A, m, N, rpb, nb, T, U, F, P, st, stw, parts, nparts, s); break;
-        case 3: fused_dispatch<3>(A, m, N, rpb, nb, T, U, F, P, st, stw, parts, nparts, s); break;
-        default: fused_dispatch<4>(A, m, N, rpb, nb, T, U, F, P, st, stw, parts, nparts, s);
+        case 1: fused_dispatch<1>(A, m, N, rpb, nb, T, U, F, P, st, rev, s); break;
+        case 2: fused_dispatch<2>(A, m, N, rpb, nb, T, U, F, P, st, rev, s); break;
+        case 3: fused_dispatch<3>(A, m, N, rpb, nb, T, U, F, P, st, rev, s); break;
+        default: fused_dispatch<4>(A, m, N, rpb, nb, T, U, F, P, st, rev, s);
     }
-    if (g_out) launch_sum_bands(P, nb, N, g_out, st, s);
+    if (g_out) launch_sum_bands(P, nb, N, g_out, st, s, stw, parts, nparts);
 }
 
 void launch_sum_bands(const float *P, int nb, int N, float *g_out, const ImgState *st,
-                      hipStream_t s) {
+                      hipStream_t s, ImgState *stw, const double *parts, int nparts) {
     if (nb < 1 || nb > kFusedMaxBands) fail(TVCS_EINVAL, "sum_bands: 1 to 256 band partials");
-    hipLaunchKernelGGL(k_sum_bands, dim3((N / 4 + 3) / 4), dim3(256), 0, s, P, nb, N, g_out, st);
+    const int nsum = (N / 4 + kSumCols4 - 1) / kSumCols4;
+    hipLaunchKernelGGL(k_sum_bands, dim3(nsum + (stw ? 1 : 0)), dim3(256), 0, s, P, nb, N, g_out,
+                       st, stw, parts, nparts);
 }
 
 }  // namespace tvcs

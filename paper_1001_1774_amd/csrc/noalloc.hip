@@ -153,7 +153,7 @@ int solve_noalloc_impl(tvcs_ctx *h, const float *f, double mu, double beta, doub
         const int parity = k & 1;
         if (nb > 0) {
             launch_gemv_fused(h->A32.as<float>(), m, N, w.U, w.F, w.P, w.P + (size_t)nb * N, w.st,
-                              s);
+                              parity & TVCS_FUSED_REV, s);
         } else {
             launch_gemv_rows(h->A32.as<float>(), m, N, w.U, N, w.F, m, w.R, m, 1, w.st, 1, s);
             launch_gemv_cols(h->A32.as<float>(), m, N, w.R, m, w.P, N, 1, w.st, 1, s);

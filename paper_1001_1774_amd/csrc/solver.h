@@ -44,6 +44,9 @@ constexpr int kGraphIters = 10;   // iterations per captured graph (even: q ping
 #ifndef TVCS_FUSED_PASS
 #define TVCS_FUSED_PASS 1         // one image, FP32 A, n^2 <= 16384: A u and A^T r in one pass
 #endif
+#ifndef TVCS_FUSED_REV
+#define TVCS_FUSED_REV 1          // the one-pass product alternates its row order per iteration
+#endif
 #ifndef TVCS_FOLD_STOP
 #define TVCS_FOLD_STOP 1          // stop rule folded into the next A u pass (one image FP32; DCT, MFMA)
 #endif
@@ -413,7 +416,8 @@ struct tvcs_ctx {
         } else if (fused() && B == 1) {
             const int nb = fused_bands(m, N);
             launch_gemv_fused(A32.as<float>(), m, N, U.as<float>(), F.as<float>(), PF.as<float>(),
-                              PF.as<float>() + (size_t)nb * N, st, work, fold_prev ? st : nullptr,
+                              PF.as<float>() + (size_t)nb * N, st, parity & TVCS_FUSED_REV, work,
+                              fold_prev ? st : nullptr,
                               fold_prev ? parts.as<double>() : nullptr,
                               fold_prev ? stop_parts(n, B) : 0);
         } else if (fold_prev) {

@@ -80,17 +80,20 @@ void launch_gemv_rows(const float *A, int m, int N, const float *U, int ldu, con
 int gemv_cols_chunks(int m, int N);   // row chunks of the A^T r partial sums
 // One image, both products in one pass (n^2 <= kFusedN): g = A^T (A U - F) into g_out
 // (N floats; null: only the band partials), through nb = fused_bands(m, N) band
-// partials in P (nb x N floats); stw as for launch_gemv_rows.  fused_bands is 0
+// partials in P (nb x N floats); rev (0/1) reverses the order of each band's rows
+// (alternated per iteration); stw as for launch_gemv_rows (applied by the
+// partial-sum kernel, so only with g_out).  fused_bands is 0
 // where the pass does not apply.  launch_sum_bands: g_out = the fixed-order sum of
 // the nb partials.
 constexpr int kFusedN = 16384;
 constexpr int kFusedMaxBands = 256;
 int fused_bands(int m, int N);
 void launch_gemv_fused(const float *A, int m, int N, const float *U, const float *F, float *P,
-                       float *g_out, const ImgState *st, hipStream_t s, ImgState *stw = nullptr,
-                       const double *parts = nullptr, int nparts = 0);
+                       float *g_out, const ImgState *st, int rev, hipStream_t s,
+                       ImgState *stw = nullptr, const double *parts = nullptr, int nparts = 0);
 void launch_sum_bands(const float *P, int nb, int N, float *g_out, const ImgState *st,
-                      hipStream_t s);
+                      hipStream_t s, ImgState *stw = nullptr, const double *parts = nullptr,
+                      int nparts = 0);
 // chunk c of vector v goes to P[c*chunk_stride + v*N + j]
 void launch_gemv_cols(const float *A, int m, int N, const float *R, int ldr, float *P,
                       long long chunk_stride, int nv, const ImgState *active, int nact,
