@@ -14,10 +14,12 @@
 //     the last kBBMemory values + sigma a g'p (non-monotone Armijo test), Phi along
 //     the line being the exact quadratic Phi(v) + a g'p + a^2/2 p'H p, g'p = -p'M p,
 //   * v += a p and r += a A p (r = A v - f is carried, so an inner step costs the
-//     products A^T r and A p).
+//     products A^T r and A p), or, for one image whose A^T (A p) comes from the
+//     one-pass product (A read once for both), g += a A^T A p with g = A^T (A v - f)
+//     carried instead of r (the last inner step needs only A p, for p'H p).
 // One pass (k_bb_apply) does the last two: every workgroup of an image computes the
 // step length from the partials itself (the same fixed-order sums, so the same a),
-// then updates its share of v and r.  The first inner step also saves u^k, and the
+// then updates its share of v and r (or g).  The first inner step also saves u^k, and the
 // last one adds the stop-rule partials ||u^{k+1} - u^k||^2 and ||u^k||^2 of its
 // pixels; k_bb_stop then applies the stop rule (eq. (stop)).
 #include "device_stop.h"
@@ -130,8 +132,9 @@ __device__ inline double bb_length(const double *__restrict__ parts, int nb, BBS
 
 // Inner step j of image b (blockIdx.y), workgroup x of nb: the step length (read
 // from bs_in, the new state written by workgroup 0 to bs_out: the workgroups of the
-// image all read the old state), then v += a p over pixels [x pc, (x + 1) pc) and
-// r += a A p over rows [x rc, (x + 1) rc), FP64 arithmetic, FP32 stores.  j == 0 first
+// image all read the old state), then v += a p over pixels [x pc, (x + 1) pc) (and
+// g += a h there, G non-null) and r += a A p over rows [x rc, (x + 1) rc) (R non-null),
+// FP64 arithmetic, FP32 stores.  j == 0 first
 // copies v to Uk (u^k); the last step (last) writes the block's ||v - u^k||^2 and
 // ||u^k||^2 to nparts (2 doubles per block, fixed-order sums) for the stop rule.
 __global__ __launch_bounds__(kThreads) void k_bb_apply(
@@ -139,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void k_bb_apply(
     const float *__restrict__ AP, int ldr, float *__restrict__ Uk, const double *__restrict__ parts,
     const BBState *__restrict__ bs_in, BBState *__restrict__ bs_out,
     const ImgState *__restrict__ st, int j, int last, double beta, double mu, double mu_tau,
-    double sigma, double *__restrict__ nparts) {
+    double sigma, double *__restrict__ nparts, float *__restrict__ G, const float *__restrict__ H) {
     const int b = blockIdx.y;
     if (!st[b].active) return;
     __shared__ double red[kThreads / 64];
@@ -172,11 +175,19 @@ __global__ __launch_bounds__(kThreads) void k_bb_apply(
             uu += o * o;
         }
     }
-    float *r = R + (size_t)b * ldr;
-    const float *ap = AP + (size_t)b * ldr;
-    const int r0 = blockIdx.x * rc, r1 = min(m, r0 + rc);
-    for (int i = r0 + threadIdx.x; i < r1; i += kThreads)
-        r[i] = (float)((double)r[i] + a * (double)ap[i]);
+    if (G) {
+        float *g = G + (size_t)b * N;
+        const float *h = H + (size_t)b * N;
+        for (int e = p0 + threadIdx.x; e < p1; e += kThreads)
+            g[e] = (float)((double)g[e] + a * (double)h[e]);
+    }
+    if (R) {
+        float *r = R + (size_t)b * ldr;
+        const float *ap = AP + (size_t)b * ldr;
+        const int r0 = blockIdx.x * rc, r1 = min(m, r0 + rc);
+        for (int i = r0 + threadIdx.x; i < r1; i += kThreads)
+            r[i] = (float)((double)r[i] + a * (double)ap[i]);
+    }
     if (last) {
         du = block_sum(du, red);
         uu = block_sum(uu, red);
@@ -201,7 +212,9 @@ int bb_blocks(int n) { return std::max(1, std::min(64, n * n / 1024)); }
 
 void launch_bb_step(int n, int m, int B, float *U, const float *P, float *R, const float *AP,
                     int ldr, float *Uk, double *parts, BBState *bs, const ImgState *st, int j,
-                    bool last, double beta, double mu, double tau, double sigma, hipStream_t s) {
+                    bool last, double beta, double mu, double tau, double sigma, hipStream_t s,
+                    float *G, const float *H) {
+    if (G && !H) fail(TVCS_EINVAL, "bb_step: the gradient update needs A^T A p");
     const int nb = bb_blocks(n);
     hipLaunchKernelGGL(k_bb_partials, dim3(nb, B), dim3(kThreads), 0, s, n, m, P, AP, ldr, parts,
                        st);
@@ -210,7 +223,7 @@ void launch_bb_step(int n, int m, int B, float *U, const float *P, float *R, con
     BBState *bs_out = bs + (size_t)((j + 1) & 1) * B;
     hipLaunchKernelGGL(k_bb_apply, dim3(nb, B), dim3(kThreads), 0, s, n * n, m, U, P, R, AP, ldr,
                        Uk, parts, bs_in, bs_out, st, j, last ? 1 : 0, beta, mu, mu / tau, sigma,
-                       parts + (size_t)3 * B * nb);
+                       parts + (size_t)3 * B * nb, G, H);
 }
 
 void launch_bb_stop(int n, int B, double *parts, ImgState *st, int parity, hipStream_t s) {

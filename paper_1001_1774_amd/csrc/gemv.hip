@@ -304,14 +304,16 @@ __device__ inline double wave_sum_dpp(double x) {
 // over the workgroup (wave shuffles, then the waves' sums in a fixed order through
 // LDS, one barrier per row; the LDS slot alternates with the row so no second
 // barrier is needed), r_i = a_i . u - f_i is rounded to FP32 (as the two-pass path
-// stores it), and r_i a_i is added to the thread's FP64 share of g.  The band's
-// partial g (FP32) goes to P[band * N ..].  (The previous iteration's stop rule,
+// stores it; F null: f = 0; Rout non-null: r_i goes to Rout[i]), and r_i a_i is
+// added to the thread's FP64 share of g.  The band's partial g (FP32) goes to
+// P[band * N ..].  (The previous iteration's stop rule,
 // which k_gemv_rows applies in its workgroup 0, is applied by k_sum_bands here:
 // with one workgroup per CU, a late workgroup 0 would hold up the whole pass.)
 template <int G, bool NT>
 __global__ __launch_bounds__(kFusedThreadsMax) void k_gemv_fused(
     const float *__restrict__ A, int m, int N, int rpb, const float *__restrict__ U,
-    const float *__restrict__ F, float *__restrict__ P, const ImgState *st, int rev) {
+    const float *__restrict__ F, float *__restrict__ P, const ImgState *st, int rev,
+    float *__restrict__ Rout) {
     if (!any_active(st, 1)) return;
     const int T = blockDim.x, t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = T >> 6;
     const int N4 = N >> 2;
@@ -349,7 +351,8 @@ __global__ __launch_bounds__(kFusedThreadsMax) void k_gemv_fused(
         __syncthreads();
         double tot = red[slot][0];
         for (int w = 1; w < nw; ++w) tot += red[slot][w];   // fixed order
-        const double r = (double)(float)(tot - (double)F[row]);
+        const double r = (double)(float)(F ? tot - (double)F[row] : tot);
+        if (Rout && t == 0) Rout[row] = (float)r;
         // keep the FP64 copies of the row from living across the barrier (they are
         // cheaper to convert again than the registers they would hold)
 #pragma unroll
@@ -529,18 +532,19 @@ int fused_bands(int m, int N) {
 
 template <int G>
 void fused_dispatch(const float *A, int m, int N, int rpb, int nb, int T, const float *U,
-                    const float *F, float *P, const ImgState *st, int rev, hipStream_t s) {
+                    const float *F, float *P, const ImgState *st, int rev, float *R,
+                    hipStream_t s) {
     if ((size_t)m * N * sizeof(float) > TVCS_GEMV_NT_BYTES)
         hipLaunchKernelGGL((k_gemv_fused<G, true>), dim3(nb), dim3(T), 0, s, A, m, N, rpb, U, F,
-                           P, st, rev);
+                           P, st, rev, R);
     else
         hipLaunchKernelGGL((k_gemv_fused<G, false>), dim3(nb), dim3(T), 0, s, A, m, N, rpb, U, F,
-                           P, st, rev);
+                           P, st, rev, R);
 }
 
 void launch_gemv_fused(const float *A, int m, int N, const float *U, const float *F, float *P,
                        float *g_out, const ImgState *st, int rev, hipStream_t s, ImgState *stw,
-                       const double *parts, int nparts) {
+                       const double *parts, int nparts, float *r_out) {
     const int nb = fused_bands(m, N);
     if (nb < 1) fail(TVCS_EINVAL, "gemv_fused: n^2 must be a multiple of 4 and at most 16384");
     if (stw && (st != stw || !parts || nparts < 1 || !g_out))
@@ -552,10 +556,10 @@ void launch_gemv_fused(const float *A, int m, int N, const float *U, const float
     const int G = (N4 + kFusedThreadsMax - 1) / kFusedThreadsMax;
     const int T = ((N4 + G - 1) / G + 63) / 64 * 64;
     switch (G) {
-        case 1: fused_dispatch<1>(A, m, N, rpb, nb, T, U, F, P, st, rev, s); break;
-        case 2: fused_dispatch<2>(A, m, N, rpb, nb, T, U, F, P, st, rev, s); break;
-        case 3: fused_dispatch<3>(A, m, N, rpb, nb, T, U, F, P, st, rev, s); break;
-        default: fused_dispatch<4>(A, m, N, rpb, nb, T, U, F, P, st, rev, s);
+        case 1: fused_dispatch<1>(A, m, N, rpb, nb, T, U, F, P, st, rev, r_out, s); break;
+        case 2: fused_dispatch<2>(A, m, N, rpb, nb, T, U, F, P, st, rev, r_out, s); break;
+        case 3: fused_dispatch<3>(A, m, N, rpb, nb, T, U, F, P, st, rev, r_out, s); break;
+        default: fused_dispatch<4>(A, m, N, rpb, nb, T, U, F, P, st, rev, r_out, s);
     }
     if (g_out) launch_sum_bands(P, nb, N, g_out, st, s, stw, parts, nparts);
 }

@@ -47,6 +47,9 @@ constexpr int kGraphIters = 10;   // iterations per captured graph (even: q ping
 #ifndef TVCS_FUSED_REV
 #define TVCS_FUSED_REV 1          // the one-pass product alternates its row order per iteration
 #endif
+#ifndef TVCS_BB_FUSED
+#define TVCS_BB_FUSED 1           // inner BB steps of one image: A p and A^T A p in one pass
+#endif
 #ifndef TVCS_FOLD_STOP
 #define TVCS_FOLD_STOP 1          // stop rule folded into the next A u pass (one image FP32; DCT, MFMA)
 #endif
@@ -86,6 +89,7 @@ struct tvcs_ctx {
     DevBuf Gacc;           // MFMA storage: the running g of the product increments (B x N)
     DevBuf adm_F, adm_U;   // request loop: f and A^T f of newly admitted slots (capP rows)
     DevBuf bb_Uk, bb_P, bb_AP, bb_parts, bb_state;   // IADM with inner BB steps
+    DevBuf bb_H;           // A^T A p of the one-pass inner steps (one image)
     DevBuf DT;             // partial DCT: the half-transformed images between passes
     DevBuf PF;             // one image, FP32 A, n^2 <= kFusedN: band partials of g, then g
     LowpWork lw{};
@@ -273,7 +277,7 @@ struct tvcs_ctx {
         }
         for (DevBuf *b : {&U, &F, &R, &P, &RHS, &Q0, &Q1, &S, &parts, &state, &obj, &lowp_work, &lamb,
                           &counters, &DT, &Gacc, &adm_F, &adm_U, &bb_Uk, &bb_P, &bb_AP, &bb_parts,
-                          &bb_state, &PF})
+                          &bb_state, &bb_H, &PF})
             b->release();
         cap = capP = 0;
     }
@@ -468,7 +472,9 @@ struct tvcs_ctx {
         bb_AP.ensure(sizeof(float) * Bp * (size_t)m);
         bb_parts.ensure(sizeof(double) * 5 * B * (size_t)bb_blocks(n));
         bb_state.ensure(sizeof(BBState) * 2 * B);
+        if (bb_fused(B)) bb_H.ensure(sizeof(float) * Nn);
     }
+    bool bb_fused(int B) const { return TVCS_BB_FUSED && fused() && B == 1; }
 
     // One outer iteration of IADM whose u-step is `inner` steps on the u-subproblem
     // of (ALP) (bb.hip): r = A u - f, then per inner step A^T r, the direction p (shrink
@@ -483,12 +489,31 @@ struct tvcs_ctx {
         const int Bp = padded(B);
         ImgState *st = state.as<ImgState>();
         float *Up = U.as<float>(), *Pd = bb_P.as<float>(), *AP = bb_AP.as<float>();
-        apply_A(Bp, B, Up, F.as<float>(), R.as<float>(), st);
+        // one image with the one-pass product: g = A^T (A u - f) is carried (g += a A^T A p)
+        // and each pass reads A once for A p and A^T A p; the row order alternates
+        // from one pass to the next, ending reversed before the last inner step's
+        // plain A p, which reads forward
+        const bool one = bb_fused(B);
+        const int nb = one ? fused_bands(m, N) : 0;
+        float *Gb = one ? PF.as<float>() + (size_t)nb * N : nullptr;
+        float *Hb = one ? bb_H.as<float>() : nullptr;
+        if (one)
+            launch_gemv_fused(A32.as<float>(), m, N, Up, F.as<float>(), PF.as<float>(), Gb, st,
+                              inner & 1, work);
+        else
+            apply_A(Bp, B, Up, F.as<float>(), R.as<float>(), st);
         const float2 *twp = tw.as<float2>();
         float2 *Sp = S.as<float2>();
         for (int j = 0; j < inner; ++j) {
-            apply_At(Bp, B, R.as<float>(), st);
+            if (!one) apply_At(Bp, B, R.as<float>(), st);
             ShrinkArgs a = shrink_args(B, Bp);
+            if (one) {   // g whole
+                a.G = Gb;
+                a.gnv = 1;
+                a.nchunk = 1;
+                a.g_chunk_stride = N;
+                a.g_group_stride = N;
+            }
             a.beta = beta;
             a.c = c;
             a.ctau = ctau;
@@ -502,10 +527,16 @@ struct tvcs_ctx {
             launch_fft_cols_solve(n, B, Sp, invd.as<double>(), twp, st, work);
             launch_fft_rows_inv(n, B, Sp, Up, parts.as<double>(), twp, st, counters.as<int>(), work,
                                 nullptr, nullptr, false, parity, Pd);
-            apply_A(Bp, B, Pd, nullptr, AP, st);
-            launch_bb_step(n, m, B, Up, Pd, R.as<float>(), AP, m, bb_Uk.as<float>(),
-                           bb_parts.as<double>(), bb_state.as<BBState>(), st, j, j == inner - 1,
-                           beta, mu, tau, kBBSigma, work);
+            const bool fwd_only = !one || j == inner - 1;
+            if (fwd_only)
+                apply_A(Bp, B, Pd, nullptr, AP, st);
+            else
+                launch_gemv_fused(A32.as<float>(), m, N, Pd, nullptr, PF.as<float>(), Hb, st,
+                                  (inner - 1 - j) & 1, work, nullptr, nullptr, 0, AP);
+            launch_bb_step(n, m, B, Up, Pd, one ? nullptr : R.as<float>(), AP, m,
+                           bb_Uk.as<float>(), bb_parts.as<double>(), bb_state.as<BBState>(), st,
+                           j, j == inner - 1, beta, mu, tau, kBBSigma, work,
+                           fwd_only ? nullptr : Gb, Hb);
         }
         // no product-form bookkeeping: every product of this path is fresh
         launch_bb_stop(n, B, bb_parts.as<double>(), st, -1, work);
@@ -591,7 +622,7 @@ struct tvcs_ctx {
                P.bytes + RHS.bytes + Q0.bytes + Q1.bytes + S.bytes + parts.bytes + state.bytes +
                obj.bytes + lowp_work.bytes + lamb.bytes + counters.bytes + Gacc.bytes + adm_F.bytes +
                adm_U.bytes + bb_Uk.bytes + bb_P.bytes + bb_AP.bytes + bb_parts.bytes +
-               bb_state.bytes + PF.bytes;
+               bb_state.bytes + bb_H.bytes + PF.bytes;
     }
 };
 

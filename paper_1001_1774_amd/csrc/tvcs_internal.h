@@ -82,15 +82,16 @@ int gemv_cols_chunks(int m, int N);   // row chunks of the A^T r partial sums
 // (N floats; null: only the band partials), through nb = fused_bands(m, N) band
 // partials in P (nb x N floats); rev (0/1) reverses the order of each band's rows
 // (alternated per iteration); stw as for launch_gemv_rows (applied by the
-// partial-sum kernel, so only with g_out).  fused_bands is 0
-// where the pass does not apply.  launch_sum_bands: g_out = the fixed-order sum of
-// the nb partials.
+// partial-sum kernel, so only with g_out); F null: f = 0; r_out (m floats, or null)
+// receives A U - F as the pass rounds it.  fused_bands is 0 where the pass does not
+// apply.  launch_sum_bands: g_out = the fixed-order sum of the nb partials.
 constexpr int kFusedN = 16384;
 constexpr int kFusedMaxBands = 256;
 int fused_bands(int m, int N);
 void launch_gemv_fused(const float *A, int m, int N, const float *U, const float *F, float *P,
                        float *g_out, const ImgState *st, int rev, hipStream_t s,
-                       ImgState *stw = nullptr, const double *parts = nullptr, int nparts = 0);
+                       ImgState *stw = nullptr, const double *parts = nullptr, int nparts = 0,
+                       float *r_out = nullptr);
 void launch_sum_bands(const float *P, int nb, int N, float *g_out, const ImgState *st,
                       hipStream_t s, ImgState *stw = nullptr, const double *parts = nullptr,
                       int nparts = 0);
@@ -206,13 +207,16 @@ struct BBState {                      // per image, rewritten at the first inner
 };
 int bb_blocks(int n);                 // partial sums per image of the BB reductions
 // Inner step j of the B images (k_bb_partials, k_bb_apply): squared norms of p, D p
-// and A p, the step length, U += a P (B x N) and R += a AP (B x m, row stride ldr);
-// j == 0 first saves U into Uk, and the last step (last) leaves the stop-rule partials
-// of U against Uk.  parts: B x bb_blocks(n) x 5 doubles; bs: 2 B states (the state
-// alternates between the halves with the parity of j).
+// and A p, the step length, U += a P (B x N) and R += a AP (B x m, row stride ldr;
+// skipped for R null); with G non-null also G += a H (B x N: the gradient
+// A^T (A v - f) carried instead of r, H = A^T A p); j == 0 first saves U into Uk, and
+// the last step (last) leaves the stop-rule partials of U against Uk.  parts:
+// B x bb_blocks(n) x 5 doubles; bs: 2 B states (the state alternates between the
+// halves with the parity of j).
 void launch_bb_step(int n, int m, int B, float *U, const float *P, float *R, const float *AP,
                     int ldr, float *Uk, double *parts, BBState *bs, const ImgState *st, int j,
-                    bool last, double beta, double mu, double tau, double sigma, hipStream_t s);
+                    bool last, double beta, double mu, double tau, double sigma, hipStream_t s,
+                    float *G = nullptr, const float *H = nullptr);
 // the stop rule for the outer step from Uk to U, from the partials the last inner
 // step left in parts
 void launch_bb_stop(int n, int B, double *parts, ImgState *st, int parity, hipStream_t s);

@@ -66,20 +66,32 @@ def test_bb_parity(T, name, J, K, bar):
 
 
 def test_bb_batch_equals_single_and_stop_rule(T):
+    """Per-image stopping against the oracle's counts (n = 32, tol 1e-3), for three
+    images solved together (two-pass products) and for each solved alone (one-pass
+    inner steps: A p and A^T A p from one read of A, g carried); and batch invariance
+    where both take the two-pass products (n = 144): bit for bit, same counts."""
     p = synth.make_problem("bbb", n=32, m=307, batch=3, seed_A=31, sigma=[1e-3, 1e-2, 1e-3])
     tau = O.default_tau(p.A)
     F = p.f.astype(np.float32)
+    ref = O.iadm_bb(p.A, p.f, p.n, p.mu, p.beta, tau, tol=1e-3, maxit=300, inner=3)
+    lim = np.maximum(2, 0.25 * ref.iters)
     with T.Solver(p.A.astype(np.float32), p.n) as s:
         s.tau = tau
         rb = s.solve_batch(F, mu=p.mu, beta=p.beta, tol=1e-3, maxit=300, iadm=True, bb_steps=3)
+        it = np.array([st["iters"] for st in rb["stats"]])
+        one = np.array([s.solve(F[b], mu=p.mu, beta=p.beta, tol=1e-3, maxit=300, iadm=True,
+                                bb_steps=3)["stats"]["iters"] for b in range(3)])
+    say(f"  outer iterations batch {it.tolist()} alone {one.tolist()} oracle {ref.iters.tolist()}")
+    assert np.all(np.abs(it - ref.iters) <= lim)
+    assert np.all(np.abs(one - ref.iters) <= lim)
+    q = synth.make_problem("bbb144", n=144, m=2074, batch=3, seed_A=35, sigma=[1e-3, 1e-2, 0])
+    Fq = q.f.astype(np.float32)
+    with T.Solver(q.A.astype(np.float32), q.n) as s:
+        rb = s.solve_batch(Fq, mu=q.mu, beta=q.beta, tol=1e-3, maxit=100, iadm=True, bb_steps=3)
         for b in range(3):
-            r1 = s.solve(F[b], mu=p.mu, beta=p.beta, tol=1e-3, maxit=300, iadm=True, bb_steps=3)
+            r1 = s.solve(Fq[b], mu=q.mu, beta=q.beta, tol=1e-3, maxit=100, iadm=True, bb_steps=3)
             assert r1["stats"]["iters"] == rb["stats"][b]["iters"]
             assert np.array_equal(r1["u"].cpu().numpy(), rb["u"][b].cpu().numpy())
-    ref = O.iadm_bb(p.A, p.f, p.n, p.mu, p.beta, tau, tol=1e-3, maxit=300, inner=3)
-    it = np.array([st["iters"] for st in rb["stats"]])
-    say(f"  outer iterations gpu {it.tolist()} oracle {ref.iters.tolist()}")
-    assert np.all(np.abs(it - ref.iters) <= np.maximum(2, 0.25 * ref.iters))
 
 
 def test_bb_reaches_the_oracle_fixed_point(T):
