@@ -28,6 +28,7 @@
 #include "tvcs_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 
 // Tile parameters (compile-time; the defaults are the measured best on MI355X)
 #ifndef TVCS_GEMV_ROWS
@@ -273,6 +274,12 @@ constexpr int kFusedThreadsMax = 1024;   // up to 16 waves: four per SIMD
 #ifndef TVCS_FUSED_DPP
 #define TVCS_FUSED_DPP 1   // the per-row wave sums through DPP moves (0: shuffles)
 #endif
+#ifndef TVCS_FUSED_ROWS
+#define TVCS_FUSED_ROWS 3  // rows held in registers (ROWS - 1 in flight while one is used)
+#endif
+#ifndef TVCS_FUSED_ACC64
+#define TVCS_FUSED_ACC64 1 // a band's share of g summed in FP64 (0: FP32)
+#endif
 // One 32-bit half of a double through a DPP move (disabled rows give 0)
 template <int CTRL, int ROWS>
 __device__ inline double dpp_f64(double x) {
@@ -326,7 +333,8 @@ __global__ __launch_bounds__(kFusedThreadsMax) void k_gemv_fused(
     __shared__ f4 us[kFusedN / 4];
     __shared__ double red[2][kFusedThreadsMax / 64];
     const int r0 = blockIdx.x * rpb, r1 = min(m, r0 + rpb);
-    double gs[G][4];
+    using acc_t = std::conditional_t<TVCS_FUSED_ACC64 != 0, double, float>;
+    acc_t gs[G][4];
     auto load = [&](f4 (&a)[G], int row) {
         const f4 *rp = reinterpret_cast<const f4 *>(A + (size_t)row * N);
 #pragma unroll
@@ -357,38 +365,40 @@ __global__ __launch_bounds__(kFusedThreadsMax) void k_gemv_fused(
         // cheaper to convert again than the registers they would hold)
 #pragma unroll
         for (int k = 0; k < G; ++k) asm volatile("" : "+v"(a[k]));
+        const acc_t ra = (acc_t)r;
 #pragma unroll
         for (int k = 0; k < G; ++k) {
-            gs[k][0] = fma((double)a[k].x, r, gs[k][0]);
-            gs[k][1] = fma((double)a[k].y, r, gs[k][1]);
-            gs[k][2] = fma((double)a[k].z, r, gs[k][2]);
-            gs[k][3] = fma((double)a[k].w, r, gs[k][3]);
+            gs[k][0] = fma((acc_t)a[k].x, ra, gs[k][0]);
+            gs[k][1] = fma((acc_t)a[k].y, ra, gs[k][1]);
+            gs[k][2] = fma((acc_t)a[k].z, ra, gs[k][2]);
+            gs[k][3] = fma((acc_t)a[k].w, ra, gs[k][3]);
         }
     };
-    // three rows in registers: rows i + 1 and i + 2 are in flight while row i is
+    // R rows in registers: rows i + 1 .. i + R - 1 are in flight while row i is
     // used.  rev: the band's rows last to first (the solve alternates the direction
     // from one iteration to the next, so that each pass starts on the rows the
     // previous one read last, which the Infinity Cache may still hold)
+    constexpr int R = TVCS_FUSED_ROWS;
     const int cnt = r1 - r0;
     auto row_of = [&](int i) { return rev ? r1 - 1 - i : r0 + i; };
-    f4 a0[G], a1[G], a2[G];
-    if (0 < cnt) load(a0, row_of(0));
-    if (1 < cnt) load(a1, row_of(1));
+    f4 rows[R][G];
+#pragma unroll
+    for (int k = 0; k < R - 1; ++k)
+        if (k < cnt) load(rows[k], row_of(k));
     // u after the first rows' loads, so that those are in flight meanwhile
 #pragma unroll
     for (int k = 0; k < G; ++k) {
         const f4 x = reinterpret_cast<const f4 *>(U)[col(k)];
         us[t + k * T] = (k < G - 1 || last_ok) ? x : f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int c = 0; c < 4; ++c) gs[k][c] = 0.0;
+        for (int c = 0; c < 4; ++c) gs[k][c] = 0;
     }
-    for (int i = 0; i < cnt; i += 3) {
-        if (i + 2 < cnt) load(a2, row_of(i + 2));
-        row_term(a0, row_of(i), i);
-        if (i + 3 < cnt) load(a0, row_of(i + 3));
-        if (i + 1 < cnt) row_term(a1, row_of(i + 1), i + 1);
-        if (i + 4 < cnt) load(a1, row_of(i + 4));
-        if (i + 2 < cnt) row_term(a2, row_of(i + 2), i + 2);
+    for (int i = 0; i < cnt; i += R) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if (i + k + R - 1 < cnt) load(rows[(k + R - 1) % R], row_of(i + k + R - 1));
+            if (i + k < cnt) row_term(rows[k], row_of(i + k), i + k);
+        }
     }
     float *out = P + (size_t)blockIdx.x * N;
 #pragma unroll
