@@ -8,7 +8,8 @@
 // p = -M^{-1} grad Phi(v), M = beta D^T D + (mu / tau) I, which the usual u-step
 // kernels compute (shrink pass with q held fixed after the first step, FFT solve,
 // the increment written to a separate array), then
-//   * the squared norms of p, D p and A p (k_bb_partials, fixed-order sums),
+//   * the squared norms of p, D p and A p (k_bb_partials, fixed-order sums; after a
+//     one-pass product, extra workgroups of its band sum),
 //   * the step length a: 1 for the first step (the IADM u-step), else the BB length
 //     (p'M p / p'H p of the previous direction), halved until Phi(v + a p) <= max of
 //     the last kBBMemory values + sigma a g'p (non-monotone Armijo test), Phi along
@@ -19,9 +20,11 @@
 //     carried instead of r (the last inner step needs only A p, for p'H p).
 // One pass (k_bb_apply) does the last two: every workgroup of an image computes the
 // step length from the partials itself (the same fixed-order sums, so the same a),
-// then updates its share of v and r (or g).  The first inner step also saves u^k, and the
-// last one adds the stop-rule partials ||u^{k+1} - u^k||^2 and ||u^k||^2 of its
-// pixels; k_bb_stop then applies the stop rule (eq. (stop)).
+// then updates its share of v and r (or g).  The first inner step also saves u^k,
+// and the last one adds the stop-rule partials ||u^{k+1} - u^k||^2 and ||u^k||^2 of
+// its pixels; k_bb_stop then applies the stop rule (eq. (stop)) (with the one-pass
+// products, the next outer step's first band sum does, but at the end of a graph).
+#include "device_bb.h"
 #include "device_stop.h"
 #include "tvcs_internal.h"
 
@@ -32,55 +35,12 @@ namespace {
 
 constexpr int kThreads = 256;
 
-__device__ inline double block_sum(double x, double *red) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) red[wave] = x;
-    __syncthreads();
-    double t = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];   // fixed order
-    return t;
-}
-
-// block x of image b: sums over pixels [x * pc, (x + 1) * pc) of p^2 and |D p|^2
-// (forward differences, periodic) and over rows [x * rc, (x + 1) * rc) of (A p)^2
-__global__ __launch_bounds__(kThreads) void k_bb_partials(int n, int m, const float *__restrict__ P,
-                                                          const float *__restrict__ AP, int ldap,
-                                                          double *__restrict__ parts,
+// block x of image b (blockIdx.y): the partial sums of the step length's norms
+__global__ __launch_bounds__(kThreads) void k_bb_partials(BBNorms nm,
                                                           const ImgState *__restrict__ st) {
     const int b = blockIdx.y;
     if (!st[b].active) return;
-    __shared__ double red[kThreads / 64];
-    const int N = n * n, nb = gridDim.x;
-    const int pc = (N + nb - 1) / nb, rc = (m + nb - 1) / nb;
-    const float *p = P + (size_t)b * N;
-    double pp = 0.0, dd = 0.0, aa = 0.0;
-    const int p0 = blockIdx.x * pc, p1 = min(N, p0 + pc);
-    for (int e = p0 + threadIdx.x; e < p1; e += kThreads) {
-        const int r = e / n, c = e - r * n;
-        const double v = p[e];
-        const double dx = (double)p[r * n + (c + 1 == n ? 0 : c + 1)] - v;
-        const double dy = (double)p[(r + 1 == n ? 0 : r + 1) * n + c] - v;
-        pp += v * v;
-        dd += dx * dx + dy * dy;
-    }
-    const float *ap = AP + (size_t)b * ldap;
-    const int r0 = blockIdx.x * rc, r1 = min(m, r0 + rc);
-    for (int i = r0 + threadIdx.x; i < r1; i += kThreads) {
-        const double v = ap[i];
-        aa += v * v;
-    }
-    pp = block_sum(pp, red);
-    dd = block_sum(dd, red);
-    aa = block_sum(aa, red);
-    if (threadIdx.x == 0) {
-        double *o = parts + ((size_t)b * nb + blockIdx.x) * 3;
-        o[0] = pp;
-        o[1] = dd;
-        o[2] = aa;
-    }
+    bb_norms_block(nm, b, blockIdx.x);
 }
 
 // The step length of inner step j for image b from the k_bb_partials sums (wave 0;
@@ -189,8 +149,8 @@ __global__ __launch_bounds__(kThreads) void k_bb_apply(
             r[i] = (float)((double)r[i] + a * (double)ap[i]);
     }
     if (last) {
-        du = block_sum(du, red);
-        uu = block_sum(uu, red);
+        du = bb_block_sum(du, red);
+        uu = bb_block_sum(uu, red);
         if (threadIdx.x == 0) {
             nparts[((size_t)b * nb + blockIdx.x) * 2] = du;
             nparts[((size_t)b * nb + blockIdx.x) * 2 + 1] = uu;
@@ -210,14 +170,19 @@ __global__ __launch_bounds__(64) void k_bb_stop(ImgState *__restrict__ st,
 
 int bb_blocks(int n) { return std::max(1, std::min(64, n * n / 1024)); }
 
+BBNorms bb_norms(int n, int m, const float *P, const float *AP, int ldap, double *parts) {
+    return BBNorms{P, AP, parts, n, m, ldap, bb_blocks(n)};
+}
+
 void launch_bb_step(int n, int m, int B, float *U, const float *P, float *R, const float *AP,
                     int ldr, float *Uk, double *parts, BBState *bs, const ImgState *st, int j,
                     bool last, double beta, double mu, double tau, double sigma, hipStream_t s,
-                    float *G, const float *H) {
+                    float *G, const float *H, bool norms_done) {
     if (G && !H) fail(TVCS_EINVAL, "bb_step: the gradient update needs A^T A p");
     const int nb = bb_blocks(n);
-    hipLaunchKernelGGL(k_bb_partials, dim3(nb, B), dim3(kThreads), 0, s, n, m, P, AP, ldr, parts,
-                       st);
+    if (!norms_done)
+        hipLaunchKernelGGL(k_bb_partials, dim3(nb, B), dim3(kThreads), 0, s,
+                           bb_norms(n, m, P, AP, ldr, parts), st);
     // the state ping-pongs between bs[0 .. B) and bs[B .. 2B) by the parity of j
     const BBState *bs_in = bs + (size_t)(j & 1) * B;
     BBState *bs_out = bs + (size_t)((j + 1) & 1) * B;

@@ -24,6 +24,7 @@
 // exact).  r = A u - f is a small residual of O(1) terms, so FP32 accumulation
 // would put an error of ~sqrt(N) eps |A||u| into it; the FP64 units have an
 // order of magnitude more throughput than this HBM-bound loop needs.
+#include "device_bb.h"
 #include "device_stop.h"
 #include "tvcs_internal.h"
 
@@ -418,14 +419,23 @@ __global__ __launch_bounds__(kFusedThreadsMax) void k_gemv_fused(
 // overlaps the sums instead of adding to one workgroup's); the other workgroups
 // may read the flag before or after, and when the rule stops the image some of
 // them still write g, which no later pass of a stopped image reads.
+// nm.parts non-null: nm.nblk workgroups before the others (dispatched first: each
+// takes longer than a workgroup of sums) write the partial sums of the BB step
+// length's norms (device_bb.h) for the image whose A p the pass just wrote.
 constexpr int kSumCols4 = 16;   // float4 columns per workgroup
 __global__ __launch_bounds__(256) void k_sum_bands(const float *__restrict__ P, int nb, int N,
                                                    float *__restrict__ out,
                                                    const ImgState *st, ImgState *stw,
-                                                   const double *parts, int nparts) {
+                                                   const double *parts, int nparts, BBNorms nm) {
     const int N4 = N >> 2;
     const int nsum = (N4 + kSumCols4 - 1) / kSumCols4;   // workgroups of sums
-    if ((int)blockIdx.x >= nsum) {   // the stop-rule workgroup
+    const int nn = nm.parts ? nm.nblk : 0;               // norm-partials workgroups
+    if ((int)blockIdx.x < nn) {
+        if (any_active(st, 1)) bb_norms_block(nm, 0, blockIdx.x);
+        return;
+    }
+    const int bx = (int)blockIdx.x - nn;
+    if (bx >= nsum) {   // the stop-rule workgroup
         if (stw && threadIdx.x < 64 && stw->active) stop_rule(stw, parts, nparts, nullptr);
         return;
     }
@@ -433,7 +443,7 @@ __global__ __launch_bounds__(256) void k_sum_bands(const float *__restrict__ P, 
     constexpr int kSub = 256 / kSumCols4;                 // 16 subsets of bands
     constexpr int kPer = kFusedMaxBands / kSub;           // bands per subset
     const int t = threadIdx.x, c = t % kSumCols4, q = t / kSumCols4;
-    const int j = blockIdx.x * kSumCols4 + c;   // float4 group
+    const int j = bx * kSumCols4 + c;   // float4 group
     const int jc = j < N4 ? j : N4 - 1;
     f4 v[kPer];
 #pragma unroll
@@ -554,12 +564,16 @@ void fused_dispatch(const float *A, int m, int N, int rpb, int nb, int T, const 
 
 void launch_gemv_fused(const float *A, int m, int N, const float *U, const float *F, float *P,
                        float *g_out, const ImgState *st, int rev, hipStream_t s, ImgState *stw,
-                       const double *parts, int nparts, float *r_out) {
+                       const double *parts, int nparts, float *r_out, const BBNorms *norms) {
     const int nb = fused_bands(m, N);
     if (nb < 1) fail(TVCS_EINVAL, "gemv_fused: n^2 must be a multiple of 4 and at most 16384");
     if (stw && (st != stw || !parts || nparts < 1 || !g_out))
         fail(TVCS_EINVAL, "gemv_fused: the folded stop rule needs the image state, its partials "
                           "and the partial-sum pass");
+    if (norms && (!g_out || !r_out || norms->P != U || norms->AP != r_out || norms->n * norms->n != N ||
+                  norms->m != m))
+        fail(TVCS_EINVAL, "gemv_fused: the BB norms are those of U and r_out, with the partial-sum "
+                          "pass");
     const int rpb = (m + nb - 1) / nb;
     // G float4 groups per thread, T threads (a multiple of 64, at most 1024)
     const int N4 = N / 4;
@@ -571,15 +585,17 @@ void launch_gemv_fused(const float *A, int m, int N, const float *U, const float
         case 3: fused_dispatch<3>(A, m, N, rpb, nb, T, U, F, P, st, rev, r_out, s); break;
         default: fused_dispatch<4>(A, m, N, rpb, nb, T, U, F, P, st, rev, r_out, s);
     }
-    if (g_out) launch_sum_bands(P, nb, N, g_out, st, s, stw, parts, nparts);
+    if (g_out) launch_sum_bands(P, nb, N, g_out, st, s, stw, parts, nparts, norms);
 }
 
 void launch_sum_bands(const float *P, int nb, int N, float *g_out, const ImgState *st,
-                      hipStream_t s, ImgState *stw, const double *parts, int nparts) {
+                      hipStream_t s, ImgState *stw, const double *parts, int nparts,
+                      const BBNorms *norms) {
     if (nb < 1 || nb > kFusedMaxBands) fail(TVCS_EINVAL, "sum_bands: 1 to 256 band partials");
     const int nsum = (N / 4 + kSumCols4 - 1) / kSumCols4;
-    hipLaunchKernelGGL(k_sum_bands, dim3(nsum + (stw ? 1 : 0)), dim3(256), 0, s, P, nb, N, g_out,
-                       st, stw, parts, nparts);
+    const BBNorms nm = norms ? *norms : BBNorms{};
+    hipLaunchKernelGGL(k_sum_bands, dim3(nsum + (stw ? 1 : 0) + (norms ? nm.nblk : 0)), dim3(256),
+                       0, s, P, nb, N, g_out, st, stw, parts, nparts, nm);
 }
 
 }  // namespace tvcs

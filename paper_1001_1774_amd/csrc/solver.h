@@ -484,22 +484,30 @@ struct tvcs_ctx {
     // u saved first.
     // With MFMA storage every product is fresh (two-part batch operand, no running g):
     // directions do not shrink the way the increments of the plain iteration do.
+    // fold_prev / stop_here as for enqueue_iteration (one-pass products only: the
+    // previous outer step's stop rule is then applied by the first band sum).
     void enqueue_iteration_bb(int B, int parity, int inner, double mu, double beta, double c,
-                              double ctau, double tau) {
+                              double ctau, double tau, bool fold_prev, bool stop_here) {
         const int Bp = padded(B);
         ImgState *st = state.as<ImgState>();
         float *Up = U.as<float>(), *Pd = bb_P.as<float>(), *AP = bb_AP.as<float>();
         // one image with the one-pass product: g = A^T (A u - f) is carried (g += a A^T A p)
         // and each pass reads A once for A p and A^T A p; the row order alternates
         // from one pass to the next, ending reversed before the last inner step's
-        // plain A p, which reads forward
+        // plain A p, which reads forward; the norms of the step length are added up by
+        // extra workgroups of the band sums
         const bool one = bb_fused(B);
         const int nb = one ? fused_bands(m, N) : 0;
         float *Gb = one ? PF.as<float>() + (size_t)nb * N : nullptr;
         float *Hb = one ? bb_H.as<float>() : nullptr;
+        double *bparts = bb_parts.as<double>();
+        const int nblk = bb_blocks(n);
+        fold_prev = fold_prev && one;
         if (one)
             launch_gemv_fused(A32.as<float>(), m, N, Up, F.as<float>(), PF.as<float>(), Gb, st,
-                              inner & 1, work);
+                              inner & 1, work, fold_prev ? st : nullptr,
+                              fold_prev ? bparts + (size_t)3 * nblk : nullptr,
+                              fold_prev ? nblk : 0);
         else
             apply_A(Bp, B, Up, F.as<float>(), R.as<float>(), st);
         const float2 *twp = tw.as<float2>();
@@ -528,18 +536,20 @@ struct tvcs_ctx {
             launch_fft_rows_inv(n, B, Sp, Up, parts.as<double>(), twp, st, counters.as<int>(), work,
                                 nullptr, nullptr, false, parity, Pd);
             const bool fwd_only = !one || j == inner - 1;
-            if (fwd_only)
+            if (fwd_only) {
                 apply_A(Bp, B, Pd, nullptr, AP, st);
-            else
+            } else {
+                const BBNorms nm = bb_norms(n, m, Pd, AP, m, bparts);
                 launch_gemv_fused(A32.as<float>(), m, N, Pd, nullptr, PF.as<float>(), Hb, st,
-                                  (inner - 1 - j) & 1, work, nullptr, nullptr, 0, AP);
+                                  (inner - 1 - j) & 1, work, nullptr, nullptr, 0, AP, &nm);
+            }
             launch_bb_step(n, m, B, Up, Pd, one ? nullptr : R.as<float>(), AP, m,
-                           bb_Uk.as<float>(), bb_parts.as<double>(), bb_state.as<BBState>(), st,
-                           j, j == inner - 1, beta, mu, tau, kBBSigma, work,
-                           fwd_only ? nullptr : Gb, Hb);
+                           bb_Uk.as<float>(), bparts, bb_state.as<BBState>(), st, j,
+                           j == inner - 1, beta, mu, tau, kBBSigma, work,
+                           fwd_only ? nullptr : Gb, Hb, !fwd_only);
         }
         // no product-form bookkeeping: every product of this path is fresh
-        launch_bb_stop(n, B, bb_parts.as<double>(), st, -1, work);
+        if (!one || stop_here) launch_bb_stop(n, B, bparts, st, -1, work);
     }
 
     void build_graph(int B, unsigned flags, double beta, double c, double ctau) {
@@ -558,7 +568,8 @@ struct tvcs_ctx {
             for (int i = 0; i < kGraphIters; ++i) {
                 if (inner > 1)
                     enqueue_iteration_bb(B, i & 1, inner, ctau * beta, beta, c, ctau,
-                                         ctau * beta / (beta * c));
+                                         ctau * beta / (beta * c), TVCS_FOLD_STOP && i > 0,
+                                         !TVCS_FOLD_STOP || i == kGraphIters - 1);
                 else
                     enqueue_iteration(B, i & 1, (flags & TVCS_IADM) != 0, beta, c, ctau,
                                       fold && i > 0, !fold || i == kGraphIters - 1);

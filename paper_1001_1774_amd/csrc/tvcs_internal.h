@@ -78,23 +78,35 @@ void launch_gemv_rows(const float *A, int m, int N, const float *U, int ldu, con
                       hipStream_t s, ImgState *stw = nullptr, const double *parts = nullptr,
                       int nparts = 0);
 int gemv_cols_chunks(int m, int N);   // row chunks of the A^T r partial sums
+// The partial sums of the BB step length's norms (device_bb.h): nblk blocks per
+// image, 3 doubles each in parts (||p||^2, ||D p||^2 over the block's pixels of P,
+// ||A p||^2 over its rows of AP, row stride ldap)
+struct BBNorms {
+    const float *P;
+    const float *AP;
+    double *parts;
+    int n, m, ldap, nblk;
+};
+BBNorms bb_norms(int n, int m, const float *P, const float *AP, int ldap, double *parts);
 // One image, both products in one pass (n^2 <= kFusedN): g = A^T (A U - F) into g_out
 // (N floats; null: only the band partials), through nb = fused_bands(m, N) band
 // partials in P (nb x N floats); rev (0/1) reverses the order of each band's rows
 // (alternated per iteration); stw as for launch_gemv_rows (applied by the
 // partial-sum kernel, so only with g_out); F null: f = 0; r_out (m floats, or null)
-// receives A U - F as the pass rounds it.  fused_bands is 0 where the pass does not
-// apply.  launch_sum_bands: g_out = the fixed-order sum of the nb partials.
+// receives A U - F as the pass rounds it; norms (non-null, with g_out and r_out):
+// extra workgroups of the partial-sum kernel write the BB norm partials of U and
+// r_out.  fused_bands is 0 where the pass does not apply.  launch_sum_bands: g_out =
+// the fixed-order sum of the nb partials.
 constexpr int kFusedN = 16384;
 constexpr int kFusedMaxBands = 256;
 int fused_bands(int m, int N);
 void launch_gemv_fused(const float *A, int m, int N, const float *U, const float *F, float *P,
                        float *g_out, const ImgState *st, int rev, hipStream_t s,
                        ImgState *stw = nullptr, const double *parts = nullptr, int nparts = 0,
-                       float *r_out = nullptr);
+                       float *r_out = nullptr, const BBNorms *norms = nullptr);
 void launch_sum_bands(const float *P, int nb, int N, float *g_out, const ImgState *st,
                       hipStream_t s, ImgState *stw = nullptr, const double *parts = nullptr,
-                      int nparts = 0);
+                      int nparts = 0, const BBNorms *norms = nullptr);
 // chunk c of vector v goes to P[c*chunk_stride + v*N + j]
 void launch_gemv_cols(const float *A, int m, int N, const float *R, int ldr, float *P,
                       long long chunk_stride, int nv, const ImgState *active, int nact,
@@ -211,14 +223,15 @@ int bb_blocks(int n);                 // partial sums per image of the BB reduct
 // skipped for R null); with G non-null also G += a H (B x N: the gradient
 // A^T (A v - f) carried instead of r, H = A^T A p); j == 0 first saves U into Uk, and
 // the last step (last) leaves the stop-rule partials of U against Uk.  parts:
-// B x bb_blocks(n) x 5 doubles; bs: 2 B states (the state alternates between the
-// halves with the parity of j).
+// B x bb_blocks(n) x 5 doubles (the norm partials first, bb_norms(n, m, P, AP, ldr,
+// parts), which norms_done says are already there); bs: 2 B states (the state
+// alternates between the halves with the parity of j).
 void launch_bb_step(int n, int m, int B, float *U, const float *P, float *R, const float *AP,
                     int ldr, float *Uk, double *parts, BBState *bs, const ImgState *st, int j,
                     bool last, double beta, double mu, double tau, double sigma, hipStream_t s,
-                    float *G = nullptr, const float *H = nullptr);
+                    float *G = nullptr, const float *H = nullptr, bool norms_done = false);
 // the stop rule for the outer step from Uk to U, from the partials the last inner
-// step left in parts
+// step left in parts (at parts + 3 B bb_blocks(n), 2 doubles per block)
 void launch_bb_stop(int n, int B, double *parts, ImgState *st, int parity, hipStream_t s);
 
 // ---------------------------------------------------------------------------
