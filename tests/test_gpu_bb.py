@@ -65,6 +65,26 @@ def test_bb_parity(T, name, J, K, bar):
     assert el <= 10 * bar   # beta (D u - q): a difference of close fields
 
 
+# One-pass inner steps where that product gives each thread 2 and 3 float4 groups of
+# columns (n = 80, 100; 100 also takes the mixed-radix FFTs), J = 3, K = 4: model error
+# (4 seeds) 7.8e-7 and 7.7e-7, so the FP32 bar.
+SIDE_CASES = [(80, 1600), (100, 2500)]
+
+
+@pytest.mark.parametrize("n,m", SIDE_CASES)
+def test_bb_parity_one_pass_sides(T, n, m):
+    p = synth.make_problem(f"bbs{n}", n=n, m=m, batch=1, seed_A=50 + n, sigma=[1e-3])
+    tau = O.default_tau(p.A)
+    say(f"case n={n} m={m} J=3 K=4")
+    ref = O.iadm_bb(p.A, p.f, p.n, p.mu, p.beta, tau, tol=0, maxit=4, inner=3)
+    with T.Solver(p.A.astype(np.float32), p.n) as s:
+        s.tau = tau
+        out = s.solve(p.f[0].astype(np.float32), mu=p.mu, beta=p.beta, maxit=4, iadm=True,
+                      bb_steps=3)
+    assert out["stats"]["iters"] == 4
+    check(out["u"].cpu().numpy(), ref.u[0], 1e-5, "u", say)
+
+
 def test_bb_batch_equals_single_and_stop_rule(T):
     """Per-image stopping against the oracle's counts (n = 32, tol 1e-3), for three
     images solved together (two-pass products) and for each solved alone (one-pass
