@@ -281,17 +281,27 @@ constexpr int kFusedThreadsMax = 1024;   // up to 16 waves: four per SIMD
 #ifndef TVCS_FUSED_ACC64
 #define TVCS_FUSED_ACC64 1 // a band's share of g summed in FP64 (0: FP32)
 #endif
-// One 32-bit half of a double through a DPP move (disabled rows give 0)
+#ifndef TVCS_FUSED_U64
+#define TVCS_FUSED_U64 1   // u held in LDS as FP64 (converted once instead of per row)
+#endif
+#ifndef TVCS_FUSED_XSUM
+#define TVCS_FUSED_XSUM 0  // the waves' sums of a row added by 16-lane DPP steps (0: serially)
+#endif
+// A double through two DPP moves of its 32-bit halves.  Rows the row mask leaves out
+// keep whatever the destination registers held: no zero is written there first, so
+// callers use those lanes' results only where the mask wrote every lane they read.
 template <int CTRL, int ROWS>
 __device__ inline double dpp_f64(double x) {
     const unsigned long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWS, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWS, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, ROWS, 0xF, false);
     return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 // The sum of x over a 64-lane wave (every lane gets it): pairs and quads by quad
 // permutes, 8 and 16 lanes by the half-row and row mirrors, then rows 0 + 1 and
-// 2 + 3 by the row-15 broadcast and all four by the row-31 broadcast into lane 63.
+// 2 + 3 by the row-15 broadcast and all four by the row-31 broadcast into lane 63
+// (rows 0 and 2 take undefined values at the broadcasts; lane 63 reads only rows the
+// masks wrote).
 __device__ inline double wave_sum_dpp(double x) {
     x += dpp_f64<0xB1, 0xF>(x);    // quad_perm [1, 0, 3, 2]
     x += dpp_f64<0x4E, 0xF>(x);    // quad_perm [2, 3, 0, 1]
@@ -308,7 +318,8 @@ __device__ inline double wave_sum_dpp(double x) {
 // Rows [band * rpb, min(m, (band + 1) * rpb)) of A, band = blockIdx.x.  Thread t of
 // T = blockDim.x owns the float4 column groups t, t + T, ..., t + (G - 1) T (only
 // the last may fall past the row: it then reads a valid group and contributes
-// zero); u sits in LDS, rows are loaded two rows ahead, a_i . u is reduced
+// zero); u sits in LDS (as FP64: 128 KiB at n^2 = 16384, converted once instead of
+// once per row), rows are loaded two rows ahead, a_i . u is reduced
 // over the workgroup (wave shuffles, then the waves' sums in a fixed order through
 // LDS, one barrier per row; the LDS slot alternates with the row so no second
 // barrier is needed), r_i = a_i . u - f_i is rounded to FP32 (as the two-pass path
@@ -331,7 +342,8 @@ __global__ __launch_bounds__(kFusedThreadsMax) void k_gemv_fused(
     auto col = [&](int k) { return k == G - 1 ? jlc : t + k * T; };
     // u in LDS (the registers go to a third row in flight); a thread reads only its
     // own groups, so the one barrier of the first row orders these stores
-    __shared__ f4 us[kFusedN / 4];
+    using u4 = std::conditional_t<TVCS_FUSED_U64 != 0, double4, f4>;
+    __shared__ u4 us[kFusedN / 4];
     __shared__ double red[2][kFusedThreadsMax / 64];
     const int r0 = blockIdx.x * rpb, r1 = min(m, r0 + rpb);
     using acc_t = std::conditional_t<TVCS_FUSED_ACC64 != 0, double, float>;
@@ -345,8 +357,8 @@ __global__ __launch_bounds__(kFusedThreadsMax) void k_gemv_fused(
         double d = 0.0;
 #pragma unroll
         for (int k = 0; k < G; ++k) {
-            const f4 x = us[t + k * T];
-            const double xd[4] = {x.x, x.y, x.z, x.w};
+            const u4 x = us[t + k * T];
+            const double xd[4] = {(double)x.x, (double)x.y, (double)x.z, (double)x.w};
             d = dot4(a[k], xd, d);
         }
         if (TVCS_FUSED_DPP) {
@@ -358,8 +370,21 @@ __global__ __launch_bounds__(kFusedThreadsMax) void k_gemv_fused(
         const int slot = idx & 1;
         if (lane == 0) red[slot][wave] = d;
         __syncthreads();
-        double tot = red[slot][0];
-        for (int w = 1; w < nw; ++w) tot += red[slot][w];   // fixed order
+        double tot;
+        if (TVCS_FUSED_XSUM) {   // lanes 0..15 of every wave add the 16 sums alike
+            double v = lane < nw ? red[slot][lane & 15] : 0.0;
+            v += dpp_f64<0xB1, 0xF>(v);
+            v += dpp_f64<0x4E, 0xF>(v);
+            v += dpp_f64<0x141, 0xF>(v);
+            v += dpp_f64<0x140, 0xF>(v);
+            const unsigned long long b = __double_as_longlong(v);
+            const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)b, 0);
+            const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 0);
+            tot = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+        } else {
+            tot = red[slot][0];
+            for (int w = 1; w < nw; ++w) tot += red[slot][w];   // fixed order
+        }
         const double r = (double)(float)(F ? tot - (double)F[row] : tot);
         if (Rout && t == 0) Rout[row] = (float)r;
         // keep the FP64 copies of the row from living across the barrier (they are
@@ -390,7 +415,8 @@ __global__ __launch_bounds__(kFusedThreadsMax) void k_gemv_fused(
 #pragma unroll
     for (int k = 0; k < G; ++k) {
         const f4 x = reinterpret_cast<const f4 *>(U)[col(k)];
-        us[t + k * T] = (k < G - 1 || last_ok) ? x : f4{0.f, 0.f, 0.f, 0.f};
+        const bool ok = k < G - 1 || last_ok;
+        us[t + k * T] = u4{ok ? x.x : 0.f, ok ? x.y : 0.f, ok ? x.z : 0.f, ok ? x.w : 0.f};
 #pragma unroll
         for (int c = 0; c < 4; ++c) gs[k][c] = 0;
     }
