@@ -287,6 +287,12 @@ constexpr int kFusedThreadsMax = 1024;   // up to 16 waves: four per SIMD
 #ifndef TVCS_FUSED_XSUM
 #define TVCS_FUSED_XSUM 0  // the waves' sums of a row added by 16-lane DPP steps (0: serially)
 #endif
+#ifndef TVCS_FUSED_INTERLEAVE
+#define TVCS_FUSED_INTERLEAVE 0   // workgroups take rows b, b + nb, ... instead of a band
+#endif
+#ifndef TVCS_FUSED_STEADY
+#define TVCS_FUSED_STEADY 0   // 1: every trip of the row loop issues its loads (no branch around them)
+#endif
 // A double through two DPP moves of its 32-bit halves.  Rows the row mask leaves out
 // keep whatever the destination registers held: no zero is written there first, so
 // callers use those lanes' results only where the mask wrote every lane they read.
@@ -345,7 +351,13 @@ __global__ __launch_bounds__(kFusedThreadsMax) void k_gemv_fused(
     using u4 = std::conditional_t<TVCS_FUSED_U64 != 0, double4, f4>;
     __shared__ u4 us[kFusedN / 4];
     __shared__ double red[2][kFusedThreadsMax / 64];
-    const int r0 = blockIdx.x * rpb, r1 = min(m, r0 + rpb);
+    // TVCS_FUSED_INTERLEAVE: workgroup b takes rows b, b + nb, b + 2 nb, ... (the
+    // workgroups then read neighbouring rows at the same time); else the band of rpb
+    // consecutive rows from b rpb
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int r0 = TVCS_FUSED_INTERLEAVE ? b : b * rpb;
+    const int r1 = TVCS_FUSED_INTERLEAVE ? m : min(m, r0 + rpb);
+    const int rstep = TVCS_FUSED_INTERLEAVE ? nb : 1;
     using acc_t = std::conditional_t<TVCS_FUSED_ACC64 != 0, double, float>;
     acc_t gs[G][4];
     auto load = [&](f4 (&a)[G], int row) {
@@ -405,8 +417,8 @@ __global__ __launch_bounds__(kFusedThreadsMax) void k_gemv_fused(
     // from one iteration to the next, so that each pass starts on the rows the
     // previous one read last, which the Infinity Cache may still hold)
     constexpr int R = TVCS_FUSED_ROWS;
-    const int cnt = r1 - r0;
-    auto row_of = [&](int i) { return rev ? r1 - 1 - i : r0 + i; };
+    const int cnt = r1 > r0 ? (r1 - r0 + rstep - 1) / rstep : 0;
+    auto row_of = [&](int i) { return r0 + rstep * (rev ? cnt - 1 - i : i); };
     f4 rows[R][G];
 #pragma unroll
     for (int k = 0; k < R - 1; ++k)
@@ -420,10 +432,19 @@ __global__ __launch_bounds__(kFusedThreadsMax) void k_gemv_fused(
 #pragma unroll
         for (int c = 0; c < 4; ++c) gs[k][c] = 0;
     }
+    // TVCS_FUSED_STEADY: every trip issues all R of its loads, one past the band's
+    // end re-reading its last row.  The memory counter retires loads in issue order
+    // and the compiler sizes each wait by the path that issues fewest loads, so with
+    // the loads under a condition a row's first use also waits for the rows issued
+    // after it; without it two rows stay in flight, yet the pass measured slower.
     for (int i = 0; i < cnt; i += R) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            if (i + k + R - 1 < cnt) load(rows[(k + R - 1) % R], row_of(i + k + R - 1));
+            const int nx = i + k + R - 1;
+            if (TVCS_FUSED_STEADY)
+                load(rows[(k + R - 1) % R], row_of(min(nx, cnt - 1)));
+            else if (nx < cnt)
+                load(rows[(k + R - 1) % R], row_of(nx));
             if (i + k < cnt) row_term(rows[k], row_of(i + k), i + k);
         }
     }
