@@ -291,11 +291,40 @@ __device__ inline float2 *idct_lines_lds(const float2 *tl, const float4 *dt, int
     return lds_fft_any<true, P2>(P, Q, n, npair, n, tl);
 }
 
-// the twiddle table of a length-n transform: 512 entries for powers of two, n otherwise
+// the twiddle table of a length-n transform: 512 entries for powers of two, n otherwise.
+// Fetched into registers first and stored to LDS later, so that a pass can issue its
+// other loads in between and wait for all of them once (a loop that stores what it
+// loads waits for each load before it issues the next).
+struct Twiddles {
+    static constexpr int kPer = (kMaxN + kThreads - 1) / kThreads;
+    float2 v[kPer];
+};
+
+template <bool P2>
+__device__ inline void fetch_twiddles(Twiddles &f, const float2 *tw, int n) {
+    const int cnt = P2 ? kMaxN : n;
+#pragma unroll
+    for (int i = 0; i < Twiddles::kPer; ++i) {
+        const int t = threadIdx.x + i * kThreads;
+        if (t < cnt) f.v[i] = tw[t];
+    }
+}
+
+template <bool P2>
+__device__ inline void store_twiddles(const Twiddles &f, float2 *tl, int n) {
+    const int cnt = P2 ? kMaxN : n;
+#pragma unroll
+    for (int i = 0; i < Twiddles::kPer; ++i) {
+        const int t = threadIdx.x + i * kThreads;
+        if (t < cnt) tl[t] = f.v[i];
+    }
+}
+
 template <bool P2>
 __device__ inline void load_twiddles(float2 *tl, const float2 *tw, int n) {
-    const int cnt = P2 ? kMaxN : n;
-    for (int t = threadIdx.x; t < cnt; t += kThreads) tl[t] = tw[t];
+    Twiddles f;
+    fetch_twiddles<P2>(f, tw, n);
+    store_twiddles<P2>(f, tl, n);
 }
 
 }  // namespace fftdev

@@ -46,6 +46,10 @@ namespace {
 
 using namespace fftdev;
 
+// elements per thread whose global operands (denominators, u) the column and inverse
+// row passes load before their FFTs (the rest after them)
+constexpr int kPrefetch = 2;
+
 // tw[t] = exp(-2 pi i t / L), t < L (L = 512 for every power-of-two n, else L = n)
 __global__ void k_twiddles(float2 *tw, int L) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -126,16 +130,22 @@ __global__ __launch_bounds__(kThreads) void k_shrink_pix(ShrinkArgs a, int rpb,
                                                          float2 *__restrict__ S,
                                                          const float2 *__restrict__ tw) {
     const int b = blockIdx.y;
-    if (!a.st[b].active) return;
     extern __shared__ float2 lds[];
     const int n = a.n, npair = rpb >> 1, h = n / 2 + 1;
     const Ring<P2> ring(n);
     const int bufsz = npair * n + rpb;
     float2 *tl = lds, *X = lds + kMaxN, *Y = X + lp_size(bufsz);
     float *gl = reinterpret_cast<float *>(Y + lp_size(bufsz));   // partial DCT: g rows
-    load_twiddles<P2>(tl, tw, n);
+    // the twiddles are fetched before the image's flag is read (both loads in
+    // flight together; the table is read whether or not the image is active)
+    Twiddles twf;
+    fetch_twiddles<P2>(twf, tw, n);
+    if (!a.st[b].active) return;
     const int row0 = xcd_block(blockIdx.x, gridDim.x) * rpb;
-    if (a.T) shrink_g_from_T<P2>(a, b, row0, rpb, tl, X, Y, gl);
+    if (a.T) {
+        store_twiddles<P2>(twf, tl, n);
+        shrink_g_from_T<P2>(a, b, row0, rpb, tl, X, Y, gl);
+    }
     float *Xf = reinterpret_cast<float *>(X);
     const int total = rpb * n;
     for (int e0 = threadIdx.x; e0 < total; e0 += kThreads * PX) {
@@ -157,6 +167,7 @@ __global__ __launch_bounds__(kThreads) void k_shrink_pix(ShrinkArgs a, int rpb,
             Xf[2 * lp((rr >> 1) * n + c) + (rr & 1)] = v;   // even row: real part, odd row: imaginary
         }
     }
+    if (!a.T) store_twiddles<P2>(twf, tl, n);   // used from the row FFT on
     __syncthreads();
     rows_fwd_tail<P2>(n, rpb, X, Y, tl, S + (size_t)b * h * n + row0);
 }
@@ -291,23 +302,47 @@ __global__ __launch_bounds__(kThreads) void k_cols_solve(int n, int cpb, float2 
                                                          const float2 *__restrict__ tw,
                                                          const ImgState *__restrict__ st) {
     const int b = blockIdx.y;
-    if (!st[b].active) return;
     extern __shared__ float2 lds[];
     const int h = n / 2 + 1;
     const int k20 = blockIdx.x * cpb;
     const int nc = min(cpb, h - k20);
     float2 *tl = lds, *X = lds + kMaxN, *Y = X + lp_size(cpb * n);
-    load_twiddles<P2>(tl, tw, n);
+    // The twiddles, each thread's first kPrefetch spectrum entries and denominators
+    // are all loaded before anything waits, and before the image's flag is read
+    // (every address is in bounds whether or not the image is active): one memory
+    // round trip instead of one per loop and one more after the forward FFT.
+    Twiddles twf;
+    fetch_twiddles<P2>(twf, tw, n);
     float2 *col = S + (size_t)b * h * n + (size_t)k20 * n;
-    for (int e = threadIdx.x; e < nc * n; e += kThreads) X[lp(e)] = col[e];
+    const double *id = inv_d + (size_t)k20 * n;
+    float2 cpre[kPrefetch];
+    double dpre[kPrefetch];
+#pragma unroll
+    for (int i = 0; i < kPrefetch; ++i) {
+        const int e = threadIdx.x + i * kThreads;
+        cpre[i] = e < nc * n ? col[e] : make_float2(0.f, 0.f);
+        dpre[i] = e < nc * n ? id[e] : 0.0;
+    }
+    if (!st[b].active) return;
+    store_twiddles<P2>(twf, tl, n);
+#pragma unroll
+    for (int i = 0; i < kPrefetch; ++i) {
+        const int e = threadIdx.x + i * kThreads;
+        if (e < nc * n) X[lp(e)] = cpre[i];
+    }
+    for (int e = threadIdx.x + kPrefetch * kThreads; e < nc * n; e += kThreads) X[lp(e)] = col[e];
     __syncthreads();
     float2 *Z = lds_fft_any<false, P2>(X, Y, n, nc, n, tl);
-    const double *id = inv_d + (size_t)k20 * n;
-    for (int e = threadIdx.x; e < nc * n; e += kThreads) {
+    auto divide = [&](int e, double d) {
         const float2 z = Z[lp(e)];
-        const double d = id[e];
         Z[lp(e)] = make_float2((float)(z.x * d), (float)(z.y * d));
+    };
+#pragma unroll
+    for (int i = 0; i < kPrefetch; ++i) {
+        const int e = threadIdx.x + i * kThreads;
+        if (e < nc * n) divide(e, dpre[i]);
     }
+    for (int e = threadIdx.x + kPrefetch * kThreads; e < nc * n; e += kThreads) divide(e, id[e]);
     __syncthreads();
     float2 *W = (Z == X) ? Y : X;
     const float2 *out = lds_fft_any<true, P2>(Z, W, n, nc, n, tl);
@@ -333,21 +368,54 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
                                                        const float4 *__restrict__ dtab,
                                                        int parity, float *__restrict__ dir) {
     const int b = blockIdx.y;
-    if (!st[b].active) return;
     extern __shared__ float2 lds[];
     const int npair = rpb >> 1, h = n / 2 + 1;
     const Ring<P2> ring(n);
     const int bufsz = npair * n + rpb;
     float2 *tl = lds, *X = lds + kMaxN, *Y = X + lp_size(bufsz);
     float4 *dt = reinterpret_cast<float4 *>(Y + lp_size(bufsz));   // DCT table (T non-null)
-    load_twiddles<P2>(tl, tw, n);
-    if (T)
-        for (int k = threadIdx.x; k < n; k += kThreads) dt[k] = dtab[k];
     const int blk = xcd_block(blockIdx.x, gridDim.x), row0 = blk * rpb;
-    // raw half spectra of the block's rows: Y[rr * h + k]
+    // The twiddles, each thread's first kPrefetch half-spectrum entries and the
+    // pixel pairs of u it will update are all loaded before anything waits, and
+    // before the image's flag is read (every address is in bounds whether or not the
+    // image is active): one memory round trip instead of one per loop and one more
+    // after the inverse FFT.
+    Twiddles twf;
+    fetch_twiddles<P2>(twf, tw, n);
     const float2 *srcS = S + (size_t)b * h * n + row0;
     const float rrpb = 1.0f / (float)rpb;
-    for (int e = threadIdx.x; e < h * rpb; e += kThreads) {
+    float *dstU = U + (size_t)b * n * n + (size_t)row0 * n;
+    float2 spre[kPrefetch];
+    float upre[kPrefetch][2];
+#pragma unroll
+    for (int i = 0; i < kPrefetch; ++i) {
+        const int e = threadIdx.x + i * kThreads;
+        spre[i] = make_float2(0.f, 0.f);
+        if (e < h * rpb) {
+            const int k = div_by(e, rpb, rrpb), rr = e - k * rpb;
+            spre[i] = srcS[(size_t)k * n + rr];
+        }
+        upre[i][0] = upre[i][1] = 0.f;
+        if (!dir && e < npair * n) {
+            const int pr = ring.div(e), j = e - ring.mul(pr);
+            upre[i][0] = dstU[(2 * pr) * n + j];
+            upre[i][1] = dstU[(2 * pr + 1) * n + j];
+        }
+    }
+    if (!st[b].active) return;
+    store_twiddles<P2>(twf, tl, n);
+    if (T)
+        for (int k = threadIdx.x; k < n; k += kThreads) dt[k] = dtab[k];
+    // raw half spectra of the block's rows: Y[rr * h + k]
+#pragma unroll
+    for (int i = 0; i < kPrefetch; ++i) {
+        const int e = threadIdx.x + i * kThreads;
+        if (e < h * rpb) {
+            const int k = div_by(e, rpb, rrpb), rr = e - k * rpb;
+            Y[rr * h + k] = spre[i];
+        }
+    }
+    for (int e = threadIdx.x + kPrefetch * kThreads; e < h * rpb; e += kThreads) {
         const int k = div_by(e, rpb, rrpb), rr = e - k * rpb;
         Y[rr * h + k] = srcS[(size_t)k * n + rr];
     }
@@ -364,7 +432,6 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
     float2 *z = lds_fft_any<true, P2>(X, Y, n, npair, n, tl);
     float2 *W = (z == X) ? Y : X;   // free: receives the new rows for the DCT
     float *Wf = reinterpret_cast<float *>(W);
-    float *dstU = U + (size_t)b * n * n + (size_t)row0 * n;
     double du2 = 0.0, u2 = 0.0;
     if (dir) {   // the increment is a search direction: stored apart, with its squared norm
         float *dstD = dir + (size_t)b * n * n + (size_t)row0 * n;
@@ -376,11 +443,11 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
             du2 += (double)v.x * v.x + (double)v.y * v.y;
         }
     }
-    for (int e = threadIdx.x; !dir && e < npair * n; e += kThreads) {
+    auto update = [&](int e, float u0, float u1) {
         const int pr = ring.div(e), j = e - ring.mul(pr);
         const float2 v = z[lp(e)];
         float *p0 = dstU + (2 * pr) * n + j, *p1 = p0 + n;
-        const double o0 = *p0, o1 = *p1;
+        const double o0 = u0, o1 = u1;
         const float n0 = (float)(o0 + (double)v.x), n1 = (float)(o1 + (double)v.y);
         const double d0 = (double)n0 - o0, d1 = (double)n1 - o1;   // the stored change
         du2 += d0 * d0 + d1 * d1;
@@ -391,6 +458,17 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(int n, int rpb, const flo
             const int q = 2 * lp(pr * n + makhoul_pos(j, n));
             Wf[q] = n0;
             Wf[q + 1] = n1;
+        }
+    };
+    if (!dir) {   // in the order e = t, t + kThreads, ... (the sums' order)
+#pragma unroll
+        for (int i = 0; i < kPrefetch; ++i) {
+            const int e = threadIdx.x + i * kThreads;
+            if (e < npair * n) update(e, upre[i][0], upre[i][1]);
+        }
+        for (int e = threadIdx.x + kPrefetch * kThreads; e < npair * n; e += kThreads) {
+            const int pr = ring.div(e), j = e - ring.mul(pr);
+            update(e, dstU[(2 * pr) * n + j], dstU[(2 * pr + 1) * n + j]);
         }
     }
     if (T) {   // the same for every thread
