@@ -19,6 +19,17 @@ namespace tvcs {
 __device__ inline void stop_rule(ImgState *st, const double *parts, int nparts, int *counter,
                                  int slot = -1) {
     const int lane = threadIdx.x & 63;
+    // the fields the rule reads are loaded with the partials (one round trip); an
+    // image that is no longer active is left alone
+    int iters = 0, status = 0, active = 0, maxit = 0;
+    double tol = 0.0;
+    if (lane == 0) {
+        iters = st->iters + 1;
+        status = st->status;
+        active = st->active;
+        tol = st->tol;
+        maxit = st->maxit;
+    }
     double sd = 0.0, su = 0.0;
     for (int p = lane; p < nparts; p += 64) {
         sd += __hip_atomic_load(parts + 2 * p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -29,19 +40,17 @@ __device__ inline void stop_rule(ImgState *st, const double *parts, int nparts, 
         sd += __shfl_xor(sd, off, 64);
         su += __shfl_xor(su, off, 64);
     }
-    if (lane == 0) {
-        const int iters = st->iters + 1;
-        int status = st->status, active = st->active;
+    if (lane == 0 && active) {
         const double du = sqrt(sd), nu = sqrt(su);
         const double rel = nu > 0.0 ? du / nu : (du > 0.0 ? INFINITY : 0.0);
         if (!isfinite(sd) || !isfinite(su)) {
             status = TVCS_ENONFINITE;
             active = 0;
-        } else if (st->tol > 0.0 && du <= st->tol * nu) {
+        } else if (tol > 0.0 && du <= tol * nu) {
             status = TVCS_OK;
             active = 0;
-        } else if (iters >= st->maxit) {
-            status = st->tol > 0.0 ? TVCS_MAXIT : TVCS_OK;
+        } else if (iters >= maxit) {
+            status = tol > 0.0 ? TVCS_MAXIT : TVCS_OK;
             active = 0;
         }
         st->iters = iters;

@@ -482,11 +482,12 @@ __global__ __launch_bounds__(256) void k_sum_bands(const float *__restrict__ P, 
         return;
     }
     const int bx = (int)blockIdx.x - nn;
-    if (bx >= nsum) {   // the stop-rule workgroup
-        if (stw && threadIdx.x < 64 && stw->active) stop_rule(stw, parts, nparts, nullptr);
+    if (bx >= nsum) {   // the stop-rule workgroup (the rule reads the flag itself)
+        if (stw && threadIdx.x < 64) stop_rule(stw, parts, nparts, nullptr);
         return;
     }
-    if (!any_active(st, 1)) return;
+    // the partials are loaded before the image's flag is read (in bounds either way),
+    // so that one memory round trip covers both
     constexpr int kSub = 256 / kSumCols4;                 // 16 subsets of bands
     constexpr int kPer = kFusedMaxBands / kSub;           // bands per subset
     const int t = threadIdx.x, c = t % kSumCols4, q = t / kSumCols4;
@@ -499,6 +500,7 @@ __global__ __launch_bounds__(256) void k_sum_bands(const float *__restrict__ P, 
         v[i] = b < nb ? reinterpret_cast<const f4 *>(P + (size_t)b * N)[jc]
                       : f4{0.f, 0.f, 0.f, 0.f};
     }
+    if (!any_active(st, 1)) return;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
