@@ -34,6 +34,8 @@ namespace tvcs {
 namespace {
 
 constexpr int kThreads = 256;
+// pixels and rows per thread whose operands k_bb_apply loads before its step length
+constexpr int kApplyPF = 4;
 
 // block x of image b (blockIdx.y): the partial sums of the step length's norms
 __global__ __launch_bounds__(kThreads) void k_bb_partials(BBNorms nm,
@@ -104,10 +106,52 @@ __global__ __launch_bounds__(kThreads) void k_bb_apply(
     const ImgState *__restrict__ st, int j, int last, double beta, double mu, double mu_tau,
     double sigma, double *__restrict__ nparts, float *__restrict__ G, const float *__restrict__ H) {
     const int b = blockIdx.y;
-    if (!st[b].active) return;
     __shared__ double red[kThreads / 64];
     __shared__ double s_a;
     const int nb = gridDim.x;
+    const int pc = (N + nb - 1) / nb, rc = (m + nb - 1) / nb;
+    const int p0 = blockIdx.x * pc, p1 = min(N, p0 + pc);
+    const int r0 = blockIdx.x * rc, r1 = min(m, r0 + rc);
+    float *u = U + (size_t)b * N;
+    const float *p = P + (size_t)b * N;
+    float *uk = Uk + (size_t)b * N;
+    float *g = G ? G + (size_t)b * N : nullptr;
+    const float *h = G ? H + (size_t)b * N : nullptr;
+    float *r = R ? R + (size_t)b * ldr : nullptr;
+    const float *ap = R ? AP + (size_t)b * ldr : nullptr;
+    // Each thread's first kApplyPF pixels and rows of every operand are loaded before
+    // the image's flag is read and before the step length is known (none depends on
+    // it, every address is in bounds either way): their memory round trip overlaps
+    // the partial sums' instead of following it.
+    // (indices past the block's range read a valid element instead, so that no load
+    // sits under a branch; those values are never used)
+    const bool wuk = last && j != 0;   // u^k is read (the first step writes it)
+    float xu[kApplyPF], xp[kApplyPF], xk[kApplyPF], xg[kApplyPF], xh[kApplyPF], xr[kApplyPF],
+        xa[kApplyPF];
+#pragma unroll
+    for (int i = 0; i < kApplyPF; ++i) {
+        const int e = min(p0 + (int)threadIdx.x + i * kThreads, N - 1);
+        xu[i] = u[e];
+        xp[i] = p[e];
+    }
+    if (wuk)
+#pragma unroll
+        for (int i = 0; i < kApplyPF; ++i) xk[i] = uk[min(p0 + (int)threadIdx.x + i * kThreads, N - 1)];
+    if (G)
+#pragma unroll
+        for (int i = 0; i < kApplyPF; ++i) {
+            const int e = min(p0 + (int)threadIdx.x + i * kThreads, N - 1);
+            xg[i] = g[e];
+            xh[i] = h[e];
+        }
+    if (R)
+#pragma unroll
+        for (int i = 0; i < kApplyPF; ++i) {
+            const int q = min(r0 + (int)threadIdx.x + i * kThreads, m - 1);
+            xr[i] = r[q];
+            xa[i] = ap[q];
+        }
+    if (!st[b].active) return;
     if (threadIdx.x < 64) {
         BBState s = bs_in[b];
         const double a = bb_length(parts, nb, s, b, j, beta, mu, mu_tau, sigma);
@@ -118,35 +162,41 @@ __global__ __launch_bounds__(kThreads) void k_bb_apply(
     }
     __syncthreads();
     const double a = s_a;
-    const int pc = (N + nb - 1) / nb, rc = (m + nb - 1) / nb;
-    const int p0 = blockIdx.x * pc, p1 = min(N, p0 + pc);
-    float *u = U + (size_t)b * N;
-    const float *p = P + (size_t)b * N;
-    float *uk = Uk + (size_t)b * N;
     double du = 0.0, uu = 0.0;
-    for (int e = p0 + threadIdx.x; e < p1; e += kThreads) {
-        const float old = u[e];
+    auto upd_u = [&](int e, float old, float pe, float ke) {
         if (j == 0) uk[e] = old;
-        const float nv = (float)((double)old + a * (double)p[e]);
+        const float nv = (float)((double)old + a * (double)pe);
         u[e] = nv;
         if (last) {
-            const double o = j == 0 ? (double)old : (double)uk[e], d = (double)nv - o;
+            const double o = j == 0 ? (double)old : (double)ke, d = (double)nv - o;
             du += d * d;
             uu += o * o;
         }
+    };
+#pragma unroll
+    for (int i = 0; i < kApplyPF; ++i) {
+        const int e = p0 + threadIdx.x + i * kThreads;
+        if (e < p1) upd_u(e, xu[i], xp[i], xk[i]);
     }
+    for (int e = p0 + threadIdx.x + kApplyPF * kThreads; e < p1; e += kThreads)
+        upd_u(e, u[e], p[e], wuk ? uk[e] : 0.f);
     if (G) {
-        float *g = G + (size_t)b * N;
-        const float *h = H + (size_t)b * N;
-        for (int e = p0 + threadIdx.x; e < p1; e += kThreads)
+#pragma unroll
+        for (int i = 0; i < kApplyPF; ++i) {
+            const int e = p0 + threadIdx.x + i * kThreads;
+            if (e < p1) g[e] = (float)((double)xg[i] + a * (double)xh[i]);
+        }
+        for (int e = p0 + threadIdx.x + kApplyPF * kThreads; e < p1; e += kThreads)
             g[e] = (float)((double)g[e] + a * (double)h[e]);
     }
     if (R) {
-        float *r = R + (size_t)b * ldr;
-        const float *ap = AP + (size_t)b * ldr;
-        const int r0 = blockIdx.x * rc, r1 = min(m, r0 + rc);
-        for (int i = r0 + threadIdx.x; i < r1; i += kThreads)
-            r[i] = (float)((double)r[i] + a * (double)ap[i]);
+#pragma unroll
+        for (int i = 0; i < kApplyPF; ++i) {
+            const int q = r0 + threadIdx.x + i * kThreads;
+            if (q < r1) r[q] = (float)((double)xr[i] + a * (double)xa[i]);
+        }
+        for (int q = r0 + threadIdx.x + kApplyPF * kThreads; q < r1; q += kThreads)
+            r[q] = (float)((double)r[q] + a * (double)ap[q]);
     }
     if (last) {
         du = bb_block_sum(du, red);

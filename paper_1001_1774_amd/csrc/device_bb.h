@@ -60,17 +60,34 @@ __device__ inline void bb_norms_block(const BBNorms &nm, int b, int x) {
     const float *p = nm.P + (size_t)b * N;
     double pp = 0.0, dd = 0.0, aa = 0.0;
     const int p0 = x * pc, p1 = min(N, p0 + pc);
-    for (int e = p0 + threadIdx.x; e < p1; e += blockDim.x) {
-        const int r = e / n, c = e - r * n;
-        const double v = p[e];
-        const double dx = (double)p[r * n + (c + 1 == n ? 0 : c + 1)] - v;
-        const double dy = (double)p[(r + 1 == n ? 0 : r + 1) * n + c] - v;
-        pp += v * v;
-        dd += dx * dx + dy * dy;
+    const int T = blockDim.x;
+    // kNormBatch pixels per thread at a time: their loads are issued together (an
+    // index past the range reads a valid pixel whose values are not used), then
+    // added in the order e = p0 + t, p0 + t + T, ...
+    constexpr int kNormBatch = 4;
+    for (int e0 = p0 + threadIdx.x; e0 < p1; e0 += kNormBatch * T) {
+        float v[kNormBatch], vx[kNormBatch], vy[kNormBatch];
+#pragma unroll
+        for (int i = 0; i < kNormBatch; ++i) {
+            const int e = min(e0 + i * T, N - 1);
+            const int r = e / n, c = e - r * n;
+            v[i] = p[e];
+            vx[i] = p[r * n + (c + 1 == n ? 0 : c + 1)];
+            vy[i] = p[(r + 1 == n ? 0 : r + 1) * n + c];
+        }
+#pragma unroll
+        for (int i = 0; i < kNormBatch; ++i) {   // selects, not branches: no load sinks
+            const bool ok = e0 + i * T < p1;
+            const double vv = v[i];
+            const double dx = (double)vx[i] - vv;
+            const double dy = (double)vy[i] - vv;
+            pp = ok ? pp + vv * vv : pp;
+            dd = ok ? dd + (dx * dx + dy * dy) : dd;
+        }
     }
     const float *ap = nm.AP + (size_t)b * nm.ldap;
     const int r0 = x * rc, r1 = min(m, r0 + rc);
-    for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+    for (int i = r0 + threadIdx.x; i < r1; i += T) {
         const double v = ap[i];
         aa += v * v;
     }
