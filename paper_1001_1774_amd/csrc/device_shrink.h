@@ -73,10 +73,14 @@ __device__ inline double g_at(const ShrinkArgs &a, int b, int p) {
 // recomputes q at the left and upper neighbours it needs for D^T ----------------
 // Everything the right-hand side at one pixel reads from memory.  Loading several
 // pixels' inputs before computing any of them keeps many loads in flight.
+// Loaded values stay in their stored FP32 form until finish_pix widens them: a
+// conversion right after a load would wait for it there, before the other loads.
 struct PixIn {
     float u0, uE, uS, uW, uSW, uN, uNE;   // u at (r,c), (r,c+1), (r+1,c), (r,c-1), (r+1,c-1), (r-1,c), (r-1,c+1)
-    D2 o0, oW, oN;                        // q^{k-1} at (r,c), (r,c-1), (r-1,c) (IADM)
-    double gk;                            // g_k = (A^T (A u - f)) at (r,c)
+    float2 q0, qW, qN;                    // q^{k-1} at (r,c), (r,c-1), (r-1,c) (IADM)
+    double gk;                            // g_k = (A^T (A u - f)) at (r,c), unless single
+    float g1;                             // single: g_k is this one stored partial
+    bool single;
 };
 
 template <bool IADM, int PL, bool P2>
@@ -97,12 +101,17 @@ __device__ inline PixIn load_pix(const ShrinkArgs &a, int b, int p, bool with_g)
     if (IADM) {
         const float2 *Q = a.Qold + (size_t)b * N;
         const int pW = ring.mul(r) + ring.wrap(c - 1), pN = ring.mul(ring.wrap(r - 1)) + c;
-        const float2 x0 = Q[p], xW = Q[pW], xN = Q[pN];
-        in.o0 = {x0.x, x0.y};
-        in.oW = {xW.x, xW.y};
-        in.oN = {xN.x, xN.y};
+        in.q0 = Q[p];
+        in.qW = Q[pW];
+        in.qN = Q[pN];
     }
-    in.gk = with_g ? g_at<PL>(a, b, p) : 0.0;
+    // one partial and no running g (one image with FP32 storage): g_k is that value
+    in.single = with_g && a.nchunk == 1 && !a.Gacc;
+    in.gk = 0.0;
+    if (in.single)
+        in.g1 = a.G[(size_t)(b / a.gnv) * a.g_group_stride + (size_t)(b % a.gnv) * N + p];
+    else if (with_g)
+        in.gk = g_at<PL>(a, b, p);
     return in;
 }
 
@@ -116,15 +125,18 @@ __device__ inline double finish_pix(const ShrinkArgs &a, int b, int p, const Pix
     const D2 dN = {(double)in.uNE - in.uN, u0 - in.uN};                  // D u at (r-1, c)
     const double ib = 1.0 / a.beta;
     const bool fz = IADM && a.frozen;   // q held fixed: the given field itself
-    const D2 q0 = fz ? in.o0 : q_of<IADM>(d0, in.o0, ib), qW = fz ? in.oW : q_of<IADM>(dW, in.oW, ib),
-             qN = fz ? in.oN : q_of<IADM>(dN, in.oN, ib);
+    const D2 o0 = {in.q0.x, in.q0.y}, oW = {in.qW.x, in.qW.y}, oN = {in.qN.x, in.qN.y};
+    const D2 q0 = fz ? o0 : q_of<IADM>(d0, o0, ib), qW = fz ? oW : q_of<IADM>(dW, oW, ib),
+             qN = fz ? oN : q_of<IADM>(dN, oN, ib);
     if (IADM && !fz) {
         const int N = a.n * a.n;
         a.Qnew[(size_t)b * N + p] = make_float2((float)q0.x, (float)q0.y);
     }
     // D^T (q - D u) at (r, c): needs (q - D u) here, at (r, c-1) and at (r-1, c)
     const double dtq = ((qW.x - dW.x) - (q0.x - d0.x)) + ((qN.y - dN.y) - (q0.y - d0.y));
-    return dtq - a.ctau * in.gk;
+    // 0 + g as g_at forms it (a partial of -0 gives +0 there too)
+    const double gk = in.single ? 0.0 + (double)in.g1 : in.gk;
+    return dtq - a.ctau * gk;
 }
 
 }  // namespace shrinkdev

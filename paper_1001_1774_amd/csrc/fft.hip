@@ -140,22 +140,38 @@ __global__ __launch_bounds__(kThreads) void k_shrink_pix(ShrinkArgs a, int rpb,
     // flight together; the table is read whether or not the image is active)
     Twiddles twf;
     fetch_twiddles<P2>(twf, tw, n);
-    if (!a.st[b].active) return;
     const int row0 = xcd_block(blockIdx.x, gridDim.x) * rpb;
+    const int total = rpb * n;
+    // Without the partial DCT's g pass and the running g of MFMA storage (which
+    // load_pix updates), loading a pixel has no side effect: the first round of
+    // pixels is then loaded before the image's flag is read (an index past the block
+    // reads its last pixel, unused, so that no load sits under a branch).
+    const bool early = !a.T && !a.Gacc;
+    shrinkdev::PixIn pre[PX];
+    if (early)
+#pragma unroll
+        for (int j = 0; j < PX; ++j)
+            pre[j] = shrinkdev::load_pix<IADM, PL, P2>(
+                a, b, ring.mul(row0) + min((int)threadIdx.x + j * kThreads, total - 1), true);
+    if (!a.st[b].active) return;
     if (a.T) {
         store_twiddles<P2>(twf, tl, n);
         shrink_g_from_T<P2>(a, b, row0, rpb, tl, X, Y, gl);
     }
     float *Xf = reinterpret_cast<float *>(X);
-    const int total = rpb * n;
     for (int e0 = threadIdx.x; e0 < total; e0 += kThreads * PX) {
         shrinkdev::PixIn in[PX];
+        if (early && e0 == (int)threadIdx.x) {
 #pragma unroll
-        for (int j = 0; j < PX; ++j) {
-            const int e = e0 + j * kThreads;
-            if (e < total) {
-                in[j] = shrinkdev::load_pix<IADM, PL, P2>(a, b, ring.mul(row0) + e, !a.T);
-                if (a.T) in[j].gk = gl[e];
+            for (int j = 0; j < PX; ++j) in[j] = pre[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < PX; ++j) {
+                const int e = e0 + j * kThreads;
+                if (e < total) {
+                    in[j] = shrinkdev::load_pix<IADM, PL, P2>(a, b, ring.mul(row0) + e, !a.T);
+                    if (a.T) in[j].gk = gl[e];
+                }
             }
         }
 #pragma unroll
