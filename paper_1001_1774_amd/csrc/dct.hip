@@ -58,6 +58,9 @@ struct DctLds {
     float2 *X, *Y; // FFT buffers
 };
 
+// entries per thread of a column block that k_dct_cols loads before its flag
+constexpr int kDctPF = 4;
+
 __device__ inline DctLds dct_lds(int n, int lines) {
     extern __shared__ float2 lds[];
     DctLds L;
@@ -73,10 +76,36 @@ size_t dct_lds_bytes(int n, int lines) {
 }
 
 
+// The twiddles and the DCT table (n <= kMaxN entries), fetched into registers and
+// stored to LDS later: a loop that stores what it loads waits for every load in turn.
+struct DctTables {
+    Twiddles tw;
+    float4 dt[(kMaxN + kThreads - 1) / kThreads];
+};
+
+template <bool P2>
+__device__ inline void fetch_tables(DctTables &f, int n, const float2 *tw, const float4 *tab) {
+    fetch_twiddles<P2>(f.tw, tw, n);
+#pragma unroll
+    for (int i = 0; i < (kMaxN + kThreads - 1) / kThreads; ++i)
+        f.dt[i] = tab[min((int)threadIdx.x + i * kThreads, n - 1)];   // in bounds, unused past n
+}
+
+template <bool P2>
+__device__ inline void store_tables(const DctTables &f, const DctLds &L, int n) {
+    store_twiddles<P2>(f.tw, L.tl, n);
+#pragma unroll
+    for (int i = 0; i < (kMaxN + kThreads - 1) / kThreads; ++i) {
+        const int k = threadIdx.x + i * kThreads;
+        if (k < n) L.dt[k] = f.dt[i];
+    }
+}
+
 template <bool P2>
 __device__ inline void load_tables(const DctLds &L, int n, const float2 *tw, const float4 *tab) {
-    load_twiddles<P2>(L.tl, tw, n);
-    for (int k = threadIdx.x; k < n; k += kThreads) L.dt[k] = tab[k];
+    DctTables f;
+    fetch_tables<P2>(f, n, tw, tab);
+    store_tables<P2>(f, L, n);
 }
 
 template <bool P2>
@@ -130,6 +159,27 @@ __global__ __launch_bounds__(kThreads) void k_dct_cols(int n, int lines, float *
                                                        const ImgState *st, ImgState *stw,
                                                        const double *parts, int nparts) {
     const int b = blockIdx.y;
+    const DctLds L = dct_lds(n, lines);
+    const Ring<P2> ring(n);
+    const int N = n * n, col0 = blockIdx.x * lines, total = lines * n;
+    float *col = T + (size_t)b * N + (size_t)col0 * n;
+    const int *sel = selT + (size_t)col0 * n;
+    float *Rb = R + (size_t)b * ldr;
+    const float *Fb = F ? F + (size_t)b * ldf : nullptr;
+    // The tables and each thread's first kDctPF entries of the block's columns and of
+    // its coefficient map are loaded first, before the stop rule and the image's flag
+    // (every address is in bounds whether or not the image is active; an index past
+    // the block reads its last entry, unused): one memory round trip for all of them.
+    DctTables tabs;
+    fetch_tables<P2>(tabs, n, tw, tab);
+    float cv[kDctPF];
+    int sv[kDctPF];
+#pragma unroll
+    for (int i = 0; i < kDctPF; ++i) {
+        const int e = min((int)threadIdx.x + i * kThreads, total - 1);
+        if (FWD) cv[i] = col[e];
+        sv[i] = sel[e];
+    }
     // stw: the first workgroup of each image first applies the previous iteration's
     // stop rule to it, as in the A u product of FP32 storage (the image's other
     // workgroups may read the flag before or after; a stopped image's r and
@@ -140,40 +190,60 @@ __global__ __launch_bounds__(kThreads) void k_dct_cols(int n, int lines, float *
         __syncthreads();
     }
     if (st && !st[b].active) return;
-    const DctLds L = dct_lds(n, lines);
-    load_tables<P2>(L, n, tw, tab);
-    const Ring<P2> ring(n);
-    const int N = n * n, col0 = blockIdx.x * lines;
-    float *col = T + (size_t)b * N + (size_t)col0 * n;
-    const int *sel = selT + (size_t)col0 * n;
-    float *Rb = R + (size_t)b * ldr;
+    // the measurements (or residuals) of the kept coefficients among those entries:
+    // issued now, used after the FFT
+    float mv[kDctPF];
+#pragma unroll
+    for (int i = 0; i < kDctPF; ++i) {
+        const int s = max(sv[i], 0);
+        mv[i] = FWD ? (Fb ? Fb[s] : 0.f) : Rb[s];
+    }
+    store_tables<P2>(tabs, L, n);
     float2 *P = L.X, *Q = L.Y;   // inverse transform: built in P from the staging in Q
     if (FWD) {
         float *Xf = reinterpret_cast<float *>(L.X);
-        for (int e = threadIdx.x; e < lines * n; e += kThreads) {
+        auto put = [&](int e, float x) {
             const int l = ring.div(e), j = e - ring.mul(l);
-            Xf[2 * lp((l >> 1) * n + makhoul_pos(j, n)) + (l & 1)] = col[e];
+            Xf[2 * lp((l >> 1) * n + makhoul_pos(j, n)) + (l & 1)] = x;
+        };
+#pragma unroll
+        for (int i = 0; i < kDctPF; ++i) {
+            const int e = threadIdx.x + i * kThreads;
+            if (e < total) put(e, cv[i]);
         }
+        for (int e = threadIdx.x + kDctPF * kThreads; e < total; e += kThreads) put(e, col[e]);
         __syncthreads();
         const float2 *Z = lds_fft_any<false, P2>(L.X, L.Y, n, lines >> 1, n, L.tl);
-        const float *Fb = F ? F + (size_t)b * ldf : nullptr;
         // the residual is staged in the FFT buffer that does not hold Z
         P = const_cast<float2 *>(Z);
         Q = (Z == L.X) ? L.Y : L.X;
         float *A = reinterpret_cast<float *>(Q);
-        for (int e = threadIdx.x; e < lines * n; e += kThreads) {
+        auto res = [&](int e, int s, float f) {
             const int l = ring.div(e), k = e - ring.mul(l);
-            const int s = sel[e];
             float rv = 0.f;
             if (s >= 0) {
-                rv = dct_coef<P2>(Z, L.dt, n, l, k) - (Fb ? Fb[s] : 0.f);
+                rv = dct_coef<P2>(Z, L.dt, n, l, k) - f;
                 Rb[s] = rv;
             }
             if (ADJ) A[e] = rv;
+        };
+#pragma unroll
+        for (int i = 0; i < kDctPF; ++i) {
+            const int e = threadIdx.x + i * kThreads;
+            if (e < total) res(e, sv[i], mv[i]);
+        }
+        for (int e = threadIdx.x + kDctPF * kThreads; e < total; e += kThreads) {
+            const int s = sel[e];
+            res(e, s, s >= 0 && Fb ? Fb[s] : 0.f);
         }
     } else {
         float *A = reinterpret_cast<float *>(Q);
-        for (int e = threadIdx.x; e < lines * n; e += kThreads) {
+#pragma unroll
+        for (int i = 0; i < kDctPF; ++i) {
+            const int e = threadIdx.x + i * kThreads;
+            if (e < total) A[e] = sv[i] >= 0 ? mv[i] : 0.f;
+        }
+        for (int e = threadIdx.x + kDctPF * kThreads; e < total; e += kThreads) {
             const int s = sel[e];
             A[e] = s >= 0 ? Rb[s] : 0.f;
         }
