@@ -85,6 +85,22 @@ def test_bb_parity_one_pass_sides(T, n, m):
     check(out["u"].cpu().numpy(), ref.u[0], 1e-5, "u", say)
 
 
+# n = 144 (N = 20736): the two-pass products, and 20 blocks of 1037 pixels per image in
+# the step-length and update passes, so those passes also run the loop that follows
+# each thread's first 4 pixels; J = 3, K = 4, the FP32 bar.
+def test_bb_parity_two_pass_side_144(T):
+    p = synth.make_problem("bbs144", n=144, m=2074, batch=1, seed_A=194, sigma=[1e-3])
+    tau = O.default_tau(p.A)
+    say("case n=144 m=2074 J=3 K=4")
+    ref = O.iadm_bb(p.A, p.f, p.n, p.mu, p.beta, tau, tol=0, maxit=4, inner=3)
+    with T.Solver(p.A.astype(np.float32), p.n) as s:
+        s.tau = tau
+        out = s.solve(p.f[0].astype(np.float32), mu=p.mu, beta=p.beta, maxit=4, iadm=True,
+                      bb_steps=3)
+    assert out["stats"]["iters"] == 4
+    check(out["u"].cpu().numpy(), ref.u[0], 1e-5, "u", say)
+
+
 def test_bb_batch_equals_single_and_stop_rule(T):
     """Per-image stopping against the oracle's counts (n = 32, tol 1e-3), for three
     images solved together (two-pass products) and for each solved alone (one-pass
